@@ -1,0 +1,578 @@
+/*
+ * CPU oracle for the six elastic distances of Herrmann & Webb, "Early
+ * Abandoning and Pruning for Elastic Distances including Dynamic Time
+ * Warping" (arXiv 2102.05221).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package's smoke check
+ * and the benchmark's CPU-baseline leg load this library.  It shares no code,
+ * header, table or constant with the device library, and the device library
+ * never loads it.
+ *
+ * Arithmetic: IEEE binary64, round to nearest even, built with
+ * -ffp-contract=off (no fused multiply-add), no fast-math.  Cell formulas use
+ * one fixed operation order per distance (documented at each formula).
+ *
+ * Contents
+ *   orc_dp        the full cost matrix of eq. (Common) for each distance
+ *                 (Section 2.3: eqs. DTW, ERP, MSM/MSMCost, TWE/TWECost, the
+ *                 WDTW weight, and the Sakoe-Chiba window of Section 2.3.2);
+ *                 the plain definition, O(L_S * L_T) memory.
+ *   orc_brute     minimum over every monotone lattice path, enumerated
+ *                 explicitly (the guarantees listed after eq. Common).
+ *   orc_eap       EAPruned, Alg. 5 (Section 4.3), in the paper's stage order,
+ *                 with a cell counter; the three readings this file takes
+ *                 where the printed algorithm is incomplete are marked READING.
+ *   orc_ub        cost of the diagonal-then-straight warping path, an upper
+ *                 bound usable as a prune-only cut-off (Section 4, intro).
+ *   orc_nn1       NN search, Alg. 1 (strict '<', lowest index wins ties).
+ *   orc_pairwise  all pairs i<j, plain DP or prune-only EAPruned.
+ *
+ * Parity status: DTW, CDTW, ERP and MSM are pinned by the paper's worked
+ * example, brute force and closed forms.  The WDTW recurrence (weight times
+ * squared difference) and the TWE reading (L1 cost, s_0 = t_0 = 0, uniform
+ * timestamps tau_i = i) are pinned by brute force and limit cases but the paper
+ * prints no value for them: parity unpinned against the paper's numbers.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_DTW = 0, ORC_CDTW = 1, ORC_WDTW = 2, ORC_ERP = 3, ORC_MSM = 4, ORC_TWE = 5 };
+
+/* prm[] layout used by every entry point: window_ratio, g, gap, c, nu, lambda */
+enum { P_WR = 0, P_G = 1, P_GAP = 2, P_C = 3, P_NU = 4, P_LAMBDA = 5 };
+
+#define INF HUGE_VAL
+
+static double dmin2(double a, double b) { return a < b ? a : b; }
+static double dmin3(double a, double b, double c) { return dmin2(dmin2(a, b), c); }
+static int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
+static int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+static int64_t iabs(int64_t a) { return a < 0 ? -a : a; }
+
+/* Window (Section 2.3.2): cells with |i - j| > w are outside the band.
+ * Reading: the workloads give the window as a ratio of the longer length,
+ * w = floor(ratio * max(L_S, L_T)); ratio >= 1 (or +inf) is no constraint.
+ * Only CDTW and ERP take a window; the other distances are unconstrained.
+ * "Unconstrained" is represented by w = max(L_S, L_T), which no |i-j| exceeds. */
+int64_t orc_window(int kind, double ratio, int64_t lx, int64_t ly)
+{
+    int64_t L = imax(lx, ly);
+    if (kind != ORC_CDTW && kind != ORC_ERP) return L;
+    if (isnan(ratio) || ratio < 0) return -1;
+    if (ratio >= 1.0) return L;
+    int64_t w = (int64_t)floor(ratio * (double)L);
+    return w > L ? L : w;
+}
+
+/* WDTW weight (eq. WDTW): w(d) = 1 / (1 + exp(-g * (d - L/2))), read with
+ * w_max = 1 and L = the longer of the two lengths. */
+void orc_wdtw_weights(double g, int64_t L, double* out)
+{
+    for (int64_t k = 0; k < L; ++k)
+        out[k] = 1.0 / (1.0 + exp(-g * ((double)k - (double)L / 2.0)));
+}
+
+/* MSM split/merge cost (eq. MSMCost), written as defined: c when np lies
+ * between x and y (either order, inclusive), else c plus the distance to the
+ * nearer of the two. */
+static double msm_cost(double np, double x, double y, double c)
+{
+    if ((x <= np && np <= y) || (x >= np && np >= y)) return c;
+    double a = fabs(np - x), b = fabs(np - y);
+    return c + dmin2(a, b);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Full cost matrix.  x (length lx) indexes rows i = 1..lx, y (length ly)
+ * indexes columns j = 1..ly; x[i-1] is s_i.  M has (lx+1)*(ly+1) entries.
+ *
+ * Borders (eq. Common corner/vborder/hborder): M(0,0) = 0.  DTW, CDTW, WDTW,
+ * MSM and TWE have +inf borders.  ERP computes them (eq. ERP):
+ *   M(i,0) = M(i-1,0) + |s_i - gap|,  M(0,j) = M(0,j-1) + |t_j - gap|.
+ * READING (window + computed borders): the border is computed on
+ * 1..min(w+1, L), as Alg. 4/5 initialise it, and is +inf beyond.
+ *
+ * Interior cell (i,j), |i-j| <= w, with d = s_i - t_j (one rounding):
+ *   DTW, CDTW  cost + min(diag, top, left),  cost = d*d      (eq. DTW)
+ *   WDTW       cost + min(...),  cost = W[|i-j|] * (d*d)
+ *   ERP        min(diag + |d|, top + |s_i - gap|, left + |t_j - gap|)
+ *              (eq. ERP; its left term is read as cost(t_j, g))
+ *   MSM        min(diag + |d|, top + C(s_i, s_{i-1}, t_j),
+ *                  left + C(t_j, s_i, t_{j-1}))            (eq. MSM)
+ *              the top term is +inf on row 1 and the left one on column 1
+ *              (they would read s_0 / t_0 and sit on +inf borders)
+ *   TWE        min(diag + ((|s_i - t_j| + |s_{i-1} - t_{j-1}|) + nu*(2|i-j|)),
+ *                  top  + ((|s_i - s_{i-1}| + nu) + lambda),
+ *                  left + ((|t_j - t_{j-1}| + nu) + lambda))  (eq. TWE/TWECost)
+ *              with s_0 = t_0 = 0, L1 cost and timestamps tau_i = i, so
+ *              nu(|tau_i - tau_j| + |tau_{i-1} - tau_{j-1}|) = nu * 2|i-j|.
+ * Returns M(lx, ly) (+inf when the window forbids every path). */
+static double cell_dp(int kind, const double* prm, const double* W, const double* x, const double* y,
+                      int64_t i, int64_t j, double diag, double top, double left)
+{
+    double si = x[i - 1], tj = y[j - 1];
+    double d = si - tj;
+    switch (kind) {
+    case ORC_DTW:
+    case ORC_CDTW: {
+        double cost = d * d;
+        return cost + dmin3(diag, top, left);
+    }
+    case ORC_WDTW: {
+        double cost = W[iabs(i - j)] * (d * d);
+        return cost + dmin3(diag, top, left);
+    }
+    case ORC_ERP: {
+        double gap = prm[P_GAP];
+        return dmin3(diag + fabs(d), top + fabs(si - gap), left + fabs(tj - gap));
+    }
+    case ORC_MSM: {
+        double c = prm[P_C];
+        double a = diag + fabs(d);
+        double b = (i == 1) ? INF : top + msm_cost(si, x[i - 2], tj, c);
+        double e = (j == 1) ? INF : left + msm_cost(tj, si, y[j - 2], c);
+        return dmin3(a, b, e);
+    }
+    case ORC_TWE: {
+        double nu = prm[P_NU], lam = prm[P_LAMBDA];
+        double sp = (i == 1) ? 0.0 : x[i - 2];
+        double tp = (j == 1) ? 0.0 : y[j - 2];
+        double match = (fabs(d) + fabs(sp - tp)) + nu * (double)(2 * iabs(i - j));
+        double delA = (fabs(si - sp) + nu) + lam;
+        double delB = (fabs(tj - tp) + nu) + lam;
+        return dmin3(diag + match, top + delA, left + delB);
+    }
+    }
+    return NAN;
+}
+
+double orc_dp(int kind, const double* x, int64_t lx, const double* y, int64_t ly, const double* prm,
+              double* M_out)
+{
+    if (lx < 1 || ly < 1) return NAN;
+    int64_t w = orc_window(kind, prm[P_WR], lx, ly);
+    if (w < 0) return NAN;
+    int64_t nc = ly + 1;
+    double* M = M_out ? M_out : (double*)malloc(sizeof(double) * (size_t)(lx + 1) * (size_t)nc);
+    double* W = NULL;
+    if (kind == ORC_WDTW) {
+        W = (double*)malloc(sizeof(double) * (size_t)imax(lx, ly));
+        orc_wdtw_weights(prm[P_G], imax(lx, ly), W);
+    }
+    double gap = prm[P_GAP];
+    for (int64_t i = 0; i <= lx; ++i) {
+        for (int64_t j = 0; j <= ly; ++j) {
+            double v;
+            if (i == 0 && j == 0) v = 0.0;
+            else if (j == 0) v = (kind == ORC_ERP && i <= w + 1) ? M[(i - 1) * nc] + fabs(x[i - 1] - gap) : INF;
+            else if (i == 0) v = (kind == ORC_ERP && j <= w + 1) ? M[j - 1] + fabs(y[j - 1] - gap) : INF;
+            else if (iabs(i - j) > w) v = INF;
+            else v = cell_dp(kind, prm, W, x, y, i, j, M[(i - 1) * nc + (j - 1)], M[(i - 1) * nc + j],
+                             M[i * nc + (j - 1)]);
+            M[i * nc + j] = v;
+        }
+    }
+    double D = M[lx * nc + ly];
+    free(W);
+    if (!M_out) free(M);
+    return D;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Brute force: every monotone lattice path from (0,0) to (lx,ly) with steps
+ * diagonal (i+1,j+1), down (i+1,j) and right (i,j+1), its cost accumulated
+ * step by step in path order with the same per-step term as the recurrence,
+ * minimised over all paths.  Border cells are reachable only along row 0 or
+ * column 0 (ERP: gap costs, within the w+1 border; others: +inf).  Paths
+ * through a +inf cell are cut off early (their cost stays +inf). */
+typedef struct {
+    int kind;
+    const double *prm, *W, *x, *y;
+    int64_t lx, ly, w;
+    double best;
+    int64_t finite_paths;
+} bf_ctx;
+
+/* cost of stepping into (a,b) by move m (0 diag, 1 down, 2 right) with cost
+ * so far acc; +inf when (a,b) may not be entered */
+static double bf_step(const bf_ctx* b, int m, int64_t a, int64_t c, double acc)
+{
+    double gap = b->prm[P_GAP];
+    if (a == 0 || c == 0) {
+        if (b->kind != ORC_ERP) return INF;
+        if (c == 0 && m == 1 && a <= b->w + 1) return acc + fabs(b->x[a - 1] - gap);
+        if (a == 0 && m == 2 && c <= b->w + 1) return acc + fabs(b->y[c - 1] - gap);
+        return INF;
+    }
+    if (iabs(a - c) > b->w) return INF;
+    double si = b->x[a - 1], tj = b->y[c - 1], d = si - tj;
+    switch (b->kind) {
+    case ORC_DTW:
+    case ORC_CDTW: return (d * d) + acc;
+    case ORC_WDTW: return (b->W[iabs(a - c)] * (d * d)) + acc;
+    case ORC_ERP:
+        if (m == 0) return acc + fabs(d);
+        if (m == 1) return acc + fabs(si - gap);
+        return acc + fabs(tj - gap);
+    case ORC_MSM: {
+        double cc = b->prm[P_C];
+        if (m == 0) return acc + fabs(d);
+        if (m == 1) return (a == 1) ? INF : acc + msm_cost(si, b->x[a - 2], tj, cc);
+        return (c == 1) ? INF : acc + msm_cost(tj, si, b->y[c - 2], cc);
+    }
+    case ORC_TWE: {
+        double nu = b->prm[P_NU], lam = b->prm[P_LAMBDA];
+        double sp = (a == 1) ? 0.0 : b->x[a - 2];
+        double tp = (c == 1) ? 0.0 : b->y[c - 2];
+        if (m == 0) return acc + ((fabs(d) + fabs(sp - tp)) + nu * (double)(2 * iabs(a - c)));
+        if (m == 1) return acc + ((fabs(si - sp) + nu) + lam);
+        return acc + ((fabs(tj - tp) + nu) + lam);
+    }
+    }
+    return NAN;
+}
+
+static void bf_rec(bf_ctx* b, int64_t i, int64_t j, double acc)
+{
+    if (acc == INF) return;
+    if (i == b->lx && j == b->ly) {
+        b->finite_paths++;
+        if (acc < b->best) b->best = acc;
+        return;
+    }
+    if (i < b->lx && j < b->ly) bf_rec(b, i + 1, j + 1, bf_step(b, 0, i + 1, j + 1, acc));
+    if (i < b->lx) bf_rec(b, i + 1, j, bf_step(b, 1, i + 1, j, acc));
+    if (j < b->ly) bf_rec(b, i, j + 1, bf_step(b, 2, i, j + 1, acc));
+}
+
+double orc_brute(int kind, const double* x, int64_t lx, const double* y, int64_t ly, const double* prm,
+                 int64_t* n_finite_paths)
+{
+    if (lx < 1 || ly < 1 || lx > 12 || ly > 12) return NAN;
+    bf_ctx b;
+    b.kind = kind;
+    b.prm = prm;
+    b.x = x;
+    b.y = y;
+    b.lx = lx;
+    b.ly = ly;
+    b.w = orc_window(kind, prm[P_WR], lx, ly);
+    if (b.w < 0) return NAN;
+    double* W = NULL;
+    if (kind == ORC_WDTW) {
+        W = (double*)malloc(sizeof(double) * (size_t)imax(lx, ly));
+        orc_wdtw_weights(prm[P_G], imax(lx, ly), W);
+    }
+    b.W = W;
+    b.best = INF;
+    b.finite_paths = 0;
+    bf_rec(&b, 0, 0, 0.0);
+    free(W);
+    if (n_finite_paths) *n_finite_paths = b.finite_paths;
+    return b.best;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The three additive terms of eq. (Common) for cell (i,j) of the matrix whose
+ * rows are R (length lr) and columns C, in the same operation order as
+ * cell_dp.  DTW-like distances add the same cost to every dependency:
+ * cost + min(a,b,c) equals min(a+cost, b+cost, c+cost) exactly because
+ * rounded addition is monotone. */
+typedef struct {
+    int kind;
+    const double *prm, *W, *R, *C;
+    int64_t lr, lc, w;
+} eap_ctx;
+
+static void terms(const eap_ctx* e, int64_t i, int64_t j, double* canon, double* arow, double* acol)
+{
+    double si = e->R[i - 1], tj = e->C[j - 1], d = si - tj;
+    switch (e->kind) {
+    case ORC_DTW:
+    case ORC_CDTW: {
+        double cost = d * d;
+        *canon = *arow = *acol = cost;
+        return;
+    }
+    case ORC_WDTW: {
+        double cost = e->W[iabs(i - j)] * (d * d);
+        *canon = *arow = *acol = cost;
+        return;
+    }
+    case ORC_ERP: {
+        double gap = e->prm[P_GAP];
+        *canon = fabs(d);
+        *arow = fabs(si - gap);
+        *acol = fabs(tj - gap);
+        return;
+    }
+    case ORC_MSM: {
+        double c = e->prm[P_C];
+        *canon = fabs(d);
+        *arow = (i == 1) ? INF : msm_cost(si, e->R[i - 2], tj, c);
+        *acol = (j == 1) ? INF : msm_cost(tj, si, e->C[j - 2], c);
+        return;
+    }
+    case ORC_TWE: {
+        double nu = e->prm[P_NU], lam = e->prm[P_LAMBDA];
+        double sp = (i == 1) ? 0.0 : e->R[i - 2];
+        double tp = (j == 1) ? 0.0 : e->C[j - 2];
+        *canon = (fabs(d) + fabs(sp - tp)) + nu * (double)(2 * iabs(i - j));
+        *arow = (fabs(si - sp) + nu) + lam;
+        *acol = (fabs(tj - tp) + nu) + lam;
+        return;
+    }
+    }
+}
+
+/* EAPruned (Alg. 5).  The shorter series goes on the columns ("co"), the
+ * longer on the rows ("li").  Returns D(S,T) when D <= cutoff, else +inf.
+ * A cell is alive when its value is <= cutoff; abandoning needs a value
+ * > cutoff, so a pair whose distance equals the cut-off is returned exactly.
+ *
+ * Per row: stage 1 sets the left border (computed while the row starts at
+ * column 1, +inf otherwise); stage 2 computes discard points (top and
+ * diagonal dependencies) while the left neighbour is dead; stage 3 computes
+ * full cells up to the previous row's pruning point; stage 4 handles the cell
+ * at the pruning point (diagonal and, unless the left is dead, left); stage 5
+ * continues from the left while cells stay alive.  next_start marks the first
+ * non-discarded column, pruning_point the previous row's pruning point and
+ * next_pruning_point the one being built (Section 4.1-4.3).
+ *
+ * READING (final value): the printed algorithm returns curr[L_co] after the
+ * last row; when that row stops before column L_co the entry is stale.  The
+ * result is curr[L_co] only if the last row's pruning point is L_co + 1 and
+ * curr[L_co] <= cutoff, else +inf.
+ * READING (initial pruning point): with a computed top border the first
+ * pruning point is 1 + the last border column whose value is <= cutoff
+ * (Section 4.1 describes computed borders; for +inf borders this is 1).
+ * READING (stage 4): "j == next_start" means the left neighbour is a discard
+ * point; with a computed left border still alive it is not, so the test also
+ * asks that curr[j-1] > cutoff.
+ * next_pruning_point starts at the initial pruning point.
+ *
+ * cells (nullable) counts the interior cells evaluated in stages 2-5;
+ * ab_i/ab_j (nullable) receive the cell at which the pair was abandoned
+ * (0,0 when it was not). */
+double orc_eap(int kind, const double* S, int64_t ls, const double* T, int64_t lt, const double* prm,
+               double cutoff, int64_t* cells, int64_t* ab_i, int64_t* ab_j)
+{
+    if (ls < 1 || lt < 1 || isnan(cutoff)) return NAN;
+    eap_ctx e;
+    e.kind = kind;
+    e.prm = prm;
+    if (ls >= lt) {
+        e.R = S; e.lr = ls; e.C = T; e.lc = lt;
+    } else {
+        e.R = T; e.lr = lt; e.C = S; e.lc = ls;
+    }
+    e.w = orc_window(kind, prm[P_WR], ls, lt);
+    if (e.w < 0) return NAN;
+    int64_t n_cells = 0;
+    if (cells) *cells = 0;
+    if (ab_i) *ab_i = 0;
+    if (ab_j) *ab_j = 0;
+    if (e.w < e.lr - e.lc) return INF;
+    double* W = NULL;
+    if (kind == ORC_WDTW) {
+        W = (double*)malloc(sizeof(double) * (size_t)e.lr);
+        orc_wdtw_weights(prm[P_G], e.lr, W);
+    }
+    e.W = W;
+    const int64_t Lco = e.lc, Lli = e.lr, w = e.w;
+    const double gap = prm[P_GAP];
+    double* prev = (double*)malloc(sizeof(double) * (size_t)(Lco + 1));
+    double* curr = (double*)malloc(sizeof(double) * (size_t)(Lco + 1));
+    for (int64_t j = 0; j <= Lco; ++j) prev[j] = curr[j] = INF;
+    curr[0] = 0.0;
+    int64_t hb = imin(w + 1, Lco);
+    for (int64_t j = 1; j <= hb; ++j) curr[j] = (kind == ORC_ERP) ? curr[j - 1] + fabs(e.C[j - 1] - gap) : INF;
+    int64_t next_start = 1;
+    int64_t pruning_point = 1;
+    for (int64_t j = 0; j <= hb; ++j)
+        if (curr[j] <= cutoff) pruning_point = j + 1;
+    int64_t next_pruning_point = pruning_point;
+    double result = INF;
+    int abandoned = 0;
+    double canon, arow, acol;
+
+    for (int64_t i = 1; i <= Lli && !abandoned; ++i) {
+        double* t = prev; prev = curr; curr = t;
+        int64_t jStart = imax(i - w, next_start);
+        int64_t jStop = imin(i + w, Lco);
+        int64_t j = jStart;
+        /* stage 1: left border */
+        curr[jStart - 1] = (jStart == 1 && kind == ORC_ERP) ? prev[0] + fabs(e.R[i - 1] - gap) : INF;
+        /* stage 2: discard points, up to (excluding) the pruning point */
+        if (curr[jStart - 1] > cutoff) {
+            for (; j < pruning_point && j == next_start; ++j) {
+                terms(&e, i, j, &canon, &arow, &acol);
+                curr[j] = dmin2(prev[j - 1] + canon, prev[j] + arow);
+                ++n_cells;
+                if (curr[j] <= cutoff) next_pruning_point = j + 1;
+                else ++next_start;
+            }
+        }
+        /* stage 3: full cells up to (excluding) the pruning point */
+        for (; j < pruning_point; ++j) {
+            terms(&e, i, j, &canon, &arow, &acol);
+            curr[j] = dmin3(prev[j - 1] + canon, prev[j] + arow, curr[j - 1] + acol);
+            ++n_cells;
+            if (curr[j] <= cutoff) next_pruning_point = j + 1;
+        }
+        /* stage 4: the cell at the pruning point */
+        if (j <= jStop) {
+            terms(&e, i, j, &canon, &arow, &acol);
+            ++n_cells;
+            if (j == next_start && curr[j - 1] > cutoff) {
+                curr[j] = prev[j - 1] + canon;
+                if (curr[j] <= cutoff) next_pruning_point = j + 1;
+                else {
+                    abandoned = 1;
+                    if (ab_i) *ab_i = i;
+                    if (ab_j) *ab_j = j;
+                    break;
+                }
+            } else {
+                curr[j] = dmin2(prev[j - 1] + canon, curr[j - 1] + acol);
+                if (curr[j] <= cutoff) next_pruning_point = j + 1;
+            }
+            ++j;
+        } else if (j == next_start) {
+            abandoned = 1;
+            if (ab_i) *ab_i = i;
+            if (ab_j) *ab_j = j;
+            break;
+        }
+        /* stage 5: after the pruning point, left dependency only */
+        for (; j <= jStop && j == next_pruning_point; ++j) {
+            terms(&e, i, j, &canon, &arow, &acol);
+            curr[j] = curr[j - 1] + acol;
+            ++n_cells;
+            if (curr[j] <= cutoff) next_pruning_point = j + 1;
+        }
+        pruning_point = next_pruning_point;
+    }
+    if (!abandoned && pruning_point == Lco + 1 && curr[Lco] <= cutoff) result = curr[Lco];
+    free(prev);
+    free(curr);
+    free(W);
+    if (cells) *cells = n_cells;
+    return result;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Upper bound from one warping path (Section 4, intro: any path's cost bounds
+ * the optimum): the diagonal (1,1)..(m,m), m = min(L_S, L_T), then straight
+ * down (or right) along the last column (row) to (L_S, L_T).  Each step adds
+ * its term exactly as the recurrence does, so the result is >= the distance
+ * in floating point too.  +inf when the window forbids the path. */
+double orc_ub(int kind, const double* x, int64_t lx, const double* y, int64_t ly, const double* prm)
+{
+    if (lx < 1 || ly < 1) return NAN;
+    bf_ctx b;
+    b.kind = kind;
+    b.prm = prm;
+    b.x = x;
+    b.y = y;
+    b.lx = lx;
+    b.ly = ly;
+    b.w = orc_window(kind, prm[P_WR], lx, ly);
+    if (b.w < 0) return NAN;
+    double* W = NULL;
+    if (kind == ORC_WDTW) {
+        W = (double*)malloc(sizeof(double) * (size_t)imax(lx, ly));
+        orc_wdtw_weights(prm[P_G], imax(lx, ly), W);
+    }
+    b.W = W;
+    double acc = 0.0;
+    int64_t m = imin(lx, ly);
+    for (int64_t k = 1; k <= m; ++k) acc = bf_step(&b, 0, k, k, acc);
+    for (int64_t i = m + 1; i <= lx; ++i) acc = bf_step(&b, 1, i, m, acc);
+    for (int64_t j = m + 1; j <= ly; ++j) acc = bf_step(&b, 2, m, j, acc);
+    free(W);
+    return acc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* NN search, Alg. 1: candidates in index order, replace on strictly smaller
+ * distance, so the lowest index wins ties.  mode 0 evaluates every candidate
+ * with the full DP; mode 1 with EAPruned using the current best as cut-off.
+ * Out: index (-1 when no candidate has a finite distance) and distance.
+ * cells_total (nullable) sums EAPruned's evaluated cells.  Queries run in
+ * parallel over nthreads OpenMP threads (<= 0: library default). */
+void orc_nn1(int kind, const double* prm, const double* q, const int64_t* q_off, int64_t nq, const double* r,
+             const int64_t* r_off, int64_t nr, int mode, int64_t* out_idx, double* out_dist, int nthreads,
+             int64_t* cells_total)
+{
+    int64_t cells_sum = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : cells_sum)
+#endif
+    for (int64_t a = 0; a < nq; ++a) {
+        const double* qa = q + q_off[a];
+        int64_t la = q_off[a + 1] - q_off[a];
+        double best = INF;
+        int64_t bi = -1;
+        for (int64_t b = 0; b < nr; ++b) {
+            const double* rb = r + r_off[b];
+            int64_t lb = r_off[b + 1] - r_off[b];
+            double d;
+            if (mode == 1) {
+                int64_t c = 0;
+                d = orc_eap(kind, qa, la, rb, lb, prm, best, &c, NULL, NULL);
+                cells_sum += c;
+            } else {
+                d = orc_dp(kind, qa, la, rb, lb, prm, NULL);
+            }
+            if (d < best) {
+                best = d;
+                bi = b;
+            }
+        }
+        out_idx[a] = bi;
+        out_dist[a] = best;
+    }
+    if (cells_total) *cells_total = cells_sum;
+}
+
+/* All pairs i < j, condensed: out[n*i - i*(i+1)/2 + (j-i-1)].  mode 1 is the
+ * full DP; mode 0 is prune-only EAPruned with the path upper bound (one ulp
+ * above it) as cut-off, which never abandons. */
+void orc_pairwise(int kind, const double* prm, const double* s, const int64_t* s_off, int64_t n, int mode,
+                  double* out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            const double* a = s + s_off[i];
+            const double* b = s + s_off[j];
+            int64_t la = s_off[i + 1] - s_off[i], lb = s_off[j + 1] - s_off[j];
+            double d;
+            if (mode == 1) d = orc_dp(kind, a, la, b, lb, prm, NULL);
+            else {
+                double ub = orc_ub(kind, a, la, b, lb, prm);
+                d = (ub == INF) ? INF : orc_eap(kind, a, la, b, lb, prm, nextafter(ub, INF), NULL, NULL, NULL);
+            }
+            out[n * i - i * (i + 1) / 2 + (j - i - 1)] = d;
+        }
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

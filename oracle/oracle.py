@@ -1,0 +1,155 @@
+"""ctypes wrapper of the CPU oracle library.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the package smoke check and the
+benchmark's CPU-baseline leg.  The device library never uses it.
+
+Parameters are passed as a dict with keys kind ('dtw', 'cdtw', 'wdtw', 'erp',
+'msm', 'twe'), window_ratio, g, gap, c, nu, lam; missing keys take the
+defaults below.  Series are float64 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+KINDS = {"dtw": 0, "cdtw": 1, "wdtw": 2, "erp": 3, "msm": 4, "twe": 5}
+
+_lib = None
+
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(
+                os.path.join(HERE, "eap_oracle.c")):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.orc_window.restype = _i64
+        L.orc_window.argtypes = [ctypes.c_int, _d, _i64, _i64]
+        L.orc_wdtw_weights.restype = None
+        L.orc_wdtw_weights.argtypes = [_d, _i64, _pd]
+        L.orc_dp.restype = _d
+        L.orc_dp.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _pd]
+        L.orc_brute.restype = _d
+        L.orc_brute.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _pi64]
+        L.orc_eap.restype = _d
+        L.orc_eap.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _d, _pi64, _pi64, _pi64]
+        L.orc_ub.restype = _d
+        L.orc_ub.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd]
+        L.orc_nn1.restype = None
+        L.orc_nn1.argtypes = [ctypes.c_int, _pd, _pd, _pi64, _i64, _pd, _pi64, _i64, ctypes.c_int, _pi64, _pd,
+                              ctypes.c_int, _pi64]
+        L.orc_pairwise.restype = None
+        L.orc_pairwise.argtypes = [ctypes.c_int, _pd, _pd, _pi64, _i64, ctypes.c_int, _pd, ctypes.c_int]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _prm(p: dict) -> np.ndarray:
+    return np.array([float(p.get("window_ratio", float("inf"))), float(p.get("g", 0.0)), float(p.get("gap", 0.0)),
+                     float(p.get("c", 0.0)), float(p.get("nu", 0.0)), float(p.get("lam", p.get("lambda", 0.0)))],
+                    dtype=np.float64)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_pd)
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(_pi64)
+
+
+def kind_id(p: dict) -> int:
+    return KINDS[p["kind"]]
+
+
+def window(p: dict, lx: int, ly: int) -> int:
+    return int(lib().orc_window(kind_id(p), float(p.get("window_ratio", float("inf"))), lx, ly))
+
+
+def wdtw_weights(g: float, L: int) -> np.ndarray:
+    out = np.empty(L, dtype=np.float64)
+    lib().orc_wdtw_weights(float(g), L, _ptr(out))
+    return out
+
+
+def dp(p: dict, x, y, return_matrix: bool = False):
+    x, y = _f64(x), _f64(y)
+    prm = _prm(p)
+    if return_matrix:
+        M = np.empty((len(x) + 1, len(y) + 1), dtype=np.float64)
+        d = lib().orc_dp(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), _ptr(M))
+        return d, M
+    return lib().orc_dp(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), None)
+
+
+def brute(p: dict, x, y):
+    x, y = _f64(x), _f64(y)
+    prm = _prm(p)
+    n = ctypes.c_int64(0)
+    d = lib().orc_brute(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), ctypes.byref(n))
+    return d, n.value
+
+
+def eap(p: dict, x, y, cutoff: float = float("inf")):
+    """EAPruned distance: (value, cells evaluated, (abandon_i, abandon_j))."""
+    x, y = _f64(x), _f64(y)
+    prm = _prm(p)
+    c, ai, aj = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    d = lib().orc_eap(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), float(cutoff), ctypes.byref(c),
+                      ctypes.byref(ai), ctypes.byref(aj))
+    return d, c.value, (ai.value, aj.value)
+
+
+def ub(p: dict, x, y) -> float:
+    x, y = _f64(x), _f64(y)
+    prm = _prm(p)
+    return lib().orc_ub(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm))
+
+
+def nn1(p: dict, q, q_off, r, r_off, mode: str = "eap", nthreads: int = 0):
+    """Alg. 1 over ragged sets; mode 'dp' (full DP) or 'eap' (EAPruned).
+    Returns (idx int64[nq], dist float64[nq], cells evaluated)."""
+    q, r = _f64(q), _f64(r)
+    q_off = np.ascontiguousarray(q_off, dtype=np.int64)
+    r_off = np.ascontiguousarray(r_off, dtype=np.int64)
+    nq, nr = len(q_off) - 1, len(r_off) - 1
+    idx = np.empty(nq, dtype=np.int64)
+    dist = np.empty(nq, dtype=np.float64)
+    cells = ctypes.c_int64(0)
+    prm = _prm(p)
+    lib().orc_nn1(kind_id(p), _ptr(prm), _ptr(q), _iptr(q_off), nq, _ptr(r), _iptr(r_off), nr,
+                  1 if mode == "eap" else 0, _iptr(idx), _ptr(dist), int(nthreads), ctypes.byref(cells))
+    return idx, dist, cells.value
+
+
+def pairwise(p: dict, s, s_off, mode: str = "prune", nthreads: int = 0) -> np.ndarray:
+    s = _f64(s)
+    s_off = np.ascontiguousarray(s_off, dtype=np.int64)
+    n = len(s_off) - 1
+    out = np.empty(n * (n - 1) // 2, dtype=np.float64)
+    prm = _prm(p)
+    lib().orc_pairwise(kind_id(p), _ptr(prm), _ptr(s), _iptr(s_off), n, 0 if mode == "prune" else 1, _ptr(out),
+                       int(nthreads))
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

@@ -1,0 +1,397 @@
+"""Pins for the CPU oracle, independent of the oracle's own code.
+
+Each test checks the oracle against something fixed outside it: numbers the
+paper prints (tests/golden), closed forms worked out by hand, limit cases that
+reduce to a textbook distance, brute-force path enumeration, and the metric
+properties the paper states.  No GPU is used here.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2102_05221_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "dtw_worked_example.txt")
+INF = math.inf
+
+
+def same(a, b):
+    """Bitwise-equal doubles (+inf equal to +inf)."""
+    return (math.isinf(a) and math.isinf(b) and a > 0 and b > 0) or (a == b and math.copysign(1, a) == math.copysign(1, b))
+
+
+def read_golden():
+    g = {"SAVED": {}, "ABANDON": {}, "EABASE_SAVED": {}}
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        tag, *v = line.split()
+        if tag in ("S", "T"):
+            g[tag] = [float(x) for x in v]
+        elif tag == "D":
+            g["D"] = float(v[0])
+        elif tag == "SAVED":
+            g["SAVED"][float(v[0])] = int(v[1])
+        elif tag == "ABANDON":
+            g["ABANDON"][float(v[0])] = (int(v[1]), int(v[2]))
+        elif tag == "EABASE_SAVED":
+            g["EABASE_SAVED"][float(v[0])] = int(v[1])
+    return g
+
+
+SIX = [
+    dict(kind="dtw"),
+    dict(kind="cdtw", window_ratio=0.3),
+    dict(kind="wdtw", g=0.3),
+    dict(kind="erp", gap=0.25, window_ratio=INF),
+    dict(kind="erp", gap=-0.4, window_ratio=0.35),
+    dict(kind="msm", c=0.5),
+    dict(kind="twe", nu=0.01, lam=0.5),
+]
+
+
+# --- the paper's worked example (Section 2.3.1 and 4.2) ---------------------
+
+def test_worked_example_value(orc):
+    g = read_golden()
+    assert orc.dp(dict(kind="dtw"), g["S"], g["T"]) == g["D"]
+    # the same value must come out with the L1 cost only if the cost is wrong:
+    l1 = orc.dp(dict(kind="erp", gap=1e30), g["S"], g["T"])
+    assert l1 != g["D"]
+
+
+@pytest.mark.parametrize("cut", [9.0, 6.0])
+def test_worked_example_pruning_counts(orc, cut):
+    g = read_golden()
+    d, cells, ab = orc.eap(dict(kind="dtw"), g["S"], g["T"], cut)
+    assert 36 - cells == g["SAVED"][cut]
+    if cut in g["ABANDON"]:
+        assert d == INF and ab == g["ABANDON"][cut]
+    else:
+        assert d == g["D"] and ab == (0, 0)
+
+
+def test_worked_example_cell_claims(orc):
+    """Cell-level statements of Section 4.1-4.2 about the same matrix."""
+    g = read_golden()
+    _, M = orc.dp(dict(kind="dtw"), g["S"], g["T"], return_matrix=True)
+    assert M[3, 1] > 9                      # (3,1) above cut-off 9: rest of column 1 discarded
+    assert M[1, 4] > 6                      # (1,4) above cut-off 6: a pruning point
+    assert all(M[1, j] > 6 for j in range(4, 7))
+    assert M[2, 2] > 6 and (M[2, 3:] <= 6).any()   # (2,2) not a pruning point
+    assert all(M[3, j] > 6 for j in range(3, 7))   # (3,3) is row 3's pruning point
+    # classic row-minimum abandoning (Alg. 4) at cut-off 6 computes full rows
+    # until the first row whose minimum exceeds the cut-off
+    rows = next(i for i in range(1, 7) if M[i, 1:].min() > 6)
+    assert (6 - rows) * 6 == g["EABASE_SAVED"][6.0]
+    # EAPruned abandons at once when (1,1) exceeds the cut-off (Section 4.2)
+    d, cells, ab = orc.eap(dict(kind="dtw"), g["S"], g["T"], M[1, 1] * 0.5)
+    assert d == INF and cells == 1 and ab == (1, 1)
+
+
+# --- closed forms and limit cases -------------------------------------------
+
+def test_length_one_closed_forms(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        a, b, gp = rng.normal(size=3)
+        assert orc.dp(dict(kind="dtw"), [a], [b]) == (a - b) * (a - b)
+        assert orc.dp(dict(kind="msm", c=0.7), [a], [b]) == abs(a - b)
+        assert orc.dp(dict(kind="twe", nu=0.3, lam=0.2), [a], [b]) == abs(a - b)
+        assert orc.dp(dict(kind="erp", gap=gp), [a], [b]) == min(abs(a - b), abs(a - gp) + abs(b - gp))
+
+
+def test_msm_split_hand_value(orc):
+    # (0) against (0, 1), c = 0.5: align 0-0, then split off a point and move it
+    # to 1: c + min(|1-0|, |1-0|) = 1.5 (eq. MSM, MSMCost)
+    assert orc.dp(dict(kind="msm", c=0.5), [0.0], [0.0, 1.0]) == 1.5
+    # new point inside [x, y]: only the split cost c
+    assert orc.dp(dict(kind="msm", c=0.5), [0.0], [0.0, 0.0]) == 0.5
+    assert orc.dp(dict(kind="msm", c=0.25), [2.0], [0.0, 1.0]) == 2.0 + 0.25
+
+
+def test_twe_hand_value(orc):
+    # (1) against (1, 2): match (1,1) costs |1-1| + |0-0| + nu*0 = 0, then a
+    # deleteB into (1,2) costs (|2-1| + nu) + lambda (eq. TWECost, tau_i = i)
+    assert orc.dp(dict(kind="twe", nu=0.1, lam=0.5), [1.0], [1.0, 2.0]) == (abs(2.0 - 1.0) + 0.1) + 0.5
+    # two matches: the second adds |s2-t2| + |s1-t1|
+    v = orc.dp(dict(kind="twe", nu=0.1, lam=100.0), [1.0, 3.0], [2.0, 5.0])
+    assert v == (abs(1.0 - 2.0) + 0.0) + ((abs(3.0 - 5.0) + abs(1.0 - 2.0)) + 0.0)
+
+
+def test_twe_off_diagonal_match_hand_value(orc):
+    # x = (0, 0, 5), y = (0, 5), nu = 1/4, lambda = 0.  Best path: match (1,1)
+    # = 0, deleteA into (2,1) = (|0-0| + nu) + 0, match (3,2) with |i-j| = 1:
+    # (|5-5| + |0-0|) + nu*2*1.  Total 0 + 0.25 + 0.5; every other path pays >= 5.
+    assert orc.dp(dict(kind="twe", nu=0.25, lam=0.0), [0.0, 0.0, 5.0], [0.0, 5.0]) == 0.75
+
+
+def test_erp_left_term_uses_column_point(orc):
+    # x = (0), y = (0, 3), gap 1: diagonal (1,1) costs 0, then the left move into
+    # (1,2) costs cost(t_2, g) = |3 - 1| = 2; all border paths cost 4.
+    assert orc.dp(dict(kind="erp", gap=1.0), [0.0], [0.0, 3.0]) == 2.0
+
+
+def test_msm_top_term_new_point_is_s_i(orc):
+    # x = (0, 0.5), y = (1): (1,1) = |0-1| = 1, then the top move into (2,1)
+    # costs C(s_2, s_1, t_1) = C(0.5, 0, 1) = c, since 0 <= 0.5 <= 1.
+    assert orc.dp(dict(kind="msm", c=0.5), [0.0, 0.5], [1.0]) == 1.5
+    assert orc.dp(dict(kind="msm", c=0.5), [1.0], [0.0, 0.5]) == 1.5
+
+
+def test_wdtw_hand_value(orc):
+    # L = 2, g = ln 3: w(0) = 1/(1+e^{g}) = 1/4, w(1) = 1/(1+e^0) = 1/2 (eq. WDTW)
+    g = math.log(3.0)
+    w = orc.wdtw_weights(g, 2)
+    assert abs(w[0] - 0.25) < 1e-15 and w[1] == 0.5
+    # x = (0, 2), y = (1, 1): (1,1) = w0*1; (1,2) = (2,1) = w1*1 + w0; (2,2) = w0*1 + w0
+    v = orc.dp(dict(kind="wdtw", g=g), [0.0, 2.0], [1.0, 1.0])
+    assert abs(v - 0.5) < 1e-15
+
+
+def seq_sum(terms):
+    acc = 0.0
+    for t in terms:
+        acc = acc + t
+    return acc
+
+
+def test_cdtw_window_zero_is_squared_euclidean(orc):
+    """Section 2.3.2: a window of 0 is the squared Euclidean distance."""
+    rng = np.random.default_rng(4)
+    for L in (1, 2, 7, 64):
+        x, y = rng.normal(size=L), rng.normal(size=L)
+        ed = 0.0
+        for a, b in zip(x, y):
+            ed = ((a - b) * (a - b)) + ed
+        assert orc.dp(dict(kind="cdtw", window_ratio=0.0), x, y) == ed
+
+
+def test_cdtw_full_window_is_dtw(orc):
+    """Section 2.3.2: a window of L is DTW."""
+    rng = np.random.default_rng(5)
+    for lx, ly in [(5, 5), (9, 6), (30, 41)]:
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        assert orc.dp(dict(kind="cdtw", window_ratio=1.0), x, y) == orc.dp(dict(kind="dtw"), x, y)
+        assert orc.window(dict(kind="cdtw", window_ratio=1.0), lx, ly) == max(lx, ly)
+
+
+def test_window_infeasible_is_inf(orc):
+    """Figure fig:CDTW(b): S of length 6, U of length 8, w = 1 admits no path."""
+    rng = np.random.default_rng(6)
+    s, u = rng.normal(size=6), rng.normal(size=8)
+    p = dict(kind="cdtw", window_ratio=0.2)          # floor(0.2 * 8) = 1
+    assert orc.window(p, 6, 8) == 1
+    assert orc.dp(p, s, u) == INF
+    assert orc.eap(p, s, u)[0] == INF
+    assert orc.dp(dict(kind="cdtw", window_ratio=0.25), s, u) < INF   # w = 2 suffices
+
+
+def test_wdtw_zero_steepness_is_half_dtw(orc):
+    rng = np.random.default_rng(7)
+    for lx, ly in [(4, 4), (11, 7), (40, 40)]:
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        assert orc.dp(dict(kind="wdtw", g=0.0), x, y) == orc.dp(dict(kind="dtw"), x, y) / 2
+
+
+def test_msm_erp_twe_l1_limits(orc):
+    """With prohibitive alternate costs only the diagonal path is finite-cost
+    enough: MSM and ERP reduce to the L1 distance, TWE to its match sum."""
+    rng = np.random.default_rng(8)
+    for L in (1, 3, 25):
+        x, y = rng.normal(size=L), rng.normal(size=L)
+        l1 = seq_sum([abs(a - b) for a, b in zip(x, y)])
+        assert orc.dp(dict(kind="msm", c=1e30), x, y) == l1
+        assert orc.dp(dict(kind="erp", gap=1e30), x, y) == l1
+        prev = 0.0
+        terms = []
+        for a, b, in zip(x, y):
+            terms.append((abs(a - b) + prev) + 0.0)
+            prev = abs(a - b)
+        assert orc.dp(dict(kind="twe", nu=0.0, lam=1e30), x, y) == seq_sum(terms)
+
+
+# --- brute force over warping paths (guarantees after eq. Common) -----------
+
+def delannoy(m, n):
+    D = [[1] * (n + 1) for _ in range(m + 1)]
+    for a in range(1, m + 1):
+        for b in range(1, n + 1):
+            D[a][b] = D[a - 1][b] + D[a][b - 1] + D[a - 1][b - 1]
+    return D[m][n]
+
+
+@pytest.mark.parametrize("p", SIX, ids=lambda p: p["kind"] + str(p.get("window_ratio", "")))
+def test_dp_equals_brute_force(orc, p):
+    rng = np.random.default_rng(11)
+    for it in range(150):
+        lx, ly = rng.integers(1, 7, size=2)
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        if it % 4 == 0:
+            x, y = np.round(x), np.round(y)          # ties and equal values
+        d = orc.dp(p, x, y)
+        b, n = orc.brute(p, x, y)
+        assert same(d, b), (p, x, y, d, b)
+
+
+def test_brute_force_counts_all_paths(orc):
+    rng = np.random.default_rng(12)
+    for lx, ly in [(1, 1), (3, 4), (6, 6), (7, 5)]:
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        _, n = orc.brute(dict(kind="dtw"), x, y)
+        assert n == delannoy(lx - 1, ly - 1)        # every finite DTW path starts at (1,1)
+        _, n = orc.brute(dict(kind="erp", gap=0.0), x, y)
+        assert n == delannoy(lx, ly)                 # ERP: border paths are finite too
+
+
+# --- invariants ---------------------------------------------------------------
+
+@pytest.mark.parametrize("p", SIX, ids=lambda p: p["kind"] + str(p.get("window_ratio", "")))
+def test_identity_and_symmetry(orc, p):
+    rng = np.random.default_rng(13)
+    for _ in range(60):
+        lx, ly = rng.integers(1, 40, size=2)
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        assert orc.dp(p, x, x) == 0.0
+        assert same(orc.dp(p, x, y), orc.dp(p, y, x))
+
+
+@pytest.mark.parametrize("p", [dict(kind="erp", gap=0.0), dict(kind="erp", gap=0.7), dict(kind="msm", c=0.5),
+                               dict(kind="msm", c=0.05), dict(kind="twe", nu=0.001, lam=1.0),
+                               dict(kind="twe", nu=0.5, lam=0.0)], ids=lambda p: p["kind"])
+def test_triangle_inequality(orc, p):
+    """ERP (Section 2.3.4) and MSM (Section 2.3.5) are metrics; TWE is one for
+    nu, lambda >= 0 (its authors' result)."""
+    rng = np.random.default_rng(14)
+    for _ in range(300):
+        L = rng.integers(1, 12, size=3)
+        x, y, z = (rng.normal(size=l) for l in L)
+        dxz, dxy, dyz = orc.dp(p, x, z), orc.dp(p, x, y), orc.dp(p, y, z)
+        assert dxz <= (dxy + dyz) * (1 + 1e-12) + 1e-300
+
+
+def test_squared_cost_breaks_triangle_for_dtw(orc):
+    # why ERP/MSM/TWE use the L1 cost: a squared cost already violates the
+    # triangle inequality on points (0), (1), (2)
+    assert orc.dp(dict(kind="dtw"), [0.0], [2.0]) > orc.dp(dict(kind="dtw"), [0.0], [1.0]) + orc.dp(
+        dict(kind="dtw"), [1.0], [2.0])
+
+
+# --- EAPruned, Alg. 5: exact result or +inf ---------------------------------
+
+@pytest.mark.parametrize("p", SIX, ids=lambda p: p["kind"] + str(p.get("window_ratio", "")))
+def test_eapruned_is_exact_or_abandoned(orc, p):
+    rng = np.random.default_rng(21)
+    for it in range(250):
+        lx, ly = rng.integers(1, 24, size=2)
+        if it % 3 == 0:
+            x = synth.znorm(np.cumsum(rng.normal(size=lx)))
+            y = synth.znorm(np.cumsum(rng.normal(size=ly)))
+        else:
+            x, y = rng.normal(size=lx), rng.normal(size=ly)
+        d = orc.dp(p, x, y)
+        cuts = [INF]
+        if d < INF:
+            cuts += [d, np.nextafter(d, -INF), 0.5 * d, 0.9 * d, 1.1 * d, 3.0 * d, 0.0]
+        for c in cuts:
+            e, cells, _ = orc.eap(p, x, y, c)
+            want = d if d <= c else INF
+            assert same(e, want), (p, lx, ly, c, e, want)
+            if c == INF and d < INF:
+                assert cells <= lx * ly
+
+
+def test_eapruned_prunes_on_long_series(orc):
+    wl = synth.make_workload(1, n_ref=6, n_query=2)
+    q = synth.unpack(wl["queries"], wl["query_off"])
+    r = synth.unpack(wl["refs"], wl["ref_off"])
+    p = dict(kind="dtw")
+    best = min(orc.dp(p, q[0], y) for y in r)
+    total = 0
+    for y in r:
+        _, cells, _ = orc.eap(p, q[0], y, best)
+        total += cells
+    assert total < 0.9 * len(r) * 128 * 128
+
+
+# --- upper bound, NN and pairwise drivers ----------------------------------
+
+@pytest.mark.parametrize("p", SIX, ids=lambda p: p["kind"] + str(p.get("window_ratio", "")))
+def test_path_upper_bound(orc, p):
+    rng = np.random.default_rng(31)
+    for _ in range(100):
+        lx, ly = rng.integers(1, 30, size=2)
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        d, u = orc.dp(p, x, y), orc.ub(p, x, y)
+        assert u >= d
+        if lx == ly and p["kind"] in ("dtw", "cdtw"):
+            ed = 0.0
+            for a, b in zip(x, y):
+                ed = ((a - b) * (a - b)) + ed
+            assert u == ed
+
+
+@pytest.mark.parametrize("kind", synth.SIX)
+def test_nn_eapruned_matches_full_dp(orc, kind):
+    wl = synth.make_workload(2, n_ref=40, n_query=12, length=48)
+    p = wl["params"][kind]
+    i1, d1, _ = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "dp")
+    i2, d2, cells = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "eap")
+    assert (i1 == i2).all() and (d1 == d2).all()
+    # the brute-force argmin with the lowest-index tie break (Alg. 1, strict <)
+    Q = synth.unpack(wl["queries"], wl["query_off"])
+    R = synth.unpack(wl["refs"], wl["ref_off"])
+    for a in range(len(Q)):
+        ds = [orc.dp(p, Q[a], r) for r in R]
+        j = int(np.argmin(ds))
+        assert i1[a] == j and d1[a] == ds[j]
+
+
+def test_nn_ties_pick_lowest_index(orc):
+    q = np.array([0.0, 1.0, 0.5])
+    r = [np.array([0.0, 1.0, 0.6]), np.array([0.0, 1.0, 0.4]), np.array([0.0, 1.0, 0.4])]
+    rv, ro = synth.pack(r)
+    for mode in ("dp", "eap"):
+        idx, dist, _ = orc.nn1(dict(kind="dtw"), q, np.array([0, 3]), rv, ro, mode)
+        assert idx[0] == 0 and dist[0] == (0.5 - 0.6) * (0.5 - 0.6) + 0.0
+
+
+def test_nn_no_finite_candidate(orc):
+    q = np.zeros(4)
+    rv, ro = synth.pack([np.zeros(9), np.ones(12)])
+    idx, dist, _ = orc.nn1(dict(kind="cdtw", window_ratio=0.1), q, np.array([0, 4]), rv, ro, "eap")
+    assert idx[0] == -1 and dist[0] == INF
+
+
+@pytest.mark.parametrize("kind", ["dtw", "cdtw", "msm", "erp", "twe", "wdtw"])
+def test_pairwise_prune_only_equals_full(orc, kind):
+    wl = synth.make_workload(3, n_ref=14, length=40)
+    p = dict(synth.DEFAULT_PARAMS[kind])
+    full = orc.pairwise(p, wl["refs"], wl["ref_off"], "full")
+    prune = orc.pairwise(p, wl["refs"], wl["ref_off"], "prune")
+    assert np.array_equal(full, prune)
+    S = synth.unpack(wl["refs"], wl["ref_off"])
+    n = len(S)
+    k = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            assert full[k] == orc.dp(p, S[i], S[j])
+            k += 1
+
+
+# --- generators -------------------------------------------------------------
+
+def test_generators_are_seeded_and_normalised():
+    a = synth.make_workload(2, n_ref=20, n_query=5)
+    b = synth.make_workload(2, n_ref=20, n_query=5)
+    assert np.array_equal(a["refs"], b["refs"]) and np.array_equal(a["queries"], b["queries"])
+    for s in synth.unpack(a["refs"], a["ref_off"]):
+        assert abs(s.mean()) < 1e-12 and abs(s.std() - 1.0) < 1e-12
+    assert set(np.unique(a["ref_labels"])) <= set(range(5))
+    c = synth.make_workload(4, n_ref=50, n_query=5)
+    lens = np.diff(c["ref_off"])
+    assert lens.min() >= 64 and lens.max() <= 2048
+    assert np.array_equal(synth.znorm(np.full(7, 3.0)), np.zeros(7))
