@@ -1,0 +1,153 @@
+/*
+ * eap.h - C ABI of libeap.so: EAPruned elastic distances on one MI355X (gfx950).
+ *
+ * Implements the distance computation with a cut-off of Herrmann & Webb,
+ * "Early Abandoning and Pruning for Elastic Distances including Dynamic Time
+ * Warping" (arXiv 2102.05221), for the six distances of its Section 2.3 (DTW,
+ * CDTW, WDTW, ERP, MSM, TWE), and the two drivers the paper uses it in: NN
+ * search (Alg. 1) and all-pairs distance matrices with pruning only.
+ *
+ * Conventions shared by every entry point
+ *  - Series values are float64 arrays in DEVICE memory.  A set of n series is
+ *    one concatenated array plus an offsets array of n+1 int64 in HOST memory:
+ *    series k is values[off[k] .. off[k+1]), length >= 1.  Offsets must start
+ *    at 0 and be non-decreasing with every length >= 1.
+ *  - Outputs are DEVICE arrays owned by the caller.  Nothing is freed or kept.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    runs asynchronously; outputs are valid once the stream has reached the
+ *    call.  Host-to-device copies of offsets are issued on the same stream
+ *    from library-owned pinned staging memory, so the caller's host arrays may
+ *    be reused as soon as the call returns.
+ *  - The library never allocates device memory inside these calls: each driver
+ *    takes a caller-provided device workspace sized by its *_workspace()
+ *    function.  One workspace must not be used by two calls in flight.
+ *  - Inputs must be finite; the library does not scan for NaN.
+ *  - Errors: argument errors return EAP_EINVAL / EAP_EWORKSPACE synchronously,
+ *    before anything is enqueued, and leave outputs untouched.  HIP failures
+ *    return EAP_EDEVICE.  eap_last_error() returns a thread-local message for
+ *    the last failing call.  No C++ exception crosses this boundary and nothing
+ *    aborts.
+ */
+#ifndef EAP_H
+#define EAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The six distances of Section 2.3 (eq. Common and the per-distance equations). */
+typedef enum { EAP_DTW = 0, EAP_CDTW = 1, EAP_WDTW = 2, EAP_ERP = 3, EAP_MSM = 4, EAP_TWE = 5 } eap_kind;
+
+typedef enum {
+    EAP_OK = 0,
+    EAP_EINVAL = -1,     /* bad argument */
+    EAP_ENOMEM = -2,     /* host staging memory could not be obtained */
+    EAP_EDEVICE = -3,    /* a HIP call failed */
+    EAP_EWORKSPACE = -4  /* workspace missing or smaller than *_workspace() */
+} eap_status;
+
+/* Distance parameters (Section 2.3).
+ *  window_ratio  CDTW and ERP only: Sakoe-Chiba window (Section 2.3.2) given
+ *                as a ratio of the longer length, w = floor(ratio * max(L_x, L_y));
+ *                >= 1 or +inf means no window; < 0 or NaN is EINVAL.
+ *                Ignored by the other distances.
+ *  g             WDTW weight steepness of eq. WDTW, finite, >= 0.
+ *  gap           ERP gap value g of eq. ERP, finite.
+ *  c             MSM split/merge cost of eq. MSMCost, finite, >= 0.
+ *  nu, lambda    TWE stiffness and delete penalty of eq. TWECost, finite, >= 0;
+ *                timestamps are the indices (tau_i = i).
+ * Costs: DTW, CDTW, WDTW use the squared difference; ERP, MSM, TWE the
+ * absolute difference. */
+typedef struct {
+    int32_t kind; /* eap_kind */
+    double window_ratio;
+    double g;
+    double gap;
+    double c;
+    double nu;
+    double lambda;
+} eap_params;
+
+/* NN search options.
+ *  precision   0 = FP64 throughout.  1 = FP32 screening sweep, then every
+ *              candidate whose FP32 distance is within the screen margin of the
+ *              query's FP32 best is recomputed in FP64; results equal the FP64
+ *              ones (indices bit-exact, distances bit-exact).
+ *  margin_rel  relative screen margin for precision 1 (>= 0, finite); the
+ *              library adds a certified absolute bound for FP32 rounding.
+ *  flags       bit 0: skip the seeding pass (every candidate starts from the
+ *              path upper bound); for ablation only. */
+typedef struct {
+    int32_t precision;
+    double margin_rel;
+    int32_t flags;
+} eap_nn_opts;
+
+/* Counters accumulated in a workspace by the calls that use it. */
+typedef struct {
+    uint64_t cells;          /* DP cells executed by the sweep kernels (incl. idle band/strip slots) */
+    uint64_t pairs;          /* pairs swept */
+    uint64_t rechecks;       /* FP64 recomputations after an FP32 screen */
+    uint64_t overflows;      /* band sweeps that had to be redone wider */
+} eap_counters;
+
+/* Distance with cut-off (Alg. 5: "Input S, T, w, cut-off; Result D or +inf").
+ *  x (lx), y (ly)  device float64 series, lengths >= 1.
+ *  cutoff          >= 0 or +inf (NaN is EINVAL).
+ *  out             device, 1 double: D(x,y) if D <= cutoff, else +inf
+ *                  (+inf also when the window admits no alignment).
+ *  ws, ws_bytes    device workspace of at least eap_distance_workspace() bytes. */
+size_t eap_distance_workspace(int64_t lx, int64_t ly, const eap_params* p);
+eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly, const eap_params* p,
+                        double cutoff, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* 1-NN search (Alg. 1): for each query, the candidate with the smallest
+ * distance, lowest index on ties (the strict '<' of Alg. 1).
+ *  q, q_off, nq        queries (device values, host offsets), nq >= 1.
+ *  r, r_off, nr        candidates (device values, host offsets), nr >= 1.
+ *  r_labels            device int32[nr] or NULL.
+ *  out_idx             device int64[nq]: index, or -1 when no candidate has a
+ *                      finite distance (window too small for every one).
+ *  out_dist            device double[nq]: the distance, or +inf.
+ *  out_label           device int32[nq] or NULL: r_labels[idx], -1 when idx < 0. */
+size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off, int64_t nr, const eap_params* p,
+                         const eap_nn_opts* o);
+eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,
+                   int64_t nr, const int32_t* r_labels, const eap_params* p, const eap_nn_opts* o, void* ws,
+                   size_t ws_bytes, int64_t* out_idx, double* out_dist, int32_t* out_label, void* stream);
+
+/* All pairs i < j of one set (Section 5, "Prune" and "Base").
+ *  mode 0  prune-only EAPruned: each pair's cut-off is one ulp above the cost
+ *          of its diagonal-then-straight warping path (an upper bound,
+ *          Section 4 intro), so nothing is abandoned and every value is exact.
+ *  mode 1  plain full dynamic programme.
+ *  out     device double[n*(n-1)/2], condensed: pair (i,j), i<j, at
+ *          n*i - i*(i+1)/2 + (j-i-1).  +inf where the window admits no path. */
+size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params* p);
+eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const eap_params* p, int32_t mode,
+                        void* ws, size_t ws_bytes, double* out, void* stream);
+
+/* Copies the counters accumulated in `ws` to host memory (synchronises `stream`).
+ * eap_reset_counters() zeroes them (asynchronously, on `stream`). */
+eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out, void* stream);
+eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream);
+
+/* Host utility: the WDTW weights the library uses for longer length L,
+ * out[k] = w(k) = 1 / (1 + exp(-g * (k - L/2))) for k = 0..L-1 (eq. WDTW with
+ * w_max = 1).  `out` is HOST memory of L doubles.  Lets a caller check the
+ * library's weights against another implementation bit for bit. */
+eap_status eap_wdtw_weights(double g, int64_t L, double* out);
+
+/* Thread-local text of the last error on this thread; valid until the next call. */
+const char* eap_last_error(void);
+
+/* Library version string. */
+const char* eap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EAP_H */

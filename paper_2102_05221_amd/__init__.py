@@ -1,0 +1,227 @@
+"""EAPruned elastic distances on MI355X: thin Python binding of libeap.so.
+
+Every call marshals torch tensors (device values, current HIP stream) and host
+offsets into the C ABI of include/eap.h; all of the computation happens in the
+library's HIP kernels.  The binding fails loudly when the library is missing:
+there is no CPU fallback.
+
+    import torch, paper_2102_05221_amd as eap
+    p = eap.params("cdtw", window_ratio=0.1)
+    idx, dist, lab = eap.nn1(q_vals, q_off, r_vals, r_off, p, ref_labels=labels)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
+           "wdtw_weights", "EapError", "lib", "KINDS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeap.so")
+KINDS = {"dtw": 0, "cdtw": 1, "wdtw": 2, "erp": 3, "msm": 4, "twe": 5}
+
+EAP_OK, EAP_EINVAL, EAP_ENOMEM, EAP_EDEVICE, EAP_EWORKSPACE = 0, -1, -2, -3, -4
+
+
+class EapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libeap error {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("window_ratio", ctypes.c_double), ("g", ctypes.c_double),
+                ("gap", ctypes.c_double), ("c", ctypes.c_double), ("nu", ctypes.c_double),
+                ("lam", ctypes.c_double)]
+
+
+class NNOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("margin_rel", ctypes.c_double), ("flags", ctypes.c_int32)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
+                ("overflows", ctypes.c_uint64)]
+
+
+_lib = None
+_vp, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pP = ctypes.POINTER(Params)
+_pO = ctypes.POINTER(NNOpts)
+
+
+def lib():
+    """The loaded libeap.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2102_05221_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.eap_last_error.restype = ctypes.c_char_p
+        L.eap_version.restype = ctypes.c_char_p
+        L.eap_distance_workspace.restype = _sz
+        L.eap_distance_workspace.argtypes = [_i64, _i64, _pP]
+        L.eap_distance.restype = ctypes.c_int
+        L.eap_distance.argtypes = [_vp, _i64, _vp, _i64, _pP, _d, _vp, _vp, _sz, _vp]
+        L.eap_nn1_workspace.restype = _sz
+        L.eap_nn1_workspace.argtypes = [_pi64, _i64, _pi64, _i64, _pP, _pO]
+        L.eap_nn1.restype = ctypes.c_int
+        L.eap_nn1.argtypes = [_vp, _pi64, _i64, _vp, _pi64, _i64, _vp, _pP, _pO, _vp, _sz, _vp, _vp, _vp, _vp]
+        L.eap_pairwise_workspace.restype = _sz
+        L.eap_pairwise_workspace.argtypes = [_pi64, _i64, _pP]
+        L.eap_pairwise.restype = ctypes.c_int
+        L.eap_pairwise.argtypes = [_vp, _pi64, _i64, _pP, ctypes.c_int32, _vp, _sz, _vp, _vp]
+        L.eap_read_counters.restype = ctypes.c_int
+        L.eap_read_counters.argtypes = [_vp, _sz, ctypes.POINTER(Counters), _vp]
+        L.eap_reset_counters.restype = ctypes.c_int
+        L.eap_reset_counters.argtypes = [_vp, _sz, _vp]
+        L.eap_wdtw_weights.restype = ctypes.c_int
+        L.eap_wdtw_weights.argtypes = [_d, _i64, ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != EAP_OK:
+        raise EapError(status, lib().eap_last_error().decode(errors="replace"))
+
+
+def params(kind: str, window_ratio: float = math.inf, g: float = 0.0, gap: float = 0.0, c: float = 0.0,
+           nu: float = 0.0, lam: float = 0.0) -> Params:
+    """Distance parameters (eap_params); `kind` is one of KINDS."""
+    return Params(KINDS[kind], float(window_ratio), float(g), float(gap), float(c), float(nu), float(lam))
+
+
+def params_from_dict(d: dict) -> Params:
+    return params(d["kind"], d.get("window_ratio", math.inf), d.get("g", 0.0), d.get("gap", 0.0), d.get("c", 0.0),
+                  d.get("nu", 0.0), d.get("lam", d.get("lambda", 0.0)))
+
+
+def _as_params(p) -> Params:
+    return p if isinstance(p, Params) else params_from_dict(p)
+
+
+def _offsets(off) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    return a
+
+
+def _stream(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA/HIP tensor")
+    return t
+
+
+def workspace(nbytes: int, device):
+    """A device byte buffer usable as a workspace."""
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def distance(x, y, p, cutoff: float = math.inf, ws=None, stream=None):
+    """D(x, y) if D <= cutoff else +inf (Alg. 5), as a 1-element float64 tensor."""
+    import torch
+    _dev_f64(x, "x")
+    _dev_f64(y, "y")
+    p = _as_params(p)
+    need = lib().eap_distance_workspace(x.numel(), y.numel(), ctypes.byref(p))
+    if ws is None:
+        ws = workspace(need, x.device)
+    out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib().eap_distance(x.data_ptr(), x.numel(), y.data_ptr(), y.numel(), ctypes.byref(p), float(cutoff),
+                              out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, x.device)))
+    return out
+
+
+def nn1_workspace_bytes(q_off, r_off, p, precision: int = 0) -> int:
+    q_off, r_off = _offsets(q_off), _offsets(r_off)
+    p = _as_params(p)
+    o = NNOpts(precision, 1e-4, 0)
+    return int(lib().eap_nn1_workspace(q_off.ctypes.data_as(_pi64), len(q_off) - 1, r_off.ctypes.data_as(_pi64),
+                                       len(r_off) - 1, ctypes.byref(p), ctypes.byref(o)))
+
+
+def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: float = 1e-4, flags: int = 0,
+        ws=None, stream=None, out=None):
+    """1-NN search (Alg. 1).  q, r: float64 device tensors of concatenated
+    series; q_off, r_off: host int64 offsets.  Returns (idx int64, dist float64,
+    label int32 or None) device tensors."""
+    import torch
+    _dev_f64(q, "queries")
+    _dev_f64(r, "candidates")
+    q_off, r_off = _offsets(q_off), _offsets(r_off)
+    nq, nr = len(q_off) - 1, len(r_off) - 1
+    p = _as_params(p)
+    o = NNOpts(int(precision), float(margin_rel), int(flags))
+    if ws is None:
+        ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device)
+    if out is None:
+        idx = torch.empty(nq, dtype=torch.int64, device=q.device)
+        dist = torch.empty(nq, dtype=torch.float64, device=q.device)
+        lab = torch.empty(nq, dtype=torch.int32, device=q.device) if ref_labels is not None else None
+    else:
+        idx, dist, lab = out
+    lab_in = 0
+    if ref_labels is not None:
+        if ref_labels.dtype != torch.int32 or not ref_labels.is_cuda:
+            raise TypeError("ref_labels must be an int32 device tensor")
+        lab_in = ref_labels.data_ptr()
+    _check(lib().eap_nn1(q.data_ptr(), q_off.ctypes.data_as(_pi64), nq, r.data_ptr(), r_off.ctypes.data_as(_pi64),
+                         nr, lab_in or None, ctypes.byref(p), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                         idx.data_ptr(), dist.data_ptr(), lab.data_ptr() if lab is not None else None,
+                         _stream(stream, q.device)))
+    return idx, dist, lab
+
+
+def pairwise_workspace_bytes(s_off, p) -> int:
+    s_off = _offsets(s_off)
+    p = _as_params(p)
+    return int(lib().eap_pairwise_workspace(s_off.ctypes.data_as(_pi64), len(s_off) - 1, ctypes.byref(p)))
+
+
+def pairwise(s, s_off, p, mode: str = "prune", ws=None, stream=None, out=None):
+    """Condensed all-pairs distances; mode 'prune' (EAPruned with the path upper
+    bound, Section 5 "Prune") or 'full' (plain DP)."""
+    import torch
+    _dev_f64(s, "series")
+    s_off = _offsets(s_off)
+    n = len(s_off) - 1
+    p = _as_params(p)
+    if ws is None:
+        ws = workspace(pairwise_workspace_bytes(s_off, p), s.device)
+    if out is None:
+        out = torch.empty(max(n * (n - 1) // 2, 1), dtype=torch.float64, device=s.device)
+    m = {"prune": 0, "full": 1}[mode]
+    _check(lib().eap_pairwise(s.data_ptr(), s_off.ctypes.data_as(_pi64), n, ctypes.byref(p), m, ws.data_ptr(),
+                              ws.numel(), out.data_ptr(), _stream(stream, s.device)))
+    return out
+
+
+def read_counters(ws, stream=None) -> dict:
+    c = Counters()
+    _check(lib().eap_read_counters(ws.data_ptr(), ws.numel(), ctypes.byref(c), _stream(stream, ws.device)))
+    return dict(cells=c.cells, pairs=c.pairs, rechecks=c.rechecks, overflows=c.overflows)
+
+
+def reset_counters(ws, stream=None):
+    _check(lib().eap_reset_counters(ws.data_ptr(), ws.numel(), _stream(stream, ws.device)))
+
+
+def wdtw_weights(g: float, L: int) -> np.ndarray:
+    out = np.empty(int(L), dtype=np.float64)
+    _check(lib().eap_wdtw_weights(float(g), int(L), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out

@@ -1,0 +1,592 @@
+// C ABI of libeap (see include/eap.h): argument checks, workspace layout,
+// kernel selection and the launch sequences of distance, NN search and
+// pairwise matrices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "eap.h"
+#include "eap_launch.h"
+
+using namespace eap;
+
+namespace {
+
+thread_local std::string g_err;
+
+eap_status fail(eap_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(EAP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kMaxLen = 1024;     // longest series the sweep kernels take
+constexpr size_t kAlign = 256;
+
+// ---------------------------------------------------------------- parameters
+eap_status check_params(const eap_params* p) {
+    if (!p) return fail(EAP_EINVAL, "params is NULL");
+    if (p->kind < EAP_DTW || p->kind > EAP_TWE) return fail(EAP_EINVAL, "unknown distance kind %d", p->kind);
+    if (p->kind == EAP_CDTW || p->kind == EAP_ERP) {
+        if (std::isnan(p->window_ratio) || p->window_ratio < 0)
+            return fail(EAP_EINVAL, "window_ratio must be >= 0 (got %g)", p->window_ratio);
+    }
+    if (p->kind == EAP_WDTW && !(std::isfinite(p->g) && p->g >= 0))
+        return fail(EAP_EINVAL, "WDTW g must be finite and >= 0");
+    if (p->kind == EAP_ERP && !std::isfinite(p->gap)) return fail(EAP_EINVAL, "ERP gap must be finite");
+    if (p->kind == EAP_MSM && !(std::isfinite(p->c) && p->c >= 0)) return fail(EAP_EINVAL, "MSM c must be >= 0");
+    if (p->kind == EAP_TWE && !(std::isfinite(p->nu) && p->nu >= 0 && std::isfinite(p->lambda) && p->lambda >= 0))
+        return fail(EAP_EINVAL, "TWE nu and lambda must be finite and >= 0");
+    return EAP_OK;
+}
+
+bool windowed(const eap_params* p) {
+    return (p->kind == EAP_CDTW || p->kind == EAP_ERP) && p->window_ratio < 1.0;
+}
+
+// Distance actually swept: CDTW without a window is DTW.
+int effective_kind(const eap_params* p) {
+    if (p->kind == EAP_CDTW && !windowed(p)) return EAP_DTW;
+    return p->kind;
+}
+
+struct SetInfo {
+    int64_t n = 0, total = 0, maxlen = 0, minlen = 0;
+};
+
+eap_status check_offsets(const int64_t* off, int64_t n, const char* what, SetInfo* info) {
+    if (!off) return fail(EAP_EINVAL, "%s offsets are NULL", what);
+    if (n < 1) return fail(EAP_EINVAL, "%s: need at least one series", what);
+    if (off[0] != 0) return fail(EAP_EINVAL, "%s offsets must start at 0", what);
+    int64_t mx = 0, mn = INT64_MAX;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t L = off[k + 1] - off[k];
+        if (L < 1) return fail(EAP_EINVAL, "%s series %lld has length %lld (< 1)", what, (long long)k, (long long)L);
+        mx = std::max(mx, L);
+        mn = std::min(mn, L);
+    }
+    if (mx > kMaxLen) return fail(EAP_EINVAL, "%s: series longer than %lld are not supported", what, (long long)kMaxLen);
+    if (off[n] > (int64_t)INT32_MAX) return fail(EAP_EINVAL, "%s: too many values", what);
+    info->n = n;
+    info->total = off[n];
+    info->maxlen = mx;
+    info->minlen = mn;
+    return EAP_OK;
+}
+
+// --------------------------------------------------------- workspace layout
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + kAlign - 1) / kAlign * kAlign;
+        return o;
+    }
+};
+
+// Header at the start of every workspace.
+struct Header {
+    unsigned long long counters[8];  // cells, pairs, rechecks, overflows
+    unsigned int queues[16];
+    unsigned int ovf_count[4];
+};
+constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
+
+// ------------------------------------------------------------------ tables
+// WDTW: G[m] = 1 / (1 + exp(-g * (m / 2))) for m = 2k - L in [-Lmax, 2 Lmax]; the
+// weight of |i-j| = k for longer length L is G[2k - L] (eq. WDTW with w_max = 1:
+// (double)k - (double)L / 2 equals m / 2 exactly).
+void wdtw_table(double g, int64_t lmax, std::vector<double>& t, int& off) {
+    off = (int)lmax;
+    t.resize((size_t)(3 * lmax + 1));
+    for (int64_t m = -lmax; m <= 2 * lmax; ++m) t[(size_t)(m + lmax)] = 1.0 / (1.0 + std::exp(-g * ((double)m / 2.0)));
+}
+
+// TWE: nu * (2|k|) for k = j - i in [-Lmax, Lmax + 1024] (eq. TWECost with tau_i = i).
+void twe_table(double nu, int64_t lmax, std::vector<double>& t, int& off) {
+    off = (int)lmax;
+    t.resize((size_t)(2 * lmax + 1024 + 1));
+    for (int64_t k = -lmax; k <= lmax + 1024; ++k) t[(size_t)(k + lmax)] = nu * (double)(2 * (k < 0 ? -k : k));
+}
+
+// Pinned staging for host-to-device copies.  Each copy waits for the previous
+// one issued from the same buffer before overwriting it.
+struct Staging {
+    std::mutex mu;
+    void* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+Staging g_stage;
+
+eap_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return EAP_OK;
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    if (g_stage.pending) {
+        HIPCHK(hipEventSynchronize(g_stage.ev));
+        g_stage.pending = false;
+    }
+    if (!g_stage.ev) HIPCHK(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
+    if (g_stage.cap < bytes) {
+        if (g_stage.buf) HIPCHK(hipHostFree(g_stage.buf));
+        g_stage.buf = nullptr;
+        g_stage.cap = 0;
+        size_t cap = std::max<size_t>(bytes, 1 << 20);
+        if (hipHostMalloc(&g_stage.buf, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(EAP_ENOMEM, "pinned staging buffer of %zu bytes", cap);
+        g_stage.cap = cap;
+    }
+    std::memcpy(g_stage.buf, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, g_stage.buf, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(g_stage.ev, s));
+    g_stage.pending = true;
+    return EAP_OK;
+}
+
+int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cus[dev] = pr.multiProcessorCount;
+        else cus[dev] = 256;
+    }
+    return cus[dev];
+}
+
+int sweep_grid(int64_t items, int group_lanes) {
+    const int groups_per_block = 256 / group_lanes;
+    int64_t need = (items + groups_per_block - 1) / groups_per_block;
+    int64_t cap = (int64_t)device_cus() * 8;
+    return (int)std::max<int64_t>(1, std::min(need, cap));
+}
+
+int pick_width(int64_t lco_max) {
+    for (int w : {128, 256, 512, 1024})
+        if (lco_max <= w) return w;
+    return 0;
+}
+
+int rows_group(int width) { return width <= 256 ? 16 : (width == 512 ? 32 : 64); }
+int band_group(int diags) { return diags <= 256 ? 16 : (diags == 512 ? 32 : 64); }
+
+int pick_diags(int64_t need) {
+    for (int d : {128, 256, 512, 1024, 2048})
+        if (need <= d) return d;
+    return 0;
+}
+
+// What the sweep of one distance needs, for sets whose longest series have
+// lengths la_max and lb_max.
+struct Plan {
+    bool band = false;     // kernel B (true) or kernel A
+    int size = 0;          // A: row width; B: diagonals of the first pass
+    int band_half = 0;     // B, unconstrained: half width of the first pass
+    int full = 0;          // B, unconstrained: diagonals of the full re-run
+};
+
+eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_t l_diff_max, bool narrow_first,
+                     Plan* pl) {
+    const int kind = effective_kind(p);
+    const int64_t lmax = std::max(la_max, lb_max);
+    const int64_t lco_max = std::min(la_max, lb_max);
+    if (kind == EAP_DTW || kind == EAP_MSM || kind == EAP_TWE || (kind == EAP_ERP && !windowed(p))) {
+        pl->band = false;
+        pl->size = pick_width(lco_max);
+        if (!pl->size) return fail(EAP_EINVAL, "series too long for the row sweep");
+        return EAP_OK;
+    }
+    pl->band = true;
+    if (kind == EAP_CDTW || kind == EAP_ERP) {
+        int64_t w = (int64_t)std::floor(p->window_ratio * (double)lmax);
+        int64_t wb = std::min<int64_t>(w + (kind == EAP_ERP ? 1 : 0), lmax);
+        pl->size = pick_diags(2 * wb + 2);
+        if (!pl->size) return fail(EAP_EINVAL, "window too wide for the band sweep");
+        pl->full = pl->size;   // the window is the band: nothing to re-run
+        return EAP_OK;
+    }
+    // WDTW: a certified narrow band first, the full band for the items it cannot certify
+    pl->full = pick_diags(la_max + lb_max);
+    if (!pl->full) return fail(EAP_EINVAL, "series too long for the band sweep");
+    if (narrow_first) {
+        pl->size = 256;
+        pl->band_half = (int)std::max<int64_t>(16, (256 - 2 - l_diff_max) / 2);
+        if (pl->size >= pl->full) {
+            pl->size = pl->full;
+            pl->band_half = (int)(2 * lmax);
+        }
+    } else {
+        pl->size = pl->full;
+        pl->band_half = (int)(2 * lmax);
+    }
+    return EAP_OK;
+}
+
+SweepArgs base_args(const eap_params* p) {
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.gap = p->gap;
+    a.c = p->c;
+    a.nu = p->nu;
+    a.lam = p->lambda;
+    a.window_ratio = windowed(p) ? p->window_ratio : 2.0;
+    return a;
+}
+
+// Device regions shared by the drivers for one (set A, set B) problem.
+struct Common {
+    size_t hdr = 0, offA = 0, offB = 0, bordA = 0, bordB = 0, tab = 0, gtab = 0;
+    std::vector<double> tabv, gtabv;
+    int tab_off = 0, gtab_off = 0;
+};
+
+void plan_common(Layout& L, Common& c, const eap_params* p, const SetInfo& A, const SetInfo* B) {
+    c.hdr = L.take(kHeaderBytes);
+    c.offA = L.take(sizeof(int64_t) * (size_t)(A.n + 1));
+    if (B) c.offB = L.take(sizeof(int64_t) * (size_t)(B->n + 1));
+    const int64_t lmax = std::max(A.maxlen, B ? B->maxlen : 0);
+    if (p->kind == EAP_ERP) {
+        c.bordA = L.take(sizeof(double) * (size_t)A.total);
+        if (B) c.bordB = L.take(sizeof(double) * (size_t)B->total);
+    }
+    if (p->kind == EAP_TWE) {
+        twe_table(p->nu, lmax, c.tabv, c.tab_off);
+        c.tab = L.take(sizeof(double) * c.tabv.size());
+    }
+    if (p->kind == EAP_WDTW) {
+        wdtw_table(p->g, lmax, c.gtabv, c.gtab_off);
+        c.gtab = L.take(sizeof(double) * c.gtabv.size());
+    }
+}
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+eap_status setup_common(void* ws, const Common& c, const eap_params* p, const double* va, const int64_t* offa,
+                        int64_t na, const double* vb, const int64_t* offb, int64_t nb, hipStream_t s,
+                        SweepArgs& a, SeriesPtrs& SA, SeriesPtrs& SB) {
+    eap_status st;
+    // work queues and overflow counts start at zero; the counters keep accumulating
+    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(at(ws, c.hdr)) + 8, 0ull,
+                           (int64_t)(kHeaderBytes / 8) - 8, s));
+    if ((st = upload(at(ws, c.offA), offa, sizeof(int64_t) * (size_t)(na + 1), s)) != EAP_OK) return st;
+    if (offb && (st = upload(at(ws, c.offB), offb, sizeof(int64_t) * (size_t)(nb + 1), s)) != EAP_OK) return st;
+    const int64_t* dA = reinterpret_cast<const int64_t*>(at(ws, c.offA));
+    const int64_t* dB = offb ? reinterpret_cast<const int64_t*>(at(ws, c.offB)) : dA;
+    SA = SeriesPtrs{va, dA, nullptr};
+    SB = SeriesPtrs{vb ? vb : va, dB, nullptr};
+    if (p->kind == EAP_ERP) {
+        double* bA = reinterpret_cast<double*>(at(ws, c.bordA));
+        HIPCHK(launch_erp_border(va, dA, na, p->gap, bA, s));
+        SA.border = bA;
+        if (offb) {
+            double* bB = reinterpret_cast<double*>(at(ws, c.bordB));
+            HIPCHK(launch_erp_border(vb, dB, nb, p->gap, bB, s));
+            SB.border = bB;
+        } else {
+            SB.border = bA;
+        }
+    }
+    if (p->kind == EAP_TWE) {
+        if ((st = upload(at(ws, c.tab), c.tabv.data(), sizeof(double) * c.tabv.size(), s)) != EAP_OK) return st;
+        a.tab = reinterpret_cast<const double*>(at(ws, c.tab));
+        a.tab_off = c.tab_off;
+        a.tab_len = (int)c.tabv.size();
+    }
+    if (p->kind == EAP_WDTW) {
+        if ((st = upload(at(ws, c.gtab), c.gtabv.data(), sizeof(double) * c.gtabv.size(), s)) != EAP_OK) return st;
+        a.gtab = reinterpret_cast<const double*>(at(ws, c.gtab));
+        a.gtab_off = c.gtab_off;
+        a.gtab_len = (int)c.gtabv.size();
+    }
+    Header* h = reinterpret_cast<Header*>(at(ws, c.hdr));
+    a.counters = h->counters;
+    return EAP_OK;
+}
+
+Header* hdr_of(void* ws, const Common& c) { return reinterpret_cast<Header*>(at(ws, c.hdr)); }
+
+// One sweep launch (kernel A or B) over `n` work slots.
+eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, unsigned int* queue, const int32_t* items,
+                 int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s) {
+    a.queue = queue;
+    a.items = items;
+    a.npairs = n;
+    const int kind = effective_kind(p);
+    (void)hipGetLastError();   // launch errors below must be this launch's own
+    hipError_t e;
+    if (band) e = launch_band(kind, false, size, a, SA, SB, sweep_grid(n, band_group(size)), s);
+    else e = launch_rows(kind, false, size, a, SA, SB, sweep_grid(n, rows_group(size)), s);
+    if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
+    return EAP_OK;
+}
+
+// Items of the narrow band pass that could not be certified are re-swept with
+// the full band.  Their list and count stay on the device: the re-run reads the
+// count at run time, so nothing synchronises the host.
+eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, unsigned int* ovf_count,
+                          const int32_t* ovf_items, int64_t max_items, unsigned int* queue, SeriesPtrs SA,
+                          SeriesPtrs SB, hipStream_t s) {
+    a.band_half = 1 << 20;
+    a.ovf_items = nullptr;
+    a.ovf_count = nullptr;
+    a.npairs_dev = ovf_count;
+    return sweep(p, true, pl.full, a, queue, ovf_items, max_items, SA, SB, s);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* eap_last_error(void) { return g_err.c_str(); }
+
+const char* eap_version(void) { return "eap-mi355x 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ distance
+static void distance_layout(int64_t lx, int64_t ly, const eap_params* p, Layout& L, Common& c, size_t* ovf) {
+    SetInfo A, B;
+    A.n = 1; A.total = lx; A.maxlen = A.minlen = lx;
+    B.n = 1; B.total = ly; B.maxlen = B.minlen = ly;
+    plan_common(L, c, p, A, &B);
+    *ovf = L.take(sizeof(int32_t) * 8);
+}
+
+size_t eap_distance_workspace(int64_t lx, int64_t ly, const eap_params* p) {
+    if (check_params(p) != EAP_OK || lx < 1 || ly < 1) return 0;
+    Layout L;
+    Common c;
+    size_t ovf;
+    distance_layout(lx, ly, p, L, c, &ovf);
+    return L.off;
+}
+
+eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly, const eap_params* p, double cutoff,
+                        double* out, void* ws, size_t ws_bytes, void* stream) {
+    eap_status st;
+    if ((st = check_params(p)) != EAP_OK) return st;
+    if (!x || !y || !out) return fail(EAP_EINVAL, "NULL series or output");
+    if (lx < 1 || ly < 1) return fail(EAP_EINVAL, "series lengths must be >= 1");
+    if (lx > kMaxLen || ly > kMaxLen) return fail(EAP_EINVAL, "series longer than %lld are not supported", (long long)kMaxLen);
+    if (std::isnan(cutoff) || cutoff < 0) return fail(EAP_EINVAL, "cutoff must be >= 0 or +inf");
+    Layout L;
+    Common c;
+    size_t ovf;
+    distance_layout(lx, ly, p, L, c, &ovf);
+    if (!ws || ws_bytes < L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, L.off);
+    Plan pl;
+    if ((st = make_plan(p, lx, ly, std::llabs(lx - ly), false, &pl)) != EAP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t offa[2] = {0, lx}, offb[2] = {0, ly};
+    SweepArgs a = base_args(p);
+    SeriesPtrs SA, SB;
+    if ((st = setup_common(ws, c, p, x, offa, 1, y, offb, 1, s, a, SA, SB)) != EAP_OK) return st;
+    // the cut-off travels in the result slot: the kernel reads it from pcut[0]
+    if ((st = upload(out, &cutoff, sizeof cutoff, s)) != EAP_OK) return st;
+    a.mode = PM_SINGLE;
+    a.nA = a.nB = 1;
+    a.pcut = out;
+    a.res = out;
+    a.band_half = pl.band_half;
+    a.ovf_items = reinterpret_cast<int32_t*>(at(ws, ovf));
+    a.ovf_count = &hdr_of(ws, c)->ovf_count[0];
+    return sweep(p, pl.band, pl.size, a, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s);
+}
+
+// ---------------------------------------------------------------------- NN
+struct NNLayout {
+    Layout L;
+    Common c;
+    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0;
+};
+
+static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params* p, NNLayout& nl) {
+    plan_common(nl.L, nl.c, p, Q, &R);
+    nl.best = nl.L.take(sizeof(unsigned long long) * (size_t)Q.n);
+    nl.seed = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
+    nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
+    nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
+    nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
+    return EAP_OK;
+}
+
+size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off, int64_t nr, const eap_params* p,
+                         const eap_nn_opts* o) {
+    (void)o;
+    SetInfo Q, R;
+    if (check_params(p) != EAP_OK || check_offsets(q_off, nq, "queries", &Q) != EAP_OK ||
+        check_offsets(r_off, nr, "candidates", &R) != EAP_OK)
+        return 0;
+    NNLayout nl;
+    nn_layout(Q, R, p, nl);
+    return nl.L.off;
+}
+
+eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,
+                   int64_t nr, const int32_t* r_labels, const eap_params* p, const eap_nn_opts* o, void* ws,
+                   size_t ws_bytes, int64_t* out_idx, double* out_dist, int32_t* out_label, void* stream) {
+    eap_status st;
+    if ((st = check_params(p)) != EAP_OK) return st;
+    if (!q || !r || !out_idx || !out_dist) return fail(EAP_EINVAL, "NULL series or output");
+    SetInfo Q, R;
+    if ((st = check_offsets(q_off, nq, "queries", &Q)) != EAP_OK) return st;
+    if ((st = check_offsets(r_off, nr, "candidates", &R)) != EAP_OK) return st;
+    if ((int64_t)nq * nr > (int64_t)INT32_MAX) return fail(EAP_EINVAL, "nq * nr exceeds 2^31 - 1");
+    if (o) {
+        if (o->precision != 0 && o->precision != 1) return fail(EAP_EINVAL, "precision must be 0 or 1");
+        if (!(std::isfinite(o->margin_rel) && o->margin_rel >= 0)) return fail(EAP_EINVAL, "margin_rel must be >= 0");
+        if (o->precision == 1) return fail(EAP_EINVAL, "precision 1 is not available in this build");
+    }
+    NNLayout nl;
+    nn_layout(Q, R, p, nl);
+    if (!ws || ws_bytes < nl.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, nl.L.off);
+    Plan pl;
+    const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
+    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, true, &pl)) != EAP_OK) return st;
+
+    hipStream_t s = (hipStream_t)stream;
+    SweepArgs a = base_args(p);
+    SeriesPtrs SQ, SR;
+    if ((st = setup_common(ws, nl.c, p, q, q_off, nq, r, r_off, nr, s, a, SQ, SR)) != EAP_OK) return st;
+    Header* h = hdr_of(ws, nl.c);
+    unsigned long long* best = reinterpret_cast<unsigned long long*>(at(ws, nl.best));
+    int32_t* seed = reinterpret_cast<int32_t*>(at(ws, nl.seed));
+    int32_t* seed_items = reinterpret_cast<int32_t*>(at(ws, nl.seed_items));
+    double* res = reinterpret_cast<double*>(at(ws, nl.res));
+    int32_t* ovf = reinterpret_cast<int32_t*>(at(ws, nl.ovf));
+    a.mode = PM_NN_ALL;
+    a.nA = nq;
+    a.nB = nr;
+    a.best = best;
+    a.res = res;
+    a.band_half = pl.band_half;
+    a.ovf_items = ovf;
+    a.ovf_count = &h->ovf_count[0];
+    const bool seeded = !(o && (o->flags & 1));
+    // 1. upper bounds from the diagonal path, the best of them seeds each query
+    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, res, s));
+    HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
+    if (seeded) {
+        // 2. sweep the seed candidate of every query under its bound
+        if ((st = sweep(p, pl.band, pl.size, a, &h->queues[0], seed_items, nq, SQ, SR, s)) != EAP_OK) return st;
+        if (pl.band && pl.size != pl.full) {
+            if ((st = rerun_overflow(p, pl, a, &h->ovf_count[0], ovf, nq, &h->queues[1], SQ, SR, s)) != EAP_OK) return st;
+            HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
+        }
+        a.skip_b = seed;
+    }
+    // 3. every other pair, under the per-query best-so-far (lowered as pairs complete)
+    if ((st = sweep(p, pl.band, pl.size, a, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+    if (pl.band && pl.size != pl.full) {
+        a.skip_b = nullptr;
+        if ((st = rerun_overflow(p, pl, a, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], SQ, SR, s)) != EAP_OK) return st;
+    }
+    // 4. lexicographic (distance, index) minimum per query
+    HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
+    return EAP_OK;
+}
+
+// ---------------------------------------------------------------- pairwise
+struct PWLayout {
+    Layout L;
+    Common c;
+    size_t cut = 0, ovf = 0;
+};
+
+static void pw_layout(const SetInfo& S, const eap_params* p, PWLayout& pl) {
+    plan_common(pl.L, pl.c, p, S, nullptr);
+    const int64_t np = S.n * (S.n - 1) / 2;
+    pl.cut = pl.L.take(sizeof(double) * (size_t)std::max<int64_t>(np, 1));
+    pl.ovf = pl.L.take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1));
+}
+
+size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params* p) {
+    SetInfo S;
+    if (check_params(p) != EAP_OK || check_offsets(s_off, n, "series", &S) != EAP_OK) return 0;
+    PWLayout pl;
+    pw_layout(S, p, pl);
+    return pl.L.off;
+}
+
+eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const eap_params* p, int32_t mode, void* ws,
+                        size_t ws_bytes, double* out, void* stream) {
+    eap_status st;
+    if ((st = check_params(p)) != EAP_OK) return st;
+    if (!s || !out) return fail(EAP_EINVAL, "NULL series or output");
+    if (mode != 0 && mode != 1) return fail(EAP_EINVAL, "mode must be 0 (prune-only) or 1 (plain DP)");
+    SetInfo S;
+    if ((st = check_offsets(s_off, n, "series", &S)) != EAP_OK) return st;
+    if (n < 2) return fail(EAP_EINVAL, "pairwise needs at least two series");
+    const int64_t np = n * (n - 1) / 2;
+    if (np > (int64_t)INT32_MAX) return fail(EAP_EINVAL, "too many pairs");
+    PWLayout pw;
+    pw_layout(S, p, pw);
+    if (!ws || ws_bytes < pw.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, pw.L.off);
+    Plan pl;
+    if ((st = make_plan(p, S.maxlen, S.maxlen, S.maxlen - S.minlen, false, &pl)) != EAP_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    SweepArgs a = base_args(p);
+    SeriesPtrs SA, SB;
+    if ((st = setup_common(ws, pw.c, p, s, s_off, n, nullptr, nullptr, n, hs, a, SA, SB)) != EAP_OK) return st;
+    Header* h = hdr_of(ws, pw.c);
+    a.mode = PM_CONDENSED;
+    a.nA = a.nB = n;
+    a.res = out;
+    a.band_half = pl.band_half;
+    a.ovf_items = reinterpret_cast<int32_t*>(at(ws, pw.ovf));
+    a.ovf_count = &h->ovf_count[0];
+    if (mode == 0) {
+        double* cut = reinterpret_cast<double*>(at(ws, pw.cut));
+        HIPCHK(launch_ub_condensed(effective_kind(p), a, s, SA.off, n, cut, hs));
+        a.pcut = cut;
+    }
+    return sweep(p, pl.band, pl.size, a, &h->queues[0], nullptr, np, SA, SB, hs);
+}
+
+eap_status eap_wdtw_weights(double g, int64_t L, double* out) {
+    if (!out || L < 1 || !(std::isfinite(g) && g >= 0)) return fail(EAP_EINVAL, "bad WDTW weight arguments");
+    std::vector<double> t;
+    int off = 0;
+    wdtw_table(g, L, t, off);
+    for (int64_t k = 0; k < L; ++k) out[k] = t[(size_t)(2 * k - L + off)];
+    return EAP_OK;
+}
+
+// ---------------------------------------------------------------- counters
+eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out, void* stream) {
+    if (!ws || ws_bytes < kHeaderBytes || !out) return fail(EAP_EINVAL, "bad workspace or output");
+    Header h;
+    HIPCHK(hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    out->cells = h.counters[0];
+    out->pairs = h.counters[1];
+    out->rechecks = h.counters[2];
+    out->overflows = h.counters[3];
+    return EAP_OK;
+}
+
+eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream) {
+    if (!ws || ws_bytes < kHeaderBytes) return fail(EAP_EINVAL, "bad workspace");
+    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws), 0ull, 8, (hipStream_t)stream));
+    return EAP_OK;
+}
+
+}  // extern "C"

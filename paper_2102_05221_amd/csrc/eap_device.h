@@ -1,0 +1,54 @@
+// Device-side helpers shared by the sweep kernels of libeap (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eap {
+
+enum Kind : int { DTW = 0, CDTW = 1, WDTW = 2, ERP = 3, MSM = 4, TWE = 5 };
+
+template <typename T> __device__ __forceinline__ T inf_v();
+template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_huge_val(); }
+template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_huge_valf(); }
+
+template <typename T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
+template <typename T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double vabs(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float vabs(float a) { return __builtin_fabsf(a); }
+
+// Lane k receives lane k-1's value (DPP wave_shr:1; lane 0 receives 0).  Must
+// be executed with every lane of the wave active, so that the source lanes
+// hold defined values.
+__device__ __forceinline__ int shr1_i32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float shr1(float v) {
+    return __builtin_bit_cast(float, shr1_i32(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double shr1(double v) {
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = shr1_i32((int)(unsigned long long)b);
+    int hi = shr1_i32((int)((unsigned long long)b >> 32));
+    unsigned long long r = (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32);
+    return __builtin_bit_cast(double, r);
+}
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+
+// Non-negative doubles order like their bit patterns, +inf above every finite.
+__device__ __forceinline__ unsigned long long dbits(double v) {
+    return (unsigned long long)__builtin_bit_cast(long long, v);
+}
+__device__ __forceinline__ double bitsd(unsigned long long b) { return __builtin_bit_cast(double, (long long)b); }
+
+// One set of series: concatenated values, int64 offsets (n+1), and for ERP the
+// running border sums B[off+i-1] = sum_{m<=i} |x_m - gap| (same layout).
+template <typename T> struct Series {
+    const T* v;
+    const int64_t* off;
+    const T* border;
+};
+
+}  // namespace eap

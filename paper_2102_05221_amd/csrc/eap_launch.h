@@ -1,0 +1,81 @@
+// Host-side launch interface between the C ABI (eap_api.cpp) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eap {
+
+// How a sweep kernel enumerates its work items.
+// A launch processes items[0..npairs) when `items` is given, else 0..npairs.
+enum PairMode : int {
+    PM_NN_ALL = 0,    // item p -> (a = p / nB, b = p % nB); skips b == skip_b[a]
+    PM_CONDENSED = 1, // item p -> pair (i, j), i < j, of set A (B == A), condensed order
+    PM_SINGLE = 3     // one pair (A[0], B[0])
+};
+
+struct SweepArgs {
+    int mode;
+    int64_t nA, nB, npairs;
+    const int32_t* skip_b;
+    const int32_t* items;
+    // NN: best-so-far cut-off per query a (bits of a non-negative double),
+    // atomically lowered by every pair that completes under it.
+    unsigned long long* best;
+    // Per-item cut-off (PM_CONDENSED: condensed index; PM_SINGLE: [0]); NULL = +inf.
+    const double* pcut;
+    // Result per item: NN modes at a*nB + b, PM_CONDENSED at the condensed
+    // index, PM_SINGLE at [0].  +inf when abandoned.
+    double* res;
+    unsigned int* queue;             // work counter, zero at launch
+    unsigned long long* counters;    // [0] cells executed, [1] pairs swept, [3] band overflows
+    // distance parameters
+    double gap, c, nu, lam;
+    // Per-diagonal tables, indexed by (j - i) + tab_off:
+    //   TWE: nu * (2|j-i|);  WDTW: weight of |j-i| for the pair's longer length
+    const double* tab;
+    int tab_off, tab_len;
+    // WDTW: G[m] = 1/(1+exp(-g*m/2)) for m = 2k - L, indexed m + gtab_off
+    const double* gtab;
+    int gtab_off, gtab_len;
+    // window (CDTW / ERP): ratio as given; <0 means none
+    double window_ratio;
+    // band kernel: half-width of the band for unconstrained distances
+    int band_half;
+    // band kernel: items whose band was too narrow are appended here
+    int32_t* ovf_items;
+    unsigned int* ovf_count;
+    // when set, the number of work slots is read from here at run time
+    const unsigned int* npairs_dev;
+};
+
+struct SeriesPtrs {
+    const void* v;
+    const int64_t* off;
+    const void* border;
+};
+
+// Row sweep (kernel A): full rows of W = G*C columns per pair.  Returns the
+// launch error.  `width` selects W (128, 256, 512, 1024); the shorter series
+// of every pair must have length <= width.
+hipError_t launch_rows(int kind, bool fp32, int width, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
+                       hipStream_t s);
+int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a);
+
+// Band sweep (kernel B): anti-diagonal sweep of a band of 2*G*C diagonals.
+hipError_t launch_band(int kind, bool fp32, int diags, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
+                       hipStream_t s);
+
+// Auxiliary kernels.
+hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s);
+hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
+hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
+                        const int64_t* roff, double* ub, hipStream_t s);
+hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
+                               double* cut, hipStream_t s);
+hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* list_a,
+                       unsigned long long* best, hipStream_t s);
+hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
+                         double* out_dist, int32_t* out_label, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+
+}  // namespace eap

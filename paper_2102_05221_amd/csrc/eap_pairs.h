@@ -1,0 +1,71 @@
+// Work-item decoding shared by the sweep kernels.
+#pragma once
+#include "eap_device.h"
+#include "eap_launch.h"
+
+namespace eap {
+
+struct Item {
+    int32_t a, b;     // series index in set A and set B
+    int64_t out;      // result slot
+    int64_t cutidx;   // index into pcut (non-NN modes)
+    bool skip;
+};
+
+// Condensed index k -> (i, j), i < j < n, with k = n*i - i*(i+1)/2 + (j-i-1).
+__device__ __forceinline__ void condensed_ij(int64_t k, int64_t n, int64_t& i, int64_t& j) {
+    double nn = (double)(2 * n - 1);
+    int64_t ii = (int64_t)((nn - sqrt(nn * nn - 8.0 * (double)k)) * 0.5);
+    if (ii < 0) ii = 0;
+    if (ii > n - 2) ii = n - 2;
+    while (ii > 0 && n * ii - ii * (ii + 1) / 2 > k) --ii;
+    while (ii < n - 2 && n * (ii + 1) - (ii + 1) * (ii + 2) / 2 <= k) ++ii;
+    i = ii;
+    j = k - (n * ii - ii * (ii + 1) / 2) + ii + 1;
+}
+
+__device__ __forceinline__ Item decode_item(const SweepArgs& A, int64_t p) {
+    Item it;
+    it.skip = false;
+    it.cutidx = p;
+    switch (A.mode) {
+    case PM_NN_ALL: {
+        int64_t a = p / A.nB, b = p - a * A.nB;
+        it.a = (int32_t)a;
+        it.b = (int32_t)b;
+        it.out = p;
+        it.skip = (A.skip_b != nullptr) && (A.skip_b[a] == (int32_t)b);
+        break;
+    }
+    case PM_CONDENSED: {
+        int64_t i, j;
+        condensed_ij(p, A.nA, i, j);
+        it.a = (int32_t)i;
+        it.b = (int32_t)j;
+        it.out = p;
+        break;
+    }
+    default: {
+        it.a = 0;
+        it.b = 0;
+        it.out = 0;
+        break;
+    }
+    }
+    return it;
+}
+
+__device__ __forceinline__ bool is_nn_mode(int mode) { return mode == PM_NN_ALL; }
+
+// The item index behind work slot p of a launch.
+__device__ __forceinline__ int64_t item_of(const SweepArgs& A, unsigned int p) {
+    return A.items ? (int64_t)A.items[p] : (int64_t)p;
+}
+
+// Sum of a per-lane counter over the wave, added once per wave.
+__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+}  // namespace eap

@@ -1,0 +1,148 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/eap.h declares, validates its arguments before touching the device,
+and computes the same WDTW weights as the oracle, bit for bit."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2102_05221_amd as eap
+from paper_2102_05221_amd import build as eap_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eap.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(eap.LIB_PATH):
+        eap_build.build()
+    return eap.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eap_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_paper_calls():
+    names = declared_functions()
+    for n in ("eap_distance", "eap_nn1", "eap_pairwise", "eap_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.eap_version()
+
+
+def _p(kind="dtw", **kw):
+    return eap.params(kind, **kw)
+
+
+def _off(*lens):
+    o = np.zeros(len(lens) + 1, dtype=np.int64)
+    o[1:] = np.cumsum(lens)
+    return o
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every case below fails validation first
+
+
+def test_distance_argument_errors(L):
+    p = _p()
+    ws = ctypes.c_void_p(0x2000)
+    need = L.eap_distance_workspace(10, 12, ctypes.byref(p))
+    assert need > 0
+    cases = [
+        (None, 10, FAKE, 12, p, 1.0, FAKE, ws, need),          # NULL x
+        (FAKE, 0, FAKE, 12, p, 1.0, FAKE, ws, need),           # empty series
+        (FAKE, 10, FAKE, 12, p, float("nan"), FAKE, ws, need), # NaN cut-off
+        (FAKE, 10, FAKE, 12, p, -1.0, FAKE, ws, need),         # negative cut-off
+        (FAKE, 10, FAKE, 12, _p("cdtw", window_ratio=-0.1), 1.0, FAKE, ws, need),
+        (FAKE, 10, FAKE, 12, _p("cdtw", window_ratio=float("nan")), 1.0, FAKE, ws, need),
+        (FAKE, 10, FAKE, 12, _p("msm", c=-1.0), 1.0, FAKE, ws, need),
+        (FAKE, 10, FAKE, 12, _p("twe", nu=-1.0), 1.0, FAKE, ws, need),
+        (FAKE, 10, FAKE, 12, _p("erp", gap=float("inf")), 1.0, FAKE, ws, need),
+        (FAKE, 10, FAKE, 12, _p("wdtw", g=float("nan")), 1.0, FAKE, ws, need),
+        (FAKE, 5000, FAKE, 12, p, 1.0, FAKE, ws, need),        # longer than supported
+    ]
+    for x, lx, y, ly, pp, cut, out, w, nb in cases:
+        st = L.eap_distance(x, lx, y, ly, ctypes.byref(pp), cut, out, w, nb, None)
+        assert st == eap.EAP_EINVAL, (lx, cut, pp.kind)
+        assert len(L.eap_last_error()) > 0
+    bad_kind = eap.Params(9, 1.0, 0, 0, 0, 0, 0)
+    assert L.eap_distance(FAKE, 3, FAKE, 3, ctypes.byref(bad_kind), 1.0, FAKE, ws, need, None) == eap.EAP_EINVAL
+    # workspace too small / missing
+    assert L.eap_distance(FAKE, 10, FAKE, 12, ctypes.byref(p), 1.0, FAKE, ws, need - 1, None) == eap.EAP_EWORKSPACE
+    assert L.eap_distance(FAKE, 10, FAKE, 12, ctypes.byref(p), 1.0, FAKE, None, need, None) == eap.EAP_EWORKSPACE
+
+
+def test_nn1_argument_errors(L):
+    p = _p("msm", c=0.5)
+    qo, ro = _off(5, 7), _off(4, 4, 9)
+    o = eap.NNOpts(0, 1e-4, 0)
+    pi = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    need = L.eap_nn1_workspace(pi(qo), 2, pi(ro), 3, ctypes.byref(p), ctypes.byref(o))
+    assert need > 0
+    ws = ctypes.c_void_p(0x2000)
+
+    def call(q=FAKE, qo_=qo, nq=2, r=FAKE, ro_=ro, nr=3, pp=p, oo=o, nb=need, idx=FAKE, dist=FAKE):
+        return L.eap_nn1(q, pi(qo_), nq, r, pi(ro_), nr, None, ctypes.byref(pp), ctypes.byref(oo), ws, nb, idx,
+                         dist, None, None)
+
+    assert call(q=None) == eap.EAP_EINVAL
+    assert call(idx=None) == eap.EAP_EINVAL
+    assert call(nq=0) == eap.EAP_EINVAL
+    assert call(qo_=np.array([1, 5, 12], dtype=np.int64)) == eap.EAP_EINVAL      # does not start at 0
+    assert call(ro_=np.array([0, 4, 4, 13], dtype=np.int64)) == eap.EAP_EINVAL   # a zero-length series
+    assert call(oo=eap.NNOpts(7, 1e-4, 0)) == eap.EAP_EINVAL
+    assert call(oo=eap.NNOpts(1, float("nan"), 0)) == eap.EAP_EINVAL
+    assert call(nb=need - 1) == eap.EAP_EWORKSPACE
+
+
+def test_pairwise_argument_errors(L):
+    p = _p("cdtw", window_ratio=0.1)
+    so = _off(6, 6, 6)
+    pi = so.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    need = L.eap_pairwise_workspace(pi, 3, ctypes.byref(p))
+    assert need > 0
+    ws = ctypes.c_void_p(0x2000)
+    assert L.eap_pairwise(FAKE, pi, 3, ctypes.byref(p), 2, ws, need, FAKE, None) == eap.EAP_EINVAL   # bad mode
+    assert L.eap_pairwise(None, pi, 3, ctypes.byref(p), 0, ws, need, FAKE, None) == eap.EAP_EINVAL
+    one = _off(6)
+    assert L.eap_pairwise(FAKE, one.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, ctypes.byref(p), 0, ws, need,
+                          FAKE, None) == eap.EAP_EINVAL
+    assert L.eap_pairwise(FAKE, pi, 3, ctypes.byref(p), 0, ws, need - 8, FAKE, None) == eap.EAP_EWORKSPACE
+
+
+def test_workspace_sizes_grow_with_the_problem(L):
+    p = _p("twe", nu=0.001, lam=1.0)
+    o = eap.NNOpts(0, 1e-4, 0)
+    pi = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    small = L.eap_nn1_workspace(pi(_off(8, 8)), 2, pi(_off(8, 8)), 2, ctypes.byref(p), ctypes.byref(o))
+    big = L.eap_nn1_workspace(pi(_off(*[100] * 20)), 20, pi(_off(*[100] * 300)), 300, ctypes.byref(p),
+                              ctypes.byref(o))
+    assert 0 < small < big
+    assert big >= 20 * 300 * 8
+
+
+def test_wdtw_weights_bit_equal_to_oracle(L, orc):
+    for g in (0.0, 0.05, 0.3, 1.0, 3.7):
+        for n in (1, 2, 7, 128, 511, 512, 1024):
+            a = eap.wdtw_weights(g, n)
+            b = orc.wdtw_weights(g, n)
+            assert a.tobytes() == b.tobytes(), (g, n)
+    assert L.eap_wdtw_weights(float("nan"), 4, None) == eap.EAP_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    monkeypatch.setattr(eap, "_lib", None)
+    monkeypatch.setattr(eap, "LIB_PATH", str(tmp_path / "libeap.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        eap.lib()

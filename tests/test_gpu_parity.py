@@ -1,0 +1,186 @@
+"""Parity of the HIP path with the CPU oracle (GPU required).
+
+Distances must agree to 1e-12 relative (the contract) and in practice bit for
+bit, since both sides evaluate every cell with the same operation order; NN
+indices and labels must agree exactly.  Inputs are seeded and synthetic.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2102_05221_amd as eap
+from paper_2102_05221_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+INF = math.inf
+RTOL = 1e-12
+
+ALL = [
+    dict(kind="dtw"),
+    dict(kind="cdtw", window_ratio=0.1),
+    dict(kind="cdtw", window_ratio=0.0),
+    dict(kind="cdtw", window_ratio=0.35),
+    dict(kind="wdtw", g=0.05),
+    dict(kind="wdtw", g=0.6),
+    dict(kind="erp", gap=0.0),
+    dict(kind="erp", gap=0.3, window_ratio=0.2),
+    dict(kind="msm", c=0.5),
+    dict(kind="twe", nu=0.001, lam=1.0),
+    dict(kind="twe", nu=0.5, lam=0.0),
+]
+
+
+def pid(p):
+    return "-".join(f"{k}={v}" for k, v in p.items())
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def close(g, o):
+    if math.isinf(o) or math.isinf(g):
+        return math.isinf(o) and math.isinf(g)
+    return abs(g - o) <= RTOL * max(abs(o), 1e-300)
+
+
+@pytest.mark.parametrize("p", ALL, ids=pid)
+def test_distance_parity_with_cutoffs(torch_dev, orc, p):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(100 + synth.SIX.index(p["kind"]))
+    lens = [(1, 1), (1, 7), (7, 1), (3, 5), (17, 16), (64, 64), (65, 130), (200, 199), (333, 512), (512, 500),
+            (1000, 1024), (257, 1)]
+    nbits = ntot = 0
+    for (lx, ly) in lens:
+        x = synth.znorm(np.cumsum(rng.normal(size=lx))) if lx > 1 else rng.normal(size=1)
+        y = synth.znorm(np.cumsum(rng.normal(size=ly))) if ly > 1 else rng.normal(size=1)
+        d = orc.dp(p, x, y)
+        cuts = [INF]
+        if d < INF:
+            cuts += [d, float(np.nextafter(d, -INF)), 0.5 * d, 1.5 * d, 0.0]
+        xd, yd = to_dev(torch, dev, x), to_dev(torch, dev, y)
+        for c in cuts:
+            log(f"distance {pid(p)} lx={lx} ly={ly} cut={c}")
+            g = float(eap.distance(xd, yd, p, c).item())
+            want = d if d <= c else INF
+            assert close(g, want), (lx, ly, c, g, want)
+            ntot += 1
+            nbits += (g == want)
+    assert nbits == ntot, f"{ntot - nbits} of {ntot} results not bit-identical"
+
+
+@pytest.mark.parametrize("kind", synth.SIX)
+def test_nn1_parity_class_templates(torch_dev, orc, kind):
+    """Workload-2 data (five warped sine classes, length 512), subsampled."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(2, n_ref=96, n_query=24)
+    p = wl["params"][kind]
+    log(f"nn1 class templates {kind}")
+    oi, od, _ = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "eap")
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    labels = torch.from_numpy(wl["ref_labels"]).to(dev)
+    gi, gd, gl = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, ref_labels=labels)
+    torch.cuda.synchronize()
+    gi, gd, gl = gi.cpu().numpy(), gd.cpu().numpy(), gl.cpu().numpy()
+    assert np.array_equal(gi, oi)
+    assert np.array_equal(gd, od)
+    assert np.array_equal(gl, wl["ref_labels"][oi])
+
+
+def test_nn1_parity_random_walk_workload_full(torch_dev, orc):
+    """Workload 1 in full: DTW, 100 x 100 random walks of length 128."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(1)
+    p = wl["params"]["dtw"]
+    log("nn1 workload 1 full")
+    oi, od, _ = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "dp")
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    labels = torch.from_numpy(wl["ref_labels"]).to(dev)
+    gi, gd, gl = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, ref_labels=labels)
+    torch.cuda.synchronize()
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    assert np.array_equal(gl.cpu().numpy(), wl["ref_labels"][oi])
+
+
+@pytest.mark.parametrize("p", ALL, ids=pid)
+def test_nn1_parity_ragged_lengths(torch_dev, orc, p):
+    """Uneven lengths (ragged tails of every strip and band size)."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(7)
+    qs = synth.random_walks(rng, 9, (5, 300))
+    rs = synth.random_walks(rng, 40, (1, 300))
+    rs[3] = qs[0].copy()            # an exact match
+    rs[11] = rs[10].copy()          # a duplicate: ties go to the lower index
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    log(f"nn1 ragged {pid(p)}")
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p)
+    torch.cuda.synchronize()
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
+def test_nn1_no_feasible_candidate(torch_dev, orc):
+    torch, dev = torch_dev
+    p = dict(kind="cdtw", window_ratio=0.05)
+    qv, qo = synth.pack([np.zeros(10), np.linspace(0, 1, 40)])
+    rv, ro = synth.pack([np.ones(80), np.ones(90), np.linspace(1, 0, 41)])
+    log("nn1 infeasible windows")
+    gi, gd, gl = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p,
+                         ref_labels=torch.tensor([4, 5, 6], dtype=torch.int32, device=dev))
+    torch.cuda.synchronize()
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    assert list(gi.cpu().numpy()) == list(oi) == [-1, 2]
+    assert gd.cpu().numpy()[0] == INF
+    assert list(gl.cpu().numpy()) == [-1, 6]
+
+
+@pytest.mark.parametrize("kind", ["dtw", "cdtw", "msm", "wdtw", "erp", "twe"])
+@pytest.mark.parametrize("mode", ["prune", "full"])
+def test_pairwise_parity(torch_dev, orc, kind, mode):
+    """Workload-3 shape (random walks, all pairs), subsampled to 14 series of
+    ragged lengths up to 1024."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(33)
+    S = synth.random_walks(rng, 14, (700, 1024))
+    sv, so = synth.pack(S)
+    p = dict(synth.DEFAULT_PARAMS[kind])
+    if kind == "cdtw":
+        p["window_ratio"] = 0.05
+    log(f"pairwise {kind} {mode}")
+    want = orc.pairwise(p, sv, so, "full")
+    got = eap.pairwise(to_dev(torch, dev, sv), so, p, mode).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def test_counters_accumulate(torch_dev):
+    torch, dev = torch_dev
+    wl = synth.make_workload(1, n_ref=20, n_query=5)
+    p = wl["params"]["dtw"]
+    ws = eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], wl["ref_off"], p), dev)
+    eap.reset_counters(ws)
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, ws=ws)
+    c1 = eap.read_counters(ws)
+    eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, ws=ws)
+    c2 = eap.read_counters(ws)
+    assert c1["pairs"] > 0 and c1["cells"] > 0
+    assert c2["pairs"] == 2 * c1["pairs"]
