@@ -1,0 +1,269 @@
+"""Benchmark: 1-NN search with the six elastic distances on one MI355X.
+
+One step is the whole hot path over one batch: for each of DTW, CDTW, WDTW,
+ERP, MSM and TWE, the 1-NN of 500 queries among 500 candidates (length 512,
+five time-warped sine classes, z-normalised; the paper's NN-classification
+workload at UCR scale, synthetic and seeded).  Inputs are resident in HBM
+before the timed region.
+
+Reported (one JSON line on stdout):
+  value        effective GCUPS: DP cells of the plain full programme (band
+               cells for CDTW) of all six searches, divided by the step time
+  queries_per_s  1-NN searches per second (500 queries x 6 distances per step)
+  plain_gpu_dp   the same searches with the plain full DP on the GPU
+  roofline     the dominant sweep kernel: executed cells per launch over its
+               mean launch time (HIP events), against the VALU cell-update
+               peak for that distance
+  cpu_baseline the CPU oracle (EAPruned NN) on a bounded sample, host threads
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS (cell updates/s) & queries/s for 1-NN search vs plain GPU DP; p50/p99 latency"
+
+# VALU roofline of gfx950: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s,
+# FP64 add/mul/min at full rate.  Minimal lane-ops per DP cell of each distance.
+LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+OPS_PER_CELL = {"dtw": 5, "cdtw": 5, "wdtw": 6, "erp": 6, "msm": 16, "twe": 8}
+HBM_PEAK_GBS = 8000.0
+
+
+def dense_cells(kind, p, q_off, r_off):
+    """Cells of the plain full DP over all (query, candidate) pairs; for a
+    windowed distance the cells inside the window (0 for infeasible pairs)."""
+    lq = np.diff(q_off).astype(np.int64)
+    lr = np.diff(r_off).astype(np.int64)
+    ratio = p.get("window_ratio", math.inf)
+    if kind not in ("cdtw", "erp") or ratio >= 1:
+        return int(lq.sum() * lr.sum())
+    memo = {}
+    total = 0
+    for a in lq:
+        for b in lr:
+            li, co = int(max(a, b)), int(min(a, b))
+            if (li, co) not in memo:
+                w = int(math.floor(ratio * float(li)))
+                if w < li - co:
+                    memo[(li, co)] = 0
+                else:
+                    i = np.arange(1, li + 1)
+                    memo[(li, co)] = int((np.minimum(i + w, co) - np.maximum(i - w, 1) + 1).clip(min=0).sum())
+            total += memo[(li, co)]
+    return total
+
+
+def swept_kind(kind, p):
+    """The distance the library sweeps (CDTW without a window is DTW)."""
+    if kind == "cdtw" and p.get("window_ratio", math.inf) >= 1:
+        return "dtw"
+    return kind
+
+
+def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist):
+    """The CPU oracle's EAPruned NN (Alg. 1 + Alg. 5) on the first nq_sample
+    queries against all candidates, every host thread."""
+    from oracle import oracle as orc
+    qo = wl["query_off"][: nq_sample + 1]
+    qv = wl["queries"][: qo[-1]]
+    cells = 0
+    secs = 0.0
+    match = True
+    for kind in kinds:
+        p = wl["params"][kind]
+        t0 = time.perf_counter()
+        idx, dist, _ = orc.nn1(p, qv, qo, wl["refs"], wl["ref_off"], "eap")
+        secs += time.perf_counter() - t0
+        cells += dense_cells(kind, p, qo, wl["ref_off"])
+        match &= bool(np.array_equal(idx, gpu_idx[kind][:nq_sample]) and np.array_equal(dist, gpu_dist[kind][:nq_sample]))
+    return dict(value=cells / secs / 1e9, unit="GCUPS", cores=orc.num_threads(), kind="oracle",
+                sample=f"EAPruned NN of the first {nq_sample} queries against all {len(wl['ref_off']) - 1} "
+                       f"candidates, {len(kinds)} distances, {secs:.1f} s",
+                nn_identical_to_gpu=match)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kinds", default="dtw,cdtw,wdtw,erp,msm,twe")
+    ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU-oracle sample (0: skip)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
+              "but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2102_05221_amd as eap
+    from paper_2102_05221_amd import synth
+
+    dev = torch.device("cuda:0")
+    kinds = [k for k in args.kinds.split(",") if k]
+    wl = synth.make_workload(2)
+    q = torch.from_numpy(wl["queries"]).to(dev)
+    r = torch.from_numpy(wl["refs"]).to(dev)
+    labels = torch.from_numpy(wl["ref_labels"]).to(dev)
+    nq, nr = len(wl["query_off"]) - 1, len(wl["ref_off"]) - 1
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], wl["ref_off"], wl["params"][k]), dev)
+          for k in kinds}
+    outs = {k: (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
+                torch.empty(nq, dtype=torch.int32, device=dev)) for k in kinds}
+    dense = {k: dense_cells(k, wl["params"][k], wl["query_off"], wl["ref_off"]) for k in kinds}
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        for k in kinds:
+            eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for k in kinds:
+        eap.reset_counters(ws[k])
+    eap.profile_take()
+    eap.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        e_a = torch.cuda.Event(enable_timing=True)
+        e_b = torch.cuda.Event(enable_timing=True)
+        e_a.record(stream)
+        step()
+        e_b.record(stream)
+        step_ms.append((e_a, e_b))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    eap.profile_enable(False)
+    prof = eap.profile_take()
+    step_ms = [a.elapsed_time(b) for a, b in step_ms]
+    ms_per_step = wall * 1e3 / args.steps
+    counters = {k: eap.read_counters(ws[k]) for k in kinds}
+
+    # per-distance times of the main sweep and the dominant kernel
+    per = {}
+    for k in kinds:
+        sk = swept_kind(k, wl["params"][k])
+        main = [x for x in prof if x["kind"] == sk and x["stage"] == 2]
+        per[k] = dict(
+            sweep_ms_per_step=sum(x["ms"] for x in prof if x["kind"] == sk) / args.steps,
+            main_sweep_ms=(sum(x["ms"] for x in main) / len(main)) if main else None,
+            main_kernel=(f"{main[0]['kernel']}{main[0]['size']}" if main else None),
+            executed_cells_per_step=counters[k]["cells"] / args.steps,
+            main_cells_per_launch=counters[k]["stage_cells"][2] / args.steps,
+            dense_cells=dense[k],
+            executed_fraction=counters[k]["cells"] / args.steps / dense[k],
+            overflows_per_step=counters[k]["overflows"] / args.steps,
+        )
+    gpu_idx = {k: outs[k][0].cpu().numpy() for k in kinds}
+    gpu_dist = {k: outs[k][1].cpu().numpy() for k in kinds}
+    gpu_lab = {k: outs[k][2].cpu().numpy() for k in kinds}
+    qlab = wl["query_labels"]
+    for k in kinds:
+        per[k]["nn_accuracy"] = float(np.mean(gpu_lab[k] == qlab))
+
+    # dominant kernel: the main sweep with the largest time per step
+    dom_kind = max(kinds, key=lambda k: per[k]["main_sweep_ms"] or 0.0)
+    d = per[dom_kind]
+    achieved = d["main_cells_per_launch"] / (d["main_sweep_ms"] * 1e-3) / 1e9
+    peak = LANE_OPS_PER_S / OPS_PER_CELL[dom_kind] / 1e9
+    roofline = dict(bound="alu", achieved=achieved, peak=peak, unit="GCUPS", frac=achieved / peak, traffic=None,
+                    kernel=f"{d['main_kernel']} sweep, {dom_kind.upper()} main stage",
+                    ops_per_cell=OPS_PER_CELL[dom_kind], launch_ms=d["main_sweep_ms"],
+                    cells_per_launch=d["main_cells_per_launch"])
+    traffic_path = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(traffic_path):
+        try:
+            tr = json.load(open(traffic_path))
+            if tr.get("kernel") == roofline["kernel"] and tr.get("source_hash") == _source_hash():
+                roofline["traffic"] = tr["hbm_bytes_per_launch"]
+        except Exception:
+            pass
+
+    # plain full DP on the GPU, same searches (outside the timed region)
+    plain = None
+    if not args.no_plain:
+        plain = {}
+        total_plain_ms = 0.0
+        same = True
+        for k in kinds:
+            pouts = (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
+                     None)
+            eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ws=ws[k], out=pouts,
+                    flags=eap.FLAG_PLAIN)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ws=ws[k], out=pouts,
+                    flags=eap.FLAG_PLAIN)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            total_plain_ms += ms
+            same &= bool(np.array_equal(pouts[0].cpu().numpy(), gpu_idx[k]) and
+                         np.array_equal(pouts[1].cpu().numpy(), gpu_dist[k]))
+            plain[k] = dict(ms=ms, gcups=dense[k] / (ms * 1e-3) / 1e9)
+        plain = dict(per_distance=plain, ms_per_step=total_plain_ms,
+                     gcups=sum(dense.values()) / (total_plain_ms * 1e-3) / 1e9,
+                     speedup_of_eapruned=total_plain_ms / ms_per_step, nn_identical=same)
+
+    cpu = None
+    if args.cpu_queries > 0:
+        cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, nq), gpu_idx, gpu_dist)
+
+    total_dense = sum(dense.values())
+    line = dict(
+        metric=METRIC,
+        value=total_dense / (ms_per_step * 1e-3) / 1e9,
+        unit="GCUPS",
+        n_gpus=1,
+        steps=args.steps,
+        warmup=args.warmup,
+        ms_per_step=ms_per_step,
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="f64",
+        data="synthetic",
+        config=dict(workload="1-NN classification, 500 queries x 500 candidates, length 512, 5 warped-sine "
+                             "classes; " + ", ".join(kinds) + " (CDTW w=10%, WDTW g=0.05, ERP gap=0, MSM c=0.5, "
+                             "TWE nu=0.001 lambda=1)",
+                    queries=nq, candidates=nr, length=512, distances=kinds, precision="fp64"),
+        queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
+        step_ms_p50=float(np.percentile(step_ms, 50)),
+        step_ms_p99=float(np.percentile(step_ms, 99)),
+        per_distance=per,
+        plain_gpu_dp=plain,
+        roofline=roofline,
+        cpu_baseline=cpu,
+    )
+    print(json.dumps(line), flush=True)
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2102_05221_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -79,20 +79,46 @@ typedef struct {
  *  margin_rel  relative screen margin for precision 1 (>= 0, finite); the
  *              library adds a certified absolute bound for FP32 rounding.
  *  flags       bit 0: skip the seeding pass (every candidate starts from the
- *              path upper bound); for ablation only. */
+ *              path upper bound); for ablation only.
+ *              bit 1: plain full dynamic programme for every pair (no cut-off,
+ *              no pruning, no abandoning): the baseline the pruned search is
+ *              measured against.  Same results. */
 typedef struct {
     int32_t precision;
     double margin_rel;
     int32_t flags;
 } eap_nn_opts;
 
-/* Counters accumulated in a workspace by the calls that use it. */
+/* Counters accumulated in a workspace by the calls that use it (zero them with
+ * eap_reset_counters() before the first read).  Cells are counted per lane
+ * slot the sweep kernels evaluate, including slots past a series' end or
+ * outside a window.  Stages: 0 seed sweep, 1 its re-run, 2 main sweep, 3 its
+ * re-run (NN); pairwise and distance use stage 2. */
 typedef struct {
-    uint64_t cells;          /* DP cells executed by the sweep kernels (incl. idle band/strip slots) */
+    uint64_t cells;          /* DP cells executed by the sweep kernels */
     uint64_t pairs;          /* pairs swept */
     uint64_t rechecks;       /* FP64 recomputations after an FP32 screen */
     uint64_t overflows;      /* band sweeps that had to be redone wider */
+    uint64_t stage_cells[4];
+    uint64_t stage_pairs[4];
 } eap_counters;
+
+/* Optional timing of the sweep kernels with HIP events (off by default).
+ * While enabled, every sweep launch is bracketed by two events on its stream.
+ * eap_profile_take() waits for the recorded launches, copies up to `cap`
+ * records into `out` (host memory), returns their number in *n and forgets
+ * them.  kernel: 0 row sweep, 1 band sweep; size: row width or band
+ * diagonals; kind: eap_kind swept. */
+typedef struct {
+    int32_t stage;
+    int32_t kernel;
+    int32_t kind;
+    int32_t size;
+    int32_t fp32;
+    float ms;
+} eap_profile_rec;
+eap_status eap_profile_enable(int32_t on);
+eap_status eap_profile_take(eap_profile_rec* out, int32_t cap, int32_t* n);
 
 /* Distance with cut-off (Alg. 5: "Input S, T, w, cut-off; Result D or +inf").
  *  x (lx), y (ly)  device float64 series, lengths >= 1.

@@ -18,7 +18,11 @@ import os
 import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
-           "wdtw_weights", "EapError", "lib", "KINDS"]
+           "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
+           "FLAG_PLAIN"]
+
+FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
+FLAG_PLAIN = 2     # plain full DP for every pair: the baseline
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeap.so")
@@ -45,7 +49,13 @@ class NNOpts(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
-                ("overflows", ctypes.c_uint64)]
+                ("overflows", ctypes.c_uint64), ("stage_cells", ctypes.c_uint64 * 4),
+                ("stage_pairs", ctypes.c_uint64 * 4)]
+
+
+class ProfileRec(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_int32), ("kernel", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("size", ctypes.c_int32), ("fp32", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -81,6 +91,10 @@ def lib():
         L.eap_read_counters.argtypes = [_vp, _sz, ctypes.POINTER(Counters), _vp]
         L.eap_reset_counters.restype = ctypes.c_int
         L.eap_reset_counters.argtypes = [_vp, _sz, _vp]
+        L.eap_profile_enable.restype = ctypes.c_int
+        L.eap_profile_enable.argtypes = [ctypes.c_int32]
+        L.eap_profile_take.restype = ctypes.c_int
+        L.eap_profile_take.argtypes = [ctypes.POINTER(ProfileRec), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.eap_wdtw_weights.restype = ctypes.c_int
         L.eap_wdtw_weights.argtypes = [_d, _i64, ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -214,11 +228,28 @@ def pairwise(s, s_off, p, mode: str = "prune", ws=None, stream=None, out=None):
 def read_counters(ws, stream=None) -> dict:
     c = Counters()
     _check(lib().eap_read_counters(ws.data_ptr(), ws.numel(), ctypes.byref(c), _stream(stream, ws.device)))
-    return dict(cells=c.cells, pairs=c.pairs, rechecks=c.rechecks, overflows=c.overflows)
+    return dict(cells=c.cells, pairs=c.pairs, rechecks=c.rechecks, overflows=c.overflows,
+                stage_cells=list(c.stage_cells), stage_pairs=list(c.stage_pairs))
 
 
 def reset_counters(ws, stream=None):
     _check(lib().eap_reset_counters(ws.data_ptr(), ws.numel(), _stream(stream, ws.device)))
+
+
+def profile_enable(on: bool = True):
+    """Time every sweep launch with HIP events (see eap_profile_enable)."""
+    _check(lib().eap_profile_enable(1 if on else 0))
+
+
+def profile_take(cap: int = 4096) -> list:
+    """Wait for the timed launches and return them as dicts (stage, kernel
+    'rows'/'band', kind, size, ms)."""
+    buf = (ProfileRec * cap)()
+    n = ctypes.c_int32(0)
+    _check(lib().eap_profile_take(buf, cap, ctypes.byref(n)))
+    inv = {v: k for k, v in KINDS.items()}
+    return [dict(stage=r.stage, kernel=("band" if r.kernel else "rows"), kind=inv.get(r.kind, r.kind), size=r.size,
+                 ms=float(r.ms)) for r in buf[:n.value]]
 
 
 def wdtw_weights(g: float, L: int) -> np.ndarray:

@@ -103,10 +103,13 @@ struct Layout {
 
 // Header at the start of every workspace.
 struct Header {
-    unsigned long long counters[8];  // cells, pairs, rechecks, overflows
+    // [0] cells, [1] pairs, [2] rechecks, [3] overflows, [4+s] cells and
+    // [8+s] pairs of stage s
+    unsigned long long counters[16];
     unsigned int queues[16];
     unsigned int ovf_count[4];
 };
+constexpr int kCounterWords = 16;
 constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
 
 // ------------------------------------------------------------------ tables
@@ -285,8 +288,8 @@ eap_status setup_common(void* ws, const Common& c, const eap_params* p, const do
                         SweepArgs& a, SeriesPtrs& SA, SeriesPtrs& SB) {
     eap_status st;
     // work queues and overflow counts start at zero; the counters keep accumulating
-    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(at(ws, c.hdr)) + 8, 0ull,
-                           (int64_t)(kHeaderBytes / 8) - 8, s));
+    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(at(ws, c.hdr)) + kCounterWords, 0ull,
+                           (int64_t)(kHeaderBytes / 8) - kCounterWords, s));
     if ((st = upload(at(ws, c.offA), offa, sizeof(int64_t) * (size_t)(na + 1), s)) != EAP_OK) return st;
     if (offb && (st = upload(at(ws, c.offB), offb, sizeof(int64_t) * (size_t)(nb + 1), s)) != EAP_OK) return st;
     const int64_t* dA = reinterpret_cast<const int64_t*>(at(ws, c.offA));
@@ -324,32 +327,74 @@ eap_status setup_common(void* ws, const Common& c, const eap_params* p, const do
 
 Header* hdr_of(void* ws, const Common& c) { return reinterpret_cast<Header*>(at(ws, c.hdr)); }
 
-// One sweep launch (kernel A or B) over `n` work slots.
-eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, unsigned int* queue, const int32_t* items,
-                 int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s) {
+// Optional event timing of sweep launches.
+struct ProfRec {
+    eap_profile_rec r;
+    hipEvent_t e0, e1;
+};
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+Profiler g_prof;
+
+// One sweep launch (kernel A or B) over `n` work slots, counted under `stage`.
+eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* h, int stage, unsigned int* queue,
+                 const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s) {
     a.queue = queue;
     a.items = items;
     a.npairs = n;
+    a.stage = &h->counters[4 + stage];
     const int kind = effective_kind(p);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (g_prof.on) {
+            e0 = g_prof.get();
+            e1 = g_prof.get();
+        }
+    }
+    if (e0 && e1) HIPCHK(hipEventRecord(e0, s));
     (void)hipGetLastError();   // launch errors below must be this launch's own
     hipError_t e;
     if (band) e = launch_band(kind, false, size, a, SA, SB, sweep_grid(n, band_group(size)), s);
     else e = launch_rows(kind, false, size, a, SA, SB, sweep_grid(n, rows_group(size)), s);
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
+    if (e0 && e1) {
+        HIPCHK(hipEventRecord(e1, s));
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        ProfRec pr;
+        pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, size, 0, 0.0f};
+        pr.e0 = e0;
+        pr.e1 = e1;
+        g_prof.pending.push_back(pr);
+    }
     return EAP_OK;
 }
 
 // Items of the narrow band pass that could not be certified are re-swept with
 // the full band.  Their list and count stay on the device: the re-run reads the
 // count at run time, so nothing synchronises the host.
-eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, unsigned int* ovf_count,
-                          const int32_t* ovf_items, int64_t max_items, unsigned int* queue, SeriesPtrs SA,
-                          SeriesPtrs SB, hipStream_t s) {
+eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, Header* h, int stage,
+                          unsigned int* ovf_count, const int32_t* ovf_items, int64_t max_items, unsigned int* queue,
+                          SeriesPtrs SA, SeriesPtrs SB, hipStream_t s) {
     a.band_half = 1 << 20;
     a.ovf_items = nullptr;
     a.ovf_count = nullptr;
     a.npairs_dev = ovf_count;
-    return sweep(p, true, pl.full, a, queue, ovf_items, max_items, SA, SB, s);
+    return sweep(p, true, pl.full, a, h, stage, queue, ovf_items, max_items, SA, SB, s);
 }
 
 }  // namespace
@@ -408,7 +453,7 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
     a.band_half = pl.band_half;
     a.ovf_items = reinterpret_cast<int32_t*>(at(ws, ovf));
     a.ovf_count = &hdr_of(ws, c)->ovf_count[0];
-    return sweep(p, pl.band, pl.size, a, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s);
+    return sweep(p, pl.band, pl.size, a, hdr_of(ws, c), 2, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s);
 }
 
 // ---------------------------------------------------------------------- NN
@@ -480,24 +525,41 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     a.band_half = pl.band_half;
     a.ovf_items = ovf;
     a.ovf_count = &h->ovf_count[0];
-    const bool seeded = !(o && (o->flags & 1));
+    const bool plain = o && (o->flags & 2);
+    const bool seeded = !plain && !(o && (o->flags & 1));
+    if (plain) {
+        // baseline: every pair by the full dynamic programme, full band for WDTW
+        a.plain = 1;
+        if (pl.band) {
+            pl.size = pl.full;
+            a.band_half = 1 << 20;
+        }
+        if ((st = sweep(p, pl.band, pl.size, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK)
+            return st;
+        HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
+        return EAP_OK;
+    }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, res, s));
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
+    const bool rerun = pl.band && pl.size != pl.full;
     if (seeded) {
         // 2. sweep the seed candidate of every query under its bound
-        if ((st = sweep(p, pl.band, pl.size, a, &h->queues[0], seed_items, nq, SQ, SR, s)) != EAP_OK) return st;
-        if (pl.band && pl.size != pl.full) {
-            if ((st = rerun_overflow(p, pl, a, &h->ovf_count[0], ovf, nq, &h->queues[1], SQ, SR, s)) != EAP_OK) return st;
+        if ((st = sweep(p, pl.band, pl.size, a, h, 0, &h->queues[0], seed_items, nq, SQ, SR, s)) != EAP_OK)
+            return st;
+        if (rerun) {
+            if ((st = rerun_overflow(p, pl, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], SQ, SR, s)) != EAP_OK)
+                return st;
             HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
         }
         a.skip_b = seed;
     }
     // 3. every other pair, under the per-query best-so-far (lowered as pairs complete)
-    if ((st = sweep(p, pl.band, pl.size, a, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK) return st;
-    if (pl.band && pl.size != pl.full) {
+    if ((st = sweep(p, pl.band, pl.size, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+    if (rerun) {
         a.skip_b = nullptr;
-        if ((st = rerun_overflow(p, pl, a, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], SQ, SR, s)) != EAP_OK) return st;
+        if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], SQ, SR, s)) != EAP_OK)
+            return st;
     }
     // 4. lexicographic (distance, index) minimum per query
     HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
@@ -558,7 +620,8 @@ eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const 
         HIPCHK(launch_ub_condensed(effective_kind(p), a, s, SA.off, n, cut, hs));
         a.pcut = cut;
     }
-    return sweep(p, pl.band, pl.size, a, &h->queues[0], nullptr, np, SA, SB, hs);
+    if (mode == 1) a.plain = 1;
+    return sweep(p, pl.band, pl.size, a, h, 2, &h->queues[0], nullptr, np, SA, SB, hs);
 }
 
 eap_status eap_wdtw_weights(double g, int64_t L, double* out) {
@@ -580,12 +643,43 @@ eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out,
     out->pairs = h.counters[1];
     out->rechecks = h.counters[2];
     out->overflows = h.counters[3];
+    for (int s = 0; s < 4; ++s) {
+        out->stage_cells[s] = h.counters[4 + s];
+        out->stage_pairs[s] = h.counters[8 + s];
+    }
     return EAP_OK;
 }
 
 eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream) {
     if (!ws || ws_bytes < kHeaderBytes) return fail(EAP_EINVAL, "bad workspace");
-    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws), 0ull, 8, (hipStream_t)stream));
+    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws), 0ull, kCounterWords, (hipStream_t)stream));
+    return EAP_OK;
+}
+
+eap_status eap_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return EAP_OK;
+}
+
+eap_status eap_profile_take(eap_profile_rec* out, int32_t cap, int32_t* n) {
+    if (!n || (cap > 0 && !out)) return fail(EAP_EINVAL, "bad profile output");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    int32_t k = 0;
+    for (auto& pr : g_prof.pending) {
+        HIPCHK(hipEventSynchronize(pr.e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
+        if (k < cap) {
+            out[k] = pr.r;
+            out[k].ms = ms;
+        }
+        ++k;
+        g_prof.pool.push_back(pr.e0);
+        g_prof.pool.push_back(pr.e1);
+    }
+    g_prof.pending.clear();
+    *n = k < cap ? k : cap;
     return EAP_OK;
 }
 

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
     const int lane = threadIdx.x & 63;
     const int k = lane & (G - 1);
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane - k));
-    const bool nn = is_nn_mode(A.mode);
+    const bool nn = is_nn_mode(A.mode) && !A.plain;
     const T gap = (T)A.gap;
 
     bool have = false, done = false, fin = false, ovf = false, lo_open = false, hi_open = false;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
                 qa = it.a;
                 out = it.out;
                 if (nn) cut = (T)bitsd(A.best[it.a]);
-                else cut = A.pcut ? (T)A.pcut[it.cutidx] : INF;
+                else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
                 const int L = Lli > Lco ? Lli : Lco;
                 const int d_end = Lco - Lli;
                 int lo_need, hi_need;
@@ -355,6 +355,8 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
     }
     wave_add_u64(&A.counters[0], ncells);
     wave_add_u64(&A.counters[1], npairs);
+    wave_add_u64(&A.stage[0], ncells);
+    wave_add_u64(&A.stage[4], npairs);
 }
 
 template <int KIND, typename T, int G, int C>

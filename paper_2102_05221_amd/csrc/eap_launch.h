@@ -28,6 +28,9 @@ struct SweepArgs {
     double* res;
     unsigned int* queue;             // work counter, zero at launch
     unsigned long long* counters;    // [0] cells executed, [1] pairs swept, [3] band overflows
+    unsigned long long* stage;       // [0] cells of this launch's stage, [4] its pairs
+    // plain DP: cut-off +inf for every item, no best-so-far, no abandoning
+    int plain;
     // distance parameters
     double gap, c, nu, lam;
     // Per-diagonal tables, indexed by (j - i) + tab_off:

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     const int lane = threadIdx.x & 63;
     const int k = lane & (G - 1);
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane - k));
-    const bool nn = is_nn_mode(A.mode);
+    const bool nn = is_nn_mode(A.mode) && !A.plain;
     const T gap = (T)A.gap, cc = (T)A.c, nu = (T)A.nu, lam = (T)A.lam;
 
     bool have = false, done = false;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                     continue;
                 }
                 if (nn) cut = (T)bitsd(A.best[it.a]);
-                else cut = A.pcut ? (T)A.pcut[it.cutidx] : INF;
+                else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
                 kend = (Lco - 1) / C;
                 uend = (Lco - 1) - kend * C;
                 // column values t_j of the strip (+inf beyond L_co) and t_{c0-1} (t_0 = 0)
@@ -224,6 +224,8 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     }
     wave_add_u64(&A.counters[0], ncells);
     wave_add_u64(&A.counters[1], npairs);
+    wave_add_u64(&A.stage[0], ncells);
+    wave_add_u64(&A.stage[4], npairs);
 }
 
 template <int KIND, typename T, int G, int C>

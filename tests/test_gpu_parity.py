@@ -171,6 +171,35 @@ def test_pairwise_parity(torch_dev, orc, kind, mode):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("kind", synth.SIX)
+def test_plain_dp_mode_gives_the_same_nn(torch_dev, kind):
+    """The plain full-DP baseline (no cut-off) and the pruned search agree."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(4, n_ref=60, n_query=10, length=(40, 260))
+    p = wl["params"][kind]
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    log(f"plain vs pruned {kind}")
+    a = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p)
+    b = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, flags=eap.FLAG_PLAIN)
+    c = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, flags=eap.FLAG_NO_SEED)
+    torch.cuda.synchronize()
+    for x in (b, c):
+        assert torch.equal(a[0], x[0]) and torch.equal(a[1], x[1])
+
+
+def test_profile_records_each_sweep(torch_dev):
+    torch, dev = torch_dev
+    wl = synth.make_workload(2, n_ref=30, n_query=4, length=64)
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    eap.profile_take()
+    eap.profile_enable(True)
+    eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"]["msm"])
+    eap.profile_enable(False)
+    recs = eap.profile_take()
+    assert [x["stage"] for x in recs] == [0, 2]
+    assert all(x["kernel"] == "rows" and x["kind"] == "msm" and x["ms"] > 0 for x in recs)
+
+
 def test_counters_accumulate(torch_dev):
     torch, dev = torch_dev
     wl = synth.make_workload(1, n_ref=20, n_query=5)
