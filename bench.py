@@ -98,7 +98,19 @@ def main():
     ap.add_argument("--kinds", default="dtw,cdtw,wdtw,erp,msm,twe")
     ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU-oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 3 plain device copies of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_mib > 0:
+        import torch
+        n = args.copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_read=n * 8, copy_bytes_written=n * 8, copies=3)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
               "but not built", file=sys.stderr)

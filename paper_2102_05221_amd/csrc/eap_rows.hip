@@ -51,11 +51,11 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     int Lli = 0, Lco = 0, kend = 0, uend = 0, row = 0;
     const int c0 = 1 + k * C;
     T cut = 0;
-    T val[C], tv[C], aux[C];
-    T dg = 0, lout = 0, sout = 0, s_next = 0, b_next = 0, sp = 0, tpm = 0;
+    T val[C], vb[C], tv[C], aux[C];
+    T dg = 0, lout = 0, sout = 0, s_next = 0, b_next = 0, sp = 0, tpm = 0, brd0 = 0, s0 = 0;
     unsigned long long ncells = 0, npairs = 0;
 #pragma unroll
-    for (int u = 0; u < C; ++u) val[u] = tv[u] = aux[u] = 0;
+    for (int u = 0; u < C; ++u) val[u] = vb[u] = tv[u] = aux[u] = 0;
 
     for (;;) {
         if (!have && !done) {
@@ -111,7 +111,16 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 if (k == 0) dg = 0;
                 else if constexpr (KIND == ERP) dg = (c0 - 1 <= Lco) ? cob[c0 - 2] : INF;
                 else dg = INF;
-                row = -k;
+                // what a lane is fed until it reaches row 1 (see the step below):
+                // ERP's border M(0, c0-1), which makes the lane recompute its own
+                // top border exactly, or +inf, which keeps +inf borders at +inf
+                if constexpr (KIND == ERP) brd0 = dg;
+                else brd0 = INF;
+                s0 = (KIND == ERP) ? gap : (T)0;
+                // start late enough that the last cell, (L_li, L_co) in lane kend,
+                // is computed by the last step of a block: the result is then read
+                // once, at the block end, from the buffer that step wrote
+                row = -k - (K - (Lli + kend) % K) % K;
                 lout = val[C - 1];
                 sout = 0;
                 sp = 0;
@@ -127,9 +136,13 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
         if (__all(done)) break;
 
         bool live_any = false;
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-            // publish last step's right edge and row value, receive the left neighbour's
+        // One step: every lane computes its strip for its current row, reading
+        // the previous row from `src` and writing `dst` (the two buffers
+        // alternate, so no value is copied).  Lanes that have not reached row 1
+        // are fed their own left-border value and s = gap (ERP) or +inf inputs,
+        // which reproduces their top border bit for bit; lanes past the last
+        // row compute values nobody reads.
+        auto step = [&](T (&src)[C], T (&dst)[C], bool check) {
             T lin = shr1(lout);
             T sin = shr1(sout);
             row += 1;
@@ -137,69 +150,78 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 lin = b_next;   // M(row, 0)
                 sin = s_next;   // s_row
             }
+            const bool ns = row <= 0;   // not started: keep the top border
+            if (ns) {
+                lin = brd0;
+                sin = s0;
+            }
             const bool act = have && row >= 1 && row <= Lli;
             if (k == 0 && act && row < Lli) {
                 s_next = li[row];
                 if constexpr (KIND == ERP) b_next = lib[row];
             }
-            if (act) {
-                T diag = dg;
-                dg = lin;
-                T left = lin;
-                T sg = 0, ds = 0, gA = 0;
-                const T* ntp = nullptr;
-                if constexpr (KIND == ERP) sg = vabs(sin - gap);
-                if constexpr (KIND == MSM) ds = sin - sp;
-                if constexpr (KIND == TWE) {
-                    gA = (vabs(sin - sp) + nu) + lam;
-                    ntp = tab + (c0 - row + A.tab_off);
-                }
-#pragma unroll
-                for (int u = 0; u < C; ++u) {
-                    const T top = val[u];
-                    const T d = sin - tv[u];
-                    T v;
-                    if constexpr (KIND == DTW || KIND == CDTW) {
-                        v = (d * d) + vmin(vmin(diag, top), left);
-                    } else if constexpr (KIND == ERP) {
-                        v = vmin(vmin(diag + vabs(d), top + sg), left + aux[u]);
-                    } else if constexpr (KIND == MSM) {
-                        // C(s_i, s_{i-1}, t_j) and C(t_j, s_i, t_{j-1}) of eq. MSMCost as
-                        // c + max(0, min(x,y) - np, np - max(x,y)), with the differences
-                        // written through d = s_i - t_j, ds = s_i - s_{i-1}, dt = t_j - t_{j-1}
-                        const T c1 = cc + vmax(vmax(vmin(-ds, -d), vmin(ds, d)), (T)0);
-                        const T c2 = cc + vmax(vmax(vmin(d, -aux[u]), vmin(-d, aux[u])), (T)0);
-                        v = vmin(vmin(diag + vabs(d), top + c1), left + c2);
-                    } else if constexpr (KIND == TWE) {
-                        const T tp = (u == 0) ? tpm : tv[u - 1];
-                        const T match = (vabs(d) + vabs(sp - tp)) + ntp[u];
-                        v = vmin(vmin(diag + match, top + gA), left + aux[u]);
-                    }
-                    diag = top;
-                    val[u] = v;
-                    left = v;
-                }
-                sp = sin;
-                ncells += C;
+            T diag = ns ? brd0 : dg;
+            if (!ns) dg = lin;          // M(0, c0-1) stays the diagonal of row 1
+            T left = lin;
+            T sg = 0, ds = 0, gA = 0;
+            const T* ntp = nullptr;
+            if constexpr (KIND == ERP) sg = vabs(sin - gap);
+            if constexpr (KIND == MSM) ds = sin - sp;
+            if constexpr (KIND == TWE) {
+                gA = (vabs(sin - sp) + nu) + lam;
+                const int rr = row < 1 ? 1 : (row > Lli ? Lli : row);
+                ntp = tab + (c0 - rr + A.tab_off);
             }
-            lout = val[C - 1];
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                const T top = src[u];
+                const T d = sin - tv[u];
+                T v;
+                if constexpr (KIND == DTW || KIND == CDTW) {
+                    v = (d * d) + vmin(vmin(diag, top), left);
+                } else if constexpr (KIND == ERP) {
+                    v = vmin(vmin(diag + vabs(d), top + sg), left + aux[u]);
+                } else if constexpr (KIND == MSM) {
+                    // C(s_i, s_{i-1}, t_j) and C(t_j, s_i, t_{j-1}) of eq. MSMCost as
+                    // c + max(0, min(x,y) - np, np - max(x,y)), with the differences
+                    // written through d = s_i - t_j, ds = s_i - s_{i-1}, dt = t_j - t_{j-1}
+                    const T c1 = cc + vmax(vmax(vmin(-ds, -d), vmin(ds, d)), (T)0);
+                    const T c2 = cc + vmax(vmax(vmin(d, -aux[u]), vmin(-d, aux[u])), (T)0);
+                    v = vmin(vmin(diag + vabs(d), top + c1), left + c2);
+                } else if constexpr (KIND == TWE) {
+                    const T tp = (u == 0) ? tpm : tv[u - 1];
+                    const T match = (vabs(d) + vabs(sp - tp)) + ntp[u];
+                    v = vmin(vmin(diag + match, top + gA), left + aux[u]);
+                }
+                dst[u] = v;
+                diag = top;
+                left = v;
+            }
+            if (row >= 1) sp = sin;
+            if (act) ncells += C;
+            lout = dst[C - 1];
             sout = sin;
-            if (t >= K - 2) {
+            if (check) {
                 bool lv;
                 if (!have || row > Lli) lv = false;
                 else if (row < 1) lv = (KIND == ERP);   // top border row: +inf except for ERP
                 else {
                     T m = lin;
 #pragma unroll
-                    for (int u = 0; u < C; ++u) m = vmin(m, val[u]);
+                    for (int u = 0; u < C; ++u) m = vmin(m, dst[u]);
                     lv = (m <= cut);
                 }
                 live_any = live_any || lv;
             }
+        };
+#pragma unroll
+        for (int t = 0; t < K; t += 2) {
+            step(val, vb, t + 1 >= K - 2);
+            step(vb, val, t + 2 >= K - 2);
         }
 
         // group decisions: finished, abandoned, or refresh the cut-off
-        const bool fin_l = have && k == kend && row >= Lli;
+        const bool fin_l = have && k == kend && row == Lli;
         const unsigned long long fm = ballot(fin_l);
         const unsigned long long lm = ballot(live_any);
         const bool fin = (fm & gmask) != 0;
