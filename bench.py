@@ -198,14 +198,18 @@ def main():
                     kernel=f"{d['main_kernel']} sweep, {dom_kind.upper()} main stage",
                     ops_per_cell=OPS_PER_CELL[dom_kind], launch_ms=d["main_sweep_ms"],
                     cells_per_launch=d["main_cells_per_launch"])
-    traffic_path = os.path.join(ROOT, "profiles", "traffic.json")
+    # HBM bytes per launch from the committed rocprofv3 counter summary, valid
+    # only while the kernel sources are the ones it was measured on
+    traffic_path = os.path.join(ROOT, "profiles", "rows_kernel_msm_nn_workload2_hbm.md")
     if os.path.exists(traffic_path):
-        try:
-            tr = json.load(open(traffic_path))
-            if tr.get("kernel") == roofline["kernel"] and tr.get("source_hash") == _source_hash():
-                roofline["traffic"] = tr["hbm_bytes_per_launch"]
-        except Exception:
-            pass
+        kv = {}
+        for ln in open(traffic_path):
+            if ":" in ln and not ln.startswith(("#", " ", "|")):
+                key, _, val = ln.partition(":")
+                kv[key.strip()] = val.strip()
+        if kv.get("kernel") == roofline["kernel"] and kv.get("source_hash") == _source_hash():
+            roofline["traffic"] = float(kv["hbm_bytes_per_launch"])
+            roofline["traffic_note"] = "HBM bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE, copy-calibrated)"
 
     # plain full DP on the GPU, same searches (outside the timed region)
     plain = None
