@@ -16,19 +16,23 @@ BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libeap.so")
 ARCH = os.environ.get("EAP_OFFLOAD_ARCH", "gfx950")
 
-# -fno-honor-nans: no cell of a sweep is ever NaN, so min/max need no quieting
-# of signalling NaNs; values are unchanged (no reassociation or contraction).
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off", "-fno-honor-nans",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
 SOURCES = ["eap_rows.hip", "eap_band.hip", "eap_aux.hip", "eap_api.cpp"]
+# The sweep kernels are built with -fno-honor-nans: none of their cells is ever
+# NaN, so min/max need no quieting of signalling NaNs and values are unchanged
+# (no reassociation or contraction).  The host-side ABI is not: its argument
+# checks must see NaN.
+NO_NANS = {"eap_rows.hip", "eap_band.hip"}
 
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = ["hipcc", *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-fno-honor-nans"] if src in NO_NANS else []
+    cmd = ["hipcc", *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
