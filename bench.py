@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--kinds", default="dtw,cdtw,wdtw,erp,msm,twe")
     ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU-oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
+    ap.add_argument("--precision", type=int, default=0, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 plain device copies of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -128,16 +131,17 @@ def main():
     r = torch.from_numpy(wl["refs"]).to(dev)
     labels = torch.from_numpy(wl["ref_labels"]).to(dev)
     nq, nr = len(wl["query_off"]) - 1, len(wl["ref_off"]) - 1
-    ws = {k: eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], wl["ref_off"], wl["params"][k]), dev)
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], wl["ref_off"], wl["params"][k], precision=1), dev)
           for k in kinds}
     outs = {k: (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
                 torch.empty(nq, dtype=torch.int32, device=dev)) for k in kinds}
     dense = {k: dense_cells(k, wl["params"][k], wl["query_off"], wl["ref_off"]) for k in kinds}
     stream = torch.cuda.current_stream(dev)
 
-    def step():
+    def step(precision=args.precision):
         for k in kinds:
-            eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k])
+            eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k],
+                    precision=precision)
 
     for _ in range(args.warmup):
         step()
@@ -181,6 +185,7 @@ def main():
             dense_cells=dense[k],
             executed_fraction=counters[k]["cells"] / args.steps / dense[k],
             overflows_per_step=counters[k]["overflows"] / args.steps,
+            fp64_rechecks_per_step=counters[k]["rechecks"] / args.steps,
         )
     gpu_idx = {k: outs[k][0].cpu().numpy() for k in kinds}
     gpu_dist = {k: outs[k][1].cpu().numpy() for k in kinds}
@@ -238,6 +243,22 @@ def main():
                      gcups=sum(dense.values()) / (total_plain_ms * 1e-3) / 1e9,
                      speedup_of_eapruned=total_plain_ms / ms_per_step, nn_identical=same)
 
+    other = None
+    if args.compare_precision:
+        op = 1 - args.precision
+        step(op)
+        torch.cuda.synchronize()
+        a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record(stream)
+        for _ in range(reps):
+            step(op)
+        b_.record(stream)
+        torch.cuda.synchronize()
+        same = all(np.array_equal(outs[k][0].cpu().numpy(), gpu_idx[k]) and
+                   np.array_equal(outs[k][1].cpu().numpy(), gpu_dist[k]) for k in kinds)
+        other = dict(precision=op, ms_per_step=a.elapsed_time(b_) / reps, nn_identical=same)
+
     cpu = None
     if args.cpu_queries > 0:
         cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, nq), gpu_idx, gpu_dist)
@@ -254,12 +275,14 @@ def main():
         higher_is_better=True,
         scaling="weak",
         vs_baseline=None,
-        dtype="f64",
+        dtype=("f32+f64" if args.precision else "f64"),
         data="synthetic",
         config=dict(workload="1-NN classification, 500 queries x 500 candidates, length 512, 5 warped-sine "
                              "classes; " + ", ".join(kinds) + " (CDTW w=10%, WDTW g=0.05, ERP gap=0, MSM c=0.5, "
                              "TWE nu=0.001 lambda=1)",
-                    queries=nq, candidates=nr, length=512, distances=kinds, precision="fp64"),
+                    queries=nq, candidates=nr, length=512, distances=kinds,
+                    precision=("fp32 screen + fp64 recheck" if args.precision else "fp64")),
+        other_precision=other,
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)),
         step_ms_p99=float(np.percentile(step_ms, 99)),

@@ -75,9 +75,13 @@ typedef struct {
  *  precision   0 = FP64 throughout.  1 = FP32 screening sweep, then every
  *              candidate whose FP32 distance is within the screen margin of the
  *              query's FP32 best is recomputed in FP64; results equal the FP64
- *              ones (indices bit-exact, distances bit-exact).
- *  margin_rel  relative screen margin for precision 1 (>= 0, finite); the
- *              library adds a certified absolute bound for FP32 rounding.
+ *              ones (indices bit-exact, distances bit-exact): the margin is
+ *              margin_rel * best32 plus twice a certified bound on the FP32
+ *              rounding error of any warping path (input rounding, per-term
+ *              rounding and the running sum), so the FP64 nearest neighbour is
+ *              always among the candidates rechecked.
+ *  margin_rel  relative part of the screen margin for precision 1 (>= 0,
+ *              finite; 1e-4 by default in the binding).
  *  flags       bit 0: skip the seeding pass (every candidate starts from the
  *              path upper bound); for ablation only.
  *              bit 1: plain full dynamic programme for every pair (no cut-off,
@@ -93,14 +97,15 @@ typedef struct {
  * eap_reset_counters() before the first read).  Cells are counted per lane
  * slot the sweep kernels evaluate, including slots past a series' end or
  * outside a window.  Stages: 0 seed sweep, 1 its re-run, 2 main sweep, 3 its
- * re-run (NN); pairwise and distance use stage 2. */
+ * re-run (NN; FP32 when precision = 1), 4 FP64 recheck, 5 its re-run;
+ * pairwise and distance use stage 2. */
 typedef struct {
     uint64_t cells;          /* DP cells executed by the sweep kernels */
     uint64_t pairs;          /* pairs swept */
     uint64_t rechecks;       /* FP64 recomputations after an FP32 screen */
     uint64_t overflows;      /* band sweeps that had to be redone wider */
-    uint64_t stage_cells[4];
-    uint64_t stage_pairs[4];
+    uint64_t stage_cells[8];
+    uint64_t stage_pairs[8];
 } eap_counters;
 
 /* Optional timing of the sweep kernels with HIP events (off by default).

@@ -49,8 +49,8 @@ class NNOpts(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
-                ("overflows", ctypes.c_uint64), ("stage_cells", ctypes.c_uint64 * 4),
-                ("stage_pairs", ctypes.c_uint64 * 4)]
+                ("overflows", ctypes.c_uint64), ("stage_cells", ctypes.c_uint64 * 8),
+                ("stage_pairs", ctypes.c_uint64 * 8)]
 
 
 class ProfileRec(ctypes.Structure):

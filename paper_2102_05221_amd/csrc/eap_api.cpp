@@ -103,13 +103,14 @@ struct Layout {
 
 // Header at the start of every workspace.
 struct Header {
-    // [0] cells, [1] pairs, [2] rechecks, [3] overflows, [4+s] cells and
-    // [8+s] pairs of stage s
-    unsigned long long counters[16];
+    // [0] cells, [1] pairs, [2] rechecks, [3] overflows, [8+s] cells and
+    // [16+s] pairs of stage s (s < 8)
+    unsigned long long counters[32];
     unsigned int queues[16];
-    unsigned int ovf_count[4];
+    unsigned int ovf_count[4];   // [0] band overflows, [2] FP64 recheck items (u64 fills clear [0..1])
+    unsigned long long absmax;   // FP32 screen: largest |value| (double bits)
 };
-constexpr int kCounterWords = 16;
+constexpr int kCounterWords = 32;
 constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
 
 // ------------------------------------------------------------------ tables
@@ -352,11 +353,11 @@ Profiler g_prof;
 
 // One sweep launch (kernel A or B) over `n` work slots, counted under `stage`.
 eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* h, int stage, unsigned int* queue,
-                 const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s) {
+                 const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s, bool fp32 = false) {
     a.queue = queue;
     a.items = items;
     a.npairs = n;
-    a.stage = &h->counters[4 + stage];
+    a.stage = &h->counters[8 + stage];
     const int kind = effective_kind(p);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     {
@@ -369,14 +370,14 @@ eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* 
     if (e0 && e1) HIPCHK(hipEventRecord(e0, s));
     (void)hipGetLastError();   // launch errors below must be this launch's own
     hipError_t e;
-    if (band) e = launch_band(kind, false, size, a, SA, SB, sweep_grid(n, band_group(size)), s);
-    else e = launch_rows(kind, false, size, a, SA, SB, sweep_grid(n, rows_group(size)), s);
+    if (band) e = launch_band(kind, fp32, size, a, SA, SB, sweep_grid(n, band_group(size)), s);
+    else e = launch_rows(kind, fp32, size, a, SA, SB, sweep_grid(n, rows_group(size)), s);
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     if (e0 && e1) {
         HIPCHK(hipEventRecord(e1, s));
         std::lock_guard<std::mutex> lk(g_prof.mu);
         ProfRec pr;
-        pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, size, 0, 0.0f};
+        pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, size, fp32 ? 1 : 0, 0.0f};
         pr.e0 = e0;
         pr.e1 = e1;
         g_prof.pending.push_back(pr);
@@ -389,12 +390,13 @@ eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* 
 // count at run time, so nothing synchronises the host.
 eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, Header* h, int stage,
                           unsigned int* ovf_count, const int32_t* ovf_items, int64_t max_items, unsigned int* queue,
-                          SeriesPtrs SA, SeriesPtrs SB, hipStream_t s) {
+                          SeriesPtrs SA, SeriesPtrs SB, hipStream_t s, bool fp32 = false) {
     a.band_half = 1 << 20;
     a.ovf_items = nullptr;
     a.ovf_count = nullptr;
     a.npairs_dev = ovf_count;
-    return sweep(p, true, pl.full, a, h, stage, queue, ovf_items, max_items, SA, SB, s);
+    a.skip_b = nullptr;
+    return sweep(p, true, pl.full, a, h, stage, queue, ovf_items, max_items, SA, SB, s, fp32);
 }
 
 }  // namespace
@@ -461,15 +463,27 @@ struct NNLayout {
     Layout L;
     Common c;
     size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0;
+    // FP32 screen
+    size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
 
-static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params* p, NNLayout& nl) {
+static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params* p, bool screen, NNLayout& nl) {
     plan_common(nl.L, nl.c, p, Q, &R);
     nl.best = nl.L.take(sizeof(unsigned long long) * (size_t)Q.n);
     nl.seed = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
+    if (screen) {
+        nl.q32 = nl.L.take(sizeof(float) * (size_t)Q.total);
+        nl.r32 = nl.L.take(sizeof(float) * (size_t)R.total);
+        if (p->kind == EAP_ERP) {
+            nl.q32b = nl.L.take(sizeof(float) * (size_t)Q.total);
+            nl.r32b = nl.L.take(sizeof(float) * (size_t)R.total);
+        }
+        nl.widen = nl.L.take(sizeof(double) * (size_t)Q.n);
+        nl.recheck = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
+    }
     return EAP_OK;
 }
 
@@ -481,7 +495,7 @@ size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off,
         check_offsets(r_off, nr, "candidates", &R) != EAP_OK)
         return 0;
     NNLayout nl;
-    nn_layout(Q, R, p, nl);
+    nn_layout(Q, R, p, o && o->precision == 1, nl);
     return nl.L.off;
 }
 
@@ -498,10 +512,10 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     if (o) {
         if (o->precision != 0 && o->precision != 1) return fail(EAP_EINVAL, "precision must be 0 or 1");
         if (!(std::isfinite(o->margin_rel) && o->margin_rel >= 0)) return fail(EAP_EINVAL, "margin_rel must be >= 0");
-        if (o->precision == 1) return fail(EAP_EINVAL, "precision 1 is not available in this build");
     }
+    const bool screen = o && o->precision == 1;
     NNLayout nl;
-    nn_layout(Q, R, p, nl);
+    nn_layout(Q, R, p, screen, nl);
     if (!ws || ws_bytes < nl.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, nl.L.off);
     Plan pl;
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
@@ -543,23 +557,69 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, res, s));
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
     const bool rerun = pl.band && pl.size != pl.full;
+    // FP32 screen: sweep single-precision copies under a widened cut-off first
+    SeriesPtrs XQ = SQ, XR = SR;
+    if (screen) {
+        float* q32 = reinterpret_cast<float*>(at(ws, nl.q32));
+        float* r32 = reinterpret_cast<float*>(at(ws, nl.r32));
+        HIPCHK(launch_to_f32(q, Q.total, q32, s));
+        HIPCHK(launch_to_f32(r, R.total, r32, s));
+        XQ = SeriesPtrs{q32, SQ.off, nullptr};
+        XR = SeriesPtrs{r32, SR.off, nullptr};
+        if (p->kind == EAP_ERP) {
+            float* qb = reinterpret_cast<float*>(at(ws, nl.q32b));
+            float* rb = reinterpret_cast<float*>(at(ws, nl.r32b));
+            HIPCHK(launch_to_f32(static_cast<const double*>(SQ.border), Q.total, qb, s));
+            HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total, rb, s));
+            XQ.border = qb;
+            XR.border = rb;
+        }
+        HIPCHK(launch_fill_u64(&h->absmax, 0ull, 1, s));
+        HIPCHK(launch_absmax(q, Q.total, &h->absmax, s));
+        HIPCHK(launch_absmax(r, R.total, &h->absmax, s));
+        double* widen = reinterpret_cast<double*>(at(ws, nl.widen));
+        HIPCHK(launch_screen_widen(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, widen, s));
+        a.widen_abs = widen;
+        a.widen_rel = o->margin_rel;
+    }
     if (seeded) {
         // 2. sweep the seed candidate of every query under its bound
-        if ((st = sweep(p, pl.band, pl.size, a, h, 0, &h->queues[0], seed_items, nq, SQ, SR, s)) != EAP_OK)
+        if ((st = sweep(p, pl.band, pl.size, a, h, 0, &h->queues[0], seed_items, nq, XQ, XR, s, screen)) != EAP_OK)
             return st;
         if (rerun) {
-            if ((st = rerun_overflow(p, pl, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], SQ, SR, s)) != EAP_OK)
+            if ((st = rerun_overflow(p, pl, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], XQ, XR, s, screen)) !=
+                EAP_OK)
                 return st;
             HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
         }
         a.skip_b = seed;
     }
     // 3. every other pair, under the per-query best-so-far (lowered as pairs complete)
-    if ((st = sweep(p, pl.band, pl.size, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+    if ((st = sweep(p, pl.band, pl.size, a, h, 2, &h->queues[2], nullptr, nq * nr, XQ, XR, s, screen)) != EAP_OK)
+        return st;
     if (rerun) {
-        a.skip_b = nullptr;
-        if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], SQ, SR, s)) != EAP_OK)
+        if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], XQ, XR, s, screen)) !=
+            EAP_OK)
             return st;
+    }
+    if (screen) {
+        // 3b. candidates within the certified FP32 error of each query's best are
+        //     recomputed in FP64; every other result becomes +inf
+        int32_t* items = reinterpret_cast<int32_t*>(at(ws, nl.recheck));
+        HIPCHK(launch_screen_filter(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, o->margin_rel, res,
+                                    best, nullptr, items, &h->ovf_count[2], &h->counters[2], s));
+        HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
+        SweepArgs b = a;
+        b.widen_abs = nullptr;
+        b.widen_rel = 0.0;
+        b.skip_b = nullptr;
+        b.npairs_dev = &h->ovf_count[2];
+        if ((st = sweep(p, pl.band, pl.size, b, h, 4, &h->queues[4], items, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+        if (rerun) {
+            if ((st = rerun_overflow(p, pl, b, h, 5, &h->ovf_count[0], ovf, nq * nr, &h->queues[5], SQ, SR, s)) !=
+                EAP_OK)
+                return st;
+        }
     }
     // 4. lexicographic (distance, index) minimum per query
     HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
@@ -643,9 +703,9 @@ eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out,
     out->pairs = h.counters[1];
     out->rechecks = h.counters[2];
     out->overflows = h.counters[3];
-    for (int s = 0; s < 4; ++s) {
-        out->stage_cells[s] = h.counters[4 + s];
-        out->stage_pairs[s] = h.counters[8 + s];
+    for (int s = 0; s < 8; ++s) {
+        out->stage_cells[s] = h.counters[8 + s];
+        out->stage_pairs[s] = h.counters[16 + s];
     }
     return EAP_OK;
 }

@@ -1,5 +1,7 @@
 // Auxiliary kernels of libeap: ERP border sums, path upper bounds, NN seeding,
 // the final lexicographic argmin, type conversion and buffer fills.
+#include <algorithm>
+
 #include "eap_pairs.h"
 
 namespace eap {
@@ -188,6 +190,106 @@ __global__ void argmin_kernel(const double* res, int64_t nq, int64_t nr, const i
     }
 }
 
+// Largest |x| over a set, as the bit pattern of a non-negative double.
+__global__ void absmax_kernel(const double* v, int64_t n, unsigned long long* out) {
+    double m = 0.0;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, __builtin_fabs(v[x]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, dbits(m));
+}
+
+// Certified bound on |D32 - D64| for any warping path whose exact cost is at
+// most B, with at most N steps, over values of magnitude <= A, in FP32 (unit
+// roundoff u = 2^-24): each term carries the rounding of its inputs
+// (u|a| + u|b|), of its own operations, and the running sum adds gamma_N on the
+// total.  Squared costs: |fl(d)^2 - d^2| <= 4uA|d| + 3u d^2 per term and
+// sum|d| <= sqrt(N sum d^2) (Cauchy-Schwarz; WDTW's weights are <= 1 and add
+// one more rounding).  L1 costs (ERP, MSM, TWE): <= u(4A + 3|term|) per term.
+// The FP64 reference carries the same error with 2^-53, covered by the factor
+// 1.01; the last term covers FP32 underflow of tiny squares.
+__device__ double screen_eps(int kind, double B, double N, double A) {
+    const double u = 0x1p-24;
+    double e;
+    if (kind == DTW || kind == CDTW || kind == WDTW) e = u * ((N + 5.0) * B + 4.0 * A * sqrt(N * B));
+    else e = u * ((N + 3.0) * B + 4.0 * N * A);
+    return 1.01 * e + N * 4e-38;
+}
+
+// Largest exact cost C that can still satisfy C <= b + eps(C), i.e. a bound on
+// the exact cost of any path whose FP32 evaluation is <= b.  eps grows like
+// sqrt(C) for the squared costs, so for b near 0 this is about (4uA)^2 N, not 0.
+__device__ double screen_bound(int kind, double b, double N, double A) {
+    const double u = 1.01 * 0x1p-24;
+    const double e0 = b + N * 4e-38;
+    double B;
+    if (kind == DTW || kind == CDTW || kind == WDTW) {
+        const double a = u * (N + 5.0), c = u * 4.0 * A * sqrt(N);
+        const double r = (c + sqrt(c * c + 4.0 * (1.0 - a) * e0)) / (2.0 * (1.0 - a));
+        B = r * r;
+    } else {
+        B = (e0 + u * 4.0 * N * A) / (1.0 - u * (N + 3.0));
+    }
+    return B * (1.0 + 1e-9);
+}
+
+// Widening of each query's FP32 cut-off during the screening sweep.  The
+// best-so-far b is an FP32 distance (or the FP64 path bound UB >= b), so the
+// exact NN distance is <= screen_bound(b) and any prefix of its path evaluates
+// in FP32 to <= b + 2 eps(screen_bound(UB)).
+__global__ void screen_widen_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
+                                    const unsigned long long* absmax, double* widen_abs) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.nA) return;
+    const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
+    double Amax = bitsd(*absmax);
+    if (kind == ERP) Amax = fmax(Amax, __builtin_fabs(gap));
+    const double ub = bitsd(A.best[q]);
+    widen_abs[q] = (ub < __builtin_huge_val()) ? 2.0 * screen_eps(kind, screen_bound(kind, ub, N, Amax), N, Amax)
+                                               : 0.0;
+}
+
+// After the FP32 sweep: every candidate of query q whose FP32 distance is
+// <= b32 + 2 eps(screen_bound(b32)) is listed for the FP64 recheck.  The FP64
+// NN cannot be elsewhere: its exact cost is <= that of the FP32 winner, which
+// is <= screen_bound(b32), and its FP32 value exceeds that by at most eps.
+// The margin m widens b32 by a relative (1 + m) on top.  The result slots are
+// reset to +inf, and best[q] becomes screen_bound(b32), an upper bound on the
+// FP64 NN distance that serves as the recheck's first cut-off.  One wave per query.
+__global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
+                                     const unsigned long long* absmax, double margin_rel, double* res,
+                                     unsigned long long* best, int32_t* items, unsigned int* count,
+                                     unsigned long long* rechecks) {
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= A.nA) return;
+    const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
+    double Amax = bitsd(*absmax);
+    if (kind == ERP) Amax = fmax(Amax, __builtin_fabs(gap));
+    const double b32 = bitsd(best[q]);
+    double thr = __builtin_huge_val(), cut64 = __builtin_huge_val();
+    if (b32 < __builtin_huge_val()) {
+        const double b = b32 * (1.0 + margin_rel);
+        cut64 = screen_bound(kind, b, N, Amax);
+        thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);
+    }
+    unsigned long long n = 0;
+    for (int64_t r = lane; r < A.nB; r += 64) {
+        const int64_t p = q * A.nB + r;
+        if (res[p] <= thr) {
+            const unsigned int k = atomicAdd(count, 1u);
+            items[k] = (int32_t)p;
+            ++n;
+        }
+        res[p] = __builtin_huge_val();
+    }
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    if (lane == 0) {
+        best[q] = dbits(cut64);
+        if (n) atomicAdd(rechecks, n);
+    }
+}
+
 static int blocks_for(int64_t n, int per) {
     int64_t b = (n + per - 1) / per;
     if (b < 1) b = 1;
@@ -207,6 +309,28 @@ hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s) 
 
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s) {
+    hipLaunchKernelGGL(absmax_kernel, dim3(std::min(blocks_for(n, 256), 1024)), dim3(256), 0, s, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_widen(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
+                               const unsigned long long* absmax, double* widen_abs, hipStream_t s) {
+    hipLaunchKernelGGL(screen_widen_kernel, dim3(blocks_for(a.nA, 256)), dim3(256), 0, s, kind, a, qoff, lr_max, gap,
+                       absmax, widen_abs);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
+                                const unsigned long long* absmax, double margin_rel, double* res,
+                                unsigned long long* best, double* widen_abs, int32_t* items, unsigned int* count,
+                                unsigned long long* rechecks, hipStream_t s) {
+    (void)widen_abs;
+    hipLaunchKernelGGL(screen_filter_kernel, dim3(blocks_for(a.nA, 4)), dim3(256), 0, s, kind, a, qoff, lr_max, gap,
+                       absmax, margin_rel, res, best, items, count, rechecks);
     return hipGetLastError();
 }
 

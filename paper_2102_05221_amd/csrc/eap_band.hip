@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
                 }
                 qa = it.a;
                 out = it.out;
-                if (nn) cut = (T)bitsd(A.best[it.a]);
+                if (nn) cut = nn_cut<T>(A, it.a);
                 else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
                 const int L = Lli > Lco ? Lli : Lco;
                 const int d_end = Lco - Lli;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
                 }
                 have = false;
             } else {
-                if (nn) cut = vmin(cut, (T)bitsd(A.best[qa]));
+                if (nn) cut = vmin(cut, nn_cut<T>(A, qa));
                 i0 += CB;
                 j0 += CB;
                 if constexpr (AHEAD) {
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
     wave_add_u64(&A.counters[0], ncells);
     wave_add_u64(&A.counters[1], npairs);
     wave_add_u64(&A.stage[0], ncells);
-    wave_add_u64(&A.stage[4], npairs);
+    wave_add_u64(&A.stage[8], npairs);
 }
 
 template <int KIND, typename T, int G, int C>

@@ -43,6 +43,14 @@ __device__ __forceinline__ unsigned long long dbits(double v) {
 }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __builtin_bit_cast(double, (long long)b); }
 
+// The next representable value above a non-negative finite t.
+__device__ __forceinline__ float round_up_next(float t) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, t) + 1u);
+}
+__device__ __forceinline__ double round_up_next(double t) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, t) + 1ull);
+}
+
 // One set of series: concatenated values, int64 offsets (n+1), and for ERP the
 // running border sums B[off+i-1] = sum_{m<=i} |x_m - gap| (same layout).
 template <typename T> struct Series {

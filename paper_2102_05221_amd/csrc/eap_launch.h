@@ -28,7 +28,7 @@ struct SweepArgs {
     double* res;
     unsigned int* queue;             // work counter, zero at launch
     unsigned long long* counters;    // [0] cells executed, [1] pairs swept, [3] band overflows
-    unsigned long long* stage;       // [0] cells of this launch's stage, [4] its pairs
+    unsigned long long* stage;       // [0] cells of this launch's stage, [8] its pairs
     // plain DP: cut-off +inf for every item, no best-so-far, no abandoning
     int plain;
     // distance parameters
@@ -49,6 +49,9 @@ struct SweepArgs {
     unsigned int* ovf_count;
     // when set, the number of work slots is read from here at run time
     const unsigned int* npairs_dev;
+    // FP32 screen: the cut-off of query a is best[a] * (1 + widen_rel) + widen_abs[a]
+    const double* widen_abs;
+    double widen_rel;
 };
 
 struct SeriesPtrs {
@@ -80,5 +83,12 @@ hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b
 hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
                          double* out_dist, int32_t* out_label, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
+                                const unsigned long long* absmax, double margin_rel, double* res,
+                                unsigned long long* best, double* widen_abs, int32_t* items, unsigned int* count,
+                                unsigned long long* rechecks, hipStream_t s);
+hipError_t launch_screen_widen(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
+                               const unsigned long long* absmax, double* widen_abs, hipStream_t s);
 
 }  // namespace eap

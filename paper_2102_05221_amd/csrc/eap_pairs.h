@@ -62,6 +62,17 @@ __device__ __forceinline__ int64_t item_of(const SweepArgs& A, unsigned int p) {
     return A.items ? (int64_t)A.items[p] : (int64_t)p;
 }
 
+// The cut-off of query a in NN mode: the best-so-far, widened for an FP32
+// screen (so that no candidate within the certified FP32 error of the best is
+// abandoned) and rounded up to T.
+template <typename T> __device__ __forceinline__ T nn_cut(const SweepArgs& A, int64_t a) {
+    double c = bitsd(A.best[a]);
+    if (A.widen_abs) c = c * (1.0 + A.widen_rel) + A.widen_abs[a];
+    T t = (T)c;
+    if ((double)t < c) t = round_up_next(t);
+    return t;
+}
+
 // Sum of a per-lane counter over the wave, added once per wave.
 __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                     if (k == 0) A.res[out] = __builtin_nan("");
                     continue;
                 }
-                if (nn) cut = (T)bitsd(A.best[it.a]);
+                if (nn) cut = nn_cut<T>(A, it.a);
                 else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
                 kend = (Lco - 1) / C;
                 uend = (Lco - 1) - kend * C;
@@ -240,14 +240,13 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
             have = false;
             if (k == 0) ++npairs;
         } else if (have && nn) {
-            const T b = (T)bitsd(A.best[qa]);
-            cut = vmin(cut, b);
+            cut = vmin(cut, nn_cut<T>(A, qa));
         }
     }
     wave_add_u64(&A.counters[0], ncells);
     wave_add_u64(&A.counters[1], npairs);
     wave_add_u64(&A.stage[0], ncells);
-    wave_add_u64(&A.stage[4], npairs);
+    wave_add_u64(&A.stage[8], npairs);
 }
 
 template <int KIND, typename T, int G, int C>

@@ -187,6 +187,57 @@ def test_plain_dp_mode_gives_the_same_nn(torch_dev, kind):
         assert torch.equal(a[0], x[0]) and torch.equal(a[1], x[1])
 
 
+@pytest.mark.parametrize("kind", synth.SIX)
+def test_fp32_screen_gives_fp64_results(torch_dev, orc, kind):
+    """Precision 1 (FP32 screen + FP64 recheck) returns the FP64 NN bit for bit,
+    also when candidates differ by far less than FP32 can resolve."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(2, n_ref=80, n_query=12, length=200)
+    rs = synth.unpack(wl["refs"], wl["ref_off"])
+    qs = synth.unpack(wl["queries"], wl["query_off"])
+    rng = np.random.default_rng(5)
+    # near-ties: copies of two queries, nudged by ~1e-9 (FP32 sees them as equal)
+    rs[5] = qs[0].copy()
+    rs[6] = qs[0].copy()
+    rs[6][17] += 1e-9
+    rs[9] = qs[1] + rng.normal(0, 1e-9, size=len(qs[1]))
+    rs[2] = qs[1] + rng.normal(0, 1e-9, size=len(qs[1]))
+    rv, ro = synth.pack(rs)
+    p = wl["params"][kind]
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, rv)
+    log(f"fp32 screen {kind}")
+    ws = eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], ro, p, precision=1), dev)
+    eap.reset_counters(ws)
+    a = eap.nn1(q, wl["query_off"], r, ro, p, precision=1, ws=ws)
+    c = eap.read_counters(ws)
+    torch.cuda.synchronize()
+    oi, od, _ = orc.nn1(p, wl["queries"], wl["query_off"], rv, ro, "dp")
+    gi, gd = a[0].cpu().numpy(), a[1].cpu().numpy()
+    bad = np.nonzero((gi != oi) | (gd != od))[0]
+    assert bad.size == 0, [(int(i), int(gi[i]), float(gd[i]), int(oi[i]), float(od[i])) for i in bad]
+    assert c["rechecks"] >= 12            # at least the NN of every query
+    # every listed candidate is recomputed once in FP64 (narrow-band overflows of
+    # WDTW finish in the full-band rerun)
+    assert c["stage_pairs"][4] + c["stage_pairs"][5] == c["rechecks"]
+
+
+def test_fp32_screen_ragged_windows(torch_dev, orc):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(8)
+    qs = synth.random_walks(rng, 7, (20, 400))
+    rs = synth.random_walks(rng, 50, (10, 400))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    for p in (dict(kind="cdtw", window_ratio=0.1), dict(kind="erp", gap=0.2, window_ratio=0.3),
+              dict(kind="wdtw", g=0.3)):
+        log(f"fp32 screen ragged {p}")
+        g = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=1)
+        torch.cuda.synchronize()
+        oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+        assert np.array_equal(g[0].cpu().numpy(), oi)
+        assert np.array_equal(g[1].cpu().numpy(), od)
+
+
 def test_profile_records_each_sweep(torch_dev):
     torch, dev = torch_dev
     wl = synth.make_workload(2, n_ref=30, n_query=4, length=64)
