@@ -8,7 +8,10 @@ before the timed region.
 
 Reported (one JSON line on stdout):
   value        effective GCUPS: DP cells of the plain full programme (band
-               cells for CDTW) of all six searches, divided by the step time
+               cells for CDTW) of all six searches, divided by the step time.
+               By default each search is the FP32 screen + FP64 recheck, whose
+               NN answers equal the FP64 sweep's bit for bit (--precision 0:
+               FP64 sweep only)
   queries_per_s  1-NN searches per second (500 queries x 6 distances per step)
   plain_gpu_dp   the same searches with the plain full DP on the GPU
   roofline     the dominant sweep kernel: executed cells per launch over its
@@ -30,10 +33,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GCUPS (cell updates/s) & queries/s for 1-NN search vs plain GPU DP; p50/p99 latency"
 
-# VALU roofline of gfx950: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s,
-# FP64 add/mul/min at full rate.  Minimal lane-ops per DP cell of each distance.
+# VALU roofline of gfx950: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
+# FP64 lane-ops/s (the published 78.6 TFLOP/s FP64 vector rate, FMA = 2 flops);
+# FP32 issues up to two lane-ops per lane and cycle, 78.6e12/s (the published
+# 157.3 TFLOP/s FP32 vector rate).  Minimal lane-ops per DP cell of each
+# distance; FP32 has three-operand min3/max3/med3, FP64 does not.
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+LANE_OPS_PER_S_F32 = 2 * LANE_OPS_PER_S
 OPS_PER_CELL = {"dtw": 5, "cdtw": 5, "wdtw": 6, "erp": 6, "msm": 16, "twe": 8}
+OPS_PER_CELL_F32 = {"dtw": 4, "cdtw": 4, "wdtw": 5, "erp": 5, "msm": 9, "twe": 7}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -98,7 +106,7 @@ def main():
     ap.add_argument("--kinds", default="dtw,cdtw,wdtw,erp,msm,twe")
     ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU-oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
-    ap.add_argument("--precision", type=int, default=0, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
+    ap.add_argument("--precision", type=int, default=1, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
     ap.add_argument("--compare-precision", action="store_true",
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -176,10 +184,13 @@ def main():
     for k in kinds:
         sk = swept_kind(k, wl["params"][k])
         main = [x for x in prof if x["kind"] == sk and x["stage"] == 2]
+        rechk = [x for x in prof if x["kind"] == sk and x["stage"] in (4, 5)]
         per[k] = dict(
             sweep_ms_per_step=sum(x["ms"] for x in prof if x["kind"] == sk) / args.steps,
             main_sweep_ms=(sum(x["ms"] for x in main) / len(main)) if main else None,
             main_kernel=(f"{main[0]['kernel']}{main[0]['size']}" if main else None),
+            main_fp32=bool(main[0]["fp32"]) if main else False,
+            recheck_ms_per_step=sum(x["ms"] for x in rechk) / args.steps,
             executed_cells_per_step=counters[k]["cells"] / args.steps,
             main_cells_per_launch=counters[k]["stage_cells"][2] / args.steps,
             dense_cells=dense[k],
@@ -198,23 +209,28 @@ def main():
     dom_kind = max(kinds, key=lambda k: per[k]["main_sweep_ms"] or 0.0)
     d = per[dom_kind]
     achieved = d["main_cells_per_launch"] / (d["main_sweep_ms"] * 1e-3) / 1e9
-    peak = LANE_OPS_PER_S / OPS_PER_CELL[dom_kind] / 1e9
+    ops = (OPS_PER_CELL_F32 if d["main_fp32"] else OPS_PER_CELL)[dom_kind]
+    peak = (LANE_OPS_PER_S_F32 if d["main_fp32"] else LANE_OPS_PER_S) / ops / 1e9
     roofline = dict(bound="alu", achieved=achieved, peak=peak, unit="GCUPS", frac=achieved / peak, traffic=None,
-                    kernel=f"{d['main_kernel']} sweep, {dom_kind.upper()} main stage",
-                    ops_per_cell=OPS_PER_CELL[dom_kind], launch_ms=d["main_sweep_ms"],
+                    kernel=f"{d['main_kernel']} sweep, {dom_kind.upper()} main stage, "
+                           f"{'fp32' if d['main_fp32'] else 'fp64'}",
+                    ops_per_cell=ops, launch_ms=d["main_sweep_ms"],
                     cells_per_launch=d["main_cells_per_launch"])
     # HBM bytes per launch from the committed rocprofv3 counter summary, valid
     # only while the kernel sources are the ones it was measured on
-    traffic_path = os.path.join(ROOT, "profiles", "rows_kernel_msm_nn_workload2_hbm.md")
-    if os.path.exists(traffic_path):
+    pdir = os.path.join(ROOT, "profiles")
+    for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if not fn.endswith("_hbm.md"):
+            continue
         kv = {}
-        for ln in open(traffic_path):
+        for ln in open(os.path.join(pdir, fn)):
             if ":" in ln and not ln.startswith(("#", " ", "|")):
                 key, _, val = ln.partition(":")
                 kv[key.strip()] = val.strip()
         if kv.get("kernel") == roofline["kernel"] and kv.get("source_hash") == _source_hash():
             roofline["traffic"] = float(kv["hbm_bytes_per_launch"])
-            roofline["traffic_note"] = "HBM bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE, copy-calibrated)"
+            roofline["traffic_note"] = f"HBM bytes per launch, profiles/{fn} (FETCH_SIZE and WRITE_SIZE, " \
+                                       "copy-calibrated)"
 
     # plain full DP on the GPU, same searches (outside the timed region)
     plain = None

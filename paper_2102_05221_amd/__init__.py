@@ -243,13 +243,13 @@ def profile_enable(on: bool = True):
 
 def profile_take(cap: int = 4096) -> list:
     """Wait for the timed launches and return them as dicts (stage, kernel
-    'rows'/'band', kind, size, ms)."""
+    'rows'/'band', kind, size, fp32, ms)."""
     buf = (ProfileRec * cap)()
     n = ctypes.c_int32(0)
     _check(lib().eap_profile_take(buf, cap, ctypes.byref(n)))
     inv = {v: k for k, v in KINDS.items()}
     return [dict(stage=r.stage, kernel=("band" if r.kernel else "rows"), kind=inv.get(r.kind, r.kind), size=r.size,
-                 ms=float(r.ms)) for r in buf[:n.value]]
+                 fp32=int(r.fp32), ms=float(r.ms)) for r in buf[:n.value]]
 
 
 def wdtw_weights(g: float, L: int) -> np.ndarray:

@@ -52,10 +52,13 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     const int c0 = 1 + k * C;
     T cut = 0;
     T val[C], vb[C], tv[C], aux[C];
+    T adv[KIND == TWE ? C : 1];   // TWE: |s_{i-1} - t_j| of the previous row
     T dg = 0, lout = 0, sout = 0, s_next = 0, b_next = 0, sp = 0, tpm = 0, brd0 = 0, s0 = 0;
     unsigned long long ncells = 0, npairs = 0;
 #pragma unroll
     for (int u = 0; u < C; ++u) val[u] = vb[u] = tv[u] = aux[u] = 0;
+#pragma unroll
+    for (int u = 0; u < (KIND == TWE ? C : 1); ++u) adv[u] = 0;
 
     for (;;) {
         if (!have && !done) {
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                     if constexpr (KIND == ERP) aux[u] = ghost ? INF : vabs(tv[u] - gap);
                     if constexpr (KIND == MSM) aux[u] = ghost ? INF : tv[u] - tprev;
                     if constexpr (KIND == TWE) aux[u] = ghost ? INF : (vabs(tv[u] - tprev) + nu) + lam;
+                    if constexpr (KIND == TWE) adv[u] = vabs((T)0 - tv[u]);   // row 0: s_0 = 0
                     // top border M(0, j): computed for ERP, +inf otherwise
                     if constexpr (KIND == ERP) val[u] = ghost ? INF : cob[c0 + u - 1];
                     else val[u] = INF;
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
             T diag = ns ? brd0 : dg;
             if (!ns) dg = lin;          // M(0, c0-1) stays the diagonal of row 1
             T left = lin;
-            T sg = 0, ds = 0, gA = 0;
+            T sg = 0, ds = 0, gA = 0, carry = 0;
             const T* ntp = nullptr;
             if constexpr (KIND == ERP) sg = vabs(sin - gap);
             if constexpr (KIND == MSM) ds = sin - sp;
@@ -184,19 +188,33 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 } else if constexpr (KIND == MSM) {
                     // C(s_i, s_{i-1}, t_j) and C(t_j, s_i, t_{j-1}) of eq. MSMCost as
                     // c + max(0, min(x,y) - np, np - max(x,y)), with the differences
-                    // written through d = s_i - t_j, ds = s_i - s_{i-1}, dt = t_j - t_{j-1}
-                    const T c1 = cc + vmax(vmax(vmin(-ds, -d), vmin(ds, d)), (T)0);
-                    const T c2 = cc + vmax(vmax(vmin(d, -aux[u]), vmin(-d, aux[u])), (T)0);
+                    // written through d = s_i - t_j, ds = s_i - s_{i-1}, dt = t_j - t_{j-1}.
+                    // max(0, min(a,b), -max(a,b)) is |med3(a, b, 0)|, one instruction
+                    // in FP32 (gfx950 has no FP64 med3); both select the same operand.
+                    T c1, c2;
+                    if constexpr (sizeof(T) == 4) {
+                        c1 = cc + vabs(__builtin_amdgcn_fmed3f(ds, d, 0.0f));
+                        c2 = cc + vabs(__builtin_amdgcn_fmed3f(d, -aux[u], 0.0f));
+                    } else {
+                        c1 = cc + vmax(vmax(vmin(-ds, -d), vmin(ds, d)), (T)0);
+                        c2 = cc + vmax(vmax(vmin(d, -aux[u]), vmin(-d, aux[u])), (T)0);
+                    }
                     v = vmin(vmin(diag + vabs(d), top + c1), left + c2);
                 } else if constexpr (KIND == TWE) {
-                    const T tp = (u == 0) ? tpm : tv[u - 1];
-                    const T match = (vabs(d) + vabs(sp - tp)) + ntp[u];
+                    // |s_{i-1} - t_{j-1}| is the previous row's |d| one column to the
+                    // left (rounded subtraction of the same operands)
+                    const T ad = vabs(d);
+                    const T adp = (u == 0) ? vabs(sp - tpm) : adv[u - 1];
+                    if (u > 0) adv[u - 1] = carry;
+                    carry = ad;
+                    const T match = (ad + adp) + ntp[u];
                     v = vmin(vmin(diag + match, top + gA), left + aux[u]);
                 }
                 dst[u] = v;
                 diag = top;
                 left = v;
             }
+            if constexpr (KIND == TWE) adv[C - 1] = carry;
             if (row >= 1) sp = sin;
             if (act) ncells += C;
             lout = dst[C - 1];
