@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU-oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
     ap.add_argument("--precision", type=int, default=1, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
+    ap.add_argument("--no-tune", action="store_true", help="skip the row-sweep autotuner (default shapes)")
     ap.add_argument("--compare-precision", action="store_true",
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -150,6 +151,16 @@ def main():
         for k in kinds:
             eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k],
                     precision=precision)
+
+    # autotune the row sweep's shape per distance on this workload (setup, untimed)
+    tuning = {}
+    if not args.no_tune:
+        for k in kinds:
+            recs = eap.tune_nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], precision=args.precision,
+                                ws=ws[k])
+            if recs:
+                tuning[k] = dict(chosen=next(f"{x['g']}x{x['c']}" for x in recs if x["chosen"]),
+                                 ms={f"{x['g']}x{x['c']}": round(x["ms"], 3) for x in recs})
 
     for _ in range(args.warmup):
         step()
@@ -299,6 +310,7 @@ def main():
                     queries=nq, candidates=nr, length=512, distances=kinds,
                     precision=("fp32 screen + fp64 recheck" if args.precision else "fp64")),
         other_precision=other,
+        tuning=tuning,
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)),
         step_ms_p99=float(np.percentile(step_ms, 99)),

@@ -11,7 +11,8 @@
  *  - Series values are float64 arrays in DEVICE memory.  A set of n series is
  *    one concatenated array plus an offsets array of n+1 int64 in HOST memory:
  *    series k is values[off[k] .. off[k+1]), length >= 1.  Offsets must start
- *    at 0 and be non-decreasing with every length >= 1.
+ *    at 0 and be non-decreasing with every length >= 1.  Lengths up to 2048
+ *    (longer series are EINVAL).
  *  - Outputs are DEVICE arrays owned by the caller.  Nothing is freed or kept.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
  *    runs asynchronously; outputs are valid once the stream has reached the
@@ -112,8 +113,8 @@ typedef struct {
  * While enabled, every sweep launch is bracketed by two events on its stream.
  * eap_profile_take() waits for the recorded launches, copies up to `cap`
  * records into `out` (host memory), returns their number in *n and forgets
- * them.  kernel: 0 row sweep, 1 band sweep; size: row width or band
- * diagonals; kind: eap_kind swept. */
+ * them.  kernel: 0 row sweep, 1 band sweep; size: strip width (row sweep) or
+ * band diagonals; group: lanes per pair; kind: eap_kind swept. */
 typedef struct {
     int32_t stage;
     int32_t kernel;
@@ -121,6 +122,7 @@ typedef struct {
     int32_t size;
     int32_t fp32;
     float ms;
+    int32_t group;
 } eap_profile_rec;
 eap_status eap_profile_enable(int32_t on);
 eap_status eap_profile_take(eap_profile_rec* out, int32_t cap, int32_t* n);
@@ -165,6 +167,35 @@ eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const 
  * eap_reset_counters() zeroes them (asynchronously, on `stream`). */
 eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out, void* stream);
 eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream);
+
+/* Row-sweep autotuner.  The row sweep runs each pair on G lanes (64/G pairs
+ * per wavefront) with C columns per lane, in strips of G*C columns; every
+ * shape gives the same results, bit for bit.  eap_tune_nn1() runs eap_nn1() on
+ * the given problem (a sample of the real one, typically) once per shape, G in
+ * {16, 32, 64} x C in {8, 16} (and C = 32 for the FP32 sweep of DTW and
+ * WDTW), at the precision of `o` (1: the shape of the
+ * FP32 screening sweep; 0: of the FP64 sweep), checks that all shapes return
+ * the same indices and distances (EAP_EDEVICE otherwise), times each over two
+ * further runs, and records the fastest for (distance, precision, class of the
+ * shorter series' longest length: <=128, <=256, <=512, <=1024, <=2048) in a
+ * process-wide table that every later call consults; without an entry a
+ * default shape is used.  Distances the row sweep does not run (CDTW, ERP
+ * with a window, WDTW in the narrow band) return EAP_OK with *n = 0.
+ * Synchronises `stream`; not for use while other calls are in flight.
+ *  ws, ws_bytes        as for eap_nn1 (its workspace fits every shape).
+ *  out_idx, out_dist   device int64[nq], double[nq]: scratch outputs.
+ *  recs, cap, n        host array receiving one record per shape timed. */
+typedef struct {
+    int32_t g, c;      /* lanes per pair, columns per lane */
+    float ms;          /* mean time of one eap_nn1 call */
+    int32_t chosen;    /* 1 for the shape recorded in the table */
+} eap_tune_rec;
+eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,
+                        int64_t nr, const eap_params* p, const eap_nn_opts* o, void* ws, size_t ws_bytes,
+                        int64_t* out_idx, double* out_dist, void* stream, eap_tune_rec* recs, int32_t cap,
+                        int32_t* n);
+/* Forgets every tuned shape (later calls use the defaults). */
+eap_status eap_tune_reset(void);
 
 /* Host utility: the WDTW weights the library uses for longer length L,
  * out[k] = w(k) = 1 / (1 + exp(-g * (k - L/2))) for k = 0..L-1 (eq. WDTW with

@@ -55,7 +55,12 @@ class Counters(ctypes.Structure):
 
 class ProfileRec(ctypes.Structure):
     _fields_ = [("stage", ctypes.c_int32), ("kernel", ctypes.c_int32), ("kind", ctypes.c_int32),
-                ("size", ctypes.c_int32), ("fp32", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("size", ctypes.c_int32), ("fp32", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("group", ctypes.c_int32)]
+
+
+class TuneRec(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_int32), ("c", ctypes.c_int32), ("ms", ctypes.c_float), ("chosen", ctypes.c_int32)]
 
 
 _lib = None
@@ -95,6 +100,11 @@ def lib():
         L.eap_profile_enable.argtypes = [ctypes.c_int32]
         L.eap_profile_take.restype = ctypes.c_int
         L.eap_profile_take.argtypes = [ctypes.POINTER(ProfileRec), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.eap_tune_nn1.restype = ctypes.c_int
+        L.eap_tune_nn1.argtypes = [_vp, _pi64, _i64, _vp, _pi64, _i64, _pP, _pO, _vp, _sz, _vp, _vp, _vp,
+                                   ctypes.POINTER(TuneRec), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.eap_tune_reset.restype = ctypes.c_int
+        L.eap_tune_reset.argtypes = []
         L.eap_wdtw_weights.restype = ctypes.c_int
         L.eap_wdtw_weights.argtypes = [_d, _i64, ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -201,6 +211,35 @@ def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: 
     return idx, dist, lab
 
 
+def tune_nn1(q, q_off, r, r_off, p, precision: int = 0, margin_rel: float = 1e-4, ws=None, stream=None) -> list:
+    """Autotune the row sweep's shape (lanes per pair, columns per lane) for
+    this distance, precision and length class on the given NN problem; later
+    calls use the fastest.  Returns one dict per shape timed (g, c, ms,
+    chosen); empty for distances the row sweep does not run."""
+    import torch
+    _dev_f64(q, "queries")
+    _dev_f64(r, "candidates")
+    q_off, r_off = _offsets(q_off), _offsets(r_off)
+    nq, nr = len(q_off) - 1, len(r_off) - 1
+    p = _as_params(p)
+    o = NNOpts(int(precision), float(margin_rel), 0)
+    if ws is None:
+        ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device)
+    idx = torch.empty(nq, dtype=torch.int64, device=q.device)
+    dist = torch.empty(nq, dtype=torch.float64, device=q.device)
+    recs = (TuneRec * 16)()
+    n = ctypes.c_int32(0)
+    _check(lib().eap_tune_nn1(q.data_ptr(), q_off.ctypes.data_as(_pi64), nq, r.data_ptr(),
+                              r_off.ctypes.data_as(_pi64), nr, ctypes.byref(p), ctypes.byref(o), ws.data_ptr(),
+                              ws.numel(), idx.data_ptr(), dist.data_ptr(), _stream(stream, q.device), recs, 16,
+                              ctypes.byref(n)))
+    return [dict(g=x.g, c=x.c, ms=float(x.ms), chosen=bool(x.chosen)) for x in recs[:n.value]]
+
+
+def tune_reset() -> None:
+    _check(lib().eap_tune_reset())
+
+
 def pairwise_workspace_bytes(s_off, p) -> int:
     s_off = _offsets(s_off)
     p = _as_params(p)
@@ -243,13 +282,14 @@ def profile_enable(on: bool = True):
 
 def profile_take(cap: int = 4096) -> list:
     """Wait for the timed launches and return them as dicts (stage, kernel
-    'rows'/'band', kind, size, fp32, ms)."""
+    'rows'/'band', kind, size = strip width or band diagonals, group = lanes
+    per pair, fp32, ms)."""
     buf = (ProfileRec * cap)()
     n = ctypes.c_int32(0)
     _check(lib().eap_profile_take(buf, cap, ctypes.byref(n)))
     inv = {v: k for k, v in KINDS.items()}
     return [dict(stage=r.stage, kernel=("band" if r.kernel else "rows"), kind=inv.get(r.kind, r.kind), size=r.size,
-                 fp32=int(r.fp32), ms=float(r.ms)) for r in buf[:n.value]]
+                 group=r.group, fp32=int(r.fp32), ms=float(r.ms)) for r in buf[:n.value]]
 
 
 def wdtw_weights(g: float, L: int) -> np.ndarray:

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -37,7 +38,8 @@ eap_status fail(eap_status s, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(EAP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int64_t kMaxLen = 1024;     // longest series the sweep kernels take
+constexpr int64_t kMaxLen = 2048;     // longest series the sweep kernels take
+constexpr int kRowsBlocksPerCU = 4;   // persistent grid of the row sweep
 constexpr size_t kAlign = 256;
 
 // ---------------------------------------------------------------- parameters
@@ -184,13 +186,23 @@ int sweep_grid(int64_t items, int group_lanes) {
     return (int)std::max<int64_t>(1, std::min(need, cap));
 }
 
-int pick_width(int64_t lco_max) {
-    for (int w : {128, 256, 512, 1024})
-        if (lco_max <= w) return w;
-    return 0;
+int rows_grid(int64_t items, int group_lanes) {
+    const int groups_per_block = 256 / group_lanes;
+    int64_t need = (items + groups_per_block - 1) / groups_per_block;
+    int64_t cap = (int64_t)device_cus() * kRowsBlocksPerCU;
+    return (int)std::max<int64_t>(1, std::min(need, cap));
 }
 
-int rows_group(int width) { return width <= 256 ? 16 : (width == 512 ? 32 : 64); }
+// Bytes of the row sweep's strip-edge buffers for a launch over `items` work
+// slots: one column of L_li + 1 values per group, for the most groups any
+// shape launches (16 lanes per pair); none when every pair fits one strip of
+// the narrowest shape.
+size_t edge_bytes(int64_t items, int64_t lli_max, int64_t lco_max) {
+    if (lco_max <= 128) return 0;
+    const int64_t groups = std::min<int64_t>((items + 15) / 16 * 16, (int64_t)device_cus() * kRowsBlocksPerCU * 16);
+    return (size_t)groups * (size_t)(lli_max + 1) * sizeof(double);
+}
+
 int band_group(int diags) { return diags <= 256 ? 16 : (diags == 512 ? 32 : 64); }
 
 int pick_diags(int64_t need) {
@@ -199,13 +211,41 @@ int pick_diags(int64_t need) {
     return 0;
 }
 
+// Row-sweep shapes: defaults, the autotuned table, and the tuner's override.
+int len_bucket(int64_t lco_max) {
+    int b = 0;
+    while (b < 5 && lco_max > ((int64_t)128 << b)) ++b;
+    return b;
+}
+
+RowsShape default_shape(int kind, bool fp32, int64_t lco_max) {
+    int c = 16;
+    if (!fp32 && (kind == EAP_TWE || kind == EAP_WDTW)) c = 8;   // their FP64 registers
+    for (int g : {16, 32, 64})
+        if ((int64_t)g * c >= lco_max) return RowsShape{g, c};
+    return RowsShape{64, c};
+}
+
+std::mutex g_tune_mu;
+std::map<int, RowsShape> g_tuned;                // key: (kind * 2 + fp32) * 8 + bucket
+thread_local RowsShape g_force[2] = {{0, 0}, {0, 0}};   // [fp32], set while tuning
+
+RowsShape rows_shape(int kind, bool fp32, int64_t lco_max) {
+    if (g_force[fp32].g) return g_force[fp32];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find((kind * 2 + (fp32 ? 1 : 0)) * 8 + len_bucket(lco_max));
+    if (it != g_tuned.end()) return it->second;
+    return default_shape(kind, fp32, lco_max);
+}
+
 // What the sweep of one distance needs, for sets whose longest series have
 // lengths la_max and lb_max.
 struct Plan {
     bool band = false;     // kernel B (true) or kernel A
-    int size = 0;          // A: row width; B: diagonals of the first pass
-    int band_half = 0;     // B, unconstrained: half width of the first pass
-    int full = 0;          // B, unconstrained: diagonals of the full re-run
+    int size = 0;          // B: diagonals
+    int band_half = 0;     // B, WDTW: half width of the certified narrow band
+    bool rerun = false;    // B, WDTW: items the narrow band cannot certify go to kernel A
+    RowsShape r64{16, 16}, r32{16, 16};   // kernel A shapes per precision
 };
 
 eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_t l_diff_max, bool narrow_first,
@@ -213,34 +253,25 @@ eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_
     const int kind = effective_kind(p);
     const int64_t lmax = std::max(la_max, lb_max);
     const int64_t lco_max = std::min(la_max, lb_max);
-    if (kind == EAP_DTW || kind == EAP_MSM || kind == EAP_TWE || (kind == EAP_ERP && !windowed(p))) {
-        pl->band = false;
-        pl->size = pick_width(lco_max);
-        if (!pl->size) return fail(EAP_EINVAL, "series too long for the row sweep");
-        return EAP_OK;
-    }
-    pl->band = true;
-    if (kind == EAP_CDTW || kind == EAP_ERP) {
+    pl->r64 = rows_shape(kind, false, lco_max);
+    pl->r32 = rows_shape(kind, true, lco_max);
+    pl->band = false;
+    pl->rerun = false;
+    if (kind == EAP_CDTW || (kind == EAP_ERP && windowed(p))) {
+        pl->band = true;
         int64_t w = (int64_t)std::floor(p->window_ratio * (double)lmax);
         int64_t wb = std::min<int64_t>(w + (kind == EAP_ERP ? 1 : 0), lmax);
         pl->size = pick_diags(2 * wb + 2);
         if (!pl->size) return fail(EAP_EINVAL, "window too wide for the band sweep");
-        pl->full = pl->size;   // the window is the band: nothing to re-run
         return EAP_OK;
     }
-    // WDTW: a certified narrow band first, the full band for the items it cannot certify
-    pl->full = pick_diags(la_max + lb_max);
-    if (!pl->full) return fail(EAP_EINVAL, "series too long for the band sweep");
-    if (narrow_first) {
+    // WDTW in an NN search with lengths that differ little: a certified narrow
+    // band around the diagonal first, the row sweep for the items it cannot certify
+    if (kind == EAP_WDTW && narrow_first && l_diff_max <= 64) {
+        pl->band = true;
         pl->size = 256;
         pl->band_half = (int)std::max<int64_t>(16, (256 - 2 - l_diff_max) / 2);
-        if (pl->size >= pl->full) {
-            pl->size = pl->full;
-            pl->band_half = (int)(2 * lmax);
-        }
-    } else {
-        pl->size = pl->full;
-        pl->band_half = (int)(2 * lmax);
+        pl->rerun = true;
     }
     return EAP_OK;
 }
@@ -352,13 +383,15 @@ struct Profiler {
 Profiler g_prof;
 
 // One sweep launch (kernel A or B) over `n` work slots, counted under `stage`.
-eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* h, int stage, unsigned int* queue,
-                 const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s, bool fp32 = false) {
+eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, Header* h, int stage,
+                 unsigned int* queue, const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s,
+                 bool fp32 = false) {
     a.queue = queue;
     a.items = items;
     a.npairs = n;
     a.stage = &h->counters[8 + stage];
     const int kind = effective_kind(p);
+    const RowsShape sh = fp32 ? pl.r32 : pl.r64;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -370,14 +403,15 @@ eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* 
     if (e0 && e1) HIPCHK(hipEventRecord(e0, s));
     (void)hipGetLastError();   // launch errors below must be this launch's own
     hipError_t e;
-    if (band) e = launch_band(kind, fp32, size, a, SA, SB, sweep_grid(n, band_group(size)), s);
-    else e = launch_rows(kind, fp32, size, a, SA, SB, sweep_grid(n, rows_group(size)), s);
+    if (band) e = launch_band(kind, fp32, pl.size, a, SA, SB, sweep_grid(n, band_group(pl.size)), s);
+    else e = launch_rows(kind, fp32, sh, a, SA, SB, rows_grid(n, sh.g), s);
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     if (e0 && e1) {
         HIPCHK(hipEventRecord(e1, s));
         std::lock_guard<std::mutex> lk(g_prof.mu);
         ProfRec pr;
-        pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, size, fp32 ? 1 : 0, 0.0f};
+        pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, band ? pl.size : sh.g * sh.c, fp32 ? 1 : 0, 0.0f,
+                               band ? band_group(pl.size) : sh.g};
         pr.e0 = e0;
         pr.e1 = e1;
         g_prof.pending.push_back(pr);
@@ -385,18 +419,17 @@ eap_status sweep(const eap_params* p, bool band, int size, SweepArgs a, Header* 
     return EAP_OK;
 }
 
-// Items of the narrow band pass that could not be certified are re-swept with
-// the full band.  Their list and count stay on the device: the re-run reads the
-// count at run time, so nothing synchronises the host.
+// Items of the narrow band pass that could not be certified are swept again by
+// the row sweep.  Their list and count stay on the device: the re-run reads
+// the count at run time, so nothing synchronises the host.
 eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, Header* h, int stage,
                           unsigned int* ovf_count, const int32_t* ovf_items, int64_t max_items, unsigned int* queue,
                           SeriesPtrs SA, SeriesPtrs SB, hipStream_t s, bool fp32 = false) {
-    a.band_half = 1 << 20;
     a.ovf_items = nullptr;
     a.ovf_count = nullptr;
     a.npairs_dev = ovf_count;
     a.skip_b = nullptr;
-    return sweep(p, true, pl.full, a, h, stage, queue, ovf_items, max_items, SA, SB, s, fp32);
+    return sweep(p, pl, false, a, h, stage, queue, ovf_items, max_items, SA, SB, s, fp32);
 }
 
 }  // namespace
@@ -409,20 +442,22 @@ const char* eap_last_error(void) { return g_err.c_str(); }
 const char* eap_version(void) { return "eap-mi355x 0.1 (gfx950)"; }
 
 // ------------------------------------------------------------------ distance
-static void distance_layout(int64_t lx, int64_t ly, const eap_params* p, Layout& L, Common& c, size_t* ovf) {
+static void distance_layout(int64_t lx, int64_t ly, const eap_params* p, Layout& L, Common& c, size_t* ovf,
+                            size_t* edge) {
     SetInfo A, B;
     A.n = 1; A.total = lx; A.maxlen = A.minlen = lx;
     B.n = 1; B.total = ly; B.maxlen = B.minlen = ly;
     plan_common(L, c, p, A, &B);
     *ovf = L.take(sizeof(int32_t) * 8);
+    *edge = L.take(edge_bytes(1, std::max(lx, ly), std::min(lx, ly)));
 }
 
 size_t eap_distance_workspace(int64_t lx, int64_t ly, const eap_params* p) {
     if (check_params(p) != EAP_OK || lx < 1 || ly < 1) return 0;
     Layout L;
     Common c;
-    size_t ovf;
-    distance_layout(lx, ly, p, L, c, &ovf);
+    size_t ovf, edge;
+    distance_layout(lx, ly, p, L, c, &ovf, &edge);
     return L.off;
 }
 
@@ -436,8 +471,8 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
     if (std::isnan(cutoff) || cutoff < 0) return fail(EAP_EINVAL, "cutoff must be >= 0 or +inf");
     Layout L;
     Common c;
-    size_t ovf;
-    distance_layout(lx, ly, p, L, c, &ovf);
+    size_t ovf, edge;
+    distance_layout(lx, ly, p, L, c, &ovf, &edge);
     if (!ws || ws_bytes < L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, L.off);
     Plan pl;
     if ((st = make_plan(p, lx, ly, std::llabs(lx - ly), false, &pl)) != EAP_OK) return st;
@@ -455,14 +490,16 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
     a.band_half = pl.band_half;
     a.ovf_items = reinterpret_cast<int32_t*>(at(ws, ovf));
     a.ovf_count = &hdr_of(ws, c)->ovf_count[0];
-    return sweep(p, pl.band, pl.size, a, hdr_of(ws, c), 2, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s);
+    a.edge = edge_bytes(1, std::max(lx, ly), std::min(lx, ly)) ? at(ws, edge) : nullptr;
+    a.edge_stride = std::max(lx, ly) + 1;
+    return sweep(p, pl, pl.band, a, hdr_of(ws, c), 2, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s);
 }
 
 // ---------------------------------------------------------------------- NN
 struct NNLayout {
     Layout L;
     Common c;
-    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0;
+    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0;
     // FP32 screen
     size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
@@ -474,6 +511,7 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
     nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
+    nl.edge = nl.L.take(edge_bytes(Q.n * R.n, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)));
     if (screen) {
         nl.q32 = nl.L.take(sizeof(float) * (size_t)Q.total);
         nl.r32 = nl.L.take(sizeof(float) * (size_t)R.total);
@@ -519,7 +557,9 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     if (!ws || ws_bytes < nl.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, nl.L.off);
     Plan pl;
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
-    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, true, &pl)) != EAP_OK) return st;
+    const bool plain = o && (o->flags & 2);
+    const bool seeded = !plain && !(o && (o->flags & 1));
+    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
 
     hipStream_t s = (hipStream_t)stream;
     SweepArgs a = base_args(p);
@@ -539,16 +579,13 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     a.band_half = pl.band_half;
     a.ovf_items = ovf;
     a.ovf_count = &h->ovf_count[0];
-    const bool plain = o && (o->flags & 2);
-    const bool seeded = !plain && !(o && (o->flags & 1));
+    a.edge = edge_bytes(nq * nr, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)) ? at(ws, nl.edge)
+                                                                                             : nullptr;
+    a.edge_stride = std::max(Q.maxlen, R.maxlen) + 1;
     if (plain) {
-        // baseline: every pair by the full dynamic programme, full band for WDTW
+        // baseline: every pair by the full dynamic programme
         a.plain = 1;
-        if (pl.band) {
-            pl.size = pl.full;
-            a.band_half = 1 << 20;
-        }
-        if ((st = sweep(p, pl.band, pl.size, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK)
+        if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK)
             return st;
         HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
         return EAP_OK;
@@ -556,7 +593,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     // 1. upper bounds from the diagonal path, the best of them seeds each query
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, res, s));
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
-    const bool rerun = pl.band && pl.size != pl.full;
+    const bool rerun = pl.rerun;
     // FP32 screen: sweep single-precision copies under a widened cut-off first
     SeriesPtrs XQ = SQ, XR = SR;
     if (screen) {
@@ -584,7 +621,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     }
     if (seeded) {
         // 2. sweep the seed candidate of every query under its bound
-        if ((st = sweep(p, pl.band, pl.size, a, h, 0, &h->queues[0], seed_items, nq, XQ, XR, s, screen)) != EAP_OK)
+        if ((st = sweep(p, pl, pl.band, a, h, 0, &h->queues[0], seed_items, nq, XQ, XR, s, screen)) != EAP_OK)
             return st;
         if (rerun) {
             if ((st = rerun_overflow(p, pl, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], XQ, XR, s, screen)) !=
@@ -595,7 +632,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         a.skip_b = seed;
     }
     // 3. every other pair, under the per-query best-so-far (lowered as pairs complete)
-    if ((st = sweep(p, pl.band, pl.size, a, h, 2, &h->queues[2], nullptr, nq * nr, XQ, XR, s, screen)) != EAP_OK)
+    if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, XQ, XR, s, screen)) != EAP_OK)
         return st;
     if (rerun) {
         if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], XQ, XR, s, screen)) !=
@@ -614,7 +651,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         b.widen_rel = 0.0;
         b.skip_b = nullptr;
         b.npairs_dev = &h->ovf_count[2];
-        if ((st = sweep(p, pl.band, pl.size, b, h, 4, &h->queues[4], items, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+        if ((st = sweep(p, pl, pl.band, b, h, 4, &h->queues[4], items, nq * nr, SQ, SR, s)) != EAP_OK) return st;
         if (rerun) {
             if ((st = rerun_overflow(p, pl, b, h, 5, &h->ovf_count[0], ovf, nq * nr, &h->queues[5], SQ, SR, s)) !=
                 EAP_OK)
@@ -630,7 +667,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
 struct PWLayout {
     Layout L;
     Common c;
-    size_t cut = 0, ovf = 0;
+    size_t cut = 0, ovf = 0, edge = 0;
 };
 
 static void pw_layout(const SetInfo& S, const eap_params* p, PWLayout& pl) {
@@ -638,6 +675,7 @@ static void pw_layout(const SetInfo& S, const eap_params* p, PWLayout& pl) {
     const int64_t np = S.n * (S.n - 1) / 2;
     pl.cut = pl.L.take(sizeof(double) * (size_t)std::max<int64_t>(np, 1));
     pl.ovf = pl.L.take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1));
+    pl.edge = pl.L.take(edge_bytes(std::max<int64_t>(np, 1), S.maxlen, S.maxlen));
 }
 
 size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params* p) {
@@ -675,13 +713,102 @@ eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const 
     a.band_half = pl.band_half;
     a.ovf_items = reinterpret_cast<int32_t*>(at(ws, pw.ovf));
     a.ovf_count = &h->ovf_count[0];
+    a.edge = edge_bytes(np, S.maxlen, S.maxlen) ? at(ws, pw.edge) : nullptr;
+    a.edge_stride = S.maxlen + 1;
     if (mode == 0) {
         double* cut = reinterpret_cast<double*>(at(ws, pw.cut));
         HIPCHK(launch_ub_condensed(effective_kind(p), a, s, SA.off, n, cut, hs));
         a.pcut = cut;
     }
     if (mode == 1) a.plain = 1;
-    return sweep(p, pl.band, pl.size, a, h, 2, &h->queues[0], nullptr, np, SA, SB, hs);
+    return sweep(p, pl, pl.band, a, h, 2, &h->queues[0], nullptr, np, SA, SB, hs);
+}
+
+eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,
+                        int64_t nr, const eap_params* p, const eap_nn_opts* o, void* ws, size_t ws_bytes,
+                        int64_t* out_idx, double* out_dist, void* stream, eap_tune_rec* recs, int32_t cap,
+                        int32_t* n) {
+    eap_status st;
+    if (!n || (cap > 0 && !recs)) return fail(EAP_EINVAL, "bad tuning output");
+    *n = 0;
+    if ((st = check_params(p)) != EAP_OK) return st;
+    if (!q || !r || !out_idx || !out_dist) return fail(EAP_EINVAL, "NULL series or output");
+    SetInfo Q, R;
+    if ((st = check_offsets(q_off, nq, "queries", &Q)) != EAP_OK) return st;
+    if ((st = check_offsets(r_off, nr, "candidates", &R)) != EAP_OK) return st;
+    const bool fp32 = o && o->precision == 1;
+    const bool plain = o && (o->flags & 2);
+    const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
+    Plan pl;
+    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
+    if (pl.band) return EAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const RowsShape all[9] = {{16, 8}, {16, 16}, {32, 8}, {32, 16}, {64, 8}, {64, 16}, {16, 32}, {32, 32}, {64, 32}};
+    std::vector<RowsShape> shapes;
+    for (const RowsShape& x : all)
+        if (rows_shape_ok(effective_kind(p), x, fp32)) shapes.push_back(x);
+    std::vector<int64_t> idx0((size_t)nq), idx((size_t)nq);
+    std::vector<double> d0((size_t)nq), d((size_t)nq);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 0.0f;
+    int best = -1, k = 0;
+    st = EAP_OK;
+    for (int v = 0; v < (int)shapes.size() && st == EAP_OK; ++v) {
+        g_force[fp32] = shapes[v];
+        st = eap_nn1(q, q_off, nq, r, r_off, nr, nullptr, p, o, ws, ws_bytes, out_idx, out_dist, nullptr, stream);
+        if (st != EAP_OK) break;
+        if (hipMemcpyAsync(idx.data(), out_idx, sizeof(int64_t) * (size_t)nq, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(d.data(), out_dist, sizeof(double) * (size_t)nq, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = fail(EAP_EDEVICE, "tuning: copying results back failed");
+            break;
+        }
+        if (v == 0) {
+            idx0 = idx;
+            d0 = d;
+        } else if (idx != idx0 || std::memcmp(d.data(), d0.data(), sizeof(double) * (size_t)nq) != 0) {
+            st = fail(EAP_EDEVICE, "tuning: row-sweep shape %dx%d disagrees with %dx%d", shapes[v].g, shapes[v].c,
+                      shapes[0].g, shapes[0].c);
+            break;
+        }
+        float ms = 0.0f;
+        if (hipEventRecord(e0, s) != hipSuccess) st = fail(EAP_EDEVICE, "tuning: event record failed");
+        for (int rep = 0; rep < 2 && st == EAP_OK; ++rep)
+            st = eap_nn1(q, q_off, nq, r, r_off, nr, nullptr, p, o, ws, ws_bytes, out_idx, out_dist, nullptr, stream);
+        if (st != EAP_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(EAP_EDEVICE, "tuning: event timing failed");
+            break;
+        }
+        ms *= 0.5f;
+        if (best < 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+        if (k < cap) recs[k] = eap_tune_rec{shapes[v].g, shapes[v].c, ms, 0};
+        ++k;
+    }
+    g_force[fp32] = RowsShape{0, 0};
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != EAP_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[(effective_kind(p) * 2 + (fp32 ? 1 : 0)) * 8 + len_bucket(std::min(Q.maxlen, R.maxlen))] =
+            shapes[best];
+    }
+    if (best < cap) recs[best].chosen = 1;
+    *n = k < cap ? k : cap;
+    return EAP_OK;
+}
+
+eap_status eap_tune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    return EAP_OK;
 }
 
 eap_status eap_wdtw_weights(double g, int64_t L, double* out) {

@@ -51,6 +51,19 @@ __device__ __forceinline__ double round_up_next(double t) {
     return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, t) + 1ull);
 }
 
+// A load that does not hit the CU's L1 (relaxed atomic at agent scope), for
+// values this wave wrote earlier to a location it had read before.
+__device__ __forceinline__ double load_nc(const double* p) {
+    unsigned long long b = __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<double*>(p)),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ float load_nc(const float* p) {
+    unsigned b = __hip_atomic_load(reinterpret_cast<unsigned*>(const_cast<float*>(p)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float, b);
+}
+
 // One set of series: concatenated values, int64 offsets (n+1), and for ERP the
 // running border sums B[off+i-1] = sum_{m<=i} |x_m - gap| (same layout).
 template <typename T> struct Series {

@@ -52,6 +52,16 @@ struct SweepArgs {
     // FP32 screen: the cut-off of query a is best[a] * (1 + widen_rel) + widen_abs[a]
     const double* widen_abs;
     double widen_rel;
+    // row sweep: per-group edge buffers of edge_stride values (T), for pairs
+    // whose shorter series is wider than one strip; NULL = no strips
+    void* edge;
+    int64_t edge_stride;
+};
+
+// Shape of the row sweep: G lanes per pair (pairs per wave = 64 / G), C
+// columns per lane, strips of W = G * C columns.
+struct RowsShape {
+    int g, c;
 };
 
 struct SeriesPtrs {
@@ -60,12 +70,13 @@ struct SeriesPtrs {
     const void* border;
 };
 
-// Row sweep (kernel A): full rows of W = G*C columns per pair.  Returns the
-// launch error.  `width` selects W (128, 256, 512, 1024); the shorter series
-// of every pair must have length <= width.
-hipError_t launch_rows(int kind, bool fp32, int width, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
+// Row sweep (kernel A): strips of W = G*C columns per pair (DTW, WDTW, ERP
+// without a window, MSM, TWE).  Returns the launch error.  Pairs wider than
+// one strip need a.edge with room for grid * 256 / G groups.
+hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
                        hipStream_t s);
 int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a);
+bool rows_shape_ok(int kind, RowsShape sh, bool fp32);
 
 // Band sweep (kernel B): anti-diagonal sweep of a band of 2*G*C diagonals.
 hipError_t launch_band(int kind, bool fp32, int diags, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,

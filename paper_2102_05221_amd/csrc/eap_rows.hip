@@ -1,28 +1,41 @@
 // Kernel A: row sweep of the cost matrix (eq. Common), one pair per group of
 // G lanes, with the early abandoning and cut-off of EAPruned (Alg. 5).
 //
-// Layout.  The shorter series of a pair goes on the columns (Alg. 3/5).  Lane
-// k of a group owns columns c0..c0+C-1 with c0 = 1 + k*C and keeps, in
+// Layout.  The shorter series of a pair goes on the columns (Alg. 3/5).  The
+// columns are cut into strips of W = G*C; the group sweeps the strips of a
+// pair one after the other.  In a strip, lane k owns columns c0..c0+C-1 with
+// c0 = cb + 1 + k*C (cb = first column of the strip minus one) and keeps, in
 // registers, its C cells of the last row it computed and the C column values
 // t_j.  Rows are skewed across the group: at step s lane k computes row
-// s - k, receiving the cell left of its strip, M(i, c0-1), and the row value
-// s_i from lane k-1 through one DPP wave shift (lane 0 reads the left border
-// and s_i from memory).  The previous left input is the diagonal of the
-// strip's first cell.  Every dependency of a cell is thus in a register of
-// its own lane or was computed by the left neighbour one step earlier.
+// s - k, receiving the cell left of its columns, M(i, c0-1), and the row value
+// s_i from lane k-1 through one DPP wave shift.  Lane 0 reads the left input
+// from the left border (first strip) or from the edge buffer, where the last
+// lane of the previous strip stored M(i, cb), one value per row.  The previous
+// left input is the diagonal of a lane's first cell.  Every dependency of a
+// cell is thus in a register of its own lane or was computed by the left
+// neighbour one step earlier.
 //
 // Abandoning.  Define sigma(i, k) = i + k, the step at which lane k computes
 // row i.  Along any warping path sigma never decreases and grows by at most 2
-// per step (the diagonal move across a strip boundary), so the cells of two
-// consecutive steps s-1, s form a cut between M(0,0) and M(L_li, L_co).  When
-// none of them is <= cut-off, no path to the end stays under the cut-off and
-// the pair is abandoned - the same criterion as Alg. 5 ("no cell of a row
-// stays under the cut-off"), applied to the staircase the group sweeps.
-// Groups test it every K steps; cells are exact whenever they are <= cut-off,
-// so the result is D when D <= cut-off and +inf otherwise.
+// per step (the diagonal move across a lane boundary), so the cells of two
+// consecutive steps s-1, s form a cut between the strip's entry and its exit.
+// When none of them is <= cut-off and no left input still to come is either,
+// no path through the strip stays under the cut-off: the strip ends (its live
+// edge rows are recorded for the next strip) or, in the last strip, the pair
+// is abandoned - the criterion of Alg. 5 ("no cell of a row stays under the
+// cut-off") applied to the staircase the group sweeps.  A strip also starts
+// at the first row whose left input is <= cut-off (the cells above it only
+// have inputs > cut-off), so each strip sweeps only the rows a live path can
+// cross: column pruning at strip granularity.  Groups decide every K steps;
+// cells are exact whenever they are <= cut-off, so the result is D when
+// D <= cut-off and +inf otherwise.
 //
 // Columns beyond L_co in the last strip hold t = +inf, which makes their
 // cells +inf for every distance, so they never count as alive.
+//
+// Per-diagonal terms (TWE's nu * 2|i-j|, WDTW's weight of |i-j|) come from an
+// LDS table; each lane reads the C + K - 1 entries its next K steps need into
+// registers at the start of every block.
 #include "eap_pairs.h"
 
 namespace eap {
@@ -30,10 +43,17 @@ namespace eap {
 template <int KIND, typename T, int G, int C>
 __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Series<T> SB) {
     constexpr int K = 8;  // steps between group decisions
+    constexpr int W = G * C;
+    constexpr bool DTAB = (KIND == TWE || KIND == WDTW);
+    constexpr int NW = DTAB ? C + K - 1 : 1;
     extern __shared__ unsigned char lds_raw[];
     T* tab = reinterpret_cast<T*>(lds_raw);
-    if constexpr (KIND == TWE) {
-        for (int m = threadIdx.x; m < A.tab_len; m += blockDim.x) tab[m] = (T)A.tab[m];
+    int tab_len = 1, tab_off = 0;
+    if constexpr (DTAB) {
+        const double* src = (KIND == TWE) ? A.tab : A.gtab;
+        tab_len = (KIND == TWE) ? A.tab_len : A.gtab_len;
+        tab_off = (KIND == TWE) ? A.tab_off : A.gtab_off;
+        for (int m = threadIdx.x; m < tab_len; m += blockDim.x) tab[m] = (T)src[m];
         __syncthreads();
     }
     const T INF = inf_v<T>();
@@ -42,23 +62,123 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane - k));
     const bool nn = is_nn_mode(A.mode) && !A.plain;
     const T gap = (T)A.gap, cc = (T)A.c, nu = (T)A.nu, lam = (T)A.lam;
+    // this group's edge buffer: M(i, cb) of the previous strip, i = 0..L_li
+    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    T* const eb = A.edge ? reinterpret_cast<T*>(A.edge) + gid * A.edge_stride : nullptr;
 
     bool have = false, done = false;
     int32_t qa = 0;
     int64_t out = 0;
-    const T* li = nullptr;
+    // Every lane loads its row inputs at every step, also in groups without a
+    // pair: until a group fetches one, li and bp point at a valid one-value
+    // range (the first value of set A), so those loads stay in bounds.
+    const T* li = SA.v;
     const T* lib = nullptr;
-    int Lli = 0, Lco = 0, kend = 0, uend = 0, row = 0;
-    const int c0 = 1 + k * C;
+    const T* co = nullptr;
+    const T* cob = nullptr;
+    int Lli = 1, Lco = 0, kend = 0, uend = 0, row = 0;
+    int nstrip = 1, si = 0, cb = 0, c0 = 1, r_start = 1;
+    int e_lo = 0, e_hi = -1;       // rows of the incoming edge that can be <= cut-off
+    int rec_lo = 0, rec_hi = -1;   // the same for the edge this strip writes (last lane)
+    bool last = true, full_top = true;
     T cut = 0;
     T val[C], vb[C], tv[C], aux[C];
     T adv[KIND == TWE ? C : 1];   // TWE: |s_{i-1} - t_j| of the previous row
-    T dg = 0, lout = 0, sout = 0, s_next = 0, b_next = 0, sp = 0, tpm = 0, brd0 = 0, s0 = 0;
+    T dwin[NW];                   // per-diagonal terms of this block
+    T dg = 0, lout = 0, sout = 0, sp = 0, tpm = 0, brd0 = 0, s0 = 0;
+    // lane 0's inputs for the next two rows (row + 1, row + 2): s_i and M(i, cb)
+    T s_n1 = 0, s_n2 = 0, b_n1 = 0, b_n2 = 0;
+    const T* bp = SA.v - 1;  // left inputs: bp[i] = M(i, cb) for e_lo <= i <= e_hi
     unsigned long long ncells = 0, npairs = 0;
 #pragma unroll
     for (int u = 0; u < C; ++u) val[u] = vb[u] = tv[u] = aux[u] = 0;
 #pragma unroll
     for (int u = 0; u < (KIND == TWE ? C : 1); ++u) adv[u] = 0;
+#pragma unroll
+    for (int m = 0; m < NW; ++m) dwin[m] = 0;
+
+    // Row value s_r and left input M(r, cb) for lane 0: the left border (first
+    // strip) or the previous strip's edge, +inf outside its live rows.  Every
+    // lane loads (rows clamped into 1..L_li, so every address is in bounds) and
+    // only lane 0's values are used: no branch in the step.
+    auto s_at = [&](int r) -> T { return li[(r < 1 ? 1 : (r > Lli ? Lli : r)) - 1]; };
+    auto b_at = [&](int r) -> T {
+        const T v = load_nc(bp + (r < 1 ? 1 : (r > Lli ? Lli : r)));
+        return (r >= e_lo && r <= e_hi) ? v : INF;
+    };
+
+    // Set up the strip si of the current pair.
+    auto start_strip = [&]() {
+        cb = si * W;
+        if (si == 0) {
+            // the left border M(i, 0): computed for ERP, +inf otherwise
+            e_lo = 1;
+            e_hi = (KIND == ERP) ? Lli : 0;
+            bp = (KIND == ERP) ? lib - 1 : li - 1;
+        } else {
+            bp = eb;
+        }
+        c0 = cb + 1 + k * C;
+        last = (si == nstrip - 1);
+        // the first row: 1, unless the strip's top border and the incoming edge
+        // are > cut-off down to some row (only for strips after the first)
+        r_start = 1;
+        if (si > 0) {
+            bool top_live = (e_lo <= 1);
+            if constexpr (KIND == ERP) top_live = top_live || (cob[cb] <= cut);   // M(0, cb+1)
+            if (!top_live) r_start = e_lo;
+        }
+        full_top = (r_start == 1);
+        // column values t_j of the strip (+inf beyond L_co) and t_{c0-1} (t_0 = 0)
+#pragma unroll
+        for (int u = 0; u < C; ++u) tv[u] = (c0 + u <= Lco) ? co[c0 + u - 1] : INF;
+        tpm = (c0 >= 2 && c0 - 1 <= Lco) ? co[c0 - 2] : (T)0;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            const T tprev = (u == 0) ? tpm : tv[u - 1];
+            const bool ghost = c0 + u > Lco;
+            if constexpr (KIND == ERP) aux[u] = ghost ? INF : vabs(tv[u] - gap);
+            if constexpr (KIND == MSM) aux[u] = ghost ? INF : tv[u] - tprev;
+            if constexpr (KIND == TWE) aux[u] = ghost ? INF : (vabs(tv[u] - tprev) + nu) + lam;
+            if constexpr (KIND == TWE) adv[u] = vabs((T)0 - tv[u]);   // row 0: s_0 = 0
+            // the row above the first: the top border M(0, j) (computed for ERP,
+            // +inf otherwise), or +inf when the strip starts lower down
+            if constexpr (KIND == ERP) val[u] = (ghost || !full_top) ? INF : cob[c0 + u - 1];
+            else val[u] = INF;
+        }
+        // M(r_start - 1, c0 - 1): the diagonal of the lane's first cell
+        T topl = INF;
+        if (full_top) {
+            if (c0 == 1) topl = 0;
+            else if constexpr (KIND == ERP) topl = (c0 - 1 <= Lco) ? cob[c0 - 2] : INF;
+        }
+        dg = topl;
+        // what a lane is fed until it reaches its first row (see the step below):
+        // ERP's border M(0, c0-1), which makes the lane recompute its own top
+        // border exactly, or +inf, which keeps +inf borders at +inf
+        brd0 = (KIND == ERP) ? topl : INF;
+        s0 = (KIND == ERP) ? gap : (T)0;
+        // the last strip starts late enough that the last cell, (L_li, L_co) in
+        // lane kend, is computed by the last step of a block: the result is then
+        // read once, at the block end, from the buffer that step wrote
+        int pad = 0;
+        if (last) {
+            const int lc = Lco - 1 - cb;
+            kend = lc / C;
+            uend = lc - kend * C;
+            pad = (K - ((Lli - r_start + 1) + kend) % K) % K;
+        }
+        row = r_start - 1 - k - pad;
+        lout = val[C - 1];
+        sout = 0;
+        sp = 0;
+        rec_lo = 1 << 30;
+        rec_hi = -1;
+        s_n1 = s_at(row + 1);
+        s_n2 = s_at(row + 2);
+        b_n1 = b_at(row + 1);
+        b_n2 = b_at(row + 2);
+    };
 
     for (;;) {
         if (!have && !done) {
@@ -76,8 +196,6 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 if (it.skip) continue;
                 const int64_t oa = SA.off[it.a], ob = SB.off[it.b];
                 const int La = (int)(SA.off[it.a + 1] - oa), Lb = (int)(SB.off[it.b + 1] - ob);
-                const T* co;
-                const T* cob;
                 if (La >= Lb) {
                     li = SA.v + oa; lib = SA.border ? SA.border + oa : nullptr; Lli = La;
                     co = SB.v + ob; cob = SB.border ? SB.border + ob : nullptr; Lco = Lb;
@@ -87,95 +205,69 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 }
                 qa = it.a;
                 out = it.out;
-                if (Lco > G * C) {   // wider than this kernel's row: refuse rather than sweep part of it
+                nstrip = (Lco + W - 1) / W;
+                if (nstrip > 1 && (!eb || Lli >= A.edge_stride)) {
+                    // no room for the strip edges: refuse rather than sweep part of the pair
                     if (k == 0) A.res[out] = __builtin_nan("");
                     continue;
                 }
                 if (nn) cut = nn_cut<T>(A, it.a);
                 else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
-                kend = (Lco - 1) / C;
-                uend = (Lco - 1) - kend * C;
-                // column values t_j of the strip (+inf beyond L_co) and t_{c0-1} (t_0 = 0)
-#pragma unroll
-                for (int u = 0; u < C; ++u) tv[u] = (c0 + u <= Lco) ? co[c0 + u - 1] : INF;
-                tpm = (c0 >= 2 && c0 - 1 <= Lco) ? co[c0 - 2] : (T)0;
-#pragma unroll
-                for (int u = 0; u < C; ++u) {
-                    const T tprev = (u == 0) ? tpm : tv[u - 1];
-                    const bool ghost = c0 + u > Lco;
-                    if constexpr (KIND == ERP) aux[u] = ghost ? INF : vabs(tv[u] - gap);
-                    if constexpr (KIND == MSM) aux[u] = ghost ? INF : tv[u] - tprev;
-                    if constexpr (KIND == TWE) aux[u] = ghost ? INF : (vabs(tv[u] - tprev) + nu) + lam;
-                    if constexpr (KIND == TWE) adv[u] = vabs((T)0 - tv[u]);   // row 0: s_0 = 0
-                    // top border M(0, j): computed for ERP, +inf otherwise
-                    if constexpr (KIND == ERP) val[u] = ghost ? INF : cob[c0 + u - 1];
-                    else val[u] = INF;
-                }
-                // diagonal of the first cell of row 1: M(0, c0-1)
-                if (k == 0) dg = 0;
-                else if constexpr (KIND == ERP) dg = (c0 - 1 <= Lco) ? cob[c0 - 2] : INF;
-                else dg = INF;
-                // what a lane is fed until it reaches row 1 (see the step below):
-                // ERP's border M(0, c0-1), which makes the lane recompute its own
-                // top border exactly, or +inf, which keeps +inf borders at +inf
-                if constexpr (KIND == ERP) brd0 = dg;
-                else brd0 = INF;
-                s0 = (KIND == ERP) ? gap : (T)0;
-                // start late enough that the last cell, (L_li, L_co) in lane kend,
-                // is computed by the last step of a block: the result is then read
-                // once, at the block end, from the buffer that step wrote
-                row = -k - (K - (Lli + kend) % K) % K;
-                lout = val[C - 1];
-                sout = 0;
-                sp = 0;
-                if (k == 0) {
-                    s_next = li[0];
-                    if constexpr (KIND == ERP) b_next = lib[0];
-                    else b_next = INF;
-                }
+                si = 0;
+                start_strip();
                 have = true;
                 break;
             }
         }
         if (__all(done)) break;
 
+        if constexpr (DTAB) {
+            // the per-diagonal terms of the next K steps: d = j - i runs over
+            // c0 - row - K .. c0 + C - 2 - row (clamped into the table; entries
+            // outside the matrix only reach cells nobody reads)
+            const int base = c0 - row - K;
+#pragma unroll
+            for (int m = 0; m < NW; ++m) {
+                int d = base + m, x;
+                if constexpr (KIND == TWE) x = d + tab_off;
+                else x = 2 * (d < 0 ? -d : d) - Lli + tab_off;
+                x = x < 0 ? 0 : (x >= tab_len ? tab_len - 1 : x);
+                dwin[m] = tab[x];
+            }
+        }
+
         bool live_any = false;
-        // One step: every lane computes its strip for its current row, reading
+        // One step: every lane computes its columns for its current row, reading
         // the previous row from `src` and writing `dst` (the two buffers
-        // alternate, so no value is copied).  Lanes that have not reached row 1
-        // are fed their own left-border value and s = gap (ERP) or +inf inputs,
-        // which reproduces their top border bit for bit; lanes past the last
-        // row compute values nobody reads.
-        auto step = [&](T (&src)[C], T (&dst)[C], bool check) {
+        // alternate, so no value is copied).  Lanes that have not reached their
+        // first row are fed their own left-border value and s = gap (ERP) or
+        // +inf inputs, which reproduces their top border bit for bit; lanes past
+        // the last row compute values nobody reads.
+        auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t) {
             T lin = shr1(lout);
             T sin = shr1(sout);
             row += 1;
             if (k == 0) {
-                lin = b_next;   // M(row, 0)
-                sin = s_next;   // s_row
+                lin = b_n1;   // M(row, cb)
+                sin = s_n1;   // s_row
             }
-            const bool ns = row <= 0;   // not started: keep the top border
+            s_n1 = s_n2;
+            b_n1 = b_n2;
+            s_n2 = s_at(row + 2);
+            b_n2 = b_at(row + 2);
+            const bool ns = row < r_start;   // not started: keep the top border
             if (ns) {
                 lin = brd0;
                 sin = s0;
             }
-            const bool act = have && row >= 1 && row <= Lli;
-            if (k == 0 && act && row < Lli) {
-                s_next = li[row];
-                if constexpr (KIND == ERP) b_next = lib[row];
-            }
+            const bool act = have && !ns && row <= Lli;
             T diag = ns ? brd0 : dg;
-            if (!ns) dg = lin;          // M(0, c0-1) stays the diagonal of row 1
+            if (!ns) dg = lin;          // M(r_start-1, c0-1) stays the diagonal of the first row
             T left = lin;
             T sg = 0, ds = 0, gA = 0, carry = 0;
-            const T* ntp = nullptr;
             if constexpr (KIND == ERP) sg = vabs(sin - gap);
             if constexpr (KIND == MSM) ds = sin - sp;
-            if constexpr (KIND == TWE) {
-                gA = (vabs(sin - sp) + nu) + lam;
-                const int rr = row < 1 ? 1 : (row > Lli ? Lli : row);
-                ntp = tab + (c0 - rr + A.tab_off);
-            }
+            if constexpr (KIND == TWE) gA = (vabs(sin - sp) + nu) + lam;
 #pragma unroll
             for (int u = 0; u < C; ++u) {
                 const T top = src[u];
@@ -183,6 +275,8 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 T v;
                 if constexpr (KIND == DTW || KIND == CDTW) {
                     v = (d * d) + vmin(vmin(diag, top), left);
+                } else if constexpr (KIND == WDTW) {
+                    v = (dwin[u - t - 1 + K] * (d * d)) + vmin(vmin(diag, top), left);
                 } else if constexpr (KIND == ERP) {
                     v = vmin(vmin(diag + vabs(d), top + sg), left + aux[u]);
                 } else if constexpr (KIND == MSM) {
@@ -207,7 +301,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                     const T adp = (u == 0) ? vabs(sp - tpm) : adv[u - 1];
                     if (u > 0) adv[u - 1] = carry;
                     carry = ad;
-                    const T match = (ad + adp) + ntp[u];
+                    const T match = (ad + adp) + dwin[u - t - 1 + K];
                     v = vmin(vmin(diag + match, top + gA), left + aux[u]);
                 }
                 dst[u] = v;
@@ -215,34 +309,60 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
                 left = v;
             }
             if constexpr (KIND == TWE) adv[C - 1] = carry;
-            if (row >= 1) sp = sin;
-            if (act) ncells += C;
+            if (!ns) sp = sin;
+            {
+                // this strip's right edge, M(row, cb + W), for the next strip
+                const T e = dst[C - 1];
+                const bool st = !last && k == G - 1 && act;
+                const bool el = st && (e <= cut);
+                rec_lo = (el && rec_lo > row) ? row : rec_lo;
+                rec_hi = el ? row : rec_hi;
+                if (st) eb[row] = e;
+            }
             lout = dst[C - 1];
             sout = sin;
             if (check) {
                 bool lv;
                 if (!have || row > Lli) lv = false;
-                else if (row < 1) lv = (KIND == ERP);   // top border row: +inf except for ERP
+                else if (ns) lv = (KIND == ERP) && full_top;   // the computed top border
                 else {
                     T m = lin;
 #pragma unroll
                     for (int u = 0; u < C; ++u) m = vmin(m, dst[u]);
                     lv = (m <= cut);
                 }
+                // left inputs still to come from the previous strip's live rows
+                if (k == 0 && have && si > 0 && row < e_hi) lv = true;
                 live_any = live_any || lv;
             }
         };
+        // the staircase of the block's last two steps is the cut tested below
 #pragma unroll
         for (int t = 0; t < K; t += 2) {
-            step(val, vb, t + 1 >= K - 2);
-            step(vb, val, t + 2 >= K - 2);
+            step(val, vb, t >= K - 2, t);
+            step(vb, val, t + 1 >= K - 2, t + 1);
+        }
+        if (have) {
+            // rows of this block in r_start..L_li: the cells counted as executed
+            const int lo = (row - K + 1 > r_start) ? row - K + 1 : r_start;
+            const int hi = row < Lli ? row : Lli;
+            if (hi >= lo) ncells += (unsigned long long)(C * (hi - lo + 1));
         }
 
-        // group decisions: finished, abandoned, or refresh the cut-off
-        const bool fin_l = have && k == kend && row == Lli;
+        // group decisions: finished, strip done, abandoned, or refresh the cut-off
+        const bool fin_l = have && last && k == kend && row == Lli;
+        // never true (the last strip is aligned to end on a block end); a guard
+        // that ends the pair with NaN rather than sweeping on past its last row
+        const bool lost_l = have && last && k == kend && row > Lli;
+        const bool send_l = have && !last && k == G - 1 && row >= Lli;
         const unsigned long long fm = ballot(fin_l);
+        const unsigned long long sm = ballot(send_l);
         const unsigned long long lm = ballot(live_any);
+        const bool lost = (ballot(lost_l) & gmask) != 0;
+        const int nlo = __shfl(rec_lo, lane - k + G - 1);
+        const int nhi = __shfl(rec_hi, lane - k + G - 1);
         const bool fin = (fm & gmask) != 0;
+        const bool send = (sm & gmask) != 0;
         const bool alive = (lm & gmask) != 0;
         if (fin_l) {
             T r = val[0];
@@ -253,12 +373,36 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
             A.res[out] = D;
             if (nn && D < __builtin_huge_val()) atomicMin(&A.best[qa], dbits(D));
         }
-        if (have && !fin && !alive && k == 0) A.res[out] = __builtin_huge_val();
-        if (have && (fin || !alive)) {
+        bool next_strip = false, drop = false;
+        if (have && lost) {
+            if (k == 0) A.res[out] = __builtin_nan("");
+            have = false;
+            if (k == 0) ++npairs;
+        }
+        if (have) {
+            if (fin) {
+                drop = true;
+            } else if (!last && (send || !alive)) {
+                if (nhi < nlo) drop = true;   // no edge row <= cut-off: no path goes on
+                else next_strip = true;
+            } else if (!alive) {
+                drop = true;
+            }
+        }
+        if (drop) {
+            if (!fin && k == 0) A.res[out] = __builtin_huge_val();
             have = false;
             if (k == 0) ++npairs;
         } else if (have && nn) {
             cut = vmin(cut, nn_cut<T>(A, qa));
+        }
+        // the edge stores of this wave complete before the next strip reads them
+        if (__any(next_strip)) __builtin_amdgcn_s_waitcnt(0);
+        if (next_strip) {
+            e_lo = nlo;
+            e_hi = nhi;
+            si += 1;
+            start_strip();
         }
     }
     wave_add_u64(&A.counters[0], ncells);
@@ -271,41 +415,60 @@ template <int KIND, typename T, int G, int C>
 static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
     Series<T> A{(const T*)SA.v, SA.off, (const T*)SA.border};
     Series<T> B{(const T*)SB.v, SB.off, (const T*)SB.border};
-    size_t lds = (KIND == TWE) ? sizeof(T) * (size_t)a.tab_len : 0;
-    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C>), dim3(grid), dim3(256), lds, s, a, A, B);
+    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C>), dim3(grid), dim3(256), rows_lds_bytes(KIND, sizeof(T) == 4, a),
+                       s, a, A, B);
     return hipGetLastError();
 }
 
 template <int KIND, typename T>
-static hipError_t go_w(int width, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
-    switch (width) {
-    case 128: return go<KIND, T, 16, 8>(a, SA, SB, grid, s);
-    case 256: return go<KIND, T, 16, 16>(a, SA, SB, grid, s);
-    case 512: return go<KIND, T, 32, 16>(a, SA, SB, grid, s);
-    case 1024: return go<KIND, T, 64, 16>(a, SA, SB, grid, s);
+static hipError_t go_w(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
+    switch (sh.g * 1000 + sh.c) {
+    case 16008: return go<KIND, T, 16, 8>(a, SA, SB, grid, s);
+    case 16016: return go<KIND, T, 16, 16>(a, SA, SB, grid, s);
+    case 32008: return go<KIND, T, 32, 8>(a, SA, SB, grid, s);
+    case 32016: return go<KIND, T, 32, 16>(a, SA, SB, grid, s);
+    case 64008: return go<KIND, T, 64, 8>(a, SA, SB, grid, s);
+    case 64016: return go<KIND, T, 64, 16>(a, SA, SB, grid, s);
+    }
+    if constexpr (sizeof(T) == 4 && (KIND == DTW || KIND == WDTW)) {   // 32 columns per lane: registers
+        switch (sh.g * 1000 + sh.c) {
+        case 16032: return go<KIND, T, 16, 32>(a, SA, SB, grid, s);
+        case 32032: return go<KIND, T, 32, 32>(a, SA, SB, grid, s);
+        case 64032: return go<KIND, T, 64, 32>(a, SA, SB, grid, s);
+        }
     }
     return hipErrorInvalidValue;
 }
 
 int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a) {
-    return kind == TWE ? (int)((fp32 ? 4 : 8) * (size_t)a.tab_len) : 0;
+    const size_t e = fp32 ? 4 : 8;
+    if (kind == TWE) return (int)(e * (size_t)a.tab_len);
+    if (kind == WDTW) return (int)(e * (size_t)a.gtab_len);
+    return 0;
 }
 
-hipError_t launch_rows(int kind, bool fp32, int width, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
+bool rows_shape_ok(int kind, RowsShape sh, bool fp32) {
+    const bool c32 = fp32 && (kind == DTW || kind == CDTW || kind == WDTW);
+    return (sh.g == 16 || sh.g == 32 || sh.g == 64) && (sh.c == 8 || sh.c == 16 || (c32 && sh.c == 32));
+}
+
+hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
                        hipStream_t s) {
     if (fp32) {
         switch (kind) {
-        case DTW: case CDTW: return go_w<DTW, float>(width, a, A, B, grid, s);
-        case ERP: return go_w<ERP, float>(width, a, A, B, grid, s);
-        case MSM: return go_w<MSM, float>(width, a, A, B, grid, s);
-        case TWE: return go_w<TWE, float>(width, a, A, B, grid, s);
+        case DTW: case CDTW: return go_w<DTW, float>(sh, a, A, B, grid, s);
+        case WDTW: return go_w<WDTW, float>(sh, a, A, B, grid, s);
+        case ERP: return go_w<ERP, float>(sh, a, A, B, grid, s);
+        case MSM: return go_w<MSM, float>(sh, a, A, B, grid, s);
+        case TWE: return go_w<TWE, float>(sh, a, A, B, grid, s);
         }
     } else {
         switch (kind) {
-        case DTW: case CDTW: return go_w<DTW, double>(width, a, A, B, grid, s);
-        case ERP: return go_w<ERP, double>(width, a, A, B, grid, s);
-        case MSM: return go_w<MSM, double>(width, a, A, B, grid, s);
-        case TWE: return go_w<TWE, double>(width, a, A, B, grid, s);
+        case DTW: case CDTW: return go_w<DTW, double>(sh, a, A, B, grid, s);
+        case WDTW: return go_w<WDTW, double>(sh, a, A, B, grid, s);
+        case ERP: return go_w<ERP, double>(sh, a, A, B, grid, s);
+        case MSM: return go_w<MSM, double>(sh, a, A, B, grid, s);
+        case TWE: return go_w<TWE, double>(sh, a, A, B, grid, s);
         }
     }
     return hipErrorInvalidValue;

@@ -85,6 +85,76 @@ def test_distance_parity_with_cutoffs(torch_dev, orc, p):
     assert nbits == ntot, f"{ntot - nbits} of {ntot} results not bit-identical"
 
 
+@pytest.mark.parametrize("p", ALL, ids=pid)
+def test_distance_parity_long_series(torch_dev, orc, p):
+    """Series up to 2048: wider than one strip of the row sweep, so the pair is
+    swept strip by strip through the edge buffer (and the band sweep takes the
+    wide windows)."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(300 + synth.SIX.index(p["kind"]))
+    nbits = ntot = 0
+    for (lx, ly) in [(1500, 2048), (2048, 2048), (1100, 300), (2048, 1), (1025, 1030), (700, 1900)]:
+        x = synth.znorm(np.cumsum(rng.normal(size=lx))) if lx > 1 else rng.normal(size=1)
+        y = synth.znorm(np.cumsum(rng.normal(size=ly))) if ly > 1 else rng.normal(size=1)
+        d = orc.dp(p, x, y)
+        cuts = [INF]
+        if d < INF:
+            cuts += [d, float(np.nextafter(d, -INF)), 0.5 * d, 1.02 * d]
+        xd, yd = to_dev(torch, dev, x), to_dev(torch, dev, y)
+        for c in cuts:
+            log(f"distance long {pid(p)} lx={lx} ly={ly} cut={c}")
+            g = float(eap.distance(xd, yd, p, c).item())
+            want = d if d <= c else INF
+            assert close(g, want), (lx, ly, c, g, want)
+            ntot += 1
+            nbits += (g == want)
+    assert nbits == ntot, f"{ntot - nbits} of {ntot} results not bit-identical"
+
+
+@pytest.mark.parametrize("kind", synth.SIX)
+def test_nn1_long_uneven_lengths(torch_dev, orc, kind):
+    """Workload-4 shape (class templates, lengths uniform in [64, 2048]),
+    subsampled; FP64 and FP32 screen + FP64 recheck."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(4, n_ref=30, n_query=6)
+    p = wl["params"][kind]
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    oi, od, _ = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "dp")
+    for precision in (0, 1):
+        log(f"nn1 long uneven {kind} precision={precision}")
+        gi, gd, _ = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, precision=precision)
+        torch.cuda.synchronize()
+        assert np.array_equal(gi.cpu().numpy(), oi)
+        assert np.array_equal(gd.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["dtw", "wdtw", "erp", "msm", "twe"])
+def test_tuner_shapes_agree(torch_dev, orc, kind, precision):
+    """Every row-sweep shape (16/32/64 lanes per pair x 8/16 columns per lane,
+    strips of 128..1024 columns) gives the same NN bit for bit (the tuner checks
+    it), and the tuned shape gives the oracle's."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(44)
+    qs = synth.random_walks(rng, 6, (100, 700))
+    rs = synth.random_walks(rng, 30, (60, 700))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(synth.DEFAULT_PARAMS[kind])
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    log(f"tuner {kind} precision={precision}")
+    try:
+        recs = eap.tune_nn1(q, qo, r, ro, p, precision=precision)
+        assert len(recs) >= 6 and sum(x["chosen"] for x in recs) == 1
+        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision)
+        torch.cuda.synchronize()
+    finally:
+        eap.tune_reset()
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
 @pytest.mark.parametrize("kind", synth.SIX)
 def test_nn1_parity_class_templates(torch_dev, orc, kind):
     """Workload-2 data (five warped sine classes, length 512), subsampled."""
