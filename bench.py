@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
     ap.add_argument("--precision", type=int, default=1, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
     ap.add_argument("--no-tune", action="store_true", help="skip the row-sweep autotuner (default shapes)")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="run the six searches of a step on six streams (default: one after the other)")
     ap.add_argument("--compare-precision", action="store_true",
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -147,10 +149,20 @@ def main():
     dense = {k: dense_cells(k, wl["params"][k], wl["query_off"], wl["ref_off"]) for k in kinds}
     stream = torch.cuda.current_stream(dev)
 
+    kstream = {k: torch.cuda.Stream(dev) for k in kinds} if args.concurrent else None
+
     def step(precision=args.precision):
+        if kstream is None:
+            for k in kinds:
+                eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k],
+                        out=outs[k], precision=precision)
+            return
         for k in kinds:
+            kstream[k].wait_stream(stream)
             eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k],
-                    precision=precision)
+                    precision=precision, stream=kstream[k])
+        for k in kinds:
+            stream.wait_stream(kstream[k])
 
     # autotune the row sweep's shape per distance on this workload (setup, untimed)
     tuning = {}

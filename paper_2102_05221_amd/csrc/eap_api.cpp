@@ -132,38 +132,44 @@ void twe_table(double nu, int64_t lmax, std::vector<double>& t, int& off) {
     for (int64_t k = -lmax; k <= lmax + 1024; ++k) t[(size_t)(k + lmax)] = nu * (double)(2 * (k < 0 ? -k : k));
 }
 
-// Pinned staging for host-to-device copies.  Each copy waits for the previous
-// one issued from the same buffer before overwriting it.
-struct Staging {
-    std::mutex mu;
+// Pinned staging for host-to-device copies: a ring of buffers, each reused
+// only after the copy issued from it last time has completed, so calls on
+// different streams do not wait for each other.
+struct StagingSlot {
     void* buf = nullptr;
     size_t cap = 0;
     hipEvent_t ev = nullptr;
     bool pending = false;
+};
+struct Staging {
+    std::mutex mu;
+    StagingSlot slot[32];
+    unsigned next = 0;
 };
 Staging g_stage;
 
 eap_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     if (bytes == 0) return EAP_OK;
     std::lock_guard<std::mutex> lk(g_stage.mu);
-    if (g_stage.pending) {
-        HIPCHK(hipEventSynchronize(g_stage.ev));
-        g_stage.pending = false;
+    StagingSlot& sl = g_stage.slot[g_stage.next++ % 32];
+    if (sl.pending) {
+        HIPCHK(hipEventSynchronize(sl.ev));
+        sl.pending = false;
     }
-    if (!g_stage.ev) HIPCHK(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
-    if (g_stage.cap < bytes) {
-        if (g_stage.buf) HIPCHK(hipHostFree(g_stage.buf));
-        g_stage.buf = nullptr;
-        g_stage.cap = 0;
-        size_t cap = std::max<size_t>(bytes, 1 << 20);
-        if (hipHostMalloc(&g_stage.buf, cap, hipHostMallocDefault) != hipSuccess)
+    if (!sl.ev) HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    if (sl.cap < bytes) {
+        if (sl.buf) HIPCHK(hipHostFree(sl.buf));
+        sl.buf = nullptr;
+        sl.cap = 0;
+        size_t cap = std::max<size_t>(bytes, 1 << 16);
+        if (hipHostMalloc(&sl.buf, cap, hipHostMallocDefault) != hipSuccess)
             return fail(EAP_ENOMEM, "pinned staging buffer of %zu bytes", cap);
-        g_stage.cap = cap;
+        sl.cap = cap;
     }
-    std::memcpy(g_stage.buf, src, bytes);
-    HIPCHK(hipMemcpyAsync(dst, g_stage.buf, bytes, hipMemcpyHostToDevice, s));
-    HIPCHK(hipEventRecord(g_stage.ev, s));
-    g_stage.pending = true;
+    std::memcpy(sl.buf, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, sl.buf, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(sl.ev, s));
+    sl.pending = true;
     return EAP_OK;
 }
 
@@ -237,6 +243,12 @@ RowsShape rows_shape(int kind, bool fp32, int64_t lco_max) {
     if (it != g_tuned.end()) return it->second;
     return default_shape(kind, fp32, lco_max);
 }
+
+// Shape for launches with few pairs (one per query: the seed and recheck
+// sweeps), which are bound by the latency of a pair's chain of steps rather
+// than by throughput: 64 lanes per pair and the fewest columns per lane
+// (steps take time in proportion to the columns a lane owns).
+RowsShape latency_shape(int64_t lco_max) { return RowsShape{64, lco_max <= 512 ? 8 : 16}; }
 
 // What the sweep of one distance needs, for sets whose longest series have
 // lengths la_max and lb_max.
@@ -499,7 +511,7 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
 struct NNLayout {
     Layout L;
     Common c;
-    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0;
+    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0, rT = 0;
     // FP32 screen
     size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
@@ -511,6 +523,7 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
     nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
+    nl.rT = nl.L.take(sizeof(double) * (size_t)(R.n * R.maxlen));
     nl.edge = nl.L.take(edge_bytes(Q.n * R.n, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)));
     if (screen) {
         nl.q32 = nl.L.take(sizeof(float) * (size_t)Q.total);
@@ -591,7 +604,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         return EAP_OK;
     }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
-    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, res, s));
+    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, (int)Q.maxlen, (int)R.maxlen,
+                        reinterpret_cast<double*>(at(ws, nl.rT)), res, s));
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
     const bool rerun = pl.rerun;
     // FP32 screen: sweep single-precision copies under a widened cut-off first
@@ -619,12 +633,15 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         a.widen_abs = widen;
         a.widen_rel = o->margin_rel;
     }
+    // the seed and recheck sweeps have one or a few pairs per query
+    Plan few = pl;
+    few.r64 = few.r32 = latency_shape(std::min(Q.maxlen, R.maxlen));
     if (seeded) {
         // 2. sweep the seed candidate of every query under its bound
-        if ((st = sweep(p, pl, pl.band, a, h, 0, &h->queues[0], seed_items, nq, XQ, XR, s, screen)) != EAP_OK)
+        if ((st = sweep(p, few, pl.band, a, h, 0, &h->queues[0], seed_items, nq, XQ, XR, s, screen)) != EAP_OK)
             return st;
         if (rerun) {
-            if ((st = rerun_overflow(p, pl, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], XQ, XR, s, screen)) !=
+            if ((st = rerun_overflow(p, few, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], XQ, XR, s, screen)) !=
                 EAP_OK)
                 return st;
             HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
@@ -651,9 +668,9 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         b.widen_rel = 0.0;
         b.skip_b = nullptr;
         b.npairs_dev = &h->ovf_count[2];
-        if ((st = sweep(p, pl, pl.band, b, h, 4, &h->queues[4], items, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+        if ((st = sweep(p, few, pl.band, b, h, 4, &h->queues[4], items, nq * nr, SQ, SR, s)) != EAP_OK) return st;
         if (rerun) {
-            if ((st = rerun_overflow(p, pl, b, h, 5, &h->ovf_count[0], ovf, nq * nr, &h->queues[5], SQ, SR, s)) !=
+            if ((st = rerun_overflow(p, few, b, h, 5, &h->ovf_count[0], ovf, nq * nr, &h->queues[5], SQ, SR, s)) !=
                 EAP_OK)
                 return st;
         }

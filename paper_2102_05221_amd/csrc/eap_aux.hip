@@ -9,12 +9,22 @@ namespace eap {
 // ERP borders (eq. ERP vborder/hborder): B[i] = B[i-1] + |x_i - gap|, one
 // series per thread, summed left to right like the recurrence.
 __global__ void erp_border_kernel(const double* v, const int64_t* off, int64_t n, double gap, double* out) {
+    constexpr int CH = 16;   // values loaded ahead of the (sequential) sum
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
+    const int64_t b = off[s], e = off[s + 1];
     double acc = 0.0;
-    for (int64_t x = off[s]; x < off[s + 1]; ++x) {
-        acc = acc + __builtin_fabs(v[x] - gap);
-        out[x] = acc;
+    for (int64_t x0 = b; x0 < e; x0 += CH) {
+        double xv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) xv[u] = v[x0 + u < e ? x0 + u : e - 1];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (x0 + u < e) {
+                acc = acc + __builtin_fabs(xv[u] - gap);
+                out[x0 + u] = acc;
+            }
+        }
     }
 }
 
@@ -31,11 +41,15 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, int
 // Cost of the warping path (1,1), (2,2), .., (m,m) followed by straight moves
 // along the longer series (Section 4: any path bounds the optimum).  Every step
 // adds its term exactly as the recurrence would, so the value is >= the
-// distance in floating point as well.  Rows are the longer series.
-__device__ double path_ub(int kind, const SweepArgs& A, const double* li, int Lli, const double* co, int Lco) {
+// distance in floating point as well.  Rows are the longer series.  The
+// series are read in chunks of 16 values per lane (one or two cache lines
+// each), so that a wave's lanes, each on its own series, reuse what they load.
+template <int KIND>
+__device__ double path_ub(const SweepArgs& A, const double* li, int Lli, const double* co, int Lco) {
+    constexpr int CH = 16;
     const double INF = __builtin_huge_val();
     const int L = Lli > Lco ? Lli : Lco;
-    if (kind == CDTW || kind == ERP) {
+    if (KIND == CDTW || KIND == ERP) {
         const double r = A.window_ratio;
         if (r < 1.0) {
             int w = (int)floor(r * (double)L);
@@ -43,40 +57,114 @@ __device__ double path_ub(int kind, const SweepArgs& A, const double* li, int Ll
         }
     }
     double wd = 1.0;   // WDTW weight of the diagonal, w(0)
-    if (kind == WDTW) {
+    if (KIND == WDTW) {
         int gi = -L + A.gtab_off;
         gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
         wd = A.gtab[gi];
     }
     double acc = 0.0;
     double sp = 0.0, tp = 0.0;
-    for (int k = 1; k <= Lco; ++k) {
-        const double s = li[k - 1], t = co[k - 1], d = s - t;
-        switch (kind) {
-        case DTW: case CDTW: acc = (d * d) + acc; break;
-        case WDTW: acc = (wd * (d * d)) + acc; break;
-        case ERP: case MSM: acc = acc + __builtin_fabs(d); break;
-        case TWE: acc = acc + ((__builtin_fabs(d) + __builtin_fabs(sp - tp)) + A.nu * 0.0); break;
+    for (int k0 = 0; k0 < Lco; k0 += CH) {
+        double sv[CH], tv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int k = (k0 + u < Lco) ? k0 + u : Lco - 1;
+            sv[u] = li[k];
+            tv[u] = co[k];
         }
-        sp = s;
-        tp = t;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (k0 + u < Lco) {
+                const double s = sv[u], t = tv[u], d = s - t;
+                if constexpr (KIND == DTW || KIND == CDTW) acc = (d * d) + acc;
+                if constexpr (KIND == WDTW) acc = (wd * (d * d)) + acc;
+                if constexpr (KIND == ERP || KIND == MSM) acc = acc + __builtin_fabs(d);
+                if constexpr (KIND == TWE) acc = acc + ((__builtin_fabs(d) + __builtin_fabs(sp - tp)) + A.nu * 0.0);
+                sp = s;
+                tp = t;
+            }
+        }
     }
     // straight down column L_co: moves (i-1, L_co) -> (i, L_co), |i - L_co| grows
     const double t = co[Lco - 1];
+    double xprev = li[Lco - 1];   // s_{i-1}
+    for (int i0 = Lco + 1; i0 <= Lli; i0 += CH) {
+        double sv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) sv[u] = li[(i0 + u <= Lli ? i0 + u : Lli) - 1];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int i = i0 + u;
+            if (i <= Lli) {
+                const double s = sv[u], d = s - t;
+                if constexpr (KIND == DTW || KIND == CDTW) acc = (d * d) + acc;
+                if constexpr (KIND == WDTW) {
+                    int gi = 2 * (i - Lco) - L + A.gtab_off;
+                    gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
+                    acc = (A.gtab[gi] * (d * d)) + acc;
+                }
+                if constexpr (KIND == ERP) acc = acc + __builtin_fabs(s - A.gap);
+                if constexpr (KIND == MSM) {
+                    // C(s_i, s_{i-1}, t) of eq. MSMCost
+                    const double x = xprev;
+                    double c;
+                    if ((x <= s && s <= t) || (x >= s && s >= t)) c = A.c;
+                    else {
+                        const double p1 = __builtin_fabs(s - x), p2 = __builtin_fabs(s - t);
+                        c = A.c + (p1 < p2 ? p1 : p2);
+                    }
+                    acc = acc + c;
+                }
+                if constexpr (KIND == TWE) acc = acc + ((__builtin_fabs(s - xprev) + A.nu) + A.lam);
+                xprev = s;
+            }
+        }
+    }
+    return acc;
+}
+
+// The same path cost with the series behind accessors: rowv(k) = s_{k+1} of
+// the longer series, colv(k) = t_{k+1} (same terms, same order).
+template <int KIND, typename FR, typename FC>
+__device__ double path_ub_acc(const SweepArgs& A, FR rowv, int Lli, FC colv, int Lco) {
+    const double INF = __builtin_huge_val();
+    const int L = Lli > Lco ? Lli : Lco;
+    if (KIND == CDTW || KIND == ERP) {
+        const double r = A.window_ratio;
+        if (r < 1.0) {
+            int w = (int)floor(r * (double)L);
+            if (w < Lli - Lco) return INF;
+        }
+    }
+    double wd = 1.0;
+    if (KIND == WDTW) {
+        int gi = -L + A.gtab_off;
+        gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
+        wd = A.gtab[gi];
+    }
+    double acc = 0.0, sp = 0.0, tp = 0.0;
+    for (int k = 0; k < Lco; ++k) {
+        const double s = rowv(k), t = colv(k), d = s - t;
+        if constexpr (KIND == DTW || KIND == CDTW) acc = (d * d) + acc;
+        if constexpr (KIND == WDTW) acc = (wd * (d * d)) + acc;
+        if constexpr (KIND == ERP || KIND == MSM) acc = acc + __builtin_fabs(d);
+        if constexpr (KIND == TWE) acc = acc + ((__builtin_fabs(d) + __builtin_fabs(sp - tp)) + A.nu * 0.0);
+        sp = s;
+        tp = t;
+    }
+    const double t = colv(Lco - 1);
+    double xprev = rowv(Lco - 1);
     for (int i = Lco + 1; i <= Lli; ++i) {
-        const double s = li[i - 1], d = s - t;
-        switch (kind) {
-        case DTW: case CDTW: acc = (d * d) + acc; break;
-        case WDTW: {
+        const double s = rowv(i - 1), d = s - t;
+        if constexpr (KIND == DTW || KIND == CDTW) acc = (d * d) + acc;
+        if constexpr (KIND == WDTW) {
             int gi = 2 * (i - Lco) - L + A.gtab_off;
             gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
             acc = (A.gtab[gi] * (d * d)) + acc;
-            break;
         }
-        case ERP: acc = acc + __builtin_fabs(s - A.gap); break;
-        case MSM: {
-            // C(s_i, s_{i-1}, t) of eq. MSMCost
-            const double x = li[i - 2];
+        if constexpr (KIND == ERP) acc = acc + __builtin_fabs(s - A.gap);
+        if constexpr (KIND == MSM) {
+            const double x = xprev;
             double c;
             if ((x <= s && s <= t) || (x >= s && s >= t)) c = A.c;
             else {
@@ -84,25 +172,50 @@ __device__ double path_ub(int kind, const SweepArgs& A, const double* li, int Ll
                 c = A.c + (p1 < p2 ? p1 : p2);
             }
             acc = acc + c;
-            break;
         }
-        case TWE: acc = acc + ((__builtin_fabs(s - li[i - 2]) + A.nu) + A.lam); break;
-        }
+        if constexpr (KIND == TWE) acc = acc + ((__builtin_fabs(s - xprev) + A.nu) + A.lam);
+        xprev = s;
     }
     return acc;
 }
 
-// UB for every (query, candidate) pair, written to ub[a*nB + b].
-__global__ void ub_nn_kernel(int kind, SweepArgs A, const double* qv, const int64_t* qoff, const double* rv,
-                             const int64_t* roff, double* ub) {
-    const int64_t total = A.nA * A.nB;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t a = p / A.nB, b = p - a * A.nB;
-        const double* x = qv + qoff[a];
-        const double* y = rv + roff[b];
-        const int lx = (int)(qoff[a + 1] - qoff[a]), ly = (int)(roff[b + 1] - roff[b]);
-        ub[p] = (lx >= ly) ? path_ub(kind, A, x, lx, y, ly) : path_ub(kind, A, y, ly, x, lx);
+// Candidates interleaved for coalesced reads: rT[k * nr + b] = value k of
+// candidate b (0 past its end).
+__global__ void interleave_kernel(const double* rv, const int64_t* roff, int64_t nr, int lmax, double* rT) {
+    const int64_t total = nr * (int64_t)lmax;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = x / nr, b = x - k * nr;
+        const int64_t o = roff[b], len = roff[b + 1] - o;
+        rT[x] = (k < len) ? rv[o + k] : 0.0;
     }
+}
+
+// UB of every (query, candidate) pair from the interleaved candidates: a block
+// takes one query (staged in LDS, read by all lanes at once) and 256
+// candidates (one per lane, coalesced).
+template <int KIND>
+__global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rT,
+                               const int64_t* roff, double* ub) {
+    extern __shared__ double qs[];
+    const int64_t nB = A.nB;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t a = blockIdx.y; a < A.nA; a += gridDim.y) {
+        const int lq = (int)(qoff[a + 1] - qoff[a]);
+        __syncthreads();
+        for (int k = threadIdx.x; k < lq; k += blockDim.x) qs[k] = qv[qoff[a] + k];
+        __syncthreads();
+        if (b < nB) {
+            const int lr = (int)(roff[b + 1] - roff[b]);
+            auto Q = [&](int k) { return qs[k]; };
+            auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
+            ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
+        }
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ double pair_ub(const SweepArgs& A, const double* x, int lx, const double* y, int ly) {
+    return (lx >= ly) ? path_ub<KIND>(A, x, lx, y, ly) : path_ub<KIND>(A, y, ly, x, lx);
 }
 
 // The next double above a non-negative value (+inf stays +inf): its bit
@@ -113,8 +226,8 @@ __device__ __forceinline__ double next_up(double u) {
 }
 
 // Prune-only cut-off for every condensed pair: one ulp above its path bound.
-__global__ void ub_condensed_kernel(int kind, SweepArgs A, const double* v, const int64_t* off, int64_t n,
-                                    double* cut) {
+template <int KIND>
+__global__ void ub_condensed_kernel(SweepArgs A, const double* v, const int64_t* off, int64_t n, double* cut) {
     const int64_t total = n * (n - 1) / 2;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
         int64_t i, j;
@@ -122,8 +235,7 @@ __global__ void ub_condensed_kernel(int kind, SweepArgs A, const double* v, cons
         const double* x = v + off[i];
         const double* y = v + off[j];
         const int lx = (int)(off[i + 1] - off[i]), ly = (int)(off[j + 1] - off[j]);
-        const double u = (lx >= ly) ? path_ub(kind, A, x, lx, y, ly) : path_ub(kind, A, y, ly, x, lx);
-        cut[p] = next_up(u);
+        cut[p] = next_up(pair_ub<KIND>(A, x, lx, y, ly));
     }
 }
 
@@ -192,11 +304,17 @@ __global__ void argmin_kernel(const double* res, int64_t nq, int64_t nr, const i
 
 // Largest |x| over a set, as the bit pattern of a non-negative double.
 __global__ void absmax_kernel(const double* v, int64_t n, unsigned long long* out) {
+    __shared__ double part[4];
     double m = 0.0;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
         m = fmax(m, __builtin_fabs(v[x]));
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, dbits(m));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {   // one atomic per block
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, part[w]);
+        atomicMax(out, dbits(m));
+    }
 }
 
 // Certified bound on |D32 - D64| for any warping path whose exact cost is at
@@ -313,7 +431,7 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 }
 
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s) {
-    hipLaunchKernelGGL(absmax_kernel, dim3(std::min(blocks_for(n, 256), 1024)), dim3(256), 0, s, v, n, out);
+    hipLaunchKernelGGL(absmax_kernel, dim3(std::min(blocks_for(n, 256 * 8), 256)), dim3(256), 0, s, v, n, out);
     return hipGetLastError();
 }
 
@@ -335,16 +453,35 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
 }
 
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
-                        const int64_t* roff, double* ub, hipStream_t s) {
-    hipLaunchKernelGGL(ub_nn_kernel, dim3(blocks_for(a.nA * a.nB, 256)), dim3(256), 0, s, kind, a, qv, qoff, rv, roff,
-                       ub);
+                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, hipStream_t s) {
+    hipLaunchKernelGGL(interleave_kernel, dim3(blocks_for(a.nB * (int64_t)lr_max, 256)), dim3(256), 0, s, rv, roff,
+                       a.nB, lr_max, rT);
+    const dim3 g((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>(a.nA, 65535)), b(256);
+    const size_t lds = sizeof(double) * (size_t)lq_max;
+    switch (kind) {
+    case DTW: hipLaunchKernelGGL(ub_nn_t_kernel<DTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case CDTW: hipLaunchKernelGGL(ub_nn_t_kernel<CDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case WDTW: hipLaunchKernelGGL(ub_nn_t_kernel<WDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case ERP: hipLaunchKernelGGL(ub_nn_t_kernel<ERP>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case MSM: hipLaunchKernelGGL(ub_nn_t_kernel<MSM>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case TWE: hipLaunchKernelGGL(ub_nn_t_kernel<TWE>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s) {
-    hipLaunchKernelGGL(ub_condensed_kernel, dim3(blocks_for(n * (n - 1) / 2, 256)), dim3(256), 0, s, kind, a, v, off,
-                       n, cut);
+    const dim3 g(blocks_for(n * (n - 1) / 2, 256)), b(256);
+    switch (kind) {
+    case DTW: hipLaunchKernelGGL(ub_condensed_kernel<DTW>, g, b, 0, s, a, v, off, n, cut); break;
+    case CDTW: hipLaunchKernelGGL(ub_condensed_kernel<CDTW>, g, b, 0, s, a, v, off, n, cut); break;
+    case WDTW: hipLaunchKernelGGL(ub_condensed_kernel<WDTW>, g, b, 0, s, a, v, off, n, cut); break;
+    case ERP: hipLaunchKernelGGL(ub_condensed_kernel<ERP>, g, b, 0, s, a, v, off, n, cut); break;
+    case MSM: hipLaunchKernelGGL(ub_condensed_kernel<MSM>, g, b, 0, s, a, v, off, n, cut); break;
+    case TWE: hipLaunchKernelGGL(ub_condensed_kernel<TWE>, g, b, 0, s, a, v, off, n, cut); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

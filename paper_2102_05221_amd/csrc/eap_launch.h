@@ -85,8 +85,10 @@ hipError_t launch_band(int kind, bool fp32, int diags, const SweepArgs& a, Serie
 // Auxiliary kernels.
 hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s);
 hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
+// Path upper bounds of all NN pairs; rT: workspace of nB * lr_max doubles for
+// the interleaved candidates.
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
-                        const int64_t* roff, double* ub, hipStream_t s);
+                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, hipStream_t s);
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s);
 hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* list_a,
