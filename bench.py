@@ -45,6 +45,18 @@ OPS_PER_CELL_F32 = {"dtw": 4, "cdtw": 4, "wdtw": 5, "erp": 5, "msm": 9, "twe": 7
 HBM_PEAK_GBS = 8000.0
 
 
+def band_cells(li, co, w):
+    """Cells (i, j), 1 <= i <= li, 1 <= j <= co, with |i - j| <= w, for arrays
+    li >= co with w >= li - co (closed form of the row-by-row count)."""
+    li, co, w = (np.asarray(x, dtype=np.int64) for x in (li, co, w))
+    m = np.clip(co - w, 0, li)
+    s_up = m * (m + 1) // 2 + m * w + (li - m) * co                     # sum of min(i + w, co)
+    n1 = np.minimum(li, w + 1)
+    t = np.maximum(li - w, 1)
+    s_lo = n1 + np.where(li >= w + 2, t * (t + 1) // 2 - 1, 0)          # sum of max(i - w, 1)
+    return s_up - s_lo + li
+
+
 def dense_cells(kind, p, q_off, r_off):
     """Cells of the plain full DP over all (query, candidate) pairs; for a
     windowed distance the cells inside the window (0 for infeasible pairs)."""
@@ -53,20 +65,14 @@ def dense_cells(kind, p, q_off, r_off):
     ratio = p.get("window_ratio", math.inf)
     if kind not in ("cdtw", "erp") or ratio >= 1:
         return int(lq.sum() * lr.sum())
-    memo = {}
-    total = 0
-    for a in lq:
-        for b in lr:
-            li, co = int(max(a, b)), int(min(a, b))
-            if (li, co) not in memo:
-                w = int(math.floor(ratio * float(li)))
-                if w < li - co:
-                    memo[(li, co)] = 0
-                else:
-                    i = np.arange(1, li + 1)
-                    memo[(li, co)] = int((np.minimum(i + w, co) - np.maximum(i - w, 1) + 1).clip(min=0).sum())
-            total += memo[(li, co)]
-    return total
+    uq, cq = np.unique(lq, return_counts=True)
+    ur, cr = np.unique(lr, return_counts=True)
+    A, B = np.meshgrid(uq, ur, indexing="ij")
+    li, co = np.maximum(A, B), np.minimum(A, B)
+    w = np.floor(ratio * li.astype(np.float64)).astype(np.int64)
+    feas = w >= li - co
+    cells = np.where(feas, band_cells(li, co, np.where(feas, w, li)), 0)
+    return int((cells * np.outer(cq, cr)).sum())
 
 
 def swept_kind(kind, p):
@@ -114,6 +120,11 @@ def main():
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 plain device copies of this many MiB (HBM counter calibration) and exit")
+    ap.add_argument("--workload", type=int, default=2, choices=(2, 4, 5),
+                    help="2: the benchmark (500 x 500, length 512); 4: batched uneven lengths, graph launch; "
+                         "5: served requests")
+    ap.add_argument("--refs", type=int, default=0, help="workloads 4/5: candidate count (0: the full workload)")
+    ap.add_argument("--queries", type=int, default=0, help="workloads 4/5: query count (0: the full workload)")
     args = ap.parse_args()
     if args.copy_mib > 0:
         import torch
@@ -134,6 +145,9 @@ def main():
 
     import paper_2102_05221_amd as eap
     from paper_2102_05221_amd import synth
+
+    if args.workload == 4:
+        return run_batched(args, torch, eap, synth)
 
     dev = torch.device("cuda:0")
     kinds = [k for k in args.kinds.split(",") if k]
@@ -332,6 +346,148 @@ def main():
         cpu_baseline=cpu,
     )
     print(json.dumps(line), flush=True)
+
+
+def run_batched(args, torch, eap, synth):
+    """Workload 4: 10,000 candidates x 1,000 queries of uneven lengths (64..2048,
+    warped-sine classes), six distances, FP32 screen + FP64 recheck, shapes
+    autotuned on a sample, and the six searches of a step captured in one HIP
+    graph: a step is one graph launch."""
+    dev = torch.device("cuda:0")
+    kinds = [k for k in args.kinds.split(",") if k]
+    wl = synth.make_workload(4, n_ref=args.refs or None, n_query=args.queries or None)
+    qo, ro = wl["query_off"], wl["ref_off"]
+    nq, nr = len(qo) - 1, len(ro) - 1
+    q = torch.from_numpy(wl["queries"]).to(dev)
+    r = torch.from_numpy(wl["refs"]).to(dev)
+    labels = torch.from_numpy(wl["ref_labels"]).to(dev)
+    P = wl["params"]
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(qo, ro, P[k], precision=1), dev) for k in kinds}
+    outs = {k: (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
+                torch.empty(nq, dtype=torch.int32, device=dev)) for k in kinds}
+    dense = {k: dense_cells(k, P[k], qo, ro) for k in kinds}
+
+    # shapes tuned on a sample (64 queries x 2000 candidates), untimed
+    sq, sr = min(64, nq), min(2000, nr)
+    tq, tr = q[: qo[sq]], r[: ro[sr]]
+    tuning = {}
+    if not args.no_tune:
+        for k in kinds:
+            recs = eap.tune_nn1(tq, qo[: sq + 1], tr, ro[: sr + 1], P[k], precision=1)
+            if recs:
+                tuning[k] = next(f"{x['g']}x{x['c']}" for x in recs if x["chosen"])
+
+    s = torch.cuda.Stream(dev)
+
+    def eager():
+        for k in kinds:
+            eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, ws=ws[k], out=outs[k], stream=s)
+
+    eager()   # uploads offsets and tables into the workspaces
+    s.synchronize()
+    want = {k: (outs[k][0].clone(), outs[k][1].clone(), outs[k][2].clone()) for k in kinds}
+    eap.capture_begin(s)
+    for k in kinds:
+        eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, flags=eap.FLAG_PREPARED, ws=ws[k], out=outs[k],
+                stream=s)
+    graph = eap.capture_end(s)
+    for _ in range(args.warmup):
+        graph.launch(stream=s)
+    s.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    step_ev = []
+    t0 = time.perf_counter()
+    ev0.record(s)
+    for _ in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        graph.launch(stream=s)
+        b.record(s)
+        step_ev.append((a, b))
+    ev1.record(s)
+    s.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    step_ms = [a.elapsed_time(b) for a, b in step_ev]
+    same = all(torch.equal(outs[k][i], want[k][i]) for k in kinds for i in range(3))
+    graph.close()
+
+    # per-distance breakdown and the dominant kernel: one eager profiled step
+    for k in kinds:
+        eap.reset_counters(ws[k], stream=s)
+    eap.profile_take()
+    eap.profile_enable(True)
+    eager()
+    s.synchronize()
+    eap.profile_enable(False)
+    prof = eap.profile_take()
+    counters = {k: eap.read_counters(ws[k], stream=s) for k in kinds}
+    per = {}
+    for k in kinds:
+        sk = swept_kind(k, P[k])
+        main = [x for x in prof if x["kind"] == sk and x["stage"] == 2]
+        per[k] = dict(sweep_ms=sum(x["ms"] for x in prof if x["kind"] == sk),
+                      main_sweep_ms=sum(x["ms"] for x in main),
+                      main_kernel=(f"{main[0]['kernel']}{main[0]['size']}" if main else None),
+                      main_fp32=bool(main[0]["fp32"]) if main else False,
+                      main_cells=counters[k]["stage_cells"][2], dense_cells=dense[k],
+                      executed_fraction=counters[k]["cells"] / dense[k] if dense[k] else None,
+                      fp64_rechecks=counters[k]["rechecks"],
+                      nn_accuracy=float(np.mean(outs[k][2].cpu().numpy() == wl["query_labels"])))
+    dom = max(kinds, key=lambda k: per[k]["main_sweep_ms"])
+    d = per[dom]
+    ops = (OPS_PER_CELL_F32 if d["main_fp32"] else OPS_PER_CELL)[dom]
+    peak = (LANE_OPS_PER_S_F32 if d["main_fp32"] else LANE_OPS_PER_S) / ops / 1e9
+    achieved = d["main_cells"] / (d["main_sweep_ms"] * 1e-3) / 1e9
+    roofline = dict(bound="alu", achieved=achieved, peak=peak, unit="GCUPS", frac=achieved / peak, traffic=None,
+                    kernel=f"{d['main_kernel']} sweep, {dom.upper()} main stage, "
+                           f"{'fp32' if d['main_fp32'] else 'fp64'}", ops_per_cell=ops,
+                    launch_ms=d["main_sweep_ms"], note="from one eager profiled step after the timed graph launches")
+
+    # plain FP64 DP on the GPU for the first queries against every candidate,
+    # scaled to the whole workload by dense cells
+    plain = None
+    if not args.no_plain:
+        pq = min(50, nq)
+        pqv = q[: qo[pq]]
+        pms = 0.0
+        pdense = 0
+        pws = {k: eap.workspace(eap.nn1_workspace_bytes(qo[: pq + 1], ro, P[k]), dev) for k in kinds}
+        for k in kinds:
+            eap.nn1(pqv, qo[: pq + 1], r, ro, P[k], ws=pws[k], flags=eap.FLAG_PLAIN, stream=s)
+            s.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            eap.nn1(pqv, qo[: pq + 1], r, ro, P[k], ws=pws[k], flags=eap.FLAG_PLAIN, stream=s)
+            b.record(s)
+            s.synchronize()
+            pms += a.elapsed_time(b)
+            pdense += dense_cells(k, P[k], qo[: pq + 1], ro)
+        gcups = pdense / (pms * 1e-3) / 1e9
+        est = sum(dense.values()) / (gcups * 1e9) * 1e3
+        plain = dict(sample=f"first {pq} queries x all {nr} candidates", gcups=gcups,
+                     ms_per_step_estimate=est, speedup_of_eapruned=est / ms_per_step)
+        del pws
+
+    cpu = None
+    if args.cpu_queries > 0:
+        gi = {k: outs[k][0].cpu().numpy() for k in kinds}
+        gd = {k: outs[k][1].cpu().numpy() for k in kinds}
+        cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, 2, nq), gi, gd)
+
+    total = sum(dense.values())
+    print(json.dumps(dict(
+        metric=METRIC, value=total / (ms_per_step * 1e-3) / 1e9, unit="GCUPS", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32+f64", data="synthetic",
+        config=dict(workload=f"batched uneven lengths: 1-NN of {nq} queries among {nr} candidates, lengths "
+                             "uniform in [64, 2048], 5 warped-sine classes, six distances, FP32 screen + FP64 "
+                             "recheck, one HIP graph launch per step", queries=nq, candidates=nr,
+                    distances=kinds),
+        queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
+        step_ms_p50=float(np.percentile(step_ms, 50)), step_ms_p99=float(np.percentile(step_ms, 99)),
+        graph_results_identical_to_eager=same, tuning=tuning, per_distance=per, plain_gpu_dp=plain,
+        roofline=roofline, cpu_baseline=cpu)), flush=True)
 
 
 def _source_hash():

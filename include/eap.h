@@ -80,14 +80,21 @@ typedef struct {
  *              margin_rel * best32 plus twice a certified bound on the FP32
  *              rounding error of any warping path (input rounding, per-term
  *              rounding and the running sum), so the FP64 nearest neighbour is
- *              always among the candidates rechecked.
+ *              always among the candidates rechecked.  WDTW whose diagonal
+ *              weight 1/(1+exp(g*L/2)) is below 1e-8 (L the longest length) is
+ *              swept in FP64 directly: its distances are too small for an FP32
+ *              screen to separate candidates.
  *  margin_rel  relative part of the screen margin for precision 1 (>= 0,
  *              finite; 1e-4 by default in the binding).
  *  flags       bit 0: skip the seeding pass (every candidate starts from the
  *              path upper bound); for ablation only.
  *              bit 1: plain full dynamic programme for every pair (no cut-off,
  *              no pruning, no abandoning): the baseline the pruned search is
- *              measured against.  Same results. */
+ *              measured against.  Same results.
+ *              bit 2: prepared: a previous call on this workspace had the same
+ *              offsets and parameters, so their host-to-device copies are
+ *              skipped and the call enqueues kernels only.  Required while the
+ *              stream is being captured into a graph (see eap_capture_begin). */
 typedef struct {
     int32_t precision;
     double margin_rel;
@@ -196,6 +203,21 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
                         int32_t* n);
 /* Forgets every tuned shape (later calls use the defaults). */
 eap_status eap_tune_reset(void);
+
+/* HIP graphs of NN searches.  eap_capture_begin() starts capturing `stream`
+ * (thread-local capture mode); every eap_nn1 call made on it until
+ * eap_capture_end() must carry flags bit 2 (prepared: run once uncaptured
+ * first, on the same workspace and inputs) and is recorded, not run.
+ * eap_capture_end() instantiates the graph; eap_graph_launch() replays all the
+ * recorded searches with one launch, on the buffers they were recorded with
+ * (their contents may change between launches, their sizes and addresses may
+ * not).  The graph contains kernels only (buffers are cleared by kernels, not
+ * memset nodes).  eap_graph_destroy() frees it (NULL is accepted). */
+typedef struct eap_graph eap_graph;
+eap_status eap_capture_begin(void* stream);
+eap_status eap_capture_end(void* stream, eap_graph** out);
+eap_status eap_graph_launch(eap_graph* g, void* stream);
+eap_status eap_graph_destroy(eap_graph* g);
 
 /* Host utility: the WDTW weights the library uses for longer length L,
  * out[k] = w(k) = 1 / (1 + exp(-g * (k - L/2))) for k = 0..L-1 (eq. WDTW with

@@ -19,10 +19,11 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN"]
+           "FLAG_PLAIN", "FLAG_PREPARED", "tune_nn1", "tune_reset", "capture_begin", "capture_end", "Graph"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
-FLAG_PLAIN = 2     # plain full DP for every pair: the baseline
+FLAG_PLAIN = 2        # plain full DP for every pair: the baseline
+FLAG_PREPARED = 4     # offsets and tables already in the workspace: kernels only (graph capture)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeap.so")
@@ -103,6 +104,14 @@ def lib():
         L.eap_tune_nn1.restype = ctypes.c_int
         L.eap_tune_nn1.argtypes = [_vp, _pi64, _i64, _vp, _pi64, _i64, _pP, _pO, _vp, _sz, _vp, _vp, _vp,
                                    ctypes.POINTER(TuneRec), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.eap_capture_begin.restype = ctypes.c_int
+        L.eap_capture_begin.argtypes = [_vp]
+        L.eap_capture_end.restype = ctypes.c_int
+        L.eap_capture_end.argtypes = [_vp, ctypes.POINTER(ctypes.c_void_p)]
+        L.eap_graph_launch.restype = ctypes.c_int
+        L.eap_graph_launch.argtypes = [_vp, _vp]
+        L.eap_graph_destroy.restype = ctypes.c_int
+        L.eap_graph_destroy.argtypes = [_vp]
         L.eap_tune_reset.restype = ctypes.c_int
         L.eap_tune_reset.argtypes = []
         L.eap_wdtw_weights.restype = ctypes.c_int
@@ -238,6 +247,41 @@ def tune_nn1(q, q_off, r, r_off, p, precision: int = 0, margin_rel: float = 1e-4
 
 def tune_reset() -> None:
     _check(lib().eap_tune_reset())
+
+
+class Graph:
+    """A HIP graph of NN searches recorded between capture_begin() and
+    capture_end(); launch() replays them all with one graph launch."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream=None, device=None):
+        import torch
+        _check(lib().eap_graph_launch(self._h, _stream(stream, device or torch.device("cuda", 0))))
+
+    def close(self):
+        if self._h:
+            _check(lib().eap_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture_begin(stream) -> None:
+    """Start recording NN searches issued on `stream` (a torch stream other than
+    the null stream); each must pass flags=FLAG_PREPARED."""
+    _check(lib().eap_capture_begin(ctypes.c_void_p(stream.cuda_stream)))
+
+
+def capture_end(stream) -> Graph:
+    h = ctypes.c_void_p(None)
+    _check(lib().eap_capture_end(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+    return Graph(h)
 
 
 def pairwise_workspace_bytes(s_off, p) -> int:

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -329,13 +330,18 @@ char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
 eap_status setup_common(void* ws, const Common& c, const eap_params* p, const double* va, const int64_t* offa,
                         int64_t na, const double* vb, const int64_t* offb, int64_t nb, hipStream_t s,
-                        SweepArgs& a, SeriesPtrs& SA, SeriesPtrs& SB) {
+                        SweepArgs& a, SeriesPtrs& SA, SeriesPtrs& SB, bool prepared = false) {
     eap_status st;
     // work queues and overflow counts start at zero; the counters keep accumulating
     HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(at(ws, c.hdr)) + kCounterWords, 0ull,
                            (int64_t)(kHeaderBytes / 8) - kCounterWords, s));
-    if ((st = upload(at(ws, c.offA), offa, sizeof(int64_t) * (size_t)(na + 1), s)) != EAP_OK) return st;
-    if (offb && (st = upload(at(ws, c.offB), offb, sizeof(int64_t) * (size_t)(nb + 1), s)) != EAP_OK) return st;
+    // offsets and tables: uploaded, unless a previous call with the same
+    // inputs left them in this workspace (the only host-to-device copies, so a
+    // prepared call enqueues kernels only and can be captured in a graph)
+    if (!prepared && (st = upload(at(ws, c.offA), offa, sizeof(int64_t) * (size_t)(na + 1), s)) != EAP_OK)
+        return st;
+    if (!prepared && offb && (st = upload(at(ws, c.offB), offb, sizeof(int64_t) * (size_t)(nb + 1), s)) != EAP_OK)
+        return st;
     const int64_t* dA = reinterpret_cast<const int64_t*>(at(ws, c.offA));
     const int64_t* dB = offb ? reinterpret_cast<const int64_t*>(at(ws, c.offB)) : dA;
     SA = SeriesPtrs{va, dA, nullptr};
@@ -353,13 +359,15 @@ eap_status setup_common(void* ws, const Common& c, const eap_params* p, const do
         }
     }
     if (p->kind == EAP_TWE) {
-        if ((st = upload(at(ws, c.tab), c.tabv.data(), sizeof(double) * c.tabv.size(), s)) != EAP_OK) return st;
+        if (!prepared && (st = upload(at(ws, c.tab), c.tabv.data(), sizeof(double) * c.tabv.size(), s)) != EAP_OK)
+            return st;
         a.tab = reinterpret_cast<const double*>(at(ws, c.tab));
         a.tab_off = c.tab_off;
         a.tab_len = (int)c.tabv.size();
     }
     if (p->kind == EAP_WDTW) {
-        if ((st = upload(at(ws, c.gtab), c.gtabv.data(), sizeof(double) * c.gtabv.size(), s)) != EAP_OK) return st;
+        if (!prepared && (st = upload(at(ws, c.gtab), c.gtabv.data(), sizeof(double) * c.gtabv.size(), s)) != EAP_OK)
+            return st;
         a.gtab = reinterpret_cast<const double*>(at(ws, c.gtab));
         a.gtab_off = c.gtab_off;
         a.gtab_len = (int)c.gtabv.size();
@@ -405,7 +413,9 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     const int kind = effective_kind(p);
     const RowsShape sh = fp32 ? pl.r32 : pl.r64;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+    if (cap == hipStreamCaptureStatusNone) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (g_prof.on) {
             e0 = g_prof.get();
@@ -508,6 +518,16 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
 }
 
 // ---------------------------------------------------------------------- NN
+// Whether an FP32 screen can separate candidates.  Its certified error bound
+// carries the rounding of the inputs, about u * max|x| per difference, at any
+// weight; WDTW's weights near the diagonal, 1 / (1 + exp(g L / 2)), make its
+// distances so small for long series that this bound would list most
+// candidates for the recheck, so WDTW then runs in FP64 throughout.
+bool screen_useful(const eap_params* p, int64_t lmax) {
+    if (p->kind != EAP_WDTW) return true;
+    return 1.0 / (1.0 + std::exp(p->g * (double)lmax / 2.0)) >= 1e-8;
+}
+
 struct NNLayout {
     Layout L;
     Common c;
@@ -546,7 +566,7 @@ size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off,
         check_offsets(r_off, nr, "candidates", &R) != EAP_OK)
         return 0;
     NNLayout nl;
-    nn_layout(Q, R, p, o && o->precision == 1, nl);
+    nn_layout(Q, R, p, o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen)), nl);
     return nl.L.off;
 }
 
@@ -564,7 +584,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         if (o->precision != 0 && o->precision != 1) return fail(EAP_EINVAL, "precision must be 0 or 1");
         if (!(std::isfinite(o->margin_rel) && o->margin_rel >= 0)) return fail(EAP_EINVAL, "margin_rel must be >= 0");
     }
-    const bool screen = o && o->precision == 1;
+    const bool screen = o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
     NNLayout nl;
     nn_layout(Q, R, p, screen, nl);
     if (!ws || ws_bytes < nl.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, nl.L.off);
@@ -572,12 +592,17 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     const bool plain = o && (o->flags & 2);
     const bool seeded = !plain && !(o && (o->flags & 1));
+    const bool prepared = o && (o->flags & 4);
     if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
 
     hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone && !prepared)
+        return fail(EAP_EINVAL, "a captured eap_nn1 needs prepared inputs (flags bit 2)");
     SweepArgs a = base_args(p);
     SeriesPtrs SQ, SR;
-    if ((st = setup_common(ws, nl.c, p, q, q_off, nq, r, r_off, nr, s, a, SQ, SR)) != EAP_OK) return st;
+    if ((st = setup_common(ws, nl.c, p, q, q_off, nq, r, r_off, nr, s, a, SQ, SR, prepared)) != EAP_OK) return st;
     Header* h = hdr_of(ws, nl.c);
     unsigned long long* best = reinterpret_cast<unsigned long long*>(at(ws, nl.best));
     int32_t* seed = reinterpret_cast<int32_t*>(at(ws, nl.seed));
@@ -753,7 +778,7 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
     SetInfo Q, R;
     if ((st = check_offsets(q_off, nq, "queries", &Q)) != EAP_OK) return st;
     if ((st = check_offsets(r_off, nr, "candidates", &R)) != EAP_OK) return st;
-    const bool fp32 = o && o->precision == 1;
+    const bool fp32 = o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
     const bool plain = o && (o->flags & 2);
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     Plan pl;
@@ -819,6 +844,52 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
     }
     if (best < cap) recs[best].chosen = 1;
     *n = k < cap ? k : cap;
+    return EAP_OK;
+}
+
+struct eap_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+eap_status eap_capture_begin(void* stream) {
+    HIPCHK(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+    return EAP_OK;
+}
+
+eap_status eap_capture_end(void* stream, eap_graph** out) {
+    if (!out) return fail(EAP_EINVAL, "NULL graph output");
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture((hipStream_t)stream, &g));
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(EAP_EDEVICE, "hipGraphInstantiate failed");
+    }
+    eap_graph* r = new (std::nothrow) eap_graph;
+    if (!r) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return fail(EAP_ENOMEM, "graph handle");
+    }
+    r->graph = g;
+    r->exec = x;
+    *out = r;
+    return EAP_OK;
+}
+
+eap_status eap_graph_launch(eap_graph* g, void* stream) {
+    if (!g || !g->exec) return fail(EAP_EINVAL, "NULL graph");
+    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return EAP_OK;
+}
+
+eap_status eap_graph_destroy(eap_graph* g) {
+    if (!g) return EAP_OK;
+    if (g->exec) HIPCHK(hipGraphExecDestroy(g->exec));
+    if (g->graph) HIPCHK(hipGraphDestroy(g->graph));
+    delete g;
     return EAP_OK;
 }
 

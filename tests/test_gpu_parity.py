@@ -155,6 +155,64 @@ def test_tuner_shapes_agree(torch_dev, orc, kind, precision):
     assert np.array_equal(gd.cpu().numpy(), od)
 
 
+def test_graph_replays_match_eager(torch_dev, orc):
+    """The six searches of a workload-4-shaped batch (FP32 screen + FP64
+    recheck) captured in one HIP graph: every replay, with eager work on the
+    same buffers in between, gives the eager results, which are the oracle's."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(4, n_ref=40, n_query=8, length=(64, 700))
+    qo, ro = wl["query_off"], wl["ref_off"]
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    P = wl["params"]
+    nq = len(qo) - 1
+    s = torch.cuda.Stream(dev)
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(qo, ro, P[k], precision=1), dev) for k in synth.SIX}
+    outs = {k: (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
+                None) for k in synth.SIX}
+    log("graph: eager pass")
+    for k in synth.SIX:
+        eap.nn1(q, qo, r, ro, P[k], precision=1, ws=ws[k], out=outs[k], stream=s)
+    s.synchronize()
+    want = {k: (outs[k][0].clone(), outs[k][1].clone()) for k in synth.SIX}
+    for k in synth.SIX:
+        oi, od, _ = orc.nn1(P[k], wl["queries"], qo, wl["refs"], ro, "dp")
+        assert np.array_equal(want[k][0].cpu().numpy(), oi) and np.array_equal(want[k][1].cpu().numpy(), od)
+    log("graph: capture")
+    eap.capture_begin(s)
+    for k in synth.SIX:
+        eap.nn1(q, qo, r, ro, P[k], precision=1, flags=eap.FLAG_PREPARED, ws=ws[k], out=outs[k], stream=s)
+    g = eap.capture_end(s)
+    try:
+        for rep in range(3):
+            log(f"graph: replay {rep}")
+            with torch.cuda.stream(s):
+                for k in synth.SIX:
+                    outs[k][0].fill_(-7)
+                    outs[k][1].fill_(-1.0)
+            # eager work on the same workspace between replays
+            eap.nn1(q, qo, r, ro, P["msm"], precision=0, ws=ws["msm"], stream=s)
+            g.launch(stream=s)
+            s.synchronize()
+            for k in synth.SIX:
+                assert torch.equal(outs[k][0], want[k][0]) and torch.equal(outs[k][1], want[k][1]), (rep, k)
+    finally:
+        g.close()
+
+
+def test_capture_needs_prepared_inputs(torch_dev):
+    torch, dev = torch_dev
+    qv, qo = synth.pack([np.linspace(0, 1, 30)])
+    rv, ro = synth.pack([np.linspace(1, 0, 30), np.zeros(20)])
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    s = torch.cuda.Stream(dev)
+    ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, dict(kind="dtw")), dev)
+    out = (torch.empty(1, dtype=torch.int64, device=dev), torch.empty(1, dtype=torch.float64, device=dev), None)
+    eap.capture_begin(s)
+    with pytest.raises(eap.EapError, match="prepared"):
+        eap.nn1(q, qo, r, ro, dict(kind="dtw"), ws=ws, stream=s, out=out)
+    eap.capture_end(s).close()
+
+
 @pytest.mark.parametrize("kind", synth.SIX)
 def test_nn1_parity_class_templates(torch_dev, orc, kind):
     """Workload-2 data (five warped sine classes, length 512), subsampled."""
