@@ -148,6 +148,8 @@ def main():
 
     if args.workload == 4:
         return run_batched(args, torch, eap, synth)
+    if args.workload == 5:
+        return run_served(args, torch, eap, synth)
 
     dev = torch.device("cuda:0")
     kinds = [k for k in args.kinds.split(",") if k]
@@ -488,6 +490,71 @@ def run_batched(args, torch, eap, synth):
         step_ms_p50=float(np.percentile(step_ms, 50)), step_ms_p99=float(np.percentile(step_ms, 99)),
         graph_results_identical_to_eager=same, tuning=tuning, per_distance=per, plain_gpu_dp=plain,
         roofline=roofline, cpu_baseline=cpu)), flush=True)
+
+
+def run_served(args, torch, eap, synth):
+    """Workload 5: a request server over 50,000 resident random walks (lengths
+    128..1024); queries (lengths 128..1024) arrive as a Poisson process at
+    2,000 q/s and are answered in batches on 4 slots (FP32 screen + FP64
+    recheck, admission by memory).  Latency = arrival -> result on the host.
+    Also the closed-loop capacity: every query submitted at once."""
+    dev = torch.device("cuda:0")
+    wl = synth.make_workload(5, n_ref=args.refs or None, n_query=args.queries or None)
+    ro, qo = wl["ref_off"], wl["query_off"]
+    nr, nq = len(ro) - 1, len(qo) - 1
+    r = torch.from_numpy(wl["refs"]).to(dev)
+    qs = [wl["queries"][qo[i]: qo[i + 1]] for i in range(nq)]
+    arrivals = wl["arrivals"][:nq]
+    kinds = [k for k in args.kinds.split(",") if k in wl["params"]] or list(wl["params"])
+    out = {}
+    for k in kinds:
+        p = wl["params"][k]
+        if not args.no_tune:   # shapes for this distance, on a sample of the traffic
+            eap.tune_nn1(torch.from_numpy(wl["queries"][: qo[32]]).to(dev), qo[:33], r, ro, p, precision=1)
+
+        def serve(times):
+            srv = eap.Server(r, ro, p, slots=4, max_batch=64, max_query_len=1024, mem_budget=8 << 30, precision=1)
+            done = {}
+            try:
+                t0 = time.perf_counter()
+                i = 0
+                while len(done) < nq:
+                    now = time.perf_counter() - t0
+                    while i < nq and times[i] <= now:
+                        srv.submit(qs[i], i)
+                        i += 1
+                    res = srv.poll()
+                    tnow = time.perf_counter() - t0
+                    for tag, idx, dist, _ in res:
+                        done[tag] = (tnow, idx, dist)
+                    if not res and (i == nq or times[i] > tnow + 2e-4):
+                        time.sleep(1e-4)
+                st = srv.stats()
+            finally:
+                srv.close()
+            lat = np.array([done[j][0] - times[j] for j in range(nq)]) * 1e3
+            span = max(v[0] for v in done.values()) - times[0]
+            return lat, span, st, done
+
+        serve(np.zeros(nq))   # warm-up: every query at once
+        lat, span, st, done = serve(arrivals - arrivals[0])
+        cap_lat, cap_span, cap_st, cap_done = serve(np.zeros(nq))
+        same = all(done[j][1:] == cap_done[j][1:] for j in range(nq))
+        offered = nq / (arrivals[-1] - arrivals[0])
+        out[k] = dict(offered_qps=offered, achieved_qps=nq / span, p50_ms=float(np.percentile(lat, 50)),
+                      p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
+                      capacity_qps=nq / cap_span, batches=st["batches"], max_batch=st["max_batch_seen"],
+                      max_inflight=st["max_inflight"], results_identical_to_closed_loop=same)
+    k0 = kinds[0]
+    print(json.dumps(dict(
+        metric=METRIC, value=out[k0]["achieved_qps"], unit="queries/s", n_gpus=1, steps=1, warmup=1,
+        ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32+f64",
+        data="synthetic",
+        config=dict(workload=f"served 1-NN: {nr} resident random walks (lengths 128..1024), {nq} queries "
+                             "(lengths 128..1024) arriving as a Poisson process at 2000 q/s, CDTW w=5% and "
+                             "MSM c=0.5, FP32 screen + FP64 recheck, 4 slots x batches of at most 64",
+                    candidates=nr, queries=nq, distances=kinds),
+        per_distance=out)), flush=True)
 
 
 def _source_hash():

@@ -219,6 +219,50 @@ eap_status eap_capture_end(void* stream, eap_graph** out);
 eap_status eap_graph_launch(eap_graph* g, void* stream);
 eap_status eap_graph_destroy(eap_graph* g);
 
+/* Request server: 1-NN queries arriving one by one against a candidate set
+ * resident on the device, answered in batches that overlap on the device.
+ * The caller owns the candidate arrays (they must outlive the server); the
+ * server allocates, once, in eap_server_create(), a device pool of
+ * mem_budget bytes split evenly into `slots`, plus pinned host buffers.
+ * Queries wait in a FIFO (host copies of their values).  eap_server_poll()
+ * never blocks: it returns the results of batches that have completed, then
+ * admits waiting queries into every free slot, as many (at most max_batch, in
+ * arrival order) as fit the slot's bytes with their values, NN workspace and
+ * outputs (admission by memory), and starts each such batch as one eap_nn1
+ * call on the slot's own stream.  Each result is the one eap_nn1 gives for
+ * that query alone (NN search does not couple queries).  One thread at a
+ * time per server.  Errors of these calls are reported by
+ * eap_server_last_error(). */
+typedef struct eap_server eap_server;
+typedef struct {
+    int32_t slots;          /* batches in flight at most, 1..16 */
+    int32_t max_batch;      /* queries per batch at most */
+    int64_t max_query_len;  /* longest query accepted */
+    size_t mem_budget;      /* device bytes for all slots */
+    int32_t precision;      /* as eap_nn_opts */
+    double margin_rel;
+} eap_server_opts;
+typedef struct {
+    int64_t tag;      /* as submitted */
+    int64_t idx;      /* NN index, -1 when no candidate is finite */
+    double dist;      /* its distance, or +inf */
+    int32_t label;    /* r_labels[idx], or -1 */
+    int32_t status;   /* 0 */
+} eap_result;
+typedef struct {
+    int64_t batches, queries, max_batch_seen, max_inflight, waiting;
+} eap_server_stats;
+eap_status eap_server_create(const double* refs, const int64_t* r_off, int64_t nr, const int32_t* r_labels,
+                             const eap_params* p, const eap_server_opts* o, eap_server** out);
+/* Queue a query of `len` host float64 values (copied). */
+eap_status eap_server_submit(eap_server* s, const double* q, int64_t len, int64_t tag);
+/* Up to `cap` results into `out` (host), their number in *n; see above. */
+eap_status eap_server_poll(eap_server* s, eap_result* out, int32_t cap, int32_t* n);
+eap_status eap_server_stats_get(const eap_server* s, eap_server_stats* out);
+/* Waits for the batches in flight and frees everything (NULL is accepted). */
+eap_status eap_server_destroy(eap_server* s);
+const char* eap_server_last_error(void);
+
 /* Host utility: the WDTW weights the library uses for longer length L,
  * out[k] = w(k) = 1 / (1 + exp(-g * (k - L/2))) for k = 0..L-1 (eq. WDTW with
  * w_max = 1).  `out` is HOST memory of L doubles.  Lets a caller check the

@@ -19,7 +19,8 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "tune_nn1", "tune_reset", "capture_begin", "capture_end", "Graph"]
+           "FLAG_PLAIN", "FLAG_PREPARED", "tune_nn1", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
 FLAG_PLAIN = 2        # plain full DP for every pair: the baseline
@@ -64,6 +65,21 @@ class TuneRec(ctypes.Structure):
     _fields_ = [("g", ctypes.c_int32), ("c", ctypes.c_int32), ("ms", ctypes.c_float), ("chosen", ctypes.c_int32)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_query_len", ctypes.c_int64),
+                ("mem_budget", ctypes.c_size_t), ("precision", ctypes.c_int32), ("margin_rel", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("idx", ctypes.c_int64), ("dist", ctypes.c_double),
+                ("label", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("queries", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64),
+                ("max_inflight", ctypes.c_int64), ("waiting", ctypes.c_int64)]
+
+
 _lib = None
 _vp, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _pi64 = ctypes.POINTER(ctypes.c_int64)
@@ -104,6 +120,18 @@ def lib():
         L.eap_tune_nn1.restype = ctypes.c_int
         L.eap_tune_nn1.argtypes = [_vp, _pi64, _i64, _vp, _pi64, _i64, _pP, _pO, _vp, _sz, _vp, _vp, _vp,
                                    ctypes.POINTER(TuneRec), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.eap_server_create.restype = ctypes.c_int
+        L.eap_server_create.argtypes = [_vp, _pi64, _i64, _vp, _pP, ctypes.POINTER(ServerOpts),
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        L.eap_server_submit.restype = ctypes.c_int
+        L.eap_server_submit.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64, _i64]
+        L.eap_server_poll.restype = ctypes.c_int
+        L.eap_server_poll.argtypes = [_vp, ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.eap_server_stats_get.restype = ctypes.c_int
+        L.eap_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+        L.eap_server_destroy.restype = ctypes.c_int
+        L.eap_server_destroy.argtypes = [_vp]
+        L.eap_server_last_error.restype = ctypes.c_char_p
         L.eap_capture_begin.restype = ctypes.c_int
         L.eap_capture_begin.argtypes = [_vp]
         L.eap_capture_end.restype = ctypes.c_int
@@ -263,6 +291,67 @@ class Graph:
     def close(self):
         if self._h:
             _check(lib().eap_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(status: int):
+    if status != EAP_OK:
+        raise EapError(status, lib().eap_server_last_error().decode(errors="replace"))
+
+
+class Server:
+    """Request server over a resident candidate set (see eap_server_* in
+    include/eap.h): submit() queues a query (host values), poll() returns the
+    finished (tag, idx, dist, label) tuples and admits waiting queries into
+    free slots without blocking."""
+
+    def __init__(self, refs, r_off, p, ref_labels=None, slots: int = 4, max_batch: int = 32,
+                 max_query_len: int = 2048, mem_budget: int = 4 << 30, precision: int = 1,
+                 margin_rel: float = 1e-4):
+        import torch
+        _dev_f64(refs, "candidates")
+        self._refs = refs
+        self._labels = ref_labels
+        self._r_off = _offsets(r_off)
+        self._p = _as_params(p)
+        o = ServerOpts(int(slots), int(max_batch), int(max_query_len), int(mem_budget), int(precision),
+                       float(margin_rel))
+        lab = None
+        if ref_labels is not None:
+            if ref_labels.dtype != torch.int32 or not ref_labels.is_cuda:
+                raise TypeError("ref_labels must be an int32 device tensor")
+            lab = ref_labels.data_ptr()
+        h = ctypes.c_void_p(None)
+        _scheck(lib().eap_server_create(refs.data_ptr(), self._r_off.ctypes.data_as(_pi64), len(self._r_off) - 1,
+                                        lab, ctypes.byref(self._p), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._buf = (Result * 4096)()
+
+    def submit(self, values, tag: int) -> None:
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        _scheck(lib().eap_server_submit(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(v),
+                                        int(tag)))
+
+    def poll(self) -> list:
+        n = ctypes.c_int32(0)
+        _scheck(lib().eap_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(n)))
+        return [(r.tag, r.idx, r.dist, r.label) for r in self._buf[:n.value]]
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _scheck(lib().eap_server_stats_get(self._h, ctypes.byref(s)))
+        return dict(batches=s.batches, queries=s.queries, max_batch_seen=s.max_batch_seen,
+                    max_inflight=s.max_inflight, waiting=s.waiting)
+
+    def close(self) -> None:
+        if self._h:
+            _scheck(lib().eap_server_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -20,7 +20,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["eap_rows.hip", "eap_band.hip", "eap_aux.hip", "eap_api.cpp"]
+SOURCES = ["eap_rows.hip", "eap_band.hip", "eap_aux.hip", "eap_api.cpp", "eap_serve.cpp"]
 # The sweep kernels are built with -fno-honor-nans: none of their cells is ever
 # NaN, so min/max need no quieting of signalling NaNs and values are unchanged
 # (no reassociation or contraction).  The host-side ABI is not: its argument

@@ -425,8 +425,15 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     if (e0 && e1) HIPCHK(hipEventRecord(e0, s));
     (void)hipGetLastError();   // launch errors below must be this launch's own
     hipError_t e;
-    if (band) e = launch_band(kind, fp32, pl.size, a, SA, SB, sweep_grid(n, band_group(pl.size)), s);
-    else e = launch_rows(kind, fp32, sh, a, SA, SB, rows_grid(n, sh.g), s);
+    const int lanes = band ? band_group(pl.size) : sh.g;
+    const int grid = band ? sweep_grid(n, lanes) : rows_grid(n, lanes);
+    // slots per queue atomic: about 8 chunks per group, so that short items
+    // (infeasible windows) do not serialise on the counter and long ones still
+    // balance; one at a time when the count is only known on the device
+    const int64_t groups = (int64_t)grid * (256 / lanes);
+    a.chunk = a.npairs_dev ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(32, n / (groups * 8)));
+    if (band) e = launch_band(kind, fp32, pl.size, a, SA, SB, grid, s);
+    else e = launch_rows(kind, fp32, sh, a, SA, SB, grid, s);
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     if (e0 && e1) {
         HIPCHK(hipEventRecord(e1, s));

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
     const T gap = (T)A.gap;
 
     bool have = false, done = false, fin = false, ovf = false, lo_open = false, hi_open = false;
+    unsigned int fnext = 0, fend = 0;   // this group's chunk of work slots
     int32_t qa = 0;
     int64_t out = 0, item = 0;
     const T* li = nullptr;
@@ -90,9 +91,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
     for (;;) {
         if (!have && !done) {
             for (;;) {
-                unsigned int p = 0;
-                if (k == 0) p = atomicAdd(A.queue, 1u);
-                p = __shfl(p, lane - k);
+                const unsigned int p = fetch_slot(A, fnext, fend, lane, k);
                 const int64_t n_items = A.npairs_dev ? (int64_t)*A.npairs_dev : A.npairs;
                 if ((int64_t)p >= n_items) {
                     done = true;

@@ -27,6 +27,7 @@ struct SweepArgs {
     // index, PM_SINGLE at [0].  +inf when abandoned.
     double* res;
     unsigned int* queue;             // work counter, zero at launch
+    int chunk;                       // work slots taken per atomic on `queue` (>= 1)
     unsigned long long* counters;    // [0] cells executed, [1] pairs swept, [3] band overflows
     unsigned long long* stage;       // [0] cells of this launch's stage, [8] its pairs
     // plain DP: cut-off +inf for every item, no best-so-far, no abandoning

@@ -73,6 +73,21 @@ template <typename T> __device__ __forceinline__ T nn_cut(const SweepArgs& A, in
     return t;
 }
 
+// Work slots are handed to a group A.chunk at a time (one atomic per chunk,
+// consecutive slots); `next`/`end` are the group's current chunk.
+__device__ __forceinline__ unsigned int fetch_slot(const SweepArgs& A, unsigned int& next, unsigned int& end,
+                                                   int lane, int k) {
+    if (next >= end) {
+        const unsigned int ch = A.chunk > 0 ? (unsigned int)A.chunk : 1u;
+        unsigned int base = 0;
+        if (k == 0) base = atomicAdd(A.queue, ch);
+        base = __shfl(base, lane - k);
+        next = base;
+        end = base + ch;
+    }
+    return next++;
+}
+
 // Sum of a per-lane counter over the wave, added once per wave.
 __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);

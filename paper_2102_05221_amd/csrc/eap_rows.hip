@@ -67,6 +67,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     T* const eb = A.edge ? reinterpret_cast<T*>(A.edge) + gid * A.edge_stride : nullptr;
 
     bool have = false, done = false;
+    unsigned int fnext = 0, fend = 0;   // this group's chunk of work slots
     int32_t qa = 0;
     int64_t out = 0;
     // Every lane loads its row inputs at every step, also in groups without a
@@ -184,9 +185,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
         if (!have && !done) {
             // fetch the next work item for this group
             for (;;) {
-                unsigned int p = 0;
-                if (k == 0) p = atomicAdd(A.queue, 1u);
-                p = __shfl(p, lane - k);
+                const unsigned int p = fetch_slot(A, fnext, fend, lane, k);
                 const int64_t n_items = A.npairs_dev ? (int64_t)*A.npairs_dev : A.npairs;
                 if ((int64_t)p >= n_items) {
                     done = true;

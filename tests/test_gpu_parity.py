@@ -213,6 +213,51 @@ def test_capture_needs_prepared_inputs(torch_dev):
     eap.capture_end(s).close()
 
 
+@pytest.mark.parametrize("p", [dict(kind="cdtw", window_ratio=0.05), dict(kind="msm", c=0.5)], ids=pid)
+def test_server_results_alone_and_in_the_mix(torch_dev, orc, p):
+    """Workload-5 shape, reduced: queries of uneven lengths submitted while
+    earlier batches run (several slots in flight, batches of several queries)
+    get exactly the result each gets alone, which is the oracle's."""
+    import time
+    torch, dev = torch_dev
+    rng = np.random.default_rng(55)
+    rs = synth.random_walks(rng, 300, (128, 400))
+    qs = synth.random_walks(rng, 40, (128, 400))
+    rs[17] = qs[3].copy()
+    rv, ro = synth.pack(rs)
+    r = to_dev(torch, dev, rv)
+    srv = eap.Server(r, ro, p, slots=3, max_batch=6, max_query_len=400, mem_budget=1 << 30, precision=1)
+    got = {}
+    try:
+        log(f"server {pid(p)}: staggered submits")
+        for i, qv in enumerate(qs):
+            srv.submit(qv, i)
+            if i % 4 == 3:
+                for tag, idx, dist, _ in srv.poll():
+                    got[tag] = (idx, dist)
+        t0 = time.time()
+        while len(got) < len(qs):
+            assert time.time() - t0 < 120, "server did not finish"
+            for tag, idx, dist, _ in srv.poll():
+                got[tag] = (idx, dist)
+            time.sleep(0.001)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["queries"] == len(qs) and st["batches"] >= 2 and st["max_batch_seen"] >= 2
+    log(f"server {pid(p)}: alone")
+    for i, qv in enumerate(qs):
+        qd = to_dev(torch, dev, qv)
+        gi, gd, _ = eap.nn1(qd, np.array([0, len(qv)]), r, ro, p, precision=1)
+        torch.cuda.synchronize()
+        assert got[i] == (int(gi.item()), float(gd.item())), i
+    qv_all, qo_all = synth.pack(qs)
+    oi, od, _ = orc.nn1(p, qv_all, qo_all, rv, ro, "dp")
+    assert [got[i][0] for i in range(len(qs))] == list(oi)
+    assert [got[i][1] for i in range(len(qs))] == list(od)
+    assert got[3] == (17, 0.0)
+
+
 @pytest.mark.parametrize("kind", synth.SIX)
 def test_nn1_parity_class_templates(torch_dev, orc, kind):
     """Workload-2 data (five warped sine classes, length 512), subsampled."""
