@@ -84,7 +84,8 @@ def swept_kind(kind, p):
 
 def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist):
     """The CPU oracle's EAPruned NN (Alg. 1 + Alg. 5) on the first nq_sample
-    queries against all candidates, every host thread."""
+    queries against all candidates, every host thread; beside it the same on
+    one thread and the oracle's full DP, on the first query."""
     from oracle import oracle as orc
     qo = wl["query_off"][: nq_sample + 1]
     qv = wl["queries"][: qo[-1]]
@@ -98,10 +99,84 @@ def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist):
         secs += time.perf_counter() - t0
         cells += dense_cells(kind, p, qo, wl["ref_off"])
         match &= bool(np.array_equal(idx, gpu_idx[kind][:nq_sample]) and np.array_equal(dist, gpu_dist[kind][:nq_sample]))
+    # the same sample by the oracle's full DP (every thread), and the first
+    # query by EAPruned on one thread
+    sd = 0.0
+    q1o = wl["query_off"][:2]
+    q1 = wl["queries"][: q1o[-1]]
+    c1 = s1 = 0.0
+    for kind in kinds:
+        p = wl["params"][kind]
+        t0 = time.perf_counter()
+        orc.nn1(p, qv, qo, wl["refs"], wl["ref_off"], "dp")
+        sd += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        orc.nn1(p, q1, q1o, wl["refs"], wl["ref_off"], "eap", nthreads=1)
+        s1 += time.perf_counter() - t0
+        c1 += dense_cells(kind, p, q1o, wl["ref_off"])
     return dict(value=cells / secs / 1e9, unit="GCUPS", cores=orc.num_threads(), kind="oracle",
                 sample=f"EAPruned NN of the first {nq_sample} queries against all {len(wl['ref_off']) - 1} "
                        f"candidates, {len(kinds)} distances, {secs:.1f} s",
-                nn_identical_to_gpu=match)
+                nn_identical_to_gpu=match,
+                full_dp_gcups=cells / sd / 1e9,
+                one_core_gcups=c1 / s1 / 1e9,
+                one_core_sample="EAPruned NN of the first query, one thread")
+
+
+def run_pairwise(args, torch, eap, synth):
+    """Workload 3: all pairs of 2,000 random walks of length 1024 (1,999,000
+    pairs), DTW, CDTW (w = 5%) and MSM, FP64: prune-only EAPruned (each pair's
+    cut-off one ulp above its path bound, so every value is exact) against the
+    plain full DP."""
+    dev = torch.device("cuda:0")
+    wl = synth.make_workload(3, n_ref=args.refs or None)
+    so = wl["ref_off"]
+    n = len(so) - 1
+    s = torch.from_numpy(wl["refs"]).to(dev)
+    kinds = [k for k in args.kinds.split(",") if k in wl["params"]] or list(wl["params"])
+    per = {}
+    tot_cells = 0
+    tot_ms = 0.0
+    for k in kinds:
+        p = wl["params"][k]
+        ws = eap.workspace(eap.pairwise_workspace_bytes(so, p), dev)
+        out = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device=dev)
+        res = {}
+        for mode in ("prune", "full"):
+            eap.pairwise(s, so, p, mode, ws=ws, out=out)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            eap.reset_counters(ws)
+            a.record()
+            for _ in range(args.steps):
+                eap.pairwise(s, so, p, mode, ws=ws, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / args.steps
+            c = eap.read_counters(ws)
+            res[mode] = (ms, c["cells"] / args.steps, out.clone())
+        # dense cells: all pairs (band cells for CDTW)
+        lens = np.diff(so)
+        if k == "cdtw":   # ordered pairs minus the diagonal, halved
+            diag = sum(dense_cells(k, p, so[i:i + 2] - so[i], so[i:i + 2] - so[i]) for i in range(n))
+            cells = (dense_cells(k, p, so, so) - diag) // 2
+        else:
+            cells = int((lens.sum() ** 2 - (lens ** 2).sum()) // 2)
+        same = bool(torch.equal(res["prune"][2], res["full"][2]))
+        per[k] = dict(prune_ms=res["prune"][0], full_ms=res["full"][0], speedup=res["full"][0] / res["prune"][0],
+                      dense_cells=cells, prune_executed_fraction=res["prune"][1] / cells,
+                      prune_gcups_effective=cells / (res["prune"][0] * 1e-3) / 1e9,
+                      full_gcups=cells / (res["full"][0] * 1e-3) / 1e9, identical=same)
+        tot_cells += cells
+        tot_ms += res["prune"][0]
+        del ws, out
+    print(json.dumps(dict(
+        metric=METRIC, value=tot_cells / (tot_ms * 1e-3) / 1e9, unit="GCUPS", n_gpus=1, steps=args.steps,
+        warmup=1, ms_per_step=tot_ms, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+        data="synthetic",
+        config=dict(workload=f"all pairs of {n} random walks, length 1024, prune-only EAPruned vs plain DP: "
+                             + ", ".join(kinds), series=n, pairs=n * (n - 1) // 2, distances=kinds),
+        per_distance=per)), flush=True)
 
 
 def main():
@@ -120,10 +195,10 @@ def main():
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 plain device copies of this many MiB (HBM counter calibration) and exit")
-    ap.add_argument("--workload", type=int, default=2, choices=(2, 4, 5),
-                    help="2: the benchmark (500 x 500, length 512); 4: batched uneven lengths, graph launch; "
-                         "5: served requests")
-    ap.add_argument("--refs", type=int, default=0, help="workloads 4/5: candidate count (0: the full workload)")
+    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5),
+                    help="2: the benchmark (500 x 500, length 512); 3: all-pairs matrix; 4: batched uneven "
+                         "lengths, graph launch; 5: served requests")
+    ap.add_argument("--refs", type=int, default=0, help="workloads 3-5: series / candidate count (0: the full workload)")
     ap.add_argument("--queries", type=int, default=0, help="workloads 4/5: query count (0: the full workload)")
     args = ap.parse_args()
     if args.copy_mib > 0:
@@ -146,6 +221,8 @@ def main():
     import paper_2102_05221_amd as eap
     from paper_2102_05221_amd import synth
 
+    if args.workload == 3:
+        return run_pairwise(args, torch, eap, synth)
     if args.workload == 4:
         return run_batched(args, torch, eap, synth)
     if args.workload == 5:
@@ -298,6 +375,32 @@ def main():
                      gcups=sum(dense.values()) / (total_plain_ms * 1e-3) / 1e9,
                      speedup_of_eapruned=total_plain_ms / ms_per_step, nn_identical=same)
 
+    # the same step with the six searches on six streams: their latency-bound
+    # stages overlap with other searches' sweeps (a secondary figure: kernel
+    # times above come from the serial step, where kernels do not overlap)
+    concurrent = None
+    if kstream is None and len(kinds) > 1:
+        cs = {k: torch.cuda.Stream(dev) for k in kinds}
+
+        def cstep():
+            for k in kinds:
+                cs[k].wait_stream(stream)
+                eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k],
+                        out=outs[k], precision=args.precision, stream=cs[k])
+            for k in kinds:
+                stream.wait_stream(cs[k])
+
+        cstep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            cstep()
+        torch.cuda.synchronize()
+        cms = (time.perf_counter() - t1) * 1e3 / args.steps
+        csame = all(np.array_equal(outs[k][0].cpu().numpy(), gpu_idx[k]) and
+                    np.array_equal(outs[k][1].cpu().numpy(), gpu_dist[k]) for k in kinds)
+        concurrent = dict(ms_per_step=cms, value=sum(dense.values()) / (cms * 1e-3) / 1e9, nn_identical=csame)
+
     other = None
     if args.compare_precision:
         op = 1 - args.precision
@@ -338,6 +441,7 @@ def main():
                     queries=nq, candidates=nr, length=512, distances=kinds,
                     precision=("fp32 screen + fp64 recheck" if args.precision else "fp64")),
         other_precision=other,
+        six_streams=concurrent,
         tuning=tuning,
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)),

@@ -505,15 +505,16 @@ double orc_ub(int kind, const double* x, int64_t lx, const double* y, int64_t ly
  * with the full DP; mode 1 with EAPruned using the current best as cut-off.
  * Out: index (-1 when no candidate has a finite distance) and distance.
  * cells_total (nullable) sums EAPruned's evaluated cells.  Queries run in
- * parallel over nthreads OpenMP threads (<= 0: library default). */
+ * parallel over nthreads OpenMP threads (<= 0: the OpenMP default); the
+ * count applies to this call only. */
 void orc_nn1(int kind, const double* prm, const double* q, const int64_t* q_off, int64_t nq, const double* r,
              const int64_t* r_off, int64_t nr, int mode, int64_t* out_idx, double* out_dist, int nthreads,
              int64_t* cells_total)
 {
     int64_t cells_sum = 0;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : cells_sum)
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : cells_sum) num_threads(nt)
 #endif
     for (int64_t a = 0; a < nq; ++a) {
         const double* qa = q + q_off[a];
@@ -549,8 +550,8 @@ void orc_pairwise(int kind, const double* prm, const double* s, const int64_t* s
                   double* out, int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
 #endif
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i + 1; j < n; ++j) {
