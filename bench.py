@@ -75,6 +75,34 @@ def dense_cells(kind, p, q_off, r_off):
     return int((cells * np.outer(cq, cr)).sum())
 
 
+def kernel_label(rec):
+    """Name of a sweep launch: kernel, width (strip columns or band diagonals),
+    lanes per pair x columns per lane."""
+    g = rec["group"]
+    c = rec["size"] // g if rec["kernel"] == "rows" else rec["size"] // (2 * g)
+    return f"{rec['kernel']}{rec['size']} {g}x{c}"
+
+
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/*_hbm.md), valid only while the kernel sources are the
+    ones it was measured on; (None, reason) otherwise."""
+    pdir = os.path.join(ROOT, "profiles")
+    for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if not fn.endswith("_hbm.md"):
+            continue
+        lines = open(os.path.join(pdir, fn)).read().splitlines()
+        hashes = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("source_hash:")]
+        if not hashes or hashes[0] != _source_hash():
+            continue
+        for ln in lines:
+            cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+            if len(cells) >= 2 and cells[0] == kernel:
+                return float(cells[1]), f"HBM bytes per launch, profiles/{fn} (FETCH_SIZE + WRITE_SIZE, " \
+                                        "copy-calibrated)"
+    return None, "no counter summary for this kernel and these sources in profiles/"
+
+
 def swept_kind(kind, p):
     """The distance the library sweeps (CDTW without a window is DTW)."""
     if kind == "cdtw" and p.get("window_ratio", math.inf) >= 1:
@@ -304,7 +332,7 @@ def main():
         per[k] = dict(
             sweep_ms_per_step=sum(x["ms"] for x in prof if x["kind"] == sk) / args.steps,
             main_sweep_ms=(sum(x["ms"] for x in main) / len(main)) if main else None,
-            main_kernel=(f"{main[0]['kernel']}{main[0]['size']}" if main else None),
+            main_kernel=(kernel_label(main[0]) if main else None),
             main_fp32=bool(main[0]["fp32"]) if main else False,
             recheck_ms_per_step=sum(x["ms"] for x in rechk) / args.steps,
             executed_cells_per_step=counters[k]["cells"] / args.steps,
@@ -334,19 +362,7 @@ def main():
                     cells_per_launch=d["main_cells_per_launch"])
     # HBM bytes per launch from the committed rocprofv3 counter summary, valid
     # only while the kernel sources are the ones it was measured on
-    pdir = os.path.join(ROOT, "profiles")
-    for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
-        if not fn.endswith("_hbm.md"):
-            continue
-        kv = {}
-        for ln in open(os.path.join(pdir, fn)):
-            if ":" in ln and not ln.startswith(("#", " ", "|")):
-                key, _, val = ln.partition(":")
-                kv[key.strip()] = val.strip()
-        if kv.get("kernel") == roofline["kernel"] and kv.get("source_hash") == _source_hash():
-            roofline["traffic"] = float(kv["hbm_bytes_per_launch"])
-            roofline["traffic_note"] = f"HBM bytes per launch, profiles/{fn} (FETCH_SIZE and WRITE_SIZE, " \
-                                       "copy-calibrated)"
+    roofline["traffic"], roofline["traffic_note"] = hbm_traffic(roofline["kernel"])
 
     # plain full DP on the GPU, same searches (outside the timed region)
     plain = None
@@ -534,7 +550,7 @@ def run_batched(args, torch, eap, synth):
         main = [x for x in prof if x["kind"] == sk and x["stage"] == 2]
         per[k] = dict(sweep_ms=sum(x["ms"] for x in prof if x["kind"] == sk),
                       main_sweep_ms=sum(x["ms"] for x in main),
-                      main_kernel=(f"{main[0]['kernel']}{main[0]['size']}" if main else None),
+                      main_kernel=(kernel_label(main[0]) if main else None),
                       main_fp32=bool(main[0]["fp32"]) if main else False,
                       main_cells=counters[k]["stage_cells"][2], dense_cells=dense[k],
                       executed_fraction=counters[k]["cells"] / dense[k] if dense[k] else None,

@@ -42,7 +42,7 @@
 
 namespace eap {
 
-__device__ __forceinline__ int shl1_i32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int shl1_i32(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ float shl1(float v) {
     return __builtin_bit_cast(float, shl1_i32(__builtin_bit_cast(int, v)));
 }

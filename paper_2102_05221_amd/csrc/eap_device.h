@@ -20,10 +20,10 @@ __device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf
 __device__ __forceinline__ double vabs(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float vabs(float a) { return __builtin_fabsf(a); }
 
-// Lane k receives lane k-1's value (DPP wave_shr:1; lane 0 receives 0).  Must
-// be executed with every lane of the wave active, so that the source lanes
-// hold defined values.
-__device__ __forceinline__ int shr1_i32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+// Lane k receives lane k-1's value (DPP wave_shr:1; lane 0 receives 0 through
+// bound_ctrl, so no old value has to be set up).  Must be executed with every
+// lane of the wave active, so that the source lanes hold defined values.
+__device__ __forceinline__ int shr1_i32(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 __device__ __forceinline__ float shr1(float v) {
     return __builtin_bit_cast(float, shr1_i32(__builtin_bit_cast(int, v)));
 }

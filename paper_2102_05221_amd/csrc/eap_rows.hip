@@ -102,10 +102,11 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
     // strip) or the previous strip's edge, +inf outside its live rows.  Every
     // lane loads (rows clamped into 1..L_li, so every address is in bounds) and
     // only lane 0's values are used: no branch in the step.
-    auto s_at = [&](int r) -> T { return li[(r < 1 ? 1 : (r > Lli ? Lli : r)) - 1]; };
-    auto b_at = [&](int r) -> T {
-        const T v = load_nc(bp + (r < 1 ? 1 : (r > Lli ? Lli : r)));
-        return (r >= e_lo && r <= e_hi) ? v : INF;
+    auto load_row = [&](int r, T& sv, T& bv) {
+        const unsigned rc = (unsigned)__builtin_elementwise_min(__builtin_elementwise_max(r, 1), Lli);
+        sv = li[rc - 1u];
+        const T x = load_nc(bp + rc);
+        bv = (r >= e_lo && r <= e_hi) ? x : INF;   // e_hi < e_lo: no live row
     };
 
     // Set up the strip si of the current pair.
@@ -175,10 +176,8 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
         sp = 0;
         rec_lo = 1 << 30;
         rec_hi = -1;
-        s_n1 = s_at(row + 1);
-        s_n2 = s_at(row + 2);
-        b_n1 = b_at(row + 1);
-        b_n2 = b_at(row + 2);
+        load_row(row + 1, s_n1, b_n1);
+        load_row(row + 2, s_n2, b_n2);
     };
 
     for (;;) {
@@ -252,8 +251,7 @@ __global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Se
             }
             s_n1 = s_n2;
             b_n1 = b_n2;
-            s_n2 = s_at(row + 2);
-            b_n2 = b_at(row + 2);
+            load_row(row + 2, s_n2, b_n2);
             const bool ns = row < r_start;   // not started: keep the top border
             if (ns) {
                 lin = brd0;
@@ -422,6 +420,8 @@ static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid,
 template <int KIND, typename T>
 static hipError_t go_w(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
     switch (sh.g * 1000 + sh.c) {
+    case 8008: return go<KIND, T, 8, 8>(a, SA, SB, grid, s);
+    case 8016: return go<KIND, T, 8, 16>(a, SA, SB, grid, s);
     case 16008: return go<KIND, T, 16, 8>(a, SA, SB, grid, s);
     case 16016: return go<KIND, T, 16, 16>(a, SA, SB, grid, s);
     case 32008: return go<KIND, T, 32, 8>(a, SA, SB, grid, s);
@@ -448,7 +448,8 @@ int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a) {
 
 bool rows_shape_ok(int kind, RowsShape sh, bool fp32) {
     const bool c32 = fp32 && (kind == DTW || kind == CDTW || kind == WDTW);
-    return (sh.g == 16 || sh.g == 32 || sh.g == 64) && (sh.c == 8 || sh.c == 16 || (c32 && sh.c == 32));
+    return (sh.g == 8 || sh.g == 16 || sh.g == 32 || sh.g == 64) &&
+           (sh.c == 8 || sh.c == 16 || (c32 && sh.g >= 16 && sh.c == 32));
 }
 
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
