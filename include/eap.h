@@ -179,7 +179,7 @@ eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream);
  * per wavefront) with C columns per lane, in strips of G*C columns; every
  * shape gives the same results, bit for bit.  eap_tune_nn1() runs eap_nn1() on
  * the given problem (a sample of the real one, typically) once per shape, G in
- * {8, 16, 32, 64} x C in {8, 16} (and C = 32 with G >= 16 for the FP32 sweep
+ * {4, 8, 16, 32, 64} x C in {8, 16} (and C = 32 with G >= 16 for the FP32 sweep
  * of DTW and WDTW), at the precision of `o` (1: the shape of the
  * FP32 screening sweep; 0: of the FP64 sweep), checks that all shapes return
  * the same indices and distances (EAP_EDEVICE otherwise), times each over two

@@ -202,11 +202,11 @@ int rows_grid(int64_t items, int group_lanes) {
 
 // Bytes of the row sweep's strip-edge buffers for a launch over `items` work
 // slots: one column of L_li + 1 values per group, for the most groups any
-// shape launches (8 lanes per pair, 32 groups per block); none when every
-// pair fits one strip of the narrowest shape (64 columns).
+// shape launches (4 lanes per pair, 64 groups per block); none when every
+// pair fits one strip of the narrowest shape (32 columns).
 size_t edge_bytes(int64_t items, int64_t lli_max, int64_t lco_max) {
-    if (lco_max <= 64) return 0;
-    const int64_t groups = std::min<int64_t>((items + 31) / 32 * 32, (int64_t)device_cus() * kRowsBlocksPerCU * 32);
+    if (lco_max <= 32) return 0;
+    const int64_t groups = std::min<int64_t>((items + 63) / 64 * 64, (int64_t)device_cus() * kRowsBlocksPerCU * 64);
     return (size_t)groups * (size_t)(lli_max + 1) * sizeof(double);
 }
 
@@ -792,8 +792,8 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
     if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
     if (pl.band) return EAP_OK;
     hipStream_t s = (hipStream_t)stream;
-    const RowsShape all[11] = {{8, 8},   {8, 16},  {16, 8},  {16, 16}, {32, 8}, {32, 16},
-                               {64, 8},  {64, 16}, {16, 32}, {32, 32}, {64, 32}};
+    const RowsShape all[13] = {{4, 8},  {4, 16},  {8, 8},   {8, 16},  {16, 8},  {16, 16}, {32, 8},
+                               {32, 16}, {64, 8}, {64, 16}, {16, 32}, {32, 32}, {64, 32}};
     std::vector<RowsShape> shapes;
     for (const RowsShape& x : all)
         if (rows_shape_ok(effective_kind(p), x, fp32)) shapes.push_back(x);

@@ -41,7 +41,7 @@
 namespace eap {
 
 template <int KIND, typename T, int G, int C>
-__global__ __launch_bounds__(256) void rows_kernel(SweepArgs A, Series<T> SA, Series<T> SB) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(SweepArgs A, Series<T> SA, Series<T> SB) {
     constexpr int K = 8;  // steps between group decisions
     constexpr int W = G * C;
     constexpr bool DTAB = (KIND == TWE || KIND == WDTW);
@@ -420,6 +420,8 @@ static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid,
 template <int KIND, typename T>
 static hipError_t go_w(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
     switch (sh.g * 1000 + sh.c) {
+    case 4008: return go<KIND, T, 4, 8>(a, SA, SB, grid, s);
+    case 4016: return go<KIND, T, 4, 16>(a, SA, SB, grid, s);
     case 8008: return go<KIND, T, 8, 8>(a, SA, SB, grid, s);
     case 8016: return go<KIND, T, 8, 16>(a, SA, SB, grid, s);
     case 16008: return go<KIND, T, 16, 8>(a, SA, SB, grid, s);
@@ -448,7 +450,7 @@ int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a) {
 
 bool rows_shape_ok(int kind, RowsShape sh, bool fp32) {
     const bool c32 = fp32 && (kind == DTW || kind == CDTW || kind == WDTW);
-    return (sh.g == 8 || sh.g == 16 || sh.g == 32 || sh.g == 64) &&
+    return (sh.g == 4 || sh.g == 8 || sh.g == 16 || sh.g == 32 || sh.g == 64) &&
            (sh.c == 8 || sh.c == 16 || (c32 && sh.g >= 16 && sh.c == 32));
 }
 
