@@ -186,8 +186,10 @@ eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream);
  * further runs, and records the fastest for (distance, precision, class of the
  * shorter series' longest length: <=128, <=256, <=512, <=1024, <=2048) in a
  * process-wide table that every later call consults; without an entry a
- * default shape is used.  Distances the row sweep does not run (CDTW, ERP
- * with a window, WDTW in the narrow band) return EAP_OK with *n = 0.
+ * default shape is used.  Distances the band sweep runs (CDTW, ERP with a
+ * window, WDTW in its narrow band) are tuned over the band sweep's lanes per
+ * pair instead (two choices per band width of 128 to 512 diagonals, 2*G*C
+ * diagonals with C = 4 or 8), per band width; records then give G and C.
  * Synchronises `stream`; not for use while other calls are in flight.
  *  ws, ws_bytes        as for eap_nn1 (its workspace fits every shape).
  *  out_idx, out_dist   device int64[nq], double[nq]: scratch outputs.

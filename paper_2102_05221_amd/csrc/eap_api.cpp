@@ -235,7 +235,9 @@ RowsShape default_shape(int kind, bool fp32, int64_t lco_max) {
 
 std::mutex g_tune_mu;
 std::map<int, RowsShape> g_tuned;                // key: (kind * 2 + fp32) * 8 + bucket
+std::map<int, int> g_tuned_band;                 // key: (kind * 2 + fp32) * 16 + log2(diagonals)
 thread_local RowsShape g_force[2] = {{0, 0}, {0, 0}};   // [fp32], set while tuning
+thread_local int g_force_band[2] = {0, 0};
 
 RowsShape rows_shape(int kind, bool fp32, int64_t lco_max) {
     if (g_force[fp32].g) return g_force[fp32];
@@ -243,6 +245,21 @@ RowsShape rows_shape(int kind, bool fp32, int64_t lco_max) {
     auto it = g_tuned.find((kind * 2 + (fp32 ? 1 : 0)) * 8 + len_bucket(lco_max));
     if (it != g_tuned.end()) return it->second;
     return default_shape(kind, fp32, lco_max);
+}
+
+int log2i(int x) {
+    int b = 0;
+    while ((1 << (b + 1)) <= x) ++b;
+    return b;
+}
+
+// Lanes per pair of the band sweep for a band of `diags` diagonals.
+int band_lanes(int kind, bool fp32, int diags) {
+    if (g_force_band[fp32] && band_shape_ok(diags, g_force_band[fp32])) return g_force_band[fp32];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned_band.find((kind * 2 + (fp32 ? 1 : 0)) * 16 + log2i(diags));
+    if (it != g_tuned_band.end()) return it->second;
+    return band_group(diags);
 }
 
 // Shape for launches with few pairs (one per query: the seed and recheck
@@ -259,6 +276,7 @@ struct Plan {
     int band_half = 0;     // B, WDTW: half width of the certified narrow band
     bool rerun = false;    // B, WDTW: items the narrow band cannot certify go to kernel A
     RowsShape r64{16, 16}, r32{16, 16};   // kernel A shapes per precision
+    int bg64 = 16, bg32 = 16;             // kernel B lanes per pair per precision
 };
 
 eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_t l_diff_max, bool narrow_first,
@@ -276,6 +294,8 @@ eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_
         int64_t wb = std::min<int64_t>(w + (kind == EAP_ERP ? 1 : 0), lmax);
         pl->size = pick_diags(2 * wb + 2);
         if (!pl->size) return fail(EAP_EINVAL, "window too wide for the band sweep");
+        pl->bg64 = band_lanes(kind, false, pl->size);
+        pl->bg32 = band_lanes(kind, true, pl->size);
         return EAP_OK;
     }
     // WDTW in an NN search with lengths that differ little: a certified narrow
@@ -285,6 +305,8 @@ eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_
         pl->size = 256;
         pl->band_half = (int)std::max<int64_t>(16, (256 - 2 - l_diff_max) / 2);
         pl->rerun = true;
+        pl->bg64 = band_lanes(kind, false, pl->size);
+        pl->bg32 = band_lanes(kind, true, pl->size);
     }
     return EAP_OK;
 }
@@ -425,14 +447,14 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     if (e0 && e1) HIPCHK(hipEventRecord(e0, s));
     (void)hipGetLastError();   // launch errors below must be this launch's own
     hipError_t e;
-    const int lanes = band ? band_group(pl.size) : sh.g;
+    const int lanes = band ? (fp32 ? pl.bg32 : pl.bg64) : sh.g;
     const int grid = band ? sweep_grid(n, lanes) : rows_grid(n, lanes);
     // slots per queue atomic: about 8 chunks per group, so that short items
     // (infeasible windows) do not serialise on the counter and long ones still
     // balance; one at a time when the count is only known on the device
     const int64_t groups = (int64_t)grid * (256 / lanes);
     a.chunk = a.npairs_dev ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(32, n / (groups * 8)));
-    if (band) e = launch_band(kind, fp32, pl.size, a, SA, SB, grid, s);
+    if (band) e = launch_band(kind, fp32, pl.size, lanes, a, SA, SB, grid, s);
     else e = launch_rows(kind, fp32, sh, a, SA, SB, grid, s);
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     if (e0 && e1) {
@@ -440,7 +462,7 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
         std::lock_guard<std::mutex> lk(g_prof.mu);
         ProfRec pr;
         pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, band ? pl.size : sh.g * sh.c, fp32 ? 1 : 0, 0.0f,
-                               band ? band_group(pl.size) : sh.g};
+                               lanes};
         pr.e0 = e0;
         pr.e1 = e1;
         g_prof.pending.push_back(pr);
@@ -790,13 +812,18 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     Plan pl;
     if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
-    if (pl.band) return EAP_OK;
+    const bool band = pl.band;
     hipStream_t s = (hipStream_t)stream;
     const RowsShape all[13] = {{4, 8},  {4, 16},  {8, 8},   {8, 16},  {16, 8},  {16, 16}, {32, 8},
                                {32, 16}, {64, 8}, {64, 16}, {16, 32}, {32, 32}, {64, 32}};
-    std::vector<RowsShape> shapes;
-    for (const RowsShape& x : all)
-        if (rows_shape_ok(effective_kind(p), x, fp32)) shapes.push_back(x);
+    std::vector<RowsShape> shapes;   // band sweep: {lanes, columns per lane}
+    if (band) {
+        for (int g : {4, 8, 16, 32, 64})
+            if (band_shape_ok(pl.size, g)) shapes.push_back(RowsShape{g, pl.size / (2 * g)});
+    } else {
+        for (const RowsShape& x : all)
+            if (rows_shape_ok(effective_kind(p), x, fp32)) shapes.push_back(x);
+    }
     std::vector<int64_t> idx0((size_t)nq), idx((size_t)nq);
     std::vector<double> d0((size_t)nq), d((size_t)nq);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -806,7 +833,8 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
     int best = -1, k = 0;
     st = EAP_OK;
     for (int v = 0; v < (int)shapes.size() && st == EAP_OK; ++v) {
-        g_force[fp32] = shapes[v];
+        if (band) g_force_band[fp32] = shapes[v].g;
+        else g_force[fp32] = shapes[v];
         st = eap_nn1(q, q_off, nq, r, r_off, nr, nullptr, p, o, ws, ws_bytes, out_idx, out_dist, nullptr, stream);
         if (st != EAP_OK) break;
         if (hipMemcpyAsync(idx.data(), out_idx, sizeof(int64_t) * (size_t)nq, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -842,13 +870,17 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
         ++k;
     }
     g_force[fp32] = RowsShape{0, 0};
+    g_force_band[fp32] = 0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != EAP_OK) return st;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[(effective_kind(p) * 2 + (fp32 ? 1 : 0)) * 8 + len_bucket(std::min(Q.maxlen, R.maxlen))] =
-            shapes[best];
+        if (band)
+            g_tuned_band[(effective_kind(p) * 2 + (fp32 ? 1 : 0)) * 16 + log2i(pl.size)] = shapes[best].g;
+        else
+            g_tuned[(effective_kind(p) * 2 + (fp32 ? 1 : 0)) * 8 + len_bucket(std::min(Q.maxlen, R.maxlen))] =
+                shapes[best];
     }
     if (best < cap) recs[best].chosen = 1;
     *n = k < cap ? k : cap;
@@ -904,6 +936,7 @@ eap_status eap_graph_destroy(eap_graph* g) {
 eap_status eap_tune_reset(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
+    g_tuned_band.clear();
     return EAP_OK;
 }
 

@@ -367,32 +367,46 @@ static hipError_t gob(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid
 }
 
 template <int KIND, typename T>
-static hipError_t gob_d(int diags, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
-    switch (diags) {
-    case 128: return gob<KIND, T, 16, 4>(a, SA, SB, grid, s);
-    case 256: return gob<KIND, T, 16, 8>(a, SA, SB, grid, s);
-    case 512: return gob<KIND, T, 32, 8>(a, SA, SB, grid, s);
-    case 1024: return gob<KIND, T, 64, 8>(a, SA, SB, grid, s);
-    case 2048: return gob<KIND, T, 64, 16>(a, SA, SB, grid, s);
+static hipError_t gob_d(int diags, int g, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
+    switch (diags * 100 + g) {
+    case 12808: return gob<KIND, T, 8, 8>(a, SA, SB, grid, s);
+    case 12816: return gob<KIND, T, 16, 4>(a, SA, SB, grid, s);
+    case 25616: return gob<KIND, T, 16, 8>(a, SA, SB, grid, s);
+    case 25632: return gob<KIND, T, 32, 4>(a, SA, SB, grid, s);
+    case 51232: return gob<KIND, T, 32, 8>(a, SA, SB, grid, s);
+    case 51264: return gob<KIND, T, 64, 4>(a, SA, SB, grid, s);
+    case 102464: return gob<KIND, T, 64, 8>(a, SA, SB, grid, s);
+    case 204864: return gob<KIND, T, 64, 16>(a, SA, SB, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_band(int kind, bool fp32, int diags, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s) {
+// The compiled band shapes: 4 or 8 diagonals per parity and lane (more only
+// for the widest band; the band's rings and weights make wider lanes spill out
+// of the register file).
+bool band_shape_ok(int diags, int g) {
+    switch (diags * 100 + g) {
+    case 12808: case 12816: case 25616: case 25632: case 51232: case 51264: case 102464: case 204864: return true;
+    }
+    return false;
+}
+
+hipError_t launch_band(int kind, bool fp32, int diags, int g, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B,
+                       int grid, hipStream_t s) {
+    if (!band_shape_ok(diags, g)) return hipErrorInvalidValue;
     if (fp32) {
         switch (kind) {
-        case DTW: return gob_d<DTW, float>(diags, a, A, B, grid, s);
-        case CDTW: return gob_d<CDTW, float>(diags, a, A, B, grid, s);
-        case WDTW: return gob_d<WDTW, float>(diags, a, A, B, grid, s);
-        case ERP: return gob_d<ERP, float>(diags, a, A, B, grid, s);
+        case DTW: return gob_d<DTW, float>(diags, g, a, A, B, grid, s);
+        case CDTW: return gob_d<CDTW, float>(diags, g, a, A, B, grid, s);
+        case WDTW: return gob_d<WDTW, float>(diags, g, a, A, B, grid, s);
+        case ERP: return gob_d<ERP, float>(diags, g, a, A, B, grid, s);
         }
     } else {
         switch (kind) {
-        case DTW: return gob_d<DTW, double>(diags, a, A, B, grid, s);
-        case CDTW: return gob_d<CDTW, double>(diags, a, A, B, grid, s);
-        case WDTW: return gob_d<WDTW, double>(diags, a, A, B, grid, s);
-        case ERP: return gob_d<ERP, double>(diags, a, A, B, grid, s);
+        case DTW: return gob_d<DTW, double>(diags, g, a, A, B, grid, s);
+        case CDTW: return gob_d<CDTW, double>(diags, g, a, A, B, grid, s);
+        case WDTW: return gob_d<WDTW, double>(diags, g, a, A, B, grid, s);
+        case ERP: return gob_d<ERP, double>(diags, g, a, A, B, grid, s);
         }
     }
     return hipErrorInvalidValue;

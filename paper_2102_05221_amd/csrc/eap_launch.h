@@ -79,9 +79,11 @@ hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, Se
 int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a);
 bool rows_shape_ok(int kind, RowsShape sh, bool fp32);
 
-// Band sweep (kernel B): anti-diagonal sweep of a band of 2*G*C diagonals.
-hipError_t launch_band(int kind, bool fp32, int diags, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s);
+// Band sweep (kernel B): anti-diagonal sweep of a band of diags = 2*G*C
+// diagonals with G lanes per pair (C in {4, 8, 16}).
+hipError_t launch_band(int kind, bool fp32, int diags, int g, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B,
+                       int grid, hipStream_t s);
+bool band_shape_ok(int diags, int g);
 
 // Auxiliary kernels.
 hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s);

@@ -258,6 +258,32 @@ def test_server_results_alone_and_in_the_mix(torch_dev, orc, p):
     assert got[3] == (17, 0.0)
 
 
+@pytest.mark.parametrize("p", [dict(kind="cdtw", window_ratio=0.1), dict(kind="erp", gap=0.3, window_ratio=0.2),
+                               dict(kind="wdtw", g=0.05)], ids=pid)
+def test_tuner_band_shapes_agree(torch_dev, orc, p):
+    """The band sweep's lane counts (windowed CDTW/ERP, WDTW's narrow band:
+    lengths within 64 of each other) agree bit for bit and with the oracle."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(45)
+    qs = synth.random_walks(rng, 6, (400, 440))
+    rs = synth.random_walks(rng, 30, (400, 440))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    for precision in (0, 1):
+        log(f"band tuner {pid(p)} precision={precision}")
+        try:
+            recs = eap.tune_nn1(q, qo, r, ro, p, precision=precision)
+            assert len(recs) == 2 and sum(x["chosen"] for x in recs) == 1
+            gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision)
+            torch.cuda.synchronize()
+        finally:
+            eap.tune_reset()
+        oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+        assert np.array_equal(gi.cpu().numpy(), oi)
+        assert np.array_equal(gd.cpu().numpy(), od)
+
+
 @pytest.mark.parametrize("kind", synth.SIX)
 def test_nn1_parity_class_templates(torch_dev, orc, kind):
     """Workload-2 data (five warped sine classes, length 512), subsampled."""
