@@ -87,8 +87,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
     T adv[KIND == TWE ? C : 1];   // TWE: |s_{i-1} - t_j| of the previous row
     T dwin[NW];                   // per-diagonal terms of this block
     T dg = 0, lout = 0, sout = 0, sp = 0, tpm = 0, brd0 = 0, s0 = 0;
-    // lane 0's inputs for the next two rows (row + 1, row + 2): s_i and M(i, cb)
-    T s_n1 = 0, s_n2 = 0, b_n1 = 0, b_n2 = 0;
+    // Lane 0's inputs of a block's K rows (s_i and M(i, cb)) are staged across
+    // the group: lane j holds rows R0 + 1 + j + G*i (i < RS; R0 = lane 0's row
+    // before the block), loaded one block ahead, and lane 0 reads the one for
+    // each step with a cross-lane permute.
+    constexpr int RS = (K + G - 1) / G;
+    T st_s[RS], st_b[RS], nx_s[RS], nx_b[RS];
+#pragma unroll
+    for (int i = 0; i < RS; ++i) st_s[i] = st_b[i] = nx_s[i] = nx_b[i] = 0;
     const T* bp = SA.v - 1;  // left inputs: bp[i] = M(i, cb) for e_lo <= i <= e_hi
     unsigned long long ncells = 0, npairs = 0;
 #pragma unroll
@@ -176,8 +182,9 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
         sp = 0;
         rec_lo = 1 << 30;
         rec_hi = -1;
-        load_row(row + 1, s_n1, b_n1);
-        load_row(row + 2, s_n2, b_n2);
+        // the first block's row inputs (the loop stages each next block)
+#pragma unroll
+        for (int i = 0; i < RS; ++i) load_row(row + k + 1 + k + G * i, st_s[i], st_b[i]);
     };
 
     for (;;) {
@@ -234,6 +241,10 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
             }
         }
 
+        // stage the next block's row inputs (lane 0's row is row + k)
+#pragma unroll
+        for (int i = 0; i < RS; ++i) load_row(row + k + K + 1 + k + G * i, nx_s[i], nx_b[i]);
+
         bool live_any = false;
         // One step: every lane computes its columns for its current row, reading
         // the previous row from `src` and writing `dst` (the two buffers
@@ -245,13 +256,16 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
             T lin = shr1(lout);
             T sin = shr1(sout);
             row += 1;
-            if (k == 0) {
-                lin = b_n1;   // M(row, cb)
-                sin = s_n1;   // s_row
+            {
+                // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G
+                const int src = lane - k + (t % G);
+                const T bv = __shfl(st_b[t / G], src);   // M(row, cb)
+                const T sv = __shfl(st_s[t / G], src);   // s_row
+                if (k == 0) {
+                    lin = bv;
+                    sin = sv;
+                }
             }
-            s_n1 = s_n2;
-            b_n1 = b_n2;
-            load_row(row + 2, s_n2, b_n2);
             const bool ns = row < r_start;   // not started: keep the top border
             if (ns) {
                 lin = brd0;
@@ -338,6 +352,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
         for (int t = 0; t < K; t += 2) {
             step(val, vb, t >= K - 2, t);
             step(vb, val, t + 1 >= K - 2, t + 1);
+        }
+#pragma unroll
+        for (int i = 0; i < RS; ++i) {
+            st_s[i] = nx_s[i];
+            st_b[i] = nx_b[i];
         }
         if (have) {
             // rows of this block in r_start..L_li: the cells counted as executed
