@@ -203,6 +203,12 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
                         int64_t nr, const eap_params* p, const eap_nn_opts* o, void* ws, size_t ws_bytes,
                         int64_t* out_idx, double* out_dist, void* stream, eap_tune_rec* recs, int32_t cap,
                         int32_t* n);
+/* Records row-sweep shape g x c for (kind, precision 0/1, the length class of
+ * lco_max, the shorter series' longest length), as eap_tune_nn1 would; lets
+ * a caller reuse tuning results or pin a shape.  EINVAL for shapes that do
+ * not exist.  The distance swept as DTW (CDTW without a window) is keyed as
+ * DTW. */
+eap_status eap_tune_set(int32_t kind, int32_t precision, int64_t lco_max, int32_t g, int32_t c);
 /* Forgets every tuned shape (later calls use the defaults). */
 eap_status eap_tune_reset(void);
 

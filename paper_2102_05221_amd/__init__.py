@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "tune_nn1", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "FLAG_PLAIN", "FLAG_PREPARED", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
@@ -140,6 +140,8 @@ def lib():
         L.eap_graph_launch.argtypes = [_vp, _vp]
         L.eap_graph_destroy.restype = ctypes.c_int
         L.eap_graph_destroy.argtypes = [_vp]
+        L.eap_tune_set.restype = ctypes.c_int
+        L.eap_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int32, _i64, ctypes.c_int32, ctypes.c_int32]
         L.eap_tune_reset.restype = ctypes.c_int
         L.eap_tune_reset.argtypes = []
         L.eap_wdtw_weights.restype = ctypes.c_int
@@ -271,6 +273,11 @@ def tune_nn1(q, q_off, r, r_off, p, precision: int = 0, margin_rel: float = 1e-4
                               ws.numel(), idx.data_ptr(), dist.data_ptr(), _stream(stream, q.device), recs, 16,
                               ctypes.byref(n)))
     return [dict(g=x.g, c=x.c, ms=float(x.ms), chosen=bool(x.chosen)) for x in recs[:n.value]]
+
+
+def tune_set(kind: str, precision: int, lco_max: int, g: int, c: int) -> None:
+    """Pin the row-sweep shape g x c for a distance, precision and length class."""
+    _check(lib().eap_tune_set(KINDS[kind], int(precision), int(lco_max), int(g), int(c)))
 
 
 def tune_reset() -> None:

@@ -933,6 +933,17 @@ eap_status eap_graph_destroy(eap_graph* g) {
     return EAP_OK;
 }
 
+eap_status eap_tune_set(int32_t kind, int32_t precision, int64_t lco_max, int32_t g, int32_t c) {
+    if (kind < EAP_DTW || kind > EAP_TWE || (precision != 0 && precision != 1) || lco_max < 1 ||
+        lco_max > kMaxLen)
+        return fail(EAP_EINVAL, "bad tuning key");
+    const RowsShape sh{g, c};
+    if (!rows_shape_ok(kind, sh, precision == 1)) return fail(EAP_EINVAL, "no row-sweep shape %dx%d", g, c);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[(kind * 2 + precision) * 8 + len_bucket(lco_max)] = sh;
+    return EAP_OK;
+}
+
 eap_status eap_tune_reset(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();

@@ -284,6 +284,79 @@ def test_tuner_band_shapes_agree(torch_dev, orc, p):
         assert np.array_equal(gd.cpu().numpy(), od)
 
 
+ROW_SHAPES64 = [(4, 8), (4, 16), (8, 8), (8, 16), (16, 8), (16, 16), (32, 8), (32, 16), (64, 8), (64, 16)]
+
+
+def test_distance_random_shapes_and_cutoffs(torch_dev, orc):
+    """Seeded random cases: distance, parameters, lengths 1..2048, a pinned
+    row-sweep shape (so most pairs run in several strips) and a cut-off at,
+    just below or under the distance: bit-identical to the oracle."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(2024)
+    kinds = ["dtw", "wdtw", "erp", "msm", "twe", "cdtw"]
+    nbad = 0
+    try:
+        for case in range(60):
+            kind = kinds[case % len(kinds)]
+            p = dict(kind=kind)
+            if kind == "wdtw":
+                p["g"] = float(rng.choice([0.0, 0.01, 0.05, 0.3]))
+            if kind == "erp":
+                p["gap"] = float(rng.normal())
+            if kind == "msm":
+                p["c"] = float(rng.choice([0.0, 0.1, 0.5, 2.0]))
+            if kind == "twe":
+                p["nu"], p["lam"] = float(rng.choice([0.0, 0.001, 0.1])), float(rng.choice([0.0, 0.5, 1.0]))
+            if kind == "cdtw":
+                p["window_ratio"] = float(rng.choice([0.02, 0.1, 0.3]))
+            lx = int(rng.integers(1, 2049)) if case % 3 else int(rng.integers(1, 300))
+            ly = int(rng.integers(max(1, lx // 3), 2049)) if case % 3 else int(rng.integers(1, 300))
+            x = synth.znorm(np.cumsum(rng.normal(size=lx))) if lx > 1 else rng.normal(size=1)
+            y = synth.znorm(np.cumsum(rng.normal(size=ly))) if ly > 1 else rng.normal(size=1)
+            g, c = ROW_SHAPES64[int(rng.integers(len(ROW_SHAPES64)))]
+            eap.tune_reset()
+            eap.tune_set("dtw" if kind == "cdtw" else kind, 0, min(lx, ly), g, c)
+            d = orc.dp(p, x, y)
+            cut = [INF, d, float(np.nextafter(d, -INF)), 0.7 * d][case % 4] if d < INF else INF
+            log(f"random case {case}: {pid(p)} lx={lx} ly={ly} shape {g}x{c} cut={cut}")
+            got = float(eap.distance(to_dev(torch, dev, x), to_dev(torch, dev, y), p, cut).item())
+            want = d if d <= cut else INF
+            nbad += not (got == want)
+            assert close(got, want), (case, got, want)
+    finally:
+        eap.tune_reset()
+    assert nbad == 0
+
+
+@pytest.mark.parametrize("kind", ["dtw", "wdtw", "erp", "msm", "twe"])
+def test_nn1_every_row_shape(torch_dev, orc, kind):
+    """NN over ragged sets (lengths 1..600) with every row-sweep shape pinned in
+    turn, FP64 and FP32 screen: each gives the oracle's result."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(77)
+    qs = synth.random_walks(rng, 5, (1, 600))
+    rs = synth.random_walks(rng, 25, (1, 600))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(synth.DEFAULT_PARAMS[kind])
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    lco = min(max(np.diff(qo)), max(np.diff(ro)))
+    try:
+        for precision in (0, 1):
+            shapes = ROW_SHAPES64 + ([(16, 32), (32, 32), (64, 32)] if precision and kind in ("dtw", "wdtw") else [])
+            for g, c in shapes:
+                eap.tune_reset()
+                eap.tune_set(kind, precision, lco, g, c)
+                log(f"nn1 {kind} precision={precision} shape {g}x{c}")
+                gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision)
+                torch.cuda.synchronize()
+                assert np.array_equal(gi.cpu().numpy(), oi), (g, c)
+                assert np.array_equal(gd.cpu().numpy(), od), (g, c)
+    finally:
+        eap.tune_reset()
+
+
 @pytest.mark.parametrize("kind", synth.SIX)
 def test_nn1_parity_class_templates(torch_dev, orc, kind):
     """Workload-2 data (five warped sine classes, length 512), subsampled."""
