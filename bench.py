@@ -142,7 +142,13 @@ def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist):
         orc.nn1(p, q1, q1o, wl["refs"], wl["ref_off"], "eap", nthreads=1)
         s1 += time.perf_counter() - t0
         c1 += dense_cells(kind, p, q1o, wl["ref_off"])
+    model = ""
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=cells / secs / 1e9, unit="GCUPS", cores=orc.num_threads(), kind="oracle",
+                host=dict(cpu_model=model, logical_cpus=os.cpu_count()),
                 sample=f"EAPruned NN of the first {nq_sample} queries against all {len(wl['ref_off']) - 1} "
                        f"candidates, {len(kinds)} distances, {secs:.1f} s",
                 nn_identical_to_gpu=match,
@@ -489,8 +495,8 @@ def run_batched(args, torch, eap, synth):
                 torch.empty(nq, dtype=torch.int32, device=dev)) for k in kinds}
     dense = {k: dense_cells(k, P[k], qo, ro) for k in kinds}
 
-    # shapes tuned on a sample (64 queries x 2000 candidates), untimed
-    sq, sr = min(64, nq), min(2000, nr)
+    # shapes tuned on a sample (100 queries x every candidate), untimed
+    sq, sr = min(100, nq), nr
     tq, tr = q[: qo[sq]], r[: ro[sr]]
     tuning = {}
     if not args.no_tune:
