@@ -209,6 +209,9 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
         }
         if (__all(done)) break;
 
+        // the query's best-so-far, read now and applied at the block end (a cut-off
+        // one block old is only larger, so still safe)
+        const T cut_next = (nn && have) ? nn_cut<T>(A, qa) : INF;
         bool live_any = false;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
                 }
                 have = false;
             } else {
-                if (nn) cut = vmin(cut, nn_cut<T>(A, qa));
+                if (nn) cut = vmin(cut, cut_next);
                 i0 += CB;
                 j0 += CB;
                 if constexpr (AHEAD) {

@@ -244,6 +244,9 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
         // stage the next block's row inputs (lane 0's row is row + k)
 #pragma unroll
         for (int i = 0; i < RS; ++i) load_row(row + k + K + 1 + k + G * i, nx_s[i], nx_b[i]);
+        // the query's best-so-far, read now and applied at the block end (a cut-off
+        // one block old is only larger, so still safe)
+        const T cut_next = (nn && have) ? nn_cut<T>(A, qa) : INF;
 
         bool live_any = false;
         // One step: every lane computes its columns for its current row, reading
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
             have = false;
             if (k == 0) ++npairs;
         } else if (have && nn) {
-            cut = vmin(cut, nn_cut<T>(A, qa));
+            cut = vmin(cut, cut_next);
         }
         // the edge stores of this wave complete before the next strip reads them
         if (__any(next_strip)) __builtin_amdgcn_s_waitcnt(0);
