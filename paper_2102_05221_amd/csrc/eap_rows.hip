@@ -42,9 +42,14 @@ namespace eap {
 
 template <int KIND, typename T, int G, int C>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(SweepArgs A, Series<T> SA, Series<T> SB) {
-    constexpr int K = 8;  // steps between group decisions
-    constexpr int W = G * C;
     constexpr bool DTAB = (KIND == TWE || KIND == WDTW);
+    // steps between group decisions: long blocks share the block-end work
+    // (ballots, cut-off, strip and pair bookkeeping) among more steps, and
+    // stage more row inputs per lane (K / G) and, for TWE and WDTW, keep
+    // C + K - 1 per-diagonal terms in registers; the distances with the most
+    // registers per column (MSM, TWE, WDTW) take shorter blocks with wide lanes
+    constexpr int K = (C > 8 && (KIND == MSM || DTAB)) ? 16 : 32;
+    constexpr int W = G * C;
     constexpr int NW = DTAB ? C + K - 1 : 1;
     extern __shared__ unsigned char lds_raw[];
     T* tab = reinterpret_cast<T*>(lds_raw);
