@@ -662,7 +662,23 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
                         reinterpret_cast<double*>(at(ws, nl.rT)), res, s));
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
     const bool rerun = pl.rerun;
-    // FP32 screen: sweep single-precision copies under a widened cut-off first
+    // the seed and recheck sweeps have one or a few pairs per query
+    Plan few = pl;
+    few.r64 = few.r32 = latency_shape(std::min(Q.maxlen, R.maxlen));
+    if (seeded) {
+        // 2. sweep the seed candidate of every query under its bound, in FP64
+        //    also when screening: its exact distance is the tightest start for
+        //    both passes, and the recheck need not compute it again
+        if ((st = sweep(p, few, pl.band, a, h, 0, &h->queues[0], seed_items, nq, SQ, SR, s)) != EAP_OK) return st;
+        if (rerun) {
+            if ((st = rerun_overflow(p, few, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], SQ, SR, s)) !=
+                EAP_OK)
+                return st;
+            HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
+        }
+        a.skip_b = seed;
+    }
+    // FP32 screen: sweep single-precision copies under a widened cut-off
     SeriesPtrs XQ = SQ, XR = SR;
     if (screen) {
         float* q32 = reinterpret_cast<float*>(at(ws, nl.q32));
@@ -683,24 +699,11 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         HIPCHK(launch_absmax(q, Q.total, &h->absmax, s));
         HIPCHK(launch_absmax(r, R.total, &h->absmax, s));
         double* widen = reinterpret_cast<double*>(at(ws, nl.widen));
+        // best[q] is now the seed's FP64 distance or the path bound: the widening
+        // at it bounds every best-so-far of the FP32 pass
         HIPCHK(launch_screen_widen(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, widen, s));
         a.widen_abs = widen;
         a.widen_rel = o->margin_rel;
-    }
-    // the seed and recheck sweeps have one or a few pairs per query
-    Plan few = pl;
-    few.r64 = few.r32 = latency_shape(std::min(Q.maxlen, R.maxlen));
-    if (seeded) {
-        // 2. sweep the seed candidate of every query under its bound
-        if ((st = sweep(p, few, pl.band, a, h, 0, &h->queues[0], seed_items, nq, XQ, XR, s, screen)) != EAP_OK)
-            return st;
-        if (rerun) {
-            if ((st = rerun_overflow(p, few, a, h, 1, &h->ovf_count[0], ovf, nq, &h->queues[1], XQ, XR, s, screen)) !=
-                EAP_OK)
-                return st;
-            HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
-        }
-        a.skip_b = seed;
     }
     // 3. every other pair, under the per-query best-so-far (lowered as pairs complete)
     if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, XQ, XR, s, screen)) != EAP_OK)
@@ -712,10 +715,11 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     }
     if (screen) {
         // 3b. candidates within the certified FP32 error of each query's best are
-        //     recomputed in FP64; every other result becomes +inf
+        //     recomputed in FP64 (the seed keeps its FP64 distance); every other
+        //     result becomes +inf
         int32_t* items = reinterpret_cast<int32_t*>(at(ws, nl.recheck));
         HIPCHK(launch_screen_filter(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, o->margin_rel, res,
-                                    best, nullptr, items, &h->ovf_count[2], &h->counters[2], s));
+                                    best, seeded ? seed : nullptr, items, &h->ovf_count[2], &h->counters[2], s));
         HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
         SweepArgs b = a;
         b.widen_abs = nullptr;

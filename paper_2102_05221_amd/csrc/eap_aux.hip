@@ -368,16 +368,19 @@ __global__ void screen_widen_kernel(int kind, SweepArgs A, const int64_t* qoff, 
 }
 
 // After the FP32 sweep: every candidate of query q whose FP32 distance is
-// <= b32 + 2 eps(screen_bound(b32)) is listed for the FP64 recheck.  The FP64
-// NN cannot be elsewhere: its exact cost is <= that of the FP32 winner, which
-// is <= screen_bound(b32), and its FP32 value exceeds that by at most eps.
-// The margin m widens b32 by a relative (1 + m) on top.  The result slots are
-// reset to +inf, and best[q] becomes screen_bound(b32), an upper bound on the
-// FP64 NN distance that serves as the recheck's first cut-off.  One wave per query.
+// <= b + 2 eps(screen_bound(b)) is listed for the FP64 recheck, where b is the
+// best-so-far (the least FP32 distance, or the seed's FP64 distance).  The
+// FP64 NN cannot be elsewhere: its exact cost is <= that of the winner, which
+// is <= screen_bound(b), and its FP32 value exceeds that by at most eps.  The
+// margin m widens b by a relative (1 + m) on top.  The seed (seed[q], swept in
+// FP64 before the screen) keeps its FP64 distance and is not listed; every
+// other result slot is reset to +inf, and best[q] becomes the smaller of
+// screen_bound(b) and the seed's distance, an upper bound on the FP64 NN
+// distance that serves as the recheck's first cut-off.  One wave per query.
 __global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
                                      const unsigned long long* absmax, double margin_rel, double* res,
-                                     unsigned long long* best, int32_t* items, unsigned int* count,
-                                     unsigned long long* rechecks) {
+                                     unsigned long long* best, const int32_t* seed, int32_t* items,
+                                     unsigned int* count, unsigned long long* rechecks) {
     const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (q >= A.nA) return;
@@ -391,8 +394,11 @@ __global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff,
         cut64 = screen_bound(kind, b, N, Amax);
         thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);
     }
+    const int64_t sb = seed ? (int64_t)seed[q] : -1;
+    const double dseed = (sb >= 0) ? res[q * A.nB + sb] : __builtin_huge_val();
     unsigned long long n = 0;
     for (int64_t r = lane; r < A.nB; r += 64) {
+        if (r == sb) continue;
         const int64_t p = q * A.nB + r;
         if (res[p] <= thr) {
             const unsigned int k = atomicAdd(count, 1u);
@@ -403,7 +409,7 @@ __global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff,
     }
     for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
     if (lane == 0) {
-        best[q] = dbits(cut64);
+        best[q] = dbits(dseed < cut64 ? dseed : cut64);
         if (n) atomicAdd(rechecks, n);
     }
 }
@@ -444,11 +450,10 @@ hipError_t launch_screen_widen(int kind, const SweepArgs& a, const int64_t* qoff
 
 hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                 const unsigned long long* absmax, double margin_rel, double* res,
-                                unsigned long long* best, double* widen_abs, int32_t* items, unsigned int* count,
+                                unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,
                                 unsigned long long* rechecks, hipStream_t s) {
-    (void)widen_abs;
     hipLaunchKernelGGL(screen_filter_kernel, dim3(blocks_for(a.nA, 4)), dim3(256), 0, s, kind, a, qoff, lr_max, gap,
-                       absmax, margin_rel, res, best, items, count, rechecks);
+                       absmax, margin_rel, res, best, seed, items, count, rechecks);
     return hipGetLastError();
 }
 

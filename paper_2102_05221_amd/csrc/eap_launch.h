@@ -102,7 +102,7 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                 const unsigned long long* absmax, double margin_rel, double* res,
-                                unsigned long long* best, double* widen_abs, int32_t* items, unsigned int* count,
+                                unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,
                                 unsigned long long* rechecks, hipStream_t s);
 hipError_t launch_screen_widen(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                const unsigned long long* absmax, double* widen_abs, hipStream_t s);

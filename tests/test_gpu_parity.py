@@ -487,7 +487,9 @@ def test_fp32_screen_gives_fp64_results(torch_dev, orc, kind):
     gi, gd = a[0].cpu().numpy(), a[1].cpu().numpy()
     bad = np.nonzero((gi != oi) | (gd != od))[0]
     assert bad.size == 0, [(int(i), int(gi[i]), float(gd[i]), int(oi[i]), float(od[i])) for i in bad]
-    assert c["rechecks"] >= 12            # at least the NN of every query
+    # the seed of each query is swept in FP64 first and not rechecked; the
+    # nudged copies of queries 0 and 1 cannot be separated in FP32 and are
+    assert c["rechecks"] >= 2
     # every listed candidate is recomputed once in FP64 (narrow-band overflows of
     # WDTW finish in the full-band rerun)
     assert c["stage_pairs"][4] + c["stage_pairs"][5] == c["rechecks"]
