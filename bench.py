@@ -347,6 +347,7 @@ def main():
             executed_fraction=counters[k]["cells"] / args.steps / dense[k],
             overflows_per_step=counters[k]["overflows"] / args.steps,
             fp64_rechecks_per_step=counters[k]["rechecks"] / args.steps,
+            lb_pruned_per_step=counters[k]["lb_pruned"] / args.steps,
         )
     gpu_idx = {k: outs[k][0].cpu().numpy() for k in kinds}
     gpu_dist = {k: outs[k][1].cpu().numpy() for k in kinds}

@@ -109,11 +109,15 @@ typedef struct {
  * pairwise and distance use stage 2. */
 typedef struct {
     uint64_t cells;          /* DP cells executed by the sweep kernels */
-    uint64_t pairs;          /* pairs swept */
+    uint64_t pairs;          /* pairs swept (CDTW NN pairs that LB_Keogh drops before
+                                the sweep are not counted here) */
     uint64_t rechecks;       /* FP64 recomputations after an FP32 screen */
     uint64_t overflows;      /* band sweeps that had to be redone wider */
     uint64_t stage_cells[8];
     uint64_t stage_pairs[8];
+    uint64_t lb_pruned;      /* CDTW NN pairs given +inf without a sweep because their
+                                LB_Keogh exceeds the cut-off: the seed's distance
+                                before the sweep, the best-so-far within it */
 } eap_counters;
 
 /* Optional timing of the sweep kernels with HIP events (off by default).
@@ -152,7 +156,12 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
  *  out_idx             device int64[nq]: index, or -1 when no candidate has a
  *                      finite distance (window too small for every one).
  *  out_dist            device double[nq]: the distance, or +inf.
- *  out_label           device int32[nq] or NULL: r_labels[idx], -1 when idx < 0. */
+ *  out_label           device int32[nq] or NULL: r_labels[idx], -1 when idx < 0.
+ * For CDTW (window ratio < 1) the search puts LB_Keogh in front of the DP
+ * (the lower-bounded search of Section 2.1, Alg. 2): a pair whose bound exceeds the
+ * cut-off is +inf without a sweep.  The bound uses the query's envelope over
+ * the widest window any of its pairs has; results are those of the search
+ * without it. */
 size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off, int64_t nr, const eap_params* p,
                          const eap_nn_opts* o);
 eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,

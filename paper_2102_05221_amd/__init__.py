@@ -52,7 +52,7 @@ class NNOpts(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("rechecks", ctypes.c_uint64),
                 ("overflows", ctypes.c_uint64), ("stage_cells", ctypes.c_uint64 * 8),
-                ("stage_pairs", ctypes.c_uint64 * 8)]
+                ("stage_pairs", ctypes.c_uint64 * 8), ("lb_pruned", ctypes.c_uint64)]
 
 
 class ProfileRec(ctypes.Structure):
@@ -408,7 +408,7 @@ def read_counters(ws, stream=None) -> dict:
     c = Counters()
     _check(lib().eap_read_counters(ws.data_ptr(), ws.numel(), ctypes.byref(c), _stream(stream, ws.device)))
     return dict(cells=c.cells, pairs=c.pairs, rechecks=c.rechecks, overflows=c.overflows,
-                stage_cells=list(c.stage_cells), stage_pairs=list(c.stage_pairs))
+                stage_cells=list(c.stage_cells), stage_pairs=list(c.stage_pairs), lb_pruned=c.lb_pruned)
 
 
 def reset_counters(ws, stream=None):

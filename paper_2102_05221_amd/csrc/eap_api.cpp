@@ -110,7 +110,8 @@ struct Header {
     // [16+s] pairs of stage s (s < 8)
     unsigned long long counters[32];
     unsigned int queues[16];
-    unsigned int ovf_count[4];   // [0] band overflows, [2] FP64 recheck items (u64 fills clear [0..1])
+    unsigned int ovf_count[4];   // [0] band overflows, [2] FP64 recheck items, [3] CDTW pairs past the
+                                 // lower bound (u64 fills clear [0..1])
     unsigned long long absmax;   // FP32 screen: largest |value| (double bits)
 };
 constexpr int kCounterWords = 32;
@@ -561,6 +562,7 @@ struct NNLayout {
     Layout L;
     Common c;
     size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0, rT = 0;
+    size_t env_up = 0, env_lo = 0, lb = 0;   // CDTW: query envelopes and LB_Keogh per pair
     // FP32 screen
     size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
@@ -573,6 +575,11 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
     nl.rT = nl.L.take(sizeof(double) * (size_t)(R.n * R.maxlen));
+    if (effective_kind(p) == EAP_CDTW) {
+        nl.env_up = nl.L.take(sizeof(double) * (size_t)(Q.n * R.maxlen));
+        nl.env_lo = nl.L.take(sizeof(double) * (size_t)(Q.n * R.maxlen));
+        nl.lb = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
+    }
     nl.edge = nl.L.take(edge_bytes(Q.n * R.n, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)));
     if (screen) {
         nl.q32 = nl.L.take(sizeof(float) * (size_t)Q.total);
@@ -658,8 +665,13 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         return EAP_OK;
     }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
+    const bool lbk = effective_kind(p) == EAP_CDTW;
+    double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, (int)Q.maxlen, (int)R.maxlen,
-                        reinterpret_cast<double*>(at(ws, nl.rT)), res, s));
+                        reinterpret_cast<double*>(at(ws, nl.rT)), res,
+                        lbk ? reinterpret_cast<double*>(at(ws, nl.env_up)) : nullptr,
+                        lbk ? reinterpret_cast<double*>(at(ws, nl.env_lo)) : nullptr, lb, s));
+    a.lb = lb;
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
     const bool rerun = pl.rerun;
     // the seed and recheck sweeps have one or a few pairs per query
@@ -705,8 +717,19 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         a.widen_abs = widen;
         a.widen_rel = o->margin_rel;
     }
-    // 3. every other pair, under the per-query best-so-far (lowered as pairs complete)
-    if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, XQ, XR, s, screen)) != EAP_OK)
+    // 3. every other pair, under the per-query best-so-far (lowered as pairs
+    //    complete); for CDTW only the pairs whose LB_Keogh does not already
+    //    exceed the seed's distance (listed in `ovf`, which CDTW does not use)
+    SweepArgs m = a;
+    const int32_t* main_items = nullptr;
+    if (lbk) {
+        HIPCHK(launch_lb_compact(lb, best, seeded ? seed : nullptr, nq, nr, res, ovf, &h->ovf_count[3],
+                                 &h->counters[4], s));
+        main_items = ovf;
+        m.npairs_dev = &h->ovf_count[3];
+        m.skip_b = nullptr;
+    }
+    if ((st = sweep(p, pl, pl.band, m, h, 2, &h->queues[2], main_items, nq * nr, XQ, XR, s, screen)) != EAP_OK)
         return st;
     if (rerun) {
         if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], XQ, XR, s, screen)) !=
@@ -974,6 +997,7 @@ eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out,
     out->pairs = h.counters[1];
     out->rechecks = h.counters[2];
     out->overflows = h.counters[3];
+    out->lb_pruned = h.counters[4];
     for (int s = 0; s < 8; ++s) {
         out->stage_cells[s] = h.counters[8 + s];
         out->stage_pairs[s] = h.counters[16 + s];

@@ -190,25 +190,76 @@ __global__ void interleave_kernel(const double* rv, const int64_t* roff, int64_t
     }
 }
 
+// CDTW lower bound (LB_Keogh): for candidate column j the query values within
+// the window, rows max(1, j-w)..min(L_q, j+w), span [lo_j, up_j]; every warping
+// path visits column j at such a row, so D >= sum_j dist(t_j, [lo_j, up_j])^2.
+// The envelope uses the widest window any pair of the query can have,
+// w = floor(ratio * max(L_q, longest candidate)), which only widens it (a
+// looser, still valid bound).  One block per query; columns with no row in
+// the window get (-inf, +inf) (such pairs are infeasible anyway).
+__global__ void envelope_kernel(const double* qv, const int64_t* qoff, int64_t nq, int lr_max, double ratio,
+                                double* up, double* lo) {
+    for (int64_t a = blockIdx.x; a < nq; a += gridDim.x) {
+        const double* s = qv + qoff[a];
+        const int lq = (int)(qoff[a + 1] - qoff[a]);
+        const int L = lq > lr_max ? lq : lr_max;
+        const int w = (int)floor(ratio * (double)L);
+        for (int j = threadIdx.x + 1; j <= lr_max; j += blockDim.x) {
+            const int i0 = j - w < 1 ? 1 : j - w, i1 = j + w < lq ? j + w : lq;
+            double u = -__builtin_huge_val(), l = __builtin_huge_val();
+            for (int i = i0; i <= i1; ++i) {
+                u = fmax(u, s[i - 1]);
+                l = fmin(l, s[i - 1]);
+            }
+            if (i0 > i1) {
+                u = __builtin_huge_val();
+                l = -__builtin_huge_val();
+            }
+            up[a * (int64_t)lr_max + j - 1] = u;
+            lo[a * (int64_t)lr_max + j - 1] = l;
+        }
+    }
+}
+
 // UB of every (query, candidate) pair from the interleaved candidates: a block
 // takes one query (staged in LDS, read by all lanes at once) and 256
-// candidates (one per lane, coalesced).
+// candidates (one per lane, coalesced).  For CDTW with an envelope it also
+// writes LB_Keogh of every pair (the envelope staged in LDS beside the query).
 template <int KIND>
 __global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rT,
-                               const int64_t* roff, double* ub) {
+                               const int64_t* roff, int lq_max, int lr_max, const double* env_up,
+                               const double* env_lo, double* lb, double* ub) {
     extern __shared__ double qs[];
+    double* eu = qs + lq_max;
+    double* el = eu + lr_max;
+    const bool with_lb = (KIND == CDTW) && lb != nullptr;
     const int64_t nB = A.nB;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t a = blockIdx.y; a < A.nA; a += gridDim.y) {
         const int lq = (int)(qoff[a + 1] - qoff[a]);
         __syncthreads();
         for (int k = threadIdx.x; k < lq; k += blockDim.x) qs[k] = qv[qoff[a] + k];
+        if (with_lb) {
+            for (int k = threadIdx.x; k < lr_max; k += blockDim.x) {
+                eu[k] = env_up[a * (int64_t)lr_max + k];
+                el[k] = env_lo[a * (int64_t)lr_max + k];
+            }
+        }
         __syncthreads();
         if (b < nB) {
             const int lr = (int)(roff[b + 1] - roff[b]);
             auto Q = [&](int k) { return qs[k]; };
             auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
             ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
+            if (with_lb) {
+                double acc = 0.0;
+                for (int j = 0; j < lr; ++j) {
+                    const double x = R(j), u = eu[j], l = el[j];
+                    const double e = x > u ? x - u : (x < l ? l - x : 0.0);
+                    acc = acc + e * e;
+                }
+                lb[a * nB + b] = acc;
+            }
         }
     }
 }
@@ -300,6 +351,39 @@ __global__ void argmin_kernel(const double* res, int64_t nq, int64_t nr, const i
         out_dist[q] = bv;
         if (out_label) out_label[q] = (bi >= 0 && labels) ? labels[bi] : -1;
     }
+}
+
+// CDTW NN: the pairs whose lower bound does not exceed the query's cut-off
+// after the seed sweep (the seed itself excluded), listed for the main sweep;
+// the others are +inf without a sweep.  Wave-level compaction: one atomic per
+// wave of 64 pairs.  The cut-off can only fall afterwards, so no NN is lost.
+__global__ void lb_compact_kernel(const double* lb, const unsigned long long* best, const int32_t* seed, int64_t nq,
+                                  int64_t nr, double* res, int32_t* items, unsigned int* count,
+                                  unsigned long long* pruned) {
+    const int64_t total = nq * nr;
+    const int lane = threadIdx.x & 63;
+    unsigned long long np = 0;
+    for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)); base < total;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = base + lane;
+        bool keep = false, drop = false;
+        if (p < total) {
+            const int64_t q = p / nr, r = p - q * nr;
+            if (!seed || seed[q] != (int32_t)r) {
+                keep = !(lb[p] * (1.0 - 1e-11) > bitsd(best[q]));
+                drop = !keep;
+                if (drop) res[p] = __builtin_huge_val();
+            }
+        }
+        const unsigned long long m = __ballot(keep);
+        unsigned int off = 0;
+        if (lane == 0 && m) off = atomicAdd(count, (unsigned int)__popcll(m));
+        off = __shfl(off, 0);
+        if (keep) items[off + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)p;
+        np += drop ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+    if (lane == 0 && np) atomicAdd(pruned, np);
 }
 
 // Largest |x| over a set, as the bit pattern of a non-negative double.
@@ -436,6 +520,14 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
+hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed, int64_t nq,
+                             int64_t nr, double* res, int32_t* items, unsigned int* count,
+                             unsigned long long* pruned, hipStream_t s) {
+    hipLaunchKernelGGL(lb_compact_kernel, dim3(std::min(blocks_for(nq * nr, 256), 4096)), dim3(256), 0, s, lb, best,
+                       seed, nq, nr, res, items, count, pruned);
+    return hipGetLastError();
+}
+
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s) {
     hipLaunchKernelGGL(absmax_kernel, dim3(std::min(blocks_for(n, 256 * 8), 256)), dim3(256), 0, s, v, n, out);
     return hipGetLastError();
@@ -458,18 +550,30 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
 }
 
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
-                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, hipStream_t s) {
+                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
+                        double* env_lo, double* lb, hipStream_t s) {
     hipLaunchKernelGGL(interleave_kernel, dim3(blocks_for(a.nB * (int64_t)lr_max, 256)), dim3(256), 0, s, rv, roff,
                        a.nB, lr_max, rT);
+    const bool with_lb = kind == CDTW && lb && env_up && env_lo;
+    if (with_lb)
+        hipLaunchKernelGGL(envelope_kernel, dim3(std::min<int64_t>(a.nA, 65535)), dim3(256), 0, s, qv, qoff, a.nA,
+                           lr_max, a.window_ratio, env_up, env_lo);
     const dim3 g((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>(a.nA, 65535)), b(256);
-    const size_t lds = sizeof(double) * (size_t)lq_max;
+    const size_t lds = sizeof(double) * ((size_t)lq_max + (with_lb ? 2 * (size_t)lr_max : 0));
+    double* L = with_lb ? lb : nullptr;
     switch (kind) {
-    case DTW: hipLaunchKernelGGL(ub_nn_t_kernel<DTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case CDTW: hipLaunchKernelGGL(ub_nn_t_kernel<CDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case WDTW: hipLaunchKernelGGL(ub_nn_t_kernel<WDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case ERP: hipLaunchKernelGGL(ub_nn_t_kernel<ERP>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case MSM: hipLaunchKernelGGL(ub_nn_t_kernel<MSM>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case TWE: hipLaunchKernelGGL(ub_nn_t_kernel<TWE>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case DTW: hipLaunchKernelGGL(ub_nn_t_kernel<DTW>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
+                                 env_lo, L, ub); break;
+    case CDTW: hipLaunchKernelGGL(ub_nn_t_kernel<CDTW>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
+                                  env_lo, L, ub); break;
+    case WDTW: hipLaunchKernelGGL(ub_nn_t_kernel<WDTW>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
+                                  env_lo, L, ub); break;
+    case ERP: hipLaunchKernelGGL(ub_nn_t_kernel<ERP>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
+                                 env_lo, L, ub); break;
+    case MSM: hipLaunchKernelGGL(ub_nn_t_kernel<MSM>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
+                                 env_lo, L, ub); break;
+    case TWE: hipLaunchKernelGGL(ub_nn_t_kernel<TWE>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
+                                 env_lo, L, ub); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -57,6 +57,9 @@ struct SweepArgs {
     // whose shorter series is wider than one strip; NULL = no strips
     void* edge;
     int64_t edge_stride;
+    // NN, CDTW: lower bound of each pair (at its result index); a pair whose
+    // bound exceeds the cut-off is not swept.  NULL = none
+    const double* lb;
 };
 
 // Shape of the row sweep: G lanes per pair (pairs per wave = 64 / G), C
@@ -89,9 +92,11 @@ bool band_shape_ok(int diags, int g);
 hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s);
 hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
 // Path upper bounds of all NN pairs; rT: workspace of nB * lr_max doubles for
-// the interleaved candidates.
+// the interleaved candidates.  For CDTW with env_up/env_lo (nA * lr_max
+// doubles each) and lb (nA * nB doubles), also LB_Keogh of every pair.
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
-                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, hipStream_t s);
+                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
+                        double* env_lo, double* lb, hipStream_t s);
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s);
 hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* list_a,
@@ -100,6 +105,9 @@ hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_
                          double* out_dist, int32_t* out_label, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed, int64_t nq,
+                             int64_t nr, double* res, int32_t* items, unsigned int* count,
+                             unsigned long long* pruned, hipStream_t s);
 hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                 const unsigned long long* absmax, double margin_rel, double* res,
                                 unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,

@@ -375,6 +375,25 @@ def test_nn1_parity_class_templates(torch_dev, orc, kind):
     assert np.array_equal(gl, wl["ref_labels"][oi])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
+    """CDTW (w = 10%) on workload-2 data: LB_Keogh skips pairs whose bound is
+    above the cut-off, and the NN is still the oracle's."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(2, n_ref=120, n_query=16)
+    p = wl["params"]["cdtw"]
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    ws = eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], wl["ref_off"], p, precision=1), dev)
+    eap.reset_counters(ws)
+    log(f"cdtw lower bound precision={precision}")
+    gi, gd, _ = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, precision=precision, ws=ws)
+    c = eap.read_counters(ws)
+    oi, od, _ = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "dp")
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    assert c["lb_pruned"] > 0
+
+
 def test_nn1_parity_random_walk_workload_full(torch_dev, orc):
     """Workload 1 in full: DTW, 100 x 100 random walks of length 128."""
     torch, dev = torch_dev
