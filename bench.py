@@ -4,7 +4,11 @@ One step is the whole hot path over one batch: for each of DTW, CDTW, WDTW,
 ERP, MSM and TWE, the 1-NN of 500 queries among 500 candidates (length 512,
 five time-warped sine classes, z-normalised; the paper's NN-classification
 workload at UCR scale, synthetic and seeded).  Inputs are resident in HBM
-before the timed region.
+before the timed region.  By default the six searches run pipelined: each on
+its own stream, their main sweeps one at a time (each waits for the previous
+search's main sweep through an event), their bound, seed, recheck and argmin
+stages overlapping the neighbouring main sweeps (--schedule serial: one after
+the other on one stream).
 
 Reported (one JSON line on stdout):
   value        effective GCUPS: DP cells of the plain full programme (band
@@ -231,8 +235,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
     ap.add_argument("--precision", type=int, default=1, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
     ap.add_argument("--no-tune", action="store_true", help="skip the row-sweep autotuner (default shapes)")
-    ap.add_argument("--concurrent", action="store_true",
-                    help="run the six searches of a step on six streams (default: one after the other)")
+    ap.add_argument("--schedule", default="pipelined", choices=("pipelined", "serial", "concurrent"),
+                    help="workload 2: how the six searches of a step share the GPU.  pipelined: one stream "
+                         "each, main sweeps one at a time (chained by events), the latency-bound stages "
+                         "overlapping them; serial: one after the other on one stream; concurrent: six "
+                         "streams, no ordering")
     ap.add_argument("--compare-precision", action="store_true",
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -284,18 +291,24 @@ def main():
     dense = {k: dense_cells(k, wl["params"][k], wl["query_off"], wl["ref_off"]) for k in kinds}
     stream = torch.cuda.current_stream(dev)
 
-    kstream = {k: torch.cuda.Stream(dev) for k in kinds} if args.concurrent else None
+    kstream = {k: torch.cuda.Stream(dev) for k in kinds}
+    main_done = {k: torch.cuda.Event() for k in kinds}
 
-    def step(precision=args.precision):
-        if kstream is None:
+    def step(precision=args.precision, schedule=args.schedule):
+        """One pass of the six searches.  The step starts and ends on `stream`
+        (the other streams fork from it and join it again)."""
+        if schedule == "serial":
             for k in kinds:
                 eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k],
                         out=outs[k], precision=precision)
             return
-        for k in kinds:
+        for i, k in enumerate(kinds):
             kstream[k].wait_stream(stream)
+            chain = {}
+            if schedule == "pipelined":
+                chain = dict(main_wait=main_done[kinds[i - 1]] if i > 0 else None, main_done=main_done[k])
             eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k],
-                    precision=precision, stream=kstream[k])
+                    precision=precision, stream=kstream[k], **chain)
         for k in kinds:
             stream.wait_stream(kstream[k])
 
@@ -406,31 +419,24 @@ def main():
                      gcups=sum(dense.values()) / (total_plain_ms * 1e-3) / 1e9,
                      speedup_of_eapruned=total_plain_ms / ms_per_step, nn_identical=same)
 
-    # the same step with the six searches on six streams: their latency-bound
-    # stages overlap with other searches' sweeps (a secondary figure: kernel
-    # times above come from the serial step, where kernels do not overlap)
-    concurrent = None
-    if kstream is None and len(kinds) > 1:
-        cs = {k: torch.cuda.Stream(dev) for k in kinds}
-
-        def cstep():
-            for k in kinds:
-                cs[k].wait_stream(stream)
-                eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k],
-                        out=outs[k], precision=args.precision, stream=cs[k])
-            for k in kinds:
-                stream.wait_stream(cs[k])
-
-        cstep()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            cstep()
-        torch.cuda.synchronize()
-        cms = (time.perf_counter() - t1) * 1e3 / args.steps
-        csame = all(np.array_equal(outs[k][0].cpu().numpy(), gpu_idx[k]) and
-                    np.array_equal(outs[k][1].cpu().numpy(), gpu_dist[k]) for k in kinds)
-        concurrent = dict(ms_per_step=cms, value=sum(dense.values()) / (cms * 1e-3) / 1e9, nn_identical=csame)
+    # the same step under the other schedules (secondary figures, after the
+    # timed region; the kernel times above come from the timed schedule)
+    schedules = {}
+    if len(kinds) > 1:
+        for sc in ("pipelined", "serial", "concurrent"):
+            if sc == args.schedule:
+                continue
+            step(schedule=sc)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                step(schedule=sc)
+            torch.cuda.synchronize()
+            cms = (time.perf_counter() - t1) * 1e3 / args.steps
+            csame = all(np.array_equal(outs[k][0].cpu().numpy(), gpu_idx[k]) and
+                        np.array_equal(outs[k][1].cpu().numpy(), gpu_dist[k]) for k in kinds)
+            schedules[sc] = dict(ms_per_step=cms, value=sum(dense.values()) / (cms * 1e-3) / 1e9,
+                                 nn_identical=csame)
 
     other = None
     if args.compare_precision:
@@ -472,7 +478,8 @@ def main():
                     queries=nq, candidates=nr, length=512, distances=kinds,
                     precision=("fp32 screen + fp64 recheck" if args.precision else "fp64")),
         other_precision=other,
-        six_streams=concurrent,
+        schedule=args.schedule,
+        other_schedules=schedules,
         tuning=tuning,
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)),

@@ -94,11 +94,23 @@ typedef struct {
  *              bit 2: prepared: a previous call on this workspace had the same
  *              offsets and parameters, so their host-to-device copies are
  *              skipped and the call enqueues kernels only.  Required while the
- *              stream is being captured into a graph (see eap_capture_begin). */
+ *              stream is being captured into a graph (see eap_capture_begin).
+ *  main_wait   hipEvent_t or NULL: the stream waits for it before the main
+ *              sweep (after the bounds, the seed sweep and the screen set-up).
+ *  main_done   hipEvent_t or NULL: recorded on the stream right after the main
+ *              sweep (and its band re-run), before the recheck and the argmin.
+ *              Several searches, each on its own stream and chained by these
+ *              events (search k waits for search k-1's main_done), run their
+ *              throughput-bound main sweeps one at a time while the
+ *              latency-bound stages of the neighbouring searches overlap
+ *              them.  Both must be NULL while the stream is being captured.
+ *              The caller owns the events; results do not depend on them. */
 typedef struct {
     int32_t precision;
     double margin_rel;
     int32_t flags;
+    void* main_wait;
+    void* main_done;
 } eap_nn_opts;
 
 /* Counters accumulated in a workspace by the calls that use it (zero them with

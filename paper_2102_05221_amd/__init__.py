@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
 
 
 class NNOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("margin_rel", ctypes.c_double), ("flags", ctypes.c_int32)]
+    _fields_ = [("precision", ctypes.c_int32), ("margin_rel", ctypes.c_double), ("flags", ctypes.c_int32),
+                ("main_wait", ctypes.c_void_p), ("main_done", ctypes.c_void_p)]
 
 
 class Counters(ctypes.Structure):
@@ -218,18 +219,32 @@ def nn1_workspace_bytes(q_off, r_off, p, precision: int = 0) -> int:
                                        len(r_off) - 1, ctypes.byref(p), ctypes.byref(o)))
 
 
+def _event_handle(ev, stream, device):
+    """The hipEvent_t of a torch.cuda.Event (None for None); torch creates the
+    event at its first record, so an unrecorded one is recorded once first."""
+    if ev is None:
+        return None
+    if not ev.cuda_event:
+        import torch
+        ev.record(stream if stream is not None else torch.cuda.current_stream(device))
+    return ctypes.c_void_p(ev.cuda_event)
+
+
 def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: float = 1e-4, flags: int = 0,
-        ws=None, stream=None, out=None):
+        ws=None, stream=None, out=None, main_wait=None, main_done=None):
     """1-NN search (Alg. 1).  q, r: float64 device tensors of concatenated
     series; q_off, r_off: host int64 offsets.  Returns (idx int64, dist float64,
-    label int32 or None) device tensors."""
+    label int32 or None) device tensors.  main_wait / main_done: optional
+    torch.cuda.Event the main sweep waits for / that is recorded after it, to
+    chain several searches on several streams."""
     import torch
     _dev_f64(q, "queries")
     _dev_f64(r, "candidates")
     q_off, r_off = _offsets(q_off), _offsets(r_off)
     nq, nr = len(q_off) - 1, len(r_off) - 1
     p = _as_params(p)
-    o = NNOpts(int(precision), float(margin_rel), int(flags))
+    o = NNOpts(int(precision), float(margin_rel), int(flags), _event_handle(main_wait, stream, q.device),
+               _event_handle(main_done, stream, q.device))
     if ws is None:
         ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device)
     if out is None:

@@ -433,6 +433,8 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     a.items = items;
     a.npairs = n;
     a.stage = &h->counters[8 + stage];
+    // seed (0, 1) and recheck (4, 5) stages: a few pairs per query
+    a.prio = (stage == 0 || stage == 1 || stage == 4 || stage == 5) ? 1 : 0;
     const int kind = effective_kind(p);
     const RowsShape sh = fp32 ? pl.r32 : pl.r64;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -636,6 +638,10 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     HIPCHK(hipStreamIsCapturing(s, &cap));
     if (cap != hipStreamCaptureStatusNone && !prepared)
         return fail(EAP_EINVAL, "a captured eap_nn1 needs prepared inputs (flags bit 2)");
+    hipEvent_t main_wait = o ? static_cast<hipEvent_t>(o->main_wait) : nullptr;
+    hipEvent_t main_done = o ? static_cast<hipEvent_t>(o->main_done) : nullptr;
+    if (cap != hipStreamCaptureStatusNone && (main_wait || main_done))
+        return fail(EAP_EINVAL, "main_wait / main_done must be NULL while the stream is captured");
     SweepArgs a = base_args(p);
     SeriesPtrs SQ, SR;
     if ((st = setup_common(ws, nl.c, p, q, q_off, nq, r, r_off, nr, s, a, SQ, SR, prepared)) != EAP_OK) return st;
@@ -659,8 +665,10 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     if (plain) {
         // baseline: every pair by the full dynamic programme
         a.plain = 1;
+        if (main_wait) HIPCHK(hipStreamWaitEvent(s, main_wait, 0));
         if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK)
             return st;
+        if (main_done) HIPCHK(hipEventRecord(main_done, s));
         HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
         return EAP_OK;
     }
@@ -729,6 +737,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         m.npairs_dev = &h->ovf_count[3];
         m.skip_b = nullptr;
     }
+    if (main_wait) HIPCHK(hipStreamWaitEvent(s, main_wait, 0));
     if ((st = sweep(p, pl, pl.band, m, h, 2, &h->queues[2], main_items, nq * nr, XQ, XR, s, screen)) != EAP_OK)
         return st;
     if (rerun) {
@@ -736,6 +745,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
             EAP_OK)
             return st;
     }
+    if (main_done) HIPCHK(hipEventRecord(main_done, s));
     if (screen) {
         // 3b. candidates within the certified FP32 error of each query's best are
         //     recomputed in FP64 (the seed keeps its FP64 distance); every other
@@ -834,6 +844,13 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
     SetInfo Q, R;
     if ((st = check_offsets(q_off, nq, "queries", &Q)) != EAP_OK) return st;
     if ((st = check_offsets(r_off, nr, "candidates", &R)) != EAP_OK) return st;
+    // the timed runs use no pipelining events
+    eap_nn_opts own{};
+    if (o) {
+        own = *o;
+        own.main_wait = own.main_done = nullptr;
+        o = &own;
+    }
     const bool fp32 = o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
     const bool plain = o && (o->flags & 2);
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));

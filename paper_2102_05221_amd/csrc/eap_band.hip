@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
     constexpr int CB = C;        // ring length
     constexpr int M2 = 2 * C;    // diagonals per lane
     constexpr int NB = 2 * CB;   // steps per block
+    if (A.prio) __builtin_amdgcn_s_setprio(2);
     // Edge values entering the rings: with small C the next block's are fetched
     // one block ahead; with large C a block is long enough to hide the fetch.
     constexpr bool AHEAD = (C <= 8);

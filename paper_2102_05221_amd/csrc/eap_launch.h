@@ -60,6 +60,9 @@ struct SweepArgs {
     // NN, CDTW: lower bound of each pair (at its result index); a pair whose
     // bound exceeds the cut-off is not swept.  NULL = none
     const double* lb;
+    // latency-bound launch (a few pairs per query): its waves take a higher
+    // issue priority than those of a throughput-bound sweep running beside it
+    int prio;
 };
 
 // Shape of the row sweep: G lanes per pair (pairs per wave = 64 / G), C

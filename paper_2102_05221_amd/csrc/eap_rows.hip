@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
     constexpr int K = (C > 8 && (KIND == MSM || DTAB)) ? 16 : 32;
     constexpr int W = G * C;
     constexpr int NW = DTAB ? C + K - 1 : 1;
+    if (A.prio) __builtin_amdgcn_s_setprio(2);
     extern __shared__ unsigned char lds_raw[];
     T* tab = reinterpret_cast<T*>(lds_raw);
     int tab_len = 1, tab_off = 0;

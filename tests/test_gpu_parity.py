@@ -207,10 +207,53 @@ def test_capture_needs_prepared_inputs(torch_dev):
     s = torch.cuda.Stream(dev)
     ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, dict(kind="dtw")), dev)
     out = (torch.empty(1, dtype=torch.int64, device=dev), torch.empty(1, dtype=torch.float64, device=dev), None)
+    ev = torch.cuda.Event()
+    ev.record(torch.cuda.current_stream(dev))   # creates the event before the capture
+    torch.cuda.synchronize()
     eap.capture_begin(s)
     with pytest.raises(eap.EapError, match="prepared"):
         eap.nn1(q, qo, r, ro, dict(kind="dtw"), ws=ws, stream=s, out=out)
+    with pytest.raises(eap.EapError, match="captured"):
+        eap.nn1(q, qo, r, ro, dict(kind="dtw"), ws=ws, stream=s, out=out, flags=eap.FLAG_PREPARED, main_done=ev)
     eap.capture_end(s).close()
+
+
+def test_pipelined_searches_match_serial(torch_dev, orc):
+    """Six searches on six streams, main sweeps chained by events (each waits
+    for the previous search's), two passes in a row: every result equals the
+    serial call's and the oracle's."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(2, n_ref=120, n_query=16)
+    qo, ro = wl["query_off"], wl["ref_off"]
+    q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, wl["refs"])
+    P = wl["params"]
+    kinds = list(P)
+    nq = len(qo) - 1
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(qo, ro, P[k], precision=1), dev) for k in kinds}
+    log("pipelined: serial reference")
+    want = {}
+    for k in kinds:
+        gi, gd, _ = eap.nn1(q, qo, r, ro, P[k], precision=1, ws=ws[k])
+        want[k] = (gi.cpu().numpy(), gd.cpu().numpy())
+        oi, od, _ = orc.nn1(P[k], wl["queries"], qo, wl["refs"], ro, "dp")
+        assert np.array_equal(want[k][0], oi) and np.array_equal(want[k][1], od), k
+    main = torch.cuda.current_stream(dev)
+    st = {k: torch.cuda.Stream(dev) for k in kinds}
+    done = {k: torch.cuda.Event() for k in kinds}
+    outs = {k: (torch.full((nq,), -7, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
+                None) for k in kinds}
+    for rep in range(2):
+        log(f"pipelined: pass {rep}")
+        for i, k in enumerate(kinds):
+            st[k].wait_stream(main)
+            eap.nn1(q, qo, r, ro, P[k], precision=1, ws=ws[k], out=outs[k], stream=st[k],
+                    main_wait=done[kinds[i - 1]] if i > 0 else None, main_done=done[k])
+        for k in kinds:
+            main.wait_stream(st[k])
+        torch.cuda.synchronize()
+        for k in kinds:
+            assert np.array_equal(outs[k][0].cpu().numpy(), want[k][0]), k
+            assert np.array_equal(outs[k][1].cpu().numpy(), want[k][1]), k
 
 
 @pytest.mark.parametrize("p", [dict(kind="cdtw", window_ratio=0.05), dict(kind="msm", c=0.5)], ids=pid)
