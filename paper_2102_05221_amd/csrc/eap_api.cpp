@@ -451,7 +451,16 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     (void)hipGetLastError();   // launch errors below must be this launch's own
     hipError_t e;
     const int lanes = band ? (fp32 ? pl.bg32 : pl.bg64) : sh.g;
-    const int grid = band ? sweep_grid(n, lanes) : rows_grid(n, lanes);
+    int grid = band ? sweep_grid(n, lanes) : rows_grid(n, lanes);
+    {
+        // a persistent grid no larger than what the device holds at once:
+        // blocks beyond it only start once the work has run out, yet
+        // measurably slow the sweep (up to a quarter for the band sweep)
+        int occ = 0;
+        const hipError_t oe = band ? launch_band(kind, fp32, pl.size, lanes, a, SA, SB, grid, s, &occ)
+                                   : launch_rows(kind, fp32, sh, a, SA, SB, grid, s, &occ);
+        if (oe == hipSuccess && occ > 0) grid = std::min(grid, device_cus() * occ);
+    }
     // slots per queue atomic: about 8 chunks per group, so that short items
     // (infeasible windows) do not serialise on the counter and long ones still
     // balance; one at a time when the count is only known on the device

@@ -377,7 +377,10 @@ __global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Se
 }
 
 template <int KIND, typename T, int G, int C>
-static hipError_t gob(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
+static hipError_t gob(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s, int* occ) {
+    if (occ)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, reinterpret_cast<const void*>(&band_kernel<KIND, T, G, C>),
+                                                            256, 0);
     Series<T> A{(const T*)SA.v, SA.off, (const T*)SA.border};
     Series<T> B{(const T*)SB.v, SB.off, (const T*)SB.border};
     hipLaunchKernelGGL((band_kernel<KIND, T, G, C>), dim3(grid), dim3(256), 0, s, a, A, B);
@@ -385,16 +388,17 @@ static hipError_t gob(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid
 }
 
 template <int KIND, typename T>
-static hipError_t gob_d(int diags, int g, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
+static hipError_t gob_d(int diags, int g, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s,
+                        int* occ) {
     switch (diags * 100 + g) {
-    case 12808: return gob<KIND, T, 8, 8>(a, SA, SB, grid, s);
-    case 12816: return gob<KIND, T, 16, 4>(a, SA, SB, grid, s);
-    case 25616: return gob<KIND, T, 16, 8>(a, SA, SB, grid, s);
-    case 25632: return gob<KIND, T, 32, 4>(a, SA, SB, grid, s);
-    case 51232: return gob<KIND, T, 32, 8>(a, SA, SB, grid, s);
-    case 51264: return gob<KIND, T, 64, 4>(a, SA, SB, grid, s);
-    case 102464: return gob<KIND, T, 64, 8>(a, SA, SB, grid, s);
-    case 204864: return gob<KIND, T, 64, 16>(a, SA, SB, grid, s);
+    case 12808: return gob<KIND, T, 8, 8>(a, SA, SB, grid, s, occ);
+    case 12816: return gob<KIND, T, 16, 4>(a, SA, SB, grid, s, occ);
+    case 25616: return gob<KIND, T, 16, 8>(a, SA, SB, grid, s, occ);
+    case 25632: return gob<KIND, T, 32, 4>(a, SA, SB, grid, s, occ);
+    case 51232: return gob<KIND, T, 32, 8>(a, SA, SB, grid, s, occ);
+    case 51264: return gob<KIND, T, 64, 4>(a, SA, SB, grid, s, occ);
+    case 102464: return gob<KIND, T, 64, 8>(a, SA, SB, grid, s, occ);
+    case 204864: return gob<KIND, T, 64, 16>(a, SA, SB, grid, s, occ);
     }
     return hipErrorInvalidValue;
 }
@@ -410,21 +414,21 @@ bool band_shape_ok(int diags, int g) {
 }
 
 hipError_t launch_band(int kind, bool fp32, int diags, int g, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B,
-                       int grid, hipStream_t s) {
+                       int grid, hipStream_t s, int* occ) {
     if (!band_shape_ok(diags, g)) return hipErrorInvalidValue;
     if (fp32) {
         switch (kind) {
-        case DTW: return gob_d<DTW, float>(diags, g, a, A, B, grid, s);
-        case CDTW: return gob_d<CDTW, float>(diags, g, a, A, B, grid, s);
-        case WDTW: return gob_d<WDTW, float>(diags, g, a, A, B, grid, s);
-        case ERP: return gob_d<ERP, float>(diags, g, a, A, B, grid, s);
+        case DTW: return gob_d<DTW, float>(diags, g, a, A, B, grid, s, occ);
+        case CDTW: return gob_d<CDTW, float>(diags, g, a, A, B, grid, s, occ);
+        case WDTW: return gob_d<WDTW, float>(diags, g, a, A, B, grid, s, occ);
+        case ERP: return gob_d<ERP, float>(diags, g, a, A, B, grid, s, occ);
         }
     } else {
         switch (kind) {
-        case DTW: return gob_d<DTW, double>(diags, g, a, A, B, grid, s);
-        case CDTW: return gob_d<CDTW, double>(diags, g, a, A, B, grid, s);
-        case WDTW: return gob_d<WDTW, double>(diags, g, a, A, B, grid, s);
-        case ERP: return gob_d<ERP, double>(diags, g, a, A, B, grid, s);
+        case DTW: return gob_d<DTW, double>(diags, g, a, A, B, grid, s, occ);
+        case CDTW: return gob_d<CDTW, double>(diags, g, a, A, B, grid, s, occ);
+        case WDTW: return gob_d<WDTW, double>(diags, g, a, A, B, grid, s, occ);
+        case ERP: return gob_d<ERP, double>(diags, g, a, A, B, grid, s, occ);
         }
     }
     return hipErrorInvalidValue;

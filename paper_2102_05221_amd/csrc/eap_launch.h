@@ -79,16 +79,17 @@ struct SeriesPtrs {
 
 // Row sweep (kernel A): strips of W = G*C columns per pair (DTW, WDTW, ERP
 // without a window, MSM, TWE).  Returns the launch error.  Pairs wider than
-// one strip need a.edge with room for grid * 256 / G groups.
+// one strip need a.edge with room for grid * 256 / G groups.  With `occ` set
+// nothing is launched: *occ = blocks of this kernel one CU holds at once.
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s);
+                       hipStream_t s, int* occ = nullptr);
 int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a);
 bool rows_shape_ok(int kind, RowsShape sh, bool fp32);
 
 // Band sweep (kernel B): anti-diagonal sweep of a band of diags = 2*G*C
-// diagonals with G lanes per pair (C in {4, 8, 16}).
+// diagonals with G lanes per pair (C in {4, 8, 16}).  `occ` as for the row sweep.
 hipError_t launch_band(int kind, bool fp32, int diags, int g, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B,
-                       int grid, hipStream_t s);
+                       int grid, hipStream_t s, int* occ = nullptr);
 bool band_shape_ok(int diags, int g);
 
 // Auxiliary kernels.

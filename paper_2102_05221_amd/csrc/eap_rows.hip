@@ -437,33 +437,37 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
 }
 
 template <int KIND, typename T, int G, int C>
-static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
+static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s, int* occ) {
+    const int lds = rows_lds_bytes(KIND, sizeof(T) == 4, a);
+    if (occ)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, reinterpret_cast<const void*>(&rows_kernel<KIND, T, G, C>),
+                                                            256, (size_t)lds);
     Series<T> A{(const T*)SA.v, SA.off, (const T*)SA.border};
     Series<T> B{(const T*)SB.v, SB.off, (const T*)SB.border};
-    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C>), dim3(grid), dim3(256), rows_lds_bytes(KIND, sizeof(T) == 4, a),
-                       s, a, A, B);
+    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C>), dim3(grid), dim3(256), lds, s, a, A, B);
     return hipGetLastError();
 }
 
 template <int KIND, typename T>
-static hipError_t go_w(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s) {
+static hipError_t go_w(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s,
+                       int* occ) {
     switch (sh.g * 1000 + sh.c) {
-    case 4008: return go<KIND, T, 4, 8>(a, SA, SB, grid, s);
-    case 4016: return go<KIND, T, 4, 16>(a, SA, SB, grid, s);
-    case 8008: return go<KIND, T, 8, 8>(a, SA, SB, grid, s);
-    case 8016: return go<KIND, T, 8, 16>(a, SA, SB, grid, s);
-    case 16008: return go<KIND, T, 16, 8>(a, SA, SB, grid, s);
-    case 16016: return go<KIND, T, 16, 16>(a, SA, SB, grid, s);
-    case 32008: return go<KIND, T, 32, 8>(a, SA, SB, grid, s);
-    case 32016: return go<KIND, T, 32, 16>(a, SA, SB, grid, s);
-    case 64008: return go<KIND, T, 64, 8>(a, SA, SB, grid, s);
-    case 64016: return go<KIND, T, 64, 16>(a, SA, SB, grid, s);
+    case 4008: return go<KIND, T, 4, 8>(a, SA, SB, grid, s, occ);
+    case 4016: return go<KIND, T, 4, 16>(a, SA, SB, grid, s, occ);
+    case 8008: return go<KIND, T, 8, 8>(a, SA, SB, grid, s, occ);
+    case 8016: return go<KIND, T, 8, 16>(a, SA, SB, grid, s, occ);
+    case 16008: return go<KIND, T, 16, 8>(a, SA, SB, grid, s, occ);
+    case 16016: return go<KIND, T, 16, 16>(a, SA, SB, grid, s, occ);
+    case 32008: return go<KIND, T, 32, 8>(a, SA, SB, grid, s, occ);
+    case 32016: return go<KIND, T, 32, 16>(a, SA, SB, grid, s, occ);
+    case 64008: return go<KIND, T, 64, 8>(a, SA, SB, grid, s, occ);
+    case 64016: return go<KIND, T, 64, 16>(a, SA, SB, grid, s, occ);
     }
     if constexpr (sizeof(T) == 4 && (KIND == DTW || KIND == WDTW)) {   // 32 columns per lane: registers
         switch (sh.g * 1000 + sh.c) {
-        case 16032: return go<KIND, T, 16, 32>(a, SA, SB, grid, s);
-        case 32032: return go<KIND, T, 32, 32>(a, SA, SB, grid, s);
-        case 64032: return go<KIND, T, 64, 32>(a, SA, SB, grid, s);
+        case 16032: return go<KIND, T, 16, 32>(a, SA, SB, grid, s, occ);
+        case 32032: return go<KIND, T, 32, 32>(a, SA, SB, grid, s, occ);
+        case 64032: return go<KIND, T, 64, 32>(a, SA, SB, grid, s, occ);
         }
     }
     return hipErrorInvalidValue;
@@ -483,22 +487,22 @@ bool rows_shape_ok(int kind, RowsShape sh, bool fp32) {
 }
 
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s) {
+                       hipStream_t s, int* occ) {
     if (fp32) {
         switch (kind) {
-        case DTW: case CDTW: return go_w<DTW, float>(sh, a, A, B, grid, s);
-        case WDTW: return go_w<WDTW, float>(sh, a, A, B, grid, s);
-        case ERP: return go_w<ERP, float>(sh, a, A, B, grid, s);
-        case MSM: return go_w<MSM, float>(sh, a, A, B, grid, s);
-        case TWE: return go_w<TWE, float>(sh, a, A, B, grid, s);
+        case DTW: case CDTW: return go_w<DTW, float>(sh, a, A, B, grid, s, occ);
+        case WDTW: return go_w<WDTW, float>(sh, a, A, B, grid, s, occ);
+        case ERP: return go_w<ERP, float>(sh, a, A, B, grid, s, occ);
+        case MSM: return go_w<MSM, float>(sh, a, A, B, grid, s, occ);
+        case TWE: return go_w<TWE, float>(sh, a, A, B, grid, s, occ);
         }
     } else {
         switch (kind) {
-        case DTW: case CDTW: return go_w<DTW, double>(sh, a, A, B, grid, s);
-        case WDTW: return go_w<WDTW, double>(sh, a, A, B, grid, s);
-        case ERP: return go_w<ERP, double>(sh, a, A, B, grid, s);
-        case MSM: return go_w<MSM, double>(sh, a, A, B, grid, s);
-        case TWE: return go_w<TWE, double>(sh, a, A, B, grid, s);
+        case DTW: case CDTW: return go_w<DTW, double>(sh, a, A, B, grid, s, occ);
+        case WDTW: return go_w<WDTW, double>(sh, a, A, B, grid, s, occ);
+        case ERP: return go_w<ERP, double>(sh, a, A, B, grid, s, occ);
+        case MSM: return go_w<MSM, double>(sh, a, A, B, grid, s, occ);
+        case TWE: return go_w<TWE, double>(sh, a, A, B, grid, s, occ);
         }
     }
     return hipErrorInvalidValue;
