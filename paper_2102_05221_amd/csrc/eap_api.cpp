@@ -128,10 +128,18 @@ void wdtw_table(double g, int64_t lmax, std::vector<double>& t, int& off) {
 }
 
 // TWE: nu * (2|k|) for k = j - i in [-Lmax, Lmax + 1024] (eq. TWECost with tau_i = i).
+// TWE's per-diagonal term nu * 2|d| for d = j - i.  The row sweep reads a
+// window of C + K - 1 consecutive entries per lane and block without bounds
+// checks, also for cells outside the matrix: with rows from -(G + K) to
+// L + G + 2K and first columns up to L + W, d stays within
+// [-(lmax + G + 3K), lmax + W + G + K + C] = [-(lmax + 160), lmax + 1136] for
+// G <= 64, K <= 32, C <= 16, W <= 1024, inside the table's range.
 void twe_table(double nu, int64_t lmax, std::vector<double>& t, int& off) {
-    off = (int)lmax;
-    t.resize((size_t)(2 * lmax + 1024 + 1));
-    for (int64_t k = -lmax; k <= lmax + 1024; ++k) t[(size_t)(k + lmax)] = nu * (double)(2 * (k < 0 ? -k : k));
+    constexpr int64_t lo = 256, hi = 1280;
+    off = (int)(lmax + lo);
+    t.resize((size_t)(2 * lmax + lo + hi + 1));
+    for (int64_t k = -(lmax + lo); k <= lmax + hi; ++k)
+        t[(size_t)(k + lmax + lo)] = nu * (double)(2 * (k < 0 ? -k : k));
 }
 
 // Pinned staging for host-to-device copies: a ring of buffers, each reused

@@ -234,16 +234,23 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
 
         if constexpr (DTAB) {
             // the per-diagonal terms of the next K steps: d = j - i runs over
-            // c0 - row - K .. c0 + C - 2 - row (clamped into the table; entries
-            // outside the matrix only reach cells nobody reads)
+            // c0 - row - K .. c0 + C - 2 - row (WDTW: clamped into the table;
+            // entries outside the matrix only reach cells nobody reads)
             const int base = c0 - row - K;
+            if constexpr (KIND == TWE) {
+                // the table covers every d this sweep forms (see its
+                // construction): one address, the entries at fixed offsets
+                const T* tp = tab + (base + tab_off);
 #pragma unroll
-            for (int m = 0; m < NW; ++m) {
-                int d = base + m, x;
-                if constexpr (KIND == TWE) x = d + tab_off;
-                else x = 2 * (d < 0 ? -d : d) - Lli + tab_off;
-                x = x < 0 ? 0 : (x >= tab_len ? tab_len - 1 : x);
-                dwin[m] = tab[x];
+                for (int m = 0; m < NW; ++m) dwin[m] = tp[m];
+            } else {
+#pragma unroll
+                for (int m = 0; m < NW; ++m) {
+                    const int d = base + m;
+                    int x = 2 * (d < 0 ? -d : d) - Lli + tab_off;
+                    x = x < 0 ? 0 : (x >= tab_len ? tab_len - 1 : x);
+                    dwin[m] = tab[x];
+                }
             }
         }
 
