@@ -748,8 +748,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     SweepArgs m = a;
     const int32_t* main_items = nullptr;
     if (lbk) {
-        HIPCHK(launch_lb_compact(lb, best, seeded ? seed : nullptr, nq, nr, res, ovf, &h->ovf_count[3],
-                                 &h->counters[4], s));
+        HIPCHK(launch_lb_compact(lb, best, seeded ? seed : nullptr, SQ.off, SR.off, a.window_ratio, nq, nr, res, ovf,
+                                 &h->ovf_count[3], &h->counters[4], s));
         main_items = ovf;
         m.npairs_dev = &h->ovf_count[3];
         m.skip_b = nullptr;

@@ -355,11 +355,13 @@ __global__ void argmin_kernel(const double* res, int64_t nq, int64_t nr, const i
 
 // CDTW NN: the pairs whose lower bound does not exceed the query's cut-off
 // after the seed sweep (the seed itself excluded), listed for the main sweep;
-// the others are +inf without a sweep.  Wave-level compaction: one atomic per
-// wave of 64 pairs.  The cut-off can only fall afterwards, so no NN is lost.
-__global__ void lb_compact_kernel(const double* lb, const unsigned long long* best, const int32_t* seed, int64_t nq,
-                                  int64_t nr, double* res, int32_t* items, unsigned int* count,
-                                  unsigned long long* pruned) {
+// the others are +inf without a sweep, as are the pairs whose window admits no
+// path (w = floor(ratio * max(L_q, L_r)) < |L_q - L_r|).  Wave-level
+// compaction: one atomic per wave of 64 pairs.  The cut-off can only fall
+// afterwards, so no NN is lost.
+__global__ void lb_compact_kernel(const double* lb, const unsigned long long* best, const int32_t* seed,
+                                  const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,
+                                  double* res, int32_t* items, unsigned int* count, unsigned long long* pruned) {
     const int64_t total = nq * nr;
     const int lane = threadIdx.x & 63;
     unsigned long long np = 0;
@@ -370,9 +372,12 @@ __global__ void lb_compact_kernel(const double* lb, const unsigned long long* be
         if (p < total) {
             const int64_t q = p / nr, r = p - q * nr;
             if (!seed || seed[q] != (int32_t)r) {
-                keep = !(lb[p] * (1.0 - 1e-11) > bitsd(best[q]));
-                drop = !keep;
-                if (drop) res[p] = __builtin_huge_val();
+                const int lq = (int)(qoff[q + 1] - qoff[q]), lr = (int)(roff[r + 1] - roff[r]);
+                const int L = lq > lr ? lq : lr, ld = lq > lr ? lq - lr : lr - lq;
+                const bool feasible = ratio >= 1.0 || (int)floor(ratio * (double)L) >= ld;
+                drop = feasible && lb[p] * (1.0 - 1e-11) > bitsd(best[q]);   // counted
+                keep = feasible && !drop;
+                if (!keep) res[p] = __builtin_huge_val();
             }
         }
         const unsigned long long m = __ballot(keep);
@@ -520,11 +525,12 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed, int64_t nq,
-                             int64_t nr, double* res, int32_t* items, unsigned int* count,
-                             unsigned long long* pruned, hipStream_t s) {
+hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed,
+                             const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,
+                             double* res, int32_t* items, unsigned int* count, unsigned long long* pruned,
+                             hipStream_t s) {
     hipLaunchKernelGGL(lb_compact_kernel, dim3(std::min(blocks_for(nq * nr, 256), 4096)), dim3(256), 0, s, lb, best,
-                       seed, nq, nr, res, items, count, pruned);
+                       seed, qoff, roff, ratio, nq, nr, res, items, count, pruned);
     return hipGetLastError();
 }
 

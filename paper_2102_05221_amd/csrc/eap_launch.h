@@ -109,9 +109,10 @@ hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_
                          double* out_dist, int32_t* out_label, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
-hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed, int64_t nq,
-                             int64_t nr, double* res, int32_t* items, unsigned int* count,
-                             unsigned long long* pruned, hipStream_t s);
+hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed,
+                             const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,
+                             double* res, int32_t* items, unsigned int* count, unsigned long long* pruned,
+                             hipStream_t s);
 hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                 const unsigned long long* absmax, double margin_rel, double* res,
                                 unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,

@@ -437,6 +437,35 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert c["lb_pruned"] > 0
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cdtw_windows_without_a_path(torch_dev, orc, precision):
+    """CDTW w = 5% over uneven lengths: pairs whose window admits no path are
+    +inf without a sweep (and are not counted as lower-bound prunes); a query
+    with no feasible candidate gets index -1 and +inf, the others the
+    oracle's NN."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(31)
+    rs = synth.random_walks(rng, 40, (100, 121)) + synth.random_walks(rng, 30, (300, 301))
+    qs = synth.random_walks(rng, 1, (40, 41)) + synth.random_walks(rng, 6, (100, 121)) + \
+        synth.random_walks(rng, 3, (290, 311))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(kind="cdtw", window_ratio=0.05)
+    ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, p, precision=1), dev)
+    eap.reset_counters(ws)
+    log(f"cdtw windows without a path precision={precision}")
+    gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=precision, ws=ws)
+    c = eap.read_counters(ws)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    assert oi[0] == -1 and np.isinf(od[0])
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    lq, lr = np.diff(qo), np.diff(ro)
+    L = np.maximum(lq[:, None], lr[None, :])
+    feasible = np.floor(0.05 * L) >= np.abs(lq[:, None] - lr[None, :])
+    assert c["lb_pruned"] <= int(feasible.sum())
+
+
 def test_nn1_parity_random_walk_workload_full(torch_dev, orc):
     """Workload 1 in full: DTW, 100 x 100 random walks of length 128."""
     torch, dev = torch_dev
