@@ -250,15 +250,48 @@ __global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qof
             const int lr = (int)(roff[b + 1] - roff[b]);
             auto Q = [&](int k) { return qs[k]; };
             auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
-            ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
             if (with_lb) {
-                double acc = 0.0;
-                for (int j = 0; j < lr; ++j) {
-                    const double x = R(j), u = eu[j], l = el[j];
+                // the path bound and LB_Keogh in one pass over the candidate's
+                // values (the bound's terms in the order path_ub_acc adds them)
+                const int L = lq > lr ? lq : lr, ld = lq > lr ? lq - lr : lr - lq;
+                double acc = 0.0, lbv = 0.0;
+                auto lbt = [&](double x, int j) {
+                    const double u = eu[j], l = el[j];
                     const double e = x > u ? x - u : (x < l ? l - x : 0.0);
-                    acc = acc + e * e;
+                    lbv = lbv + e * e;
+                };
+                if (A.window_ratio < 1.0 && (int)floor(A.window_ratio * (double)L) < ld) {
+                    acc = __builtin_huge_val();   // the window admits no path
+                } else if (lq >= lr) {
+                    // rows: the query; the diagonal, then down the last column
+                    for (int k = 0; k < lr; ++k) {
+                        const double x = R(k), d = Q(k) - x;
+                        acc = (d * d) + acc;
+                        lbt(x, k);
+                    }
+                    const double tl = R(lr - 1);
+                    for (int i = lr + 1; i <= lq; ++i) {
+                        const double d = Q(i - 1) - tl;
+                        acc = (d * d) + acc;
+                    }
+                } else {
+                    // rows: the candidate
+                    for (int k = 0; k < lq; ++k) {
+                        const double x = R(k), d = x - Q(k);
+                        acc = (d * d) + acc;
+                        lbt(x, k);
+                    }
+                    const double tl = Q(lq - 1);
+                    for (int i = lq + 1; i <= lr; ++i) {
+                        const double x = R(i - 1), d = x - tl;
+                        acc = (d * d) + acc;
+                        lbt(x, i - 1);
+                    }
                 }
-                lb[a * nB + b] = acc;
+                ub[a * nB + b] = acc;
+                lb[a * nB + b] = lbv;
+            } else {
+                ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
             }
         }
     }
