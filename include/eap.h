@@ -217,7 +217,7 @@ eap_status eap_reset_counters(void* ws, size_t ws_bytes, void* stream);
  *  recs, cap, n        host array receiving one record per shape timed. */
 typedef struct {
     int32_t g, c;      /* lanes per pair, columns per lane */
-    float ms;          /* mean time of one eap_nn1 call */
+    float ms;          /* fastest of three timed eap_nn1 calls */
     int32_t chosen;    /* 1 for the shape recorded in the table */
 } eap_tune_rec;
 eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,

@@ -35,6 +35,23 @@ __device__ __forceinline__ double shr1(double v) {
     return __builtin_bit_cast(double, r);
 }
 
+// Within each row of 16 lanes: lane k > 0 receives lane k-1's v, lane 0 of
+// the row keeps `first` (DPP row_shr:1 without bound_ctrl leaves lanes whose
+// source lies outside the row unwritten).  For groups of exactly 16 lanes
+// this shifts within the group and feeds its first lane in one instruction.
+__device__ __forceinline__ float row_shr1_or(float v, float first) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, first),
+                                                                 __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double row_shr1_or(double v, double first) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long f = __builtin_bit_cast(unsigned long long, first);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)b, 0x111, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(b >> 32), 0x111, 0xf, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
 // Non-negative doubles order like their bit patterns, +inf above every finite.

@@ -40,8 +40,18 @@
 
 namespace eap {
 
+// Blocks per CU the register budget is sized for: 3 (168 VGPRs) for FP32,
+// except TWE and ERP lanes of 16 or more columns, which spill heavily at that
+// budget and run faster with 256 VGPRs at 2 blocks per CU (measured on the
+// 500 x 500, length-512 NN workload: TWE 8x16 3.49 against 4.87 ms); FP64: 2.
+template <int KIND, typename T, int C>
+constexpr int rows_min_blocks() {
+    return (sizeof(T) == 4 && !(C >= 16 && (KIND == TWE || KIND == ERP))) ? 3 : 2;
+}
+
 template <int KIND, typename T, int G, int C>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(SweepArgs A, Series<T> SA, Series<T> SB) {
+__global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_kernel(SweepArgs A, Series<T> SA,
+                                                                                     Series<T> SB) {
     constexpr bool DTAB = (KIND == TWE || KIND == WDTW);
     // steps between group decisions: long blocks share the block-end work
     // (ballots, cut-off, strip and pair bookkeeping) among more steps, and
@@ -269,17 +279,24 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) void rows_kernel(Swe
         // +inf inputs, which reproduces their top border bit for bit; lanes past
         // the last row compute values nobody reads.
         auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t) {
-            T lin = shr1(lout);
-            T sin = shr1(sout);
+            T lin, sin;
             row += 1;
             {
                 // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G
                 const int src = lane - k + (t % G);
                 const T bv = __shfl(st_b[t / G], src);   // M(row, cb)
                 const T sv = __shfl(st_s[t / G], src);   // s_row
-                if (k == 0) {
-                    lin = bv;
-                    sin = sv;
+                if constexpr (G == 16) {
+                    // a group is one DPP row: shift and feed lane 0 at once
+                    lin = row_shr1_or(lout, bv);
+                    sin = row_shr1_or(sout, sv);
+                } else {
+                    lin = shr1(lout);
+                    sin = shr1(sout);
+                    if (k == 0) {
+                        lin = bv;
+                        sin = sv;
+                    }
                 }
             }
             const bool ns = row < r_start;   // not started: keep the top border
