@@ -223,75 +223,90 @@ __global__ void envelope_kernel(const double* qv, const int64_t* qoff, int64_t n
 
 // UB of every (query, candidate) pair from the interleaved candidates: a block
 // takes one query (staged in LDS, read by all lanes at once) and 256
-// candidates (one per lane, coalesced).  For CDTW with an envelope it also
-// writes LB_Keogh of every pair (the envelope staged in LDS beside the query).
+// candidates (one per lane, coalesced).
 template <int KIND>
 __global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rT,
-                               const int64_t* roff, int lq_max, int lr_max, const double* env_up,
-                               const double* env_lo, double* lb, double* ub) {
+                               const int64_t* roff, double* ub) {
     extern __shared__ double qs[];
-    double* eu = qs + lq_max;
-    double* el = eu + lr_max;
-    const bool with_lb = (KIND == CDTW) && lb != nullptr;
     const int64_t nB = A.nB;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t a = blockIdx.y; a < A.nA; a += gridDim.y) {
         const int lq = (int)(qoff[a + 1] - qoff[a]);
         __syncthreads();
         for (int k = threadIdx.x; k < lq; k += blockDim.x) qs[k] = qv[qoff[a] + k];
-        if (with_lb) {
-            for (int k = threadIdx.x; k < lr_max; k += blockDim.x) {
-                eu[k] = env_up[a * (int64_t)lr_max + k];
-                el[k] = env_lo[a * (int64_t)lr_max + k];
-            }
-        }
         __syncthreads();
         if (b < nB) {
             const int lr = (int)(roff[b + 1] - roff[b]);
             auto Q = [&](int k) { return qs[k]; };
             auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
-            if (with_lb) {
-                // the path bound and LB_Keogh in one pass over the candidate's
-                // values (the bound's terms in the order path_ub_acc adds them)
-                const int L = lq > lr ? lq : lr, ld = lq > lr ? lq - lr : lr - lq;
-                double acc = 0.0, lbv = 0.0;
-                auto lbt = [&](double x, int j) {
-                    const double u = eu[j], l = el[j];
-                    const double e = x > u ? x - u : (x < l ? l - x : 0.0);
-                    lbv = lbv + e * e;
-                };
-                if (A.window_ratio < 1.0 && (int)floor(A.window_ratio * (double)L) < ld) {
-                    acc = __builtin_huge_val();   // the window admits no path
-                } else if (lq >= lr) {
-                    // rows: the query; the diagonal, then down the last column
-                    for (int k = 0; k < lr; ++k) {
-                        const double x = R(k), d = Q(k) - x;
-                        acc = (d * d) + acc;
-                        lbt(x, k);
-                    }
-                    const double tl = R(lr - 1);
-                    for (int i = lr + 1; i <= lq; ++i) {
-                        const double d = Q(i - 1) - tl;
-                        acc = (d * d) + acc;
-                    }
-                } else {
-                    // rows: the candidate
-                    for (int k = 0; k < lq; ++k) {
-                        const double x = R(k), d = x - Q(k);
-                        acc = (d * d) + acc;
-                        lbt(x, k);
-                    }
-                    const double tl = Q(lq - 1);
-                    for (int i = lq + 1; i <= lr; ++i) {
-                        const double x = R(i - 1), d = x - tl;
-                        acc = (d * d) + acc;
-                        lbt(x, i - 1);
-                    }
-                }
-                ub[a * nB + b] = acc;
-                lb[a * nB + b] = lbv;
-            } else {
-                ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
+            ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
+        }
+    }
+}
+
+// CDTW: the path bound and LB_Keogh of QT queries against 256 candidates per
+// block, in one pass over each candidate's values (read once for all QT
+// queries; the queries in LDS, their envelopes by block-uniform loads).  Each
+// bound adds its terms in path order (the diagonal, then the longer series'
+// tail), like path_ub_acc; (a - b)^2 and (b - a)^2 are the same double.
+template <int QT>
+__global__ void ub_lb_cdtw_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rT,
+                                  const int64_t* roff, int lq_max, int lr_max, const double* env_up,
+                                  const double* env_lo, double* lb, double* ub) {
+    extern __shared__ double qs[];   // QT x lq_max
+    const int64_t nB = A.nB;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double ratio = A.window_ratio;
+    for (int64_t a0 = (int64_t)blockIdx.y * QT; a0 < A.nA; a0 += (int64_t)gridDim.y * QT) {
+        const int nqt = (int)((A.nA - a0) < QT ? (A.nA - a0) : QT);
+        int lq[QT];
+#pragma unroll
+        for (int t = 0; t < QT; ++t) lq[t] = t < nqt ? (int)(qoff[a0 + t + 1] - qoff[a0 + t]) : 0;
+        __syncthreads();
+        for (int t = 0; t < nqt; ++t)
+            for (int k = threadIdx.x; k < lq[t]; k += blockDim.x) qs[t * lq_max + k] = qv[qoff[a0 + t] + k];
+        __syncthreads();
+        if (b >= nB) continue;
+        const int lr = (int)(roff[b + 1] - roff[b]);
+        auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
+        double acc[QT], lbv[QT];
+        bool on[QT];
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+            const int L = lq[t] > lr ? lq[t] : lr, ld = lq[t] > lr ? lq[t] - lr : lr - lq[t];
+            on[t] = t < nqt && !(ratio < 1.0 && (int)floor(ratio * (double)L) < ld);
+            acc[t] = on[t] ? 0.0 : __builtin_huge_val();   // +inf: the window admits no path
+            lbv[t] = 0.0;
+        }
+        for (int j = 0; j < lr; ++j) {
+            const double x = R(j);
+#pragma unroll
+            for (int t = 0; t < QT; ++t) {
+                if (!on[t]) continue;
+                // the diagonal while both series last, then down the candidate
+                const double y = j < lq[t] ? qs[t * lq_max + j] : qs[t * lq_max + lq[t] - 1];
+                const double d = x - y;
+                acc[t] = (d * d) + acc[t];
+                const double u = env_up[(a0 + t) * lr_max + j], l = env_lo[(a0 + t) * lr_max + j];
+                const double e = x > u ? x - u : (x < l ? l - x : 0.0);
+                lbv[t] = lbv[t] + e * e;
+            }
+        }
+        // queries longer than the candidate: their tail against its last value
+        const double xl = R(lr - 1);
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+            if (!on[t]) continue;
+            for (int i = lr; i < lq[t]; ++i) {
+                const double d = qs[t * lq_max + i] - xl;
+                acc[t] = (d * d) + acc[t];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+            if (t < nqt) {
+                ub[(a0 + t) * nB + b] = acc[t];
+                lb[(a0 + t) * nB + b] = lbv[t];
             }
         }
     }
@@ -593,26 +608,26 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
                         double* env_lo, double* lb, hipStream_t s) {
     hipLaunchKernelGGL(interleave_kernel, dim3(blocks_for(a.nB * (int64_t)lr_max, 256)), dim3(256), 0, s, rv, roff,
                        a.nB, lr_max, rT);
-    const bool with_lb = kind == CDTW && lb && env_up && env_lo;
-    if (with_lb)
+    if (kind == CDTW && lb && env_up && env_lo) {
+        // CDTW: the query envelopes, then bound and LB_Keogh of 4 queries per
+        // pass over the candidates (at most 4 x 2048 doubles of LDS)
         hipLaunchKernelGGL(envelope_kernel, dim3(std::min<int64_t>(a.nA, 65535)), dim3(256), 0, s, qv, qoff, a.nA,
                            lr_max, a.window_ratio, env_up, env_lo);
+        constexpr int QT = 4;
+        const dim3 gq((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>((a.nA + QT - 1) / QT, 65535));
+        hipLaunchKernelGGL(ub_lb_cdtw_kernel<QT>, gq, dim3(256), sizeof(double) * (size_t)QT * (size_t)lq_max, s, a,
+                           qv, qoff, rT, roff, lq_max, lr_max, env_up, env_lo, lb, ub);
+        return hipGetLastError();
+    }
     const dim3 g((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>(a.nA, 65535)), b(256);
-    const size_t lds = sizeof(double) * ((size_t)lq_max + (with_lb ? 2 * (size_t)lr_max : 0));
-    double* L = with_lb ? lb : nullptr;
+    const size_t lds = sizeof(double) * (size_t)lq_max;
     switch (kind) {
-    case DTW: hipLaunchKernelGGL(ub_nn_t_kernel<DTW>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
-                                 env_lo, L, ub); break;
-    case CDTW: hipLaunchKernelGGL(ub_nn_t_kernel<CDTW>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
-                                  env_lo, L, ub); break;
-    case WDTW: hipLaunchKernelGGL(ub_nn_t_kernel<WDTW>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
-                                  env_lo, L, ub); break;
-    case ERP: hipLaunchKernelGGL(ub_nn_t_kernel<ERP>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
-                                 env_lo, L, ub); break;
-    case MSM: hipLaunchKernelGGL(ub_nn_t_kernel<MSM>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
-                                 env_lo, L, ub); break;
-    case TWE: hipLaunchKernelGGL(ub_nn_t_kernel<TWE>, g, b, lds, s, a, qv, qoff, rT, roff, lq_max, lr_max, env_up,
-                                 env_lo, L, ub); break;
+    case DTW: hipLaunchKernelGGL(ub_nn_t_kernel<DTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case CDTW: hipLaunchKernelGGL(ub_nn_t_kernel<CDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case WDTW: hipLaunchKernelGGL(ub_nn_t_kernel<WDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case ERP: hipLaunchKernelGGL(ub_nn_t_kernel<ERP>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case MSM: hipLaunchKernelGGL(ub_nn_t_kernel<MSM>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case TWE: hipLaunchKernelGGL(ub_nn_t_kernel<TWE>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
