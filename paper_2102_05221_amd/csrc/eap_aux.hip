@@ -181,12 +181,28 @@ __device__ double path_ub_acc(const SweepArgs& A, FR rowv, int Lli, FC colv, int
 
 // Candidates interleaved for coalesced reads: rT[k * nr + b] = value k of
 // candidate b (0 past its end).
+// A tile of 64 series x 64 positions per block, through LDS: each wave reads
+// 64 consecutive values of one series and writes 64 consecutive series of one
+// position.  Grid: (ceil(nr / 64), ceil(lmax / 64)), 256 threads.
 __global__ void interleave_kernel(const double* rv, const int64_t* roff, int64_t nr, int lmax, double* rT) {
-    const int64_t total = nr * (int64_t)lmax;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = x / nr, b = x - k * nr;
-        const int64_t o = roff[b], len = roff[b + 1] - o;
-        rT[x] = (k < len) ? rv[o + k] : 0.0;
+    __shared__ double tile[64][65];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * 64;
+    const int k0 = blockIdx.y * 64;
+    for (int i = w; i < 64; i += 4) {
+        const int64_t b = b0 + i;
+        double v = 0.0;
+        if (b < nr) {
+            const int64_t o = roff[b], len = roff[b + 1] - o;
+            if (k0 + lane < len) v = rv[o + k0 + lane];
+        }
+        tile[i][lane] = v;
+    }
+    __syncthreads();
+    for (int kk = w; kk < 64; kk += 4) {
+        const int k = k0 + kk;
+        const int64_t b = b0 + lane;
+        if (k < lmax && b < nr) rT[(int64_t)k * nr + b] = tile[lane][kk];
     }
 }
 
@@ -278,18 +294,38 @@ __global__ void ub_lb_cdtw_kernel(SweepArgs A, const double* qv, const int64_t* 
             acc[t] = on[t] ? 0.0 : __builtin_huge_val();   // +inf: the window admits no path
             lbv[t] = 0.0;
         }
-        for (int j = 0; j < lr; ++j) {
-            const double x = R(j);
+        // candidate values and envelope entries in chunks of CH (loads issued
+        // together; indexes clamped into the series), terms added in order
+        constexpr int CH = 8;
+        for (int j0 = 0; j0 < lr; j0 += CH) {
+            double xv[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) xv[u] = R(j0 + u < lr ? j0 + u : lr - 1);
 #pragma unroll
             for (int t = 0; t < QT; ++t) {
                 if (!on[t]) continue;
-                // the diagonal while both series last, then down the candidate
-                const double y = j < lq[t] ? qs[t * lq_max + j] : qs[t * lq_max + lq[t] - 1];
-                const double d = x - y;
-                acc[t] = (d * d) + acc[t];
-                const double u = env_up[(a0 + t) * lr_max + j], l = env_lo[(a0 + t) * lr_max + j];
-                const double e = x > u ? x - u : (x < l ? l - x : 0.0);
-                lbv[t] = lbv[t] + e * e;
+                const double* eu = env_up + (a0 + t) * lr_max;
+                const double* el = env_lo + (a0 + t) * lr_max;
+                double uv[CH], lv[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int jj = j0 + u < lr ? j0 + u : lr - 1;
+                    uv[u] = eu[jj];
+                    lv[u] = el[jj];
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int j = j0 + u;
+                    if (j < lr) {
+                        // the diagonal while both series last, then down the candidate
+                        const double x = xv[u];
+                        const double y = j < lq[t] ? qs[t * lq_max + j] : qs[t * lq_max + lq[t] - 1];
+                        const double d = x - y;
+                        acc[t] = (d * d) + acc[t];
+                        const double e = x > uv[u] ? x - uv[u] : (x < lv[u] ? lv[u] - x : 0.0);
+                        lbv[t] = lbv[t] + e * e;
+                    }
+                }
             }
         }
         // queries longer than the candidate: their tail against its last value
@@ -338,66 +374,102 @@ __global__ void ub_condensed_kernel(SweepArgs A, const double* v, const int64_t*
     }
 }
 
-// Per query: the candidate with the smallest upper bound (lowest index on
-// ties) is swept first, with that bound as its cut-off.  One wave per query.
-__global__ void seed_kernel(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* items,
-                            unsigned long long* best) {
-    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (q >= nq) return;
-    double bv = __builtin_huge_val();
-    int64_t bi = nr;
-    for (int64_t r = lane; r < nr; r += 64) {
-        const double u = ub[q * nr + r];
-        if (u < bv || (u == bv && r < bi)) {
-            bv = u;
-            bi = r;
-        }
-    }
+// Per-query scans over the nr candidates (seed choice, argmin, screen
+// filter): TPQ threads per query (64, 256 or 1024, from nr), a block of
+// max(256, TPQ) threads holding 256 / TPQ queries when TPQ < 256; queries by
+// grid stride.  Lexicographic (value, index) minima: the combination of two
+// partial minima is associative, so the order of the reduction does not
+// change the result.
+__device__ __forceinline__ bool lex_less(double v, int64_t i, double bv, int64_t bi) {
+    return v < bv || (v == bv && i >= 0 && (bi < 0 || i < bi));
+}
+
+template <int TPQ>
+__device__ __forceinline__ void group_min(double& bv, int64_t& bi, double* sv, int64_t* si) {
     for (int o = 32; o > 0; o >>= 1) {
         const double ov = __shfl_xor(bv, o);
         const int64_t oi = __shfl_xor(bi, o);
-        if (ov < bv || (ov == bv && oi < bi)) {
+        if (lex_less(ov, oi, bv, bi)) {
             bv = ov;
             bi = oi;
         }
     }
-    if (lane == 0) {
-        if (bi >= nr) bi = 0;
-        seed_b[q] = (int32_t)bi;
-        items[q] = (int32_t)(q * nr + bi);
-        best[q] = dbits(bv);
+    if constexpr (TPQ > 64) {
+        // one query per block: the waves' minima through LDS, the result to all
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            sv[threadIdx.x >> 6] = bv;
+            si[threadIdx.x >> 6] = bi;
+        }
+        __syncthreads();
+        bv = sv[0];
+        bi = si[0];
+        for (int w = 1; w < TPQ / 64; ++w)
+            if (lex_less(sv[w], si[w], bv, bi)) {
+                bv = sv[w];
+                bi = si[w];
+            }
+    }
+}
+
+// Per query: the candidate with the smallest upper bound (lowest index on
+// ties) is swept first, with that bound as its cut-off.
+template <int TPQ>
+__global__ void seed_kernel(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* items,
+                            unsigned long long* best) {
+    constexpr int QPB = TPQ >= 256 ? 1 : 256 / TPQ;
+    __shared__ double sv[TPQ / 64];
+    __shared__ int64_t si[TPQ / 64];
+    const int tq = threadIdx.x % TPQ;
+    for (int64_t q0 = (int64_t)blockIdx.x * QPB; q0 < nq; q0 += (int64_t)gridDim.x * QPB) {
+        const int64_t q = q0 + threadIdx.x / TPQ;
+        double bv = __builtin_huge_val();
+        int64_t bi = -1;
+        if (q < nq)
+            for (int64_t r = tq; r < nr; r += TPQ) {
+                const double u = ub[q * nr + r];
+                if (lex_less(u, r, bv, bi)) {
+                    bv = u;
+                    bi = r;
+                }
+            }
+        group_min<TPQ>(bv, bi, sv, si);
+        if (tq == 0 && q < nq) {
+            if (bi < 0) bi = 0;   // every bound +inf: any candidate, cut-off +inf
+            seed_b[q] = (int32_t)bi;
+            items[q] = (int32_t)(q * nr + bi);
+            best[q] = dbits(bv);
+        }
     }
 }
 
 // Alg. 1's result: the lexicographically smallest (distance, index) per query;
-// index -1 and +inf when no candidate is finite.  One wave per query.
+// index -1 and +inf when no candidate is finite.
+template <int TPQ>
 __global__ void argmin_kernel(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
                               double* out_dist, int32_t* out_label) {
-    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (q >= nq) return;
-    double bv = __builtin_huge_val();
-    int64_t bi = -1;
-    for (int64_t r = lane; r < nr; r += 64) {
-        const double d = res[q * nr + r];
-        if (d < bv) {   // per lane r increases, so strict '<' keeps the lowest index
-            bv = d;
-            bi = r;
+    constexpr int QPB = TPQ >= 256 ? 1 : 256 / TPQ;
+    __shared__ double sv[TPQ / 64];
+    __shared__ int64_t si[TPQ / 64];
+    const int tq = threadIdx.x % TPQ;
+    for (int64_t q0 = (int64_t)blockIdx.x * QPB; q0 < nq; q0 += (int64_t)gridDim.x * QPB) {
+        const int64_t q = q0 + threadIdx.x / TPQ;
+        double bv = __builtin_huge_val();
+        int64_t bi = -1;
+        if (q < nq)
+            for (int64_t r = tq; r < nr; r += TPQ) {
+                const double d = res[q * nr + r];
+                if (d < bv) {   // r increases per thread, so strict '<' keeps the lowest index
+                    bv = d;
+                    bi = r;
+                }
+            }
+        group_min<TPQ>(bv, bi, sv, si);
+        if (tq == 0 && q < nq) {
+            out_idx[q] = bi;
+            out_dist[q] = bv;
+            if (out_label) out_label[q] = (bi >= 0 && labels) ? labels[bi] : -1;
         }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o);
-        const int64_t oi = __shfl_xor(bi, o);
-        if (ov < bv || (ov == bv && oi >= 0 && (bi < 0 || oi < bi))) {
-            bv = ov;
-            bi = oi;
-        }
-    }
-    if (lane == 0) {
-        out_idx[q] = bi;
-        out_dist[q] = bv;
-        if (out_label) out_label[q] = (bi >= 0 && labels) ? labels[bi] : -1;
     }
 }
 
@@ -513,43 +585,56 @@ __global__ void screen_widen_kernel(int kind, SweepArgs A, const int64_t* qoff, 
 // FP64 before the screen) keeps its FP64 distance and is not listed; every
 // other result slot is reset to +inf, and best[q] becomes the smaller of
 // screen_bound(b) and the seed's distance, an upper bound on the FP64 NN
-// distance that serves as the recheck's first cut-off.  One wave per query.
+// distance that serves as the recheck's first cut-off.  TPQ threads per query.
+template <int TPQ>
 __global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
                                      const unsigned long long* absmax, double margin_rel, double* res,
                                      unsigned long long* best, const int32_t* seed, int32_t* items,
                                      unsigned int* count, unsigned long long* rechecks) {
-    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (q >= A.nA) return;
-    const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
-    double Amax = bitsd(*absmax);
-    if (kind == ERP) Amax = fmax(Amax, __builtin_fabs(gap));
-    const double b32 = bitsd(best[q]);
-    double thr = __builtin_huge_val(), cut64 = __builtin_huge_val();
-    if (b32 < __builtin_huge_val()) {
-        const double b = b32 * (1.0 + margin_rel);
-        cut64 = screen_bound(kind, b, N, Amax);
-        thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);
-    }
-    const int64_t sb = seed ? (int64_t)seed[q] : -1;
-    const double dseed = (sb >= 0) ? res[q * A.nB + sb] : __builtin_huge_val();
-    unsigned long long n = 0;
-    for (int64_t r = lane; r < A.nB; r += 64) {
-        if (r == sb) continue;
-        const int64_t p = q * A.nB + r;
-        if (res[p] <= thr) {
-            const unsigned int k = atomicAdd(count, 1u);
-            items[k] = (int32_t)p;
-            ++n;
+    constexpr int QPB = TPQ >= 256 ? 1 : 256 / TPQ;
+    const int tq = threadIdx.x % TPQ;
+    const double Ab = bitsd(*absmax);
+    for (int64_t q0 = (int64_t)blockIdx.x * QPB; q0 < A.nA; q0 += (int64_t)gridDim.x * QPB) {
+        const int64_t q = q0 + threadIdx.x / TPQ;
+        const bool on = q < A.nA;
+        double thr = __builtin_huge_val(), cut64 = __builtin_huge_val(), dseed = __builtin_huge_val();
+        int64_t sb = -1;
+        unsigned long long n = 0;
+        if (on) {
+            const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
+            const double Amax = (kind == ERP) ? fmax(Ab, __builtin_fabs(gap)) : Ab;
+            const double b32 = bitsd(best[q]);
+            if (b32 < __builtin_huge_val()) {
+                const double b = b32 * (1.0 + margin_rel);
+                cut64 = screen_bound(kind, b, N, Amax);
+                thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);
+            }
+            sb = seed ? (int64_t)seed[q] : -1;
+            dseed = (sb >= 0) ? res[q * A.nB + sb] : __builtin_huge_val();
+            for (int64_t r = tq; r < A.nB; r += TPQ) {
+                if (r == sb) continue;
+                const int64_t p = q * A.nB + r;
+                if (res[p] <= thr) {
+                    const unsigned int k = atomicAdd(count, 1u);
+                    items[k] = (int32_t)p;
+                    ++n;
+                }
+                res[p] = __builtin_huge_val();
+            }
         }
-        res[p] = __builtin_huge_val();
-    }
-    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
-    if (lane == 0) {
-        best[q] = dbits(dseed < cut64 ? dseed : cut64);
-        if (n) atomicAdd(rechecks, n);
+        for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+        if ((threadIdx.x & 63) == 0 && n) atomicAdd(rechecks, n);
+        // every thread of the query has read best[q] before it is replaced
+        if constexpr (TPQ > 64) __syncthreads();
+        if (on && tq == 0) best[q] = dbits(dseed < cut64 ? dseed : cut64);
     }
 }
+
+// Threads per query for the per-query scans over nr candidates: one wave up
+// to 1024 candidates, a 256-thread block up to 4096, else a 1024-thread block
+// (with a few queries and many candidates a wave's chain of loads is the
+// whole kernel's time).
+static int scan_threads(int64_t nr) { return nr > 4096 ? 1024 : (nr > 1024 ? 256 : 64); }
 
 static int blocks_for(int64_t n, int per) {
     int64_t b = (n + per - 1) / per;
@@ -598,25 +683,50 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
                                 const unsigned long long* absmax, double margin_rel, double* res,
                                 unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,
                                 unsigned long long* rechecks, hipStream_t s) {
-    hipLaunchKernelGGL(screen_filter_kernel, dim3(blocks_for(a.nA, 4)), dim3(256), 0, s, kind, a, qoff, lr_max, gap,
-                       absmax, margin_rel, res, best, seed, items, count, rechecks);
+    switch (scan_threads(a.nB)) {
+    case 1024: hipLaunchKernelGGL(screen_filter_kernel<1024>, dim3(blocks_for(a.nA, 1)), dim3(1024), 0, s, kind, a,
+                                  qoff, lr_max, gap, absmax, margin_rel, res, best, seed, items, count, rechecks); break;
+    case 256: hipLaunchKernelGGL(screen_filter_kernel<256>, dim3(blocks_for(a.nA, 1)), dim3(256), 0, s, kind, a, qoff,
+                                 lr_max, gap, absmax, margin_rel, res, best, seed, items, count, rechecks); break;
+    default: hipLaunchKernelGGL(screen_filter_kernel<64>, dim3(blocks_for(a.nA, 4)), dim3(256), 0, s, kind, a, qoff,
+                                lr_max, gap, absmax, margin_rel, res, best, seed, items, count, rechecks); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
                         const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
                         double* env_lo, double* lb, hipStream_t s) {
-    hipLaunchKernelGGL(interleave_kernel, dim3(blocks_for(a.nB * (int64_t)lr_max, 256)), dim3(256), 0, s, rv, roff,
-                       a.nB, lr_max, rT);
+    hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((a.nB + 63) / 64), (unsigned)((lr_max + 63) / 64)), dim3(256),
+                       0, s, rv, roff, a.nB, lr_max, rT);
     if (kind == CDTW && lb && env_up && env_lo) {
-        // CDTW: the query envelopes, then bound and LB_Keogh of 4 queries per
-        // pass over the candidates (at most 4 x 2048 doubles of LDS)
+        // CDTW: the query envelopes, then bound and LB_Keogh of up to 4 queries
+        // per pass over the candidates (at most 4 x 2048 doubles of LDS)
         hipLaunchKernelGGL(envelope_kernel, dim3(std::min<int64_t>(a.nA, 65535)), dim3(256), 0, s, qv, qoff, a.nA,
                            lr_max, a.window_ratio, env_up, env_lo);
-        constexpr int QT = 4;
-        const dim3 gq((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>((a.nA + QT - 1) / QT, 65535));
-        hipLaunchKernelGGL(ub_lb_cdtw_kernel<QT>, gq, dim3(256), sizeof(double) * (size_t)QT * (size_t)lq_max, s, a,
-                           qv, qoff, rT, roff, lq_max, lr_max, env_up, env_lo, lb, ub);
+        // queries per block: 4 when the grid still has at least 2 blocks per CU
+        // (fewer reads of the candidates), else 2 or 1 (more blocks)
+        const int64_t bx = (a.nB + 255) / 256;
+        int cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        int qt = 1;
+        for (int c : {4, 2})
+            if (bx * ((a.nA + c - 1) / c) >= 2 * (int64_t)cus) {
+                qt = c;
+                break;
+            }
+        const dim3 gq((unsigned)bx, (unsigned)std::min<int64_t>((a.nA + qt - 1) / qt, 65535));
+        const size_t lds = sizeof(double) * (size_t)qt * (size_t)lq_max;
+        switch (qt) {
+        case 4: hipLaunchKernelGGL(ub_lb_cdtw_kernel<4>, gq, dim3(256), lds, s, a, qv, qoff, rT, roff, lq_max, lr_max,
+                                   env_up, env_lo, lb, ub); break;
+        case 2: hipLaunchKernelGGL(ub_lb_cdtw_kernel<2>, gq, dim3(256), lds, s, a, qv, qoff, rT, roff, lq_max, lr_max,
+                                   env_up, env_lo, lb, ub); break;
+        default: hipLaunchKernelGGL(ub_lb_cdtw_kernel<1>, gq, dim3(256), lds, s, a, qv, qoff, rT, roff, lq_max,
+                                    lr_max, env_up, env_lo, lb, ub); break;
+        }
         return hipGetLastError();
     }
     const dim3 g((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>(a.nA, 65535)), b(256);
@@ -650,14 +760,27 @@ hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, co
 
 hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* items,
                        unsigned long long* best, hipStream_t s) {
-    hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(nq, 4)), dim3(256), 0, s, ub, nq, nr, seed_b, items, best);
+    switch (scan_threads(nr)) {
+    case 1024: hipLaunchKernelGGL(seed_kernel<1024>, dim3(blocks_for(nq, 1)), dim3(1024), 0, s, ub, nq, nr, seed_b,
+                                  items, best); break;
+    case 256: hipLaunchKernelGGL(seed_kernel<256>, dim3(blocks_for(nq, 1)), dim3(256), 0, s, ub, nq, nr, seed_b, items,
+                                 best); break;
+    default: hipLaunchKernelGGL(seed_kernel<64>, dim3(blocks_for(nq, 4)), dim3(256), 0, s, ub, nq, nr, seed_b, items,
+                                best); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
                          double* out_dist, int32_t* out_label, hipStream_t s) {
-    hipLaunchKernelGGL(argmin_kernel, dim3(blocks_for(nq, 4)), dim3(256), 0, s, res, nq, nr, labels, out_idx,
-                       out_dist, out_label);
+    switch (scan_threads(nr)) {
+    case 1024: hipLaunchKernelGGL(argmin_kernel<1024>, dim3(blocks_for(nq, 1)), dim3(1024), 0, s, res, nq, nr, labels,
+                                  out_idx, out_dist, out_label); break;
+    case 256: hipLaunchKernelGGL(argmin_kernel<256>, dim3(blocks_for(nq, 1)), dim3(256), 0, s, res, nq, nr, labels,
+                                 out_idx, out_dist, out_label); break;
+    default: hipLaunchKernelGGL(argmin_kernel<64>, dim3(blocks_for(nq, 4)), dim3(256), 0, s, res, nq, nr, labels,
+                                out_idx, out_dist, out_label); break;
+    }
     return hipGetLastError();
 }
 

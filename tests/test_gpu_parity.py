@@ -437,6 +437,30 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert c["lb_pruned"] > 0
 
 
+@pytest.mark.parametrize("nr", [2000, 5000])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["dtw", "cdtw", "msm"])
+def test_nn1_many_candidates(torch_dev, orc, kind, precision, nr):
+    """Thousands of short candidates (the per-query scans run 256 or 1024
+    threads per query); duplicated candidates check the lowest-index rule."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(nr + precision)
+    rs = synth.random_walks(rng, nr, (24, 40))
+    qs = synth.random_walks(rng, 5, (24, 40))
+    rs[nr - 3] = qs[1].copy()            # an exact match late in the set ...
+    rs[nr - 1] = qs[1].copy()            # ... and its duplicate: the lower index wins
+    rs[7] = rs[nr // 2].copy()
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = {"dtw": dict(kind="dtw"), "cdtw": dict(kind="cdtw", window_ratio=0.2), "msm": dict(kind="msm", c=0.5)}[kind]
+    log(f"nn1 many candidates {kind} precision={precision} nr={nr}")
+    gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=precision)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    assert oi[1] == nr - 3 and od[1] == 0.0
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_cdtw_windows_without_a_path(torch_dev, orc, precision):
     """CDTW w = 5% over uneven lengths: pairs whose window admits no path are
