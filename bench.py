@@ -5,10 +5,10 @@ ERP, MSM and TWE, the 1-NN of 500 queries among 500 candidates (length 512,
 five time-warped sine classes, z-normalised; the paper's NN-classification
 workload at UCR scale, synthetic and seeded).  Inputs are resident in HBM
 before the timed region.  By default the six searches run pipelined: each on
-its own stream, their main sweeps one at a time (each waits for the previous
-search's main sweep through an event), their bound, seed, recheck and argmin
-stages overlapping the neighbouring main sweeps (--schedule serial: one after
-the other on one stream).
+one of three streams (round-robin), their main sweeps one at a time (each
+waits for the previous search's main sweep through an event), their bound,
+seed, recheck and argmin stages overlapping the neighbouring main sweeps
+(--schedule serial: one after the other on one stream).
 
 Reported (one JSON line on stdout):
   value        effective GCUPS: DP cells of the plain full programme (band
@@ -292,6 +292,13 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     kstream = {k: torch.cuda.Stream(dev) for k in kinds}
+    # pipelined: three streams, the searches round-robin over them.  HIP maps
+    # streams onto a few hardware queues (4 by default, one taken by torch's
+    # stream), and work on a queue runs in order: with six streams two
+    # consecutive searches could share one, and the second's bound and seed
+    # stages would wait behind the first's main sweep and recheck.  With three,
+    # a queue's next search follows one whose main sweep ended two sweeps ago.
+    pstream = [torch.cuda.Stream(dev) for _ in range(3)]
     main_done = {k: torch.cuda.Event() for k in kinds}
 
     def step(precision=args.precision, schedule=args.schedule):
@@ -302,15 +309,21 @@ def main():
                 eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k],
                         out=outs[k], precision=precision)
             return
+        used = []
         for i, k in enumerate(kinds):
-            kstream[k].wait_stream(stream)
             chain = {}
             if schedule == "pipelined":
+                ks = pstream[i % len(pstream)]
                 chain = dict(main_wait=main_done[kinds[i - 1]] if i > 0 else None, main_done=main_done[k])
+            else:
+                ks = kstream[k]
+            if ks not in used:
+                ks.wait_stream(stream)
+                used.append(ks)
             eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k], out=outs[k],
-                    precision=precision, stream=kstream[k], **chain)
-        for k in kinds:
-            stream.wait_stream(kstream[k])
+                    precision=precision, stream=ks, **chain)
+        for ks in used:
+            stream.wait_stream(ks)
 
     # autotune the row sweep's shape per distance on this workload (setup, untimed)
     tuning = {}
