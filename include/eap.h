@@ -95,6 +95,13 @@ typedef struct {
  *              offsets and parameters, so their host-to-device copies are
  *              skipped and the call enqueues kernels only.  Required while the
  *              stream is being captured into a graph (see eap_capture_begin).
+ *              bit 3: candidates prepared: a previous call on this workspace
+ *              had the same candidates (values, offsets), parameters and
+ *              precision, with any queries; what it derived from the
+ *              candidates alone (their device offsets, ERP borders,
+ *              interleaved and FP32 copies, |x| maximum), which sits at the
+ *              workspace's start, is reused.  For a resident candidate set
+ *              searched by batch after batch (the request server uses it).
  *  main_wait   hipEvent_t or NULL: the stream waits for it before the main
  *              sweep (after the bounds, the seed sweep and the screen set-up).
  *  main_done   hipEvent_t or NULL: recorded on the stream right after the main

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -113,9 +114,14 @@ struct Header {
     unsigned int ovf_count[4];   // [0] band overflows, [2] FP64 recheck items, [3] CDTW pairs past the
                                  // lower bound (u64 fills clear [0..1])
     unsigned long long absmax;   // FP32 screen: largest |value| (double bits)
+    // kept across calls: largest |value| of the candidates (NN, precision 1),
+    // reused by calls with the candidates-prepared flag
+    unsigned long long absmax_r;
 };
 constexpr int kCounterWords = 32;
 constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
+// header words cleared by every call: the queues, counts and absmax
+constexpr int kClearedWords = (int)(offsetof(Header, absmax_r) / 8) - kCounterWords;
 
 // ------------------------------------------------------------------ tables
 // WDTW: G[m] = 1 / (1 + exp(-g * (m / 2))) for m = 2k - L in [-Lmax, 2 Lmax]; the
@@ -361,17 +367,21 @@ char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
 eap_status setup_common(void* ws, const Common& c, const eap_params* p, const double* va, const int64_t* offa,
                         int64_t na, const double* vb, const int64_t* offb, int64_t nb, hipStream_t s,
-                        SweepArgs& a, SeriesPtrs& SA, SeriesPtrs& SB, bool prepared = false) {
+                        SweepArgs& a, SeriesPtrs& SA, SeriesPtrs& SB, bool prepared = false,
+                        bool b_ready = false) {
     eap_status st;
     // work queues and overflow counts start at zero; the counters keep accumulating
     HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(at(ws, c.hdr)) + kCounterWords, 0ull,
-                           (int64_t)(kHeaderBytes / 8) - kCounterWords, s));
+                           kClearedWords, s));
     // offsets and tables: uploaded, unless a previous call with the same
     // inputs left them in this workspace (the only host-to-device copies, so a
     // prepared call enqueues kernels only and can be captured in a graph)
     if (!prepared && (st = upload(at(ws, c.offA), offa, sizeof(int64_t) * (size_t)(na + 1), s)) != EAP_OK)
         return st;
-    if (!prepared && offb && (st = upload(at(ws, c.offB), offb, sizeof(int64_t) * (size_t)(nb + 1), s)) != EAP_OK)
+    // set B's offsets and ERP borders: also kept when a previous call left them
+    // (b_ready: the NN candidates, unchanged since)
+    if (!prepared && !b_ready && offb &&
+        (st = upload(at(ws, c.offB), offb, sizeof(int64_t) * (size_t)(nb + 1), s)) != EAP_OK)
         return st;
     const int64_t* dA = reinterpret_cast<const int64_t*>(at(ws, c.offA));
     const int64_t* dB = offb ? reinterpret_cast<const int64_t*>(at(ws, c.offB)) : dA;
@@ -383,7 +393,7 @@ eap_status setup_common(void* ws, const Common& c, const eap_params* p, const do
         SA.border = bA;
         if (offb) {
             double* bB = reinterpret_cast<double*>(at(ws, c.bordB));
-            HIPCHK(launch_erp_border(vb, dB, nb, p->gap, bB, s));
+            if (!b_ready) HIPCHK(launch_erp_border(vb, dB, nb, p->gap, bB, s));
             SB.border = bB;
         } else {
             SB.border = bA;
@@ -441,8 +451,10 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     a.items = items;
     a.npairs = n;
     a.stage = &h->counters[8 + stage];
-    // seed (0, 1) and recheck (4, 5) stages: a few pairs per query
-    a.prio = (stage == 0 || stage == 1 || stage == 4 || stage == 5) ? 1 : 0;
+    // seed stages (0, 1): a few pairs per query, and a search's main sweep
+    // waits for them; rechecks (4, 5) keep the normal priority, so that beside
+    // another search's main sweep they take only the issue slots it leaves
+    a.prio = (stage == 0 || stage == 1) ? 1 : 0;
     const int kind = effective_kind(p);
     const RowsShape sh = fp32 ? pl.r32 : pl.r64;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -586,14 +598,39 @@ struct NNLayout {
     size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
 
-static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params* p, bool screen, NNLayout& nl) {
-    plan_common(nl.L, nl.c, p, Q, &R);
+// NN workspace.  The candidate side comes first (header, candidate offsets,
+// ERP borders, interleaved copy, FP32 copies when precision is 1): its place
+// depends on the candidates alone, so a later call on the same workspace with
+// other queries and the candidates-prepared flag finds what an earlier call
+// derived.  Then the query side and the per-pair arrays.
+static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params* p, bool prec1, bool screen,
+                            NNLayout& nl) {
+    Layout& L = nl.L;
+    Common& c = nl.c;
+    c.hdr = L.take(kHeaderBytes);
+    c.offB = L.take(sizeof(int64_t) * (size_t)(R.n + 1));
+    if (p->kind == EAP_ERP) c.bordB = L.take(sizeof(double) * (size_t)R.total);
+    nl.rT = L.take(sizeof(double) * (size_t)(R.n * R.maxlen));
+    if (prec1) {
+        nl.r32 = L.take(sizeof(float) * (size_t)R.total);
+        if (p->kind == EAP_ERP) nl.r32b = L.take(sizeof(float) * (size_t)R.total);
+    }
+    c.offA = L.take(sizeof(int64_t) * (size_t)(Q.n + 1));
+    if (p->kind == EAP_ERP) c.bordA = L.take(sizeof(double) * (size_t)Q.total);
+    const int64_t lmax = std::max(Q.maxlen, R.maxlen);
+    if (p->kind == EAP_TWE) {
+        twe_table(p->nu, lmax, c.tabv, c.tab_off);
+        c.tab = L.take(sizeof(double) * c.tabv.size());
+    }
+    if (p->kind == EAP_WDTW) {
+        wdtw_table(p->g, lmax, c.gtabv, c.gtab_off);
+        c.gtab = L.take(sizeof(double) * c.gtabv.size());
+    }
     nl.best = nl.L.take(sizeof(unsigned long long) * (size_t)Q.n);
     nl.seed = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
-    nl.rT = nl.L.take(sizeof(double) * (size_t)(R.n * R.maxlen));
     if (effective_kind(p) == EAP_CDTW) {
         nl.env_up = nl.L.take(sizeof(double) * (size_t)(Q.n * R.maxlen));
         nl.env_lo = nl.L.take(sizeof(double) * (size_t)(Q.n * R.maxlen));
@@ -602,11 +639,7 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
     nl.edge = nl.L.take(edge_bytes(Q.n * R.n, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)));
     if (screen) {
         nl.q32 = nl.L.take(sizeof(float) * (size_t)Q.total);
-        nl.r32 = nl.L.take(sizeof(float) * (size_t)R.total);
-        if (p->kind == EAP_ERP) {
-            nl.q32b = nl.L.take(sizeof(float) * (size_t)Q.total);
-            nl.r32b = nl.L.take(sizeof(float) * (size_t)R.total);
-        }
+        if (p->kind == EAP_ERP) nl.q32b = nl.L.take(sizeof(float) * (size_t)Q.total);
         nl.widen = nl.L.take(sizeof(double) * (size_t)Q.n);
         nl.recheck = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
     }
@@ -621,7 +654,8 @@ size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off,
         check_offsets(r_off, nr, "candidates", &R) != EAP_OK)
         return 0;
     NNLayout nl;
-    nn_layout(Q, R, p, o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen)), nl);
+    const bool prec1 = o && o->precision == 1;
+    nn_layout(Q, R, p, prec1, prec1 && screen_useful(p, std::max(Q.maxlen, R.maxlen)), nl);
     return nl.L.off;
 }
 
@@ -639,15 +673,17 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         if (o->precision != 0 && o->precision != 1) return fail(EAP_EINVAL, "precision must be 0 or 1");
         if (!(std::isfinite(o->margin_rel) && o->margin_rel >= 0)) return fail(EAP_EINVAL, "margin_rel must be >= 0");
     }
-    const bool screen = o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
+    const bool prec1 = o && o->precision == 1;
+    const bool screen = prec1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
     NNLayout nl;
-    nn_layout(Q, R, p, screen, nl);
+    nn_layout(Q, R, p, prec1, screen, nl);
     if (!ws || ws_bytes < nl.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, nl.L.off);
     Plan pl;
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     const bool plain = o && (o->flags & 2);
     const bool seeded = !plain && !(o && (o->flags & 1));
     const bool prepared = o && (o->flags & 4);
+    const bool cand_ready = o && (o->flags & 8);
     if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
 
     hipStream_t s = (hipStream_t)stream;
@@ -661,8 +697,23 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         return fail(EAP_EINVAL, "main_wait / main_done must be NULL while the stream is captured");
     SweepArgs a = base_args(p);
     SeriesPtrs SQ, SR;
-    if ((st = setup_common(ws, nl.c, p, q, q_off, nq, r, r_off, nr, s, a, SQ, SR, prepared)) != EAP_OK) return st;
+    if ((st = setup_common(ws, nl.c, p, q, q_off, nq, r, r_off, nr, s, a, SQ, SR, prepared, cand_ready)) != EAP_OK)
+        return st;
     Header* h = hdr_of(ws, nl.c);
+    double* rT = reinterpret_cast<double*>(at(ws, nl.rT));
+    if (!cand_ready) {
+        // what the candidates alone determine, kept for calls with flags bit 3:
+        // the interleaved copy, and for precision 1 the FP32 copies and |x| maximum
+        HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, rT, s));
+        if (prec1) {
+            HIPCHK(launch_to_f32(r, R.total, reinterpret_cast<float*>(at(ws, nl.r32)), s));
+            if (p->kind == EAP_ERP)
+                HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total,
+                                     reinterpret_cast<float*>(at(ws, nl.r32b)), s));
+            HIPCHK(launch_fill_u64(&h->absmax_r, 0ull, 1, s));
+            HIPCHK(launch_absmax(r, R.total, &h->absmax_r, s));
+        }
+    }
     unsigned long long* best = reinterpret_cast<unsigned long long*>(at(ws, nl.best));
     int32_t* seed = reinterpret_cast<int32_t*>(at(ws, nl.seed));
     int32_t* seed_items = reinterpret_cast<int32_t*>(at(ws, nl.seed_items));
@@ -692,8 +743,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     // 1. upper bounds from the diagonal path, the best of them seeds each query
     const bool lbk = effective_kind(p) == EAP_CDTW;
     double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
-    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, (int)Q.maxlen, (int)R.maxlen,
-                        reinterpret_cast<double*>(at(ws, nl.rT)), res,
+    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env_up)) : nullptr,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env_lo)) : nullptr, lb, s));
     a.lb = lb;
@@ -721,20 +771,19 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         float* q32 = reinterpret_cast<float*>(at(ws, nl.q32));
         float* r32 = reinterpret_cast<float*>(at(ws, nl.r32));
         HIPCHK(launch_to_f32(q, Q.total, q32, s));
-        HIPCHK(launch_to_f32(r, R.total, r32, s));
         XQ = SeriesPtrs{q32, SQ.off, nullptr};
         XR = SeriesPtrs{r32, SR.off, nullptr};
         if (p->kind == EAP_ERP) {
             float* qb = reinterpret_cast<float*>(at(ws, nl.q32b));
             float* rb = reinterpret_cast<float*>(at(ws, nl.r32b));
             HIPCHK(launch_to_f32(static_cast<const double*>(SQ.border), Q.total, qb, s));
-            HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total, rb, s));
             XQ.border = qb;
             XR.border = rb;
         }
+        // |x| maximum over queries and candidates (theirs computed above or kept)
         HIPCHK(launch_fill_u64(&h->absmax, 0ull, 1, s));
         HIPCHK(launch_absmax(q, Q.total, &h->absmax, s));
-        HIPCHK(launch_absmax(r, R.total, &h->absmax, s));
+        HIPCHK(launch_max_u64(&h->absmax, &h->absmax_r, s));
         double* widen = reinterpret_cast<double*>(at(ws, nl.widen));
         // best[q] is now the seed's FP64 distance or the path bound: the widening
         // at it bounds every best-so-far of the FP32 pass

@@ -658,6 +658,22 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
+hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((nr + 63) / 64), (unsigned)((lr_max + 63) / 64)), dim3(256),
+                       0, s, rv, roff, nr, lr_max, rT);
+    return hipGetLastError();
+}
+
+__global__ void max_u64_kernel(unsigned long long* dst, const unsigned long long* src) {
+    if (threadIdx.x == 0) atomicMax(dst, *src);
+}
+
+hipError_t launch_max_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s) {
+    hipLaunchKernelGGL(max_u64_kernel, dim3(1), dim3(64), 0, s, dst, src);
+    return hipGetLastError();
+}
+
 hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed,
                              const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,
                              double* res, int32_t* items, unsigned int* count, unsigned long long* pruned,
@@ -697,8 +713,7 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
                         const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
                         double* env_lo, double* lb, hipStream_t s) {
-    hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((a.nB + 63) / 64), (unsigned)((lr_max + 63) / 64)), dim3(256),
-                       0, s, rv, roff, a.nB, lr_max, rT);
+    (void)rv;
     if (kind == CDTW && lb && env_up && env_lo) {
         // CDTW: the query envelopes, then bound and LB_Keogh of up to 4 queries
         // per pass over the candidates (at most 4 x 2048 doubles of LDS)

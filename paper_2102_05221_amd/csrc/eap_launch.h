@@ -98,6 +98,14 @@ hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
 // Path upper bounds of all NN pairs; rT: workspace of nB * lr_max doubles for
 // the interleaved candidates.  For CDTW with env_up/env_lo (nA * lr_max
 // doubles each) and lb (nA * nB doubles), also LB_Keogh of every pair.
+// Candidates interleaved for coalesced reads: rT[k * nr + b] = value k of
+// candidate b (0 past its end), k < lr_max.
+hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT,
+                             hipStream_t s);
+// *dst = max(*dst, *src) (u64), one thread.
+hipError_t launch_max_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s);
+// Path upper bound of every (query, candidate) pair from rT (launch_interleave);
+// for CDTW with env_up / env_lo / lb also the query envelopes and LB_Keogh.
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
                         const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
                         double* env_lo, double* lb, hipStream_t s);

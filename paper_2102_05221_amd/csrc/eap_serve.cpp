@@ -57,6 +57,7 @@ struct Slot {
     double* hdist = nullptr;
     int32_t* hlab = nullptr;
     bool busy = false;
+    bool cand_ready = false;   // the slot's workspace holds the candidates' derived data
     std::vector<int64_t> tags;
 };
 
@@ -92,12 +93,14 @@ void free_server(eap_server* s) {
     delete s;
 }
 
-// Bytes a batch of these queries needs in a slot: values, NN workspace, outputs.
+// Bytes a batch of these queries needs in a slot: NN workspace (at the slot's
+// start, so that what it derived from the candidates stays in place from batch
+// to batch), values, outputs.
 size_t batch_bytes(const eap_server* s, const std::vector<int64_t>& qoff) {
     const int64_t nq = (int64_t)qoff.size() - 1;
     const size_t ws = eap_nn1_workspace(qoff.data(), nq, s->r_off.data(), s->nr, &s->p, &s->nn);
     if (ws == 0) return SIZE_MAX;
-    return up(sizeof(double) * (size_t)qoff.back()) + up(ws) + up(sizeof(int64_t) * (size_t)nq) +
+    return up(ws) + up(sizeof(double) * (size_t)qoff.back()) + up(sizeof(int64_t) * (size_t)nq) +
            up(sizeof(double) * (size_t)nq) + up(sizeof(int32_t) * (size_t)nq);
 }
 
@@ -123,10 +126,10 @@ eap_status launch_batch(eap_server* s, Slot& sl) {
     }
     const size_t ws_bytes = eap_nn1_workspace(qoff.data(), nq, s->r_off.data(), s->nr, &s->p, &s->nn);
     char* at = sl.dev;
-    double* dq = reinterpret_cast<double*>(at);
-    at += up(sizeof(double) * (size_t)qoff.back());
     void* ws = at;
     at += up(ws_bytes);
+    double* dq = reinterpret_cast<double*>(at);
+    at += up(sizeof(double) * (size_t)qoff.back());
     int64_t* didx = reinterpret_cast<int64_t*>(at);
     at += up(sizeof(int64_t) * (size_t)nq);
     double* ddist = reinterpret_cast<double*>(at);
@@ -135,9 +138,16 @@ eap_status launch_batch(eap_server* s, Slot& sl) {
     if (hipMemcpyAsync(dq, sl.hq, sizeof(double) * (size_t)qoff.back(), hipMemcpyHostToDevice, sl.stream) !=
         hipSuccess)
         return sfail(EAP_EDEVICE, "query upload failed");
-    eap_status e = eap_nn1(dq, qoff.data(), nq, s->refs, s->r_off.data(), s->nr, s->labels, &s->p, &s->nn, ws,
+    // after the slot's first batch, the candidates' derived data is reused
+    eap_nn_opts nn = s->nn;
+    if (sl.cand_ready) nn.flags |= 8;
+    eap_status e = eap_nn1(dq, qoff.data(), nq, s->refs, s->r_off.data(), s->nr, s->labels, &s->p, &nn, ws,
                            ws_bytes, didx, ddist, s->labels ? dlab : nullptr, sl.stream);
-    if (e != EAP_OK) return sfail(e, "batch search: %s", eap_last_error());
+    if (e != EAP_OK) {
+        sl.cand_ready = false;
+        return sfail(e, "batch search: %s", eap_last_error());
+    }
+    sl.cand_ready = true;
     if (hipMemcpyAsync(sl.hidx, didx, sizeof(int64_t) * (size_t)nq, hipMemcpyDeviceToHost, sl.stream) !=
             hipSuccess ||
         hipMemcpyAsync(sl.hdist, ddist, sizeof(double) * (size_t)nq, hipMemcpyDeviceToHost, sl.stream) !=

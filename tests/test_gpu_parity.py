@@ -437,6 +437,34 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert c["lb_pruned"] > 0
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["erp", "cdtw", "msm", "wdtw"])
+def test_candidates_prepared_flag(torch_dev, orc, kind, precision):
+    """One workspace, three query batches of different sizes and lengths
+    against the same candidates; the second and third reuse what the first
+    derived from the candidates (flags bit 3).  Every batch gets the oracle's
+    NN."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(77 + precision)
+    rs = synth.random_walks(rng, 60, (40, 160))
+    rv, ro = synth.pack(rs)
+    r = to_dev(torch, dev, rv)
+    p = {"erp": dict(kind="erp", gap=0.3), "cdtw": dict(kind="cdtw", window_ratio=0.1),
+         "msm": dict(kind="msm", c=0.5), "wdtw": dict(kind="wdtw", g=0.1)}[kind]
+    batches = [synth.random_walks(rng, 5, (40, 160)), synth.random_walks(rng, 9, (100, 220)),
+               synth.random_walks(rng, 3, (30, 60))]
+    packed = [synth.pack(b) for b in batches]
+    nbytes = max(eap.nn1_workspace_bytes(qo, ro, p, precision=precision) for _, qo in packed)
+    ws = eap.workspace(nbytes, dev)
+    for i, (qv, qo) in enumerate(packed):
+        log(f"candidates prepared {kind} precision={precision} batch {i}")
+        gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, r, ro, p, precision=precision, ws=ws,
+                            flags=eap.FLAG_CANDIDATES if i > 0 else 0)
+        oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+        assert np.array_equal(gi.cpu().numpy(), oi), i
+        assert np.array_equal(gd.cpu().numpy(), od), i
+
+
 @pytest.mark.parametrize("nr", [2000, 5000])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("kind", ["dtw", "cdtw", "msm"])
