@@ -743,7 +743,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     // 1. upper bounds from the diagonal path, the best of them seeds each query
     const bool lbk = effective_kind(p) == EAP_CDTW;
     double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
-    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, r, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
+    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env_up)) : nullptr,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env_lo)) : nullptr, lb, s));
     a.lb = lb;

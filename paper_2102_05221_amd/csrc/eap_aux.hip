@@ -10,19 +10,19 @@ namespace eap {
 // series per thread, summed left to right like the recurrence.
 __global__ void erp_border_kernel(const double* v, const int64_t* off, int64_t n, double gap, double* out) {
     constexpr int CH = 16;   // values loaded ahead of the (sequential) sum
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t b = off[s], e = off[s + 1];
-    double acc = 0.0;
-    for (int64_t x0 = b; x0 < e; x0 += CH) {
-        double xv[CH];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = off[s], e = off[s + 1];
+        double acc = 0.0;
+        for (int64_t x0 = b; x0 < e; x0 += CH) {
+            double xv[CH];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) xv[u] = v[x0 + u < e ? x0 + u : e - 1];
+            for (int u = 0; u < CH; ++u) xv[u] = v[x0 + u < e ? x0 + u : e - 1];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            if (x0 + u < e) {
-                acc = acc + __builtin_fabs(xv[u] - gap);
-                out[x0 + u] = acc;
+            for (int u = 0; u < CH; ++u) {
+                if (x0 + u < e) {
+                    acc = acc + __builtin_fabs(xv[u] - gap);
+                    out[x0 + u] = acc;
+                }
             }
         }
     }
@@ -566,14 +566,14 @@ __device__ double screen_bound(int kind, double b, double N, double A) {
 // in FP32 to <= b + 2 eps(screen_bound(UB)).
 __global__ void screen_widen_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
                                     const unsigned long long* absmax, double* widen_abs) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= A.nA) return;
-    const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
     double Amax = bitsd(*absmax);
     if (kind == ERP) Amax = fmax(Amax, __builtin_fabs(gap));
-    const double ub = bitsd(A.best[q]);
-    widen_abs[q] = (ub < __builtin_huge_val()) ? 2.0 * screen_eps(kind, screen_bound(kind, ub, N, Amax), N, Amax)
-                                               : 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < A.nA; q += (int64_t)gridDim.x * blockDim.x) {
+        const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
+        const double ub = bitsd(A.best[q]);
+        widen_abs[q] = (ub < __builtin_huge_val()) ? 2.0 * screen_eps(kind, screen_bound(kind, ub, N, Amax), N, Amax)
+                                                   : 0.0;
+    }
 }
 
 // After the FP32 sweep: every candidate of query q whose FP32 distance is
@@ -710,10 +710,9 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
     return hipGetLastError();
 }
 
-hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
-                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
-                        double* env_lo, double* lb, hipStream_t s) {
-    (void)rv;
+hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const int64_t* roff,
+                        int lq_max, int lr_max, double* rT, double* ub, double* env_up, double* env_lo, double* lb,
+                        hipStream_t s) {
     if (kind == CDTW && lb && env_up && env_lo) {
         // CDTW: the query envelopes, then bound and LB_Keogh of up to 4 queries
         // per pass over the candidates (at most 4 x 2048 doubles of LDS)

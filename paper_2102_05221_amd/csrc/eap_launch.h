@@ -106,9 +106,9 @@ hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, 
 hipError_t launch_max_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s);
 // Path upper bound of every (query, candidate) pair from rT (launch_interleave);
 // for CDTW with env_up / env_lo / lb also the query envelopes and LB_Keogh.
-hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
-                        const int64_t* roff, int lq_max, int lr_max, double* rT, double* ub, double* env_up,
-                        double* env_lo, double* lb, hipStream_t s);
+hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const int64_t* roff,
+                        int lq_max, int lr_max, double* rT, double* ub, double* env_up, double* env_lo, double* lb,
+                        hipStream_t s);
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s);
 hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* list_a,

@@ -465,6 +465,28 @@ def test_candidates_prepared_flag(torch_dev, orc, kind, precision):
         assert np.array_equal(gd.cpu().numpy(), od), i
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["dtw", "cdtw", "erp"])
+def test_nn1_many_queries(torch_dev, orc, kind, precision):
+    """300,000 short queries (more than the largest grid of the per-query
+    kernels covers in one pass, so every one of them strides) against three
+    candidates; every query gets the oracle's NN."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(5 + precision)
+    nq = 300_000
+    lq = rng.integers(2, 5, nq)
+    qo = np.concatenate([[0], np.cumsum(lq)]).astype(np.int64)
+    qv = rng.standard_normal(int(qo[-1]))
+    rs = [rng.standard_normal(3), rng.standard_normal(4), rng.standard_normal(2)]
+    rv, ro = synth.pack(rs)
+    p = {"dtw": dict(kind="dtw"), "cdtw": dict(kind="cdtw", window_ratio=0.5), "erp": dict(kind="erp", gap=0.1)}[kind]
+    log(f"nn1 many queries {kind} precision={precision}")
+    gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=precision)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
 @pytest.mark.parametrize("nr", [2000, 5000])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("kind", ["dtw", "cdtw", "msm"])
