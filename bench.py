@@ -230,16 +230,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kinds", default="dtw,cdtw,wdtw,erp,msm,twe")
     ap.add_argument("--cpu-queries", type=int, default=500,
-                    help="queries in the CPU-oracle EAPruned sample (0: skip; about 7 s for all 500 of the "
+                    help="queries in the CPU-oracle EAPruned sample (0: skip; about 5 s for all 500 of the "
                          "default workload on 16 threads)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
     ap.add_argument("--precision", type=int, default=1, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
     ap.add_argument("--no-tune", action="store_true", help="skip the row-sweep autotuner (default shapes)")
     ap.add_argument("--schedule", default="pipelined", choices=("pipelined", "serial", "concurrent"),
-                    help="workload 2: how the six searches of a step share the GPU.  pipelined: one stream "
-                         "each, main sweeps one at a time (chained by events), the latency-bound stages "
-                         "overlapping them; serial: one after the other on one stream; concurrent: six "
-                         "streams, no ordering")
+                    help="workload 2: how the six searches of a step share the GPU.  pipelined: three "
+                         "streams (round-robin), main sweeps one at a time (chained by events), the "
+                         "latency-bound stages overlapping them; serial: one after the other on one stream; "
+                         "concurrent: six streams, no ordering")
     ap.add_argument("--compare-precision", action="store_true",
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,

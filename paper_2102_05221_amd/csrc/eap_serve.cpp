@@ -10,8 +10,11 @@
 // the slot: at most max_batch queries whose values, NN workspace and outputs
 // fit the slot's bytes (admission by memory).  Each batch is one eap_nn1 call
 // on the slot's stream, so batches admitted while others are running overlap
-// on the device.  A query is answered by the same search whether it runs
-// alone or in a batch: its result does not depend on the other queries.
+// on the device.  A slot's NN workspace sits at the start of its bytes; what
+// a search derives from the candidates alone sits at the workspace's start,
+// so from the slot's second batch on it is reused (flags bit 3).  A query is
+// answered by the same search whether it runs alone or in a batch: its result
+// does not depend on the other queries.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
