@@ -153,3 +153,30 @@ def pairwise(p: dict, s, s_off, mode: str = "prune", nthreads: int = 0) -> np.nd
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def derivative(v, off) -> np.ndarray:
+    """First-derivative series for the derivative variants (DDTW, DCDTW,
+    DWDTW: the distance of the derivative series, Section 2.3 names them
+    without a formula).  Reading: the estimate of Keogh and Pazzani (2001),
+    for 1 < i < m: d_i = ((q_i - q_{i-1}) + (q_{i+1} - q_{i-1}) / 2) / 2,
+    evaluated in that order in binary64; the ends copy their neighbours,
+    d_1 = d_2 and d_m = d_{m-1}; m = 2 gives d_1 = d_2 = q_2 - q_1 and m = 1
+    gives 0.  A plain loop over the values of each series."""
+    v = _f64(v)
+    off = np.asarray(off, dtype=np.int64)
+    out = np.empty_like(v)
+    for s in range(len(off) - 1):
+        a, m = int(off[s]), int(off[s + 1] - off[s])
+        q = v[a:a + m]
+        if m == 1:
+            out[a] = 0.0
+            continue
+        if m == 2:
+            out[a] = out[a + 1] = q[1] - q[0]
+            continue
+        for i in range(1, m - 1):
+            out[a + i] = ((q[i] - q[i - 1]) + (q[i + 1] - q[i - 1]) / 2.0) / 2.0
+        out[a] = out[a + 1]
+        out[a + m - 1] = out[a + m - 2]
+    return out

@@ -395,3 +395,38 @@ def test_generators_are_seeded_and_normalised():
     lens = np.diff(c["ref_off"])
     assert lens.min() >= 64 and lens.max() <= 2048
     assert np.array_equal(synth.znorm(np.full(7, 3.0)), np.zeros(7))
+
+
+# Derivative series (DDTW, DCDTW, DWDTW; the estimate of Keogh and Pazzani,
+# a reading recorded with the oracle's function).
+
+def test_derivative_closed_forms(orc):
+    i = np.arange(12.0)
+    # linear a*i + b: every estimate is the slope a (exact for these values)
+    d = orc.derivative(0.5 * i + 3.0, [0, 12])
+    assert np.array_equal(d, np.full(12, 0.5))
+    # i^2: interior ((2i-1) + 2i) / 2 = 2i - 0.5, ends copied from their neighbours
+    d = orc.derivative(i * i, [0, 12])
+    want = 2.0 * i - 0.5
+    want[0], want[-1] = want[1], want[-2]
+    assert np.array_equal(d, want)
+    # a constant: 0
+    assert np.array_equal(orc.derivative(np.full(7, -2.25), [0, 7]), np.zeros(7))
+
+
+def test_derivative_hand_values_and_short_series(orc):
+    # series [3, 1, 4], [1], [5, 2], [7]: ((1-3) + (4-3)/2)/2 = -0.75 copied to
+    # both ends; a single value gives 0; two values give their difference twice
+    v = np.array([3.0, 1.0, 4.0, 1.0, 5.0, 2.0, 7.0])
+    d = orc.derivative(v, [0, 3, 4, 6, 7])
+    assert np.array_equal(d, np.array([-0.75, -0.75, -0.75, 0.0, -3.0, -3.0, 0.0]))
+
+
+def test_ddtw_of_linear_series_closed_form(orc):
+    # derivatives of slopes 1 and 3 are the constants 1 and 3: every warping
+    # path has at least max(m, n) cells, each costing (1-3)^2, so DDTW = 4 max(m, n)
+    x, y = np.arange(10.0), 3.0 * np.arange(7.0) + 1.0
+    v = np.concatenate([x, y])
+    d = orc.derivative(v, [0, 10, 17])
+    for p in (dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.5)):
+        assert orc.dp(p, d[:10], d[10:]) == 40.0
