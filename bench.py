@@ -114,12 +114,16 @@ def swept_kind(kind, p):
     return kind
 
 
-def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist):
+def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist, derivative=False):
     """The CPU oracle's EAPruned NN (Alg. 1 + Alg. 5) on the first nq_sample
     queries against all candidates, every host thread; beside it the oracle's
     full DP on at most 64 of those queries (every thread) and EAPruned on the
-    first query, one thread."""
+    first query, one thread.  derivative: on the oracle's derivative series
+    of the same inputs (the transform itself untimed)."""
     from oracle import oracle as orc
+    if derivative:
+        wl = dict(wl, queries=orc.derivative(wl["queries"], wl["query_off"]),
+                  refs=orc.derivative(wl["refs"], wl["ref_off"]))
     qo = wl["query_off"][: nq_sample + 1]
     qv = wl["queries"][: qo[-1]]
     cells = 0
@@ -223,12 +227,15 @@ def run_pairwise(args, torch, eap, synth):
         per_distance=per)), flush=True)
 
 
+ap_default_kinds = "dtw,cdtw,wdtw,erp,msm,twe"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--kinds", default="dtw,cdtw,wdtw,erp,msm,twe")
+    ap.add_argument("--kinds", default=ap_default_kinds)
     ap.add_argument("--cpu-queries", type=int, default=500,
                     help="queries in the CPU-oracle EAPruned sample (0: skip; about 5 s for all 500 of the "
                          "default workload on 16 threads)")
@@ -240,6 +247,9 @@ def main():
                          "streams (round-robin), main sweeps one at a time (chained by events), the "
                          "latency-bound stages overlapping them; serial: one after the other on one stream; "
                          "concurrent: six streams, no ordering")
+    ap.add_argument("--derivative", action="store_true",
+                    help="workload 2 with the derivative variants: the series' first derivatives computed "
+                         "inside every step, then DDTW, DCDTW and DWDTW (default --kinds dtw,cdtw,wdtw)")
     ap.add_argument("--compare-precision", action="store_true",
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -278,11 +288,27 @@ def main():
         return run_served(args, torch, eap, synth)
 
     dev = torch.device("cuda:0")
+    if args.derivative and args.kinds == ap_default_kinds:
+        args.kinds = "dtw,cdtw,wdtw"
     kinds = [k for k in args.kinds.split(",") if k]
     wl = synth.make_workload(2)
     q = torch.from_numpy(wl["queries"]).to(dev)
     r = torch.from_numpy(wl["refs"]).to(dev)
     labels = torch.from_numpy(wl["ref_labels"]).to(dev)
+    derive = None
+    if args.derivative:
+        # the searches read the derivative series, recomputed at the start of
+        # every step from the raw series (part of the timed work)
+        q_raw, r_raw = q, r
+        q, r = torch.empty_like(q_raw), torch.empty_like(r_raw)
+        dws = eap.workspace(max(eap.lib().eap_derivative_workspace(len(wl["query_off"]) - 1),
+                                eap.lib().eap_derivative_workspace(len(wl["ref_off"]) - 1)), dev)
+
+        def derive():
+            eap.derivative(q_raw, wl["query_off"], ws=dws, out=q)
+            eap.derivative(r_raw, wl["ref_off"], ws=dws, out=r)
+
+        derive()
     nq, nr = len(wl["query_off"]) - 1, len(wl["ref_off"]) - 1
     ws = {k: eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], wl["ref_off"], wl["params"][k], precision=1), dev)
           for k in kinds}
@@ -304,6 +330,8 @@ def main():
     def step(precision=args.precision, schedule=args.schedule):
         """One pass of the six searches.  The step starts and ends on `stream`
         (the other streams fork from it and join it again)."""
+        if derive:
+            derive()
         if schedule == "serial":
             for k in kinds:
                 eap.nn1(q, wl["query_off"], r, wl["ref_off"], wl["params"][k], ref_labels=labels, ws=ws[k],
@@ -469,7 +497,7 @@ def main():
 
     cpu = None
     if args.cpu_queries > 0:
-        cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, nq), gpu_idx, gpu_dist)
+        cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, nq), gpu_idx, gpu_dist, derivative=args.derivative)
 
     total_dense = sum(dense.values())
     line = dict(
@@ -486,8 +514,9 @@ def main():
         dtype=("f32+f64" if args.precision else "f64"),
         data="synthetic",
         config=dict(workload="1-NN classification, 500 queries x 500 candidates, length 512, 5 warped-sine "
-                             "classes; " + ", ".join(kinds) + " (CDTW w=10%, WDTW g=0.05, ERP gap=0, MSM c=0.5, "
-                             "TWE nu=0.001 lambda=1)",
+                             "classes; " + ("derivative variants (first-derivative series computed in every "
+                                            "step) of " if args.derivative else "") + ", ".join(kinds) +
+                             " (CDTW w=10%, WDTW g=0.05, ERP gap=0, MSM c=0.5, TWE nu=0.001 lambda=1)",
                     queries=nq, candidates=nr, length=512, distances=kinds,
                     precision=("fp32 screen + fp64 recheck" if args.precision else "fp64")),
         other_precision=other,

@@ -198,6 +198,20 @@ size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params*
 eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const eap_params* p, int32_t mode,
                         void* ws, size_t ws_bytes, double* out, void* stream);
 
+/* Derivative series, for the derivative variants DDTW, DCDTW and DWDTW
+ * (Section 2.3 names them: the distance of the series' first derivatives,
+ * with no formula given).  The estimate of Keogh and Pazzani: for 1 < i < m,
+ * d_i = ((q_i - q_{i-1}) + (q_{i+1} - q_{i-1}) / 2) / 2 in that order in
+ * binary64; d_1 = d_2 and d_m = d_{m-1}; m = 2 gives d_1 = d_2 = q_2 - q_1,
+ * m = 1 gives 0.  A derivative variant is then eap_nn1 / eap_pairwise /
+ * eap_distance of DTW, CDTW or WDTW on the derivative series.
+ *  v, off, n   device values, host offsets (n >= 1 series, lengths >= 1).
+ *  out         device double[off[n]], not overlapping v.
+ *  ws          device workspace of eap_derivative_workspace(n) bytes. */
+size_t eap_derivative_workspace(int64_t n);
+eap_status eap_derivative(const double* v, const int64_t* off, int64_t n, double* out, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* Copies the counters accumulated in `ws` to host memory (synchronises `stream`).
  * eap_reset_counters() zeroes them (asynchronously, on `stream`). */
 eap_status eap_read_counters(const void* ws, size_t ws_bytes, eap_counters* out, void* stream);

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "derivative", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
@@ -111,6 +111,10 @@ def lib():
         L.eap_pairwise_workspace.argtypes = [_pi64, _i64, _pP]
         L.eap_pairwise.restype = ctypes.c_int
         L.eap_pairwise.argtypes = [_vp, _pi64, _i64, _pP, ctypes.c_int32, _vp, _sz, _vp, _vp]
+        L.eap_derivative_workspace.restype = _sz
+        L.eap_derivative_workspace.argtypes = [_i64]
+        L.eap_derivative.restype = ctypes.c_int
+        L.eap_derivative.argtypes = [_vp, _pi64, _i64, _vp, _vp, _sz, _vp]
         L.eap_read_counters.restype = ctypes.c_int
         L.eap_read_counters.argtypes = [_vp, _sz, ctypes.POINTER(Counters), _vp]
         L.eap_reset_counters.restype = ctypes.c_int
@@ -394,6 +398,23 @@ def capture_end(stream) -> Graph:
     h = ctypes.c_void_p(None)
     _check(lib().eap_capture_end(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
     return Graph(h)
+
+
+def derivative(v, off, ws=None, stream=None, out=None):
+    """Derivative series of the concatenated series v (device float64) with
+    host offsets off, for DDTW / DCDTW / DWDTW (the estimate of Keogh and
+    Pazzani; see eap_derivative in include/eap.h).  Returns a device tensor."""
+    import torch
+    _dev_f64(v, "series")
+    off = _offsets(off)
+    n = len(off) - 1
+    if ws is None:
+        ws = workspace(int(lib().eap_derivative_workspace(n)), v.device)
+    if out is None:
+        out = torch.empty_like(v)
+    _check(lib().eap_derivative(v.data_ptr(), off.ctypes.data_as(_pi64), n, out.data_ptr(), ws.data_ptr(),
+                                ws.numel(), _stream(stream, v.device)))
+    return out
 
 
 def pairwise_workspace_bytes(s_off, p) -> int:

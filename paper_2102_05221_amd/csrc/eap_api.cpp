@@ -852,6 +852,29 @@ static void pw_layout(const SetInfo& S, const eap_params* p, PWLayout& pl) {
     pl.edge = pl.L.take(edge_bytes(std::max<int64_t>(np, 1), S.maxlen, S.maxlen));
 }
 
+size_t eap_derivative_workspace(int64_t n) {
+    if (n < 1) return 0;
+    return (sizeof(int64_t) * (size_t)(n + 1) + kAlign - 1) / kAlign * kAlign;
+}
+
+eap_status eap_derivative(const double* v, const int64_t* off, int64_t n, double* out, void* ws, size_t ws_bytes,
+                          void* stream) {
+    eap_status st;
+    if (!v || !out) return fail(EAP_EINVAL, "NULL series or output");
+    SetInfo S;
+    if ((st = check_offsets(off, n, "series", &S)) != EAP_OK) return st;
+    const size_t need = eap_derivative_workspace(n);
+    if (!ws || ws_bytes < need) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    const char* vb = reinterpret_cast<const char*>(v);
+    const char* ob = reinterpret_cast<const char*>(out);
+    const size_t bytes = sizeof(double) * (size_t)S.total;
+    if (vb < ob + bytes && ob < vb + bytes) return fail(EAP_EINVAL, "out overlaps the input values");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload(ws, off, sizeof(int64_t) * (size_t)(n + 1), s)) != EAP_OK) return st;
+    HIPCHK(launch_derivative(v, reinterpret_cast<const int64_t*>(ws), n, out, s));
+    return EAP_OK;
+}
+
 size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params* p) {
     SetInfo S;
     if (check_params(p) != EAP_OK || check_offsets(s_off, n, "series", &S) != EAP_OK) return 0;

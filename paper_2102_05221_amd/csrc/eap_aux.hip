@@ -28,6 +28,28 @@ __global__ void erp_border_kernel(const double* v, const int64_t* off, int64_t n
     }
 }
 
+// Derivative series (Keogh-Pazzani estimate): one block per series, series by
+// grid stride.  The two ends repeat the estimate at their neighbour.
+__global__ void derivative_kernel(const double* v, const int64_t* off, int64_t n, double* out) {
+    for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
+        const int64_t a = off[s];
+        const int m = (int)(off[s + 1] - a);
+        const double* q = v + a;
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+            double d;
+            if (m == 1) {
+                d = 0.0;
+            } else if (m == 2) {
+                d = q[1] - q[0];
+            } else {
+                const int c = i < 1 ? 1 : (i > m - 2 ? m - 2 : i);
+                d = ((q[c] - q[c - 1]) + (q[c + 1] - q[c - 1]) / 2.0) / 2.0;
+            }
+            out[a + i] = d;
+        }
+    }
+}
+
 __global__ void to_f32_kernel(const double* v, int64_t n, float* out) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
         out[x] = (float)v[x];
@@ -645,6 +667,12 @@ static int blocks_for(int64_t n, int per) {
 
 hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s) {
     hipLaunchKernelGGL(erp_border_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, s, v, off, n, gap, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(derivative_kernel, dim3((unsigned)std::min<int64_t>(n, 65535)), dim3(256), 0, s, v, off, n,
+                       out);
     return hipGetLastError();
 }
 

@@ -121,6 +121,22 @@ def test_pairwise_argument_errors(L):
     assert L.eap_pairwise(FAKE, pi, 3, ctypes.byref(p), 0, ws, need - 8, FAKE, None) == eap.EAP_EWORKSPACE
 
 
+def test_derivative_argument_errors(L):
+    so = _off(6, 1, 9)
+    pi = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    need = L.eap_derivative_workspace(3)
+    assert need >= 4 * 8 and L.eap_derivative_workspace(0) == 0
+    ws = ctypes.c_void_p(0x2000)
+    out = ctypes.c_void_p(0x100000)
+    assert L.eap_derivative(None, pi(so), 3, out, ws, need, None) == eap.EAP_EINVAL
+    assert L.eap_derivative(FAKE, pi(so), 3, None, ws, need, None) == eap.EAP_EINVAL
+    assert L.eap_derivative(FAKE, pi(so), 0, out, ws, need, None) == eap.EAP_EINVAL
+    assert L.eap_derivative(FAKE, pi(_off(6, 0, 9)), 3, out, ws, need, None) == eap.EAP_EINVAL   # zero length
+    assert L.eap_derivative(FAKE, pi(so), 3, ctypes.c_void_p(0x1008), ws, need, None) == eap.EAP_EINVAL  # overlap
+    assert L.eap_derivative(FAKE, pi(so), 3, out, ws, need - 1, None) == eap.EAP_EWORKSPACE
+    assert L.eap_derivative(FAKE, pi(so), 3, out, None, need, None) == eap.EAP_EWORKSPACE
+
+
 def test_workspace_sizes_grow_with_the_problem(L):
     p = _p("twe", nu=0.001, lam=1.0)
     o = eap.NNOpts(0, 1e-4, 0)

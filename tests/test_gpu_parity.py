@@ -437,6 +437,39 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert c["lb_pruned"] > 0
 
 
+def test_derivative_series_bit_equal_to_oracle(torch_dev, orc):
+    """The derivative series of ragged series (lengths 1 to 300, the short
+    cases included) equal the oracle's bit for bit."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(12)
+    lens = [1, 2, 3, 4] + list(rng.integers(1, 300, 60))
+    s = [rng.standard_normal(int(m)) * 3.0 for m in lens]
+    v, o = synth.pack(s)
+    log("derivative series")
+    g = eap.derivative(to_dev(torch, dev, v), o).cpu().numpy()
+    assert np.array_equal(g, orc.derivative(v, o))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["dtw", "cdtw", "wdtw"])
+def test_derivative_variant_nn_parity(torch_dev, orc, kind, precision):
+    """DDTW / DCDTW / DWDTW: NN search over the derivative series (device
+    transform, then the usual search) gives the oracle's NN on the oracle's
+    derivative series."""
+    torch, dev = torch_dev
+    wl = synth.make_workload(2, n_ref=80, n_query=10)
+    p = wl["params"][kind]
+    qo, ro = wl["query_off"], wl["ref_off"]
+    log(f"derivative variant {kind} precision={precision}")
+    qd = eap.derivative(to_dev(torch, dev, wl["queries"]), qo)
+    rd = eap.derivative(to_dev(torch, dev, wl["refs"]), ro)
+    gi, gd, _ = eap.nn1(qd, qo, rd, ro, p, precision=precision)
+    oq, orr = orc.derivative(wl["queries"], qo), orc.derivative(wl["refs"], ro)
+    oi, od, _ = orc.nn1(p, oq, qo, orr, ro, "dp")
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("kind", ["erp", "cdtw", "msm", "wdtw"])
 def test_candidates_prepared_flag(torch_dev, orc, kind, precision):
