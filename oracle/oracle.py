@@ -10,6 +10,7 @@ defaults below.  Series are float64 numpy arrays.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -179,4 +180,32 @@ def derivative(v, off) -> np.ndarray:
             out[a + i] = ((q[i] - q[i - 1]) + (q[i + 1] - q[i - 1]) / 2.0) / 2.0
         out[a] = out[a + 1]
         out[a + m - 1] = out[a + m - 2]
+    return out
+
+
+def subseq_windows(s, m: int) -> np.ndarray:
+    """Candidates of a sub-sequence search (Section 5.3: the closest match of
+    a query within a long series): every window of length m, z-normalised on
+    its own as the UCR suite does (reading: population standard deviation; a
+    constant window gives zeros).  For window w, in binary64 and in this order:
+    mean = (sum over k, left to right, of s[w+k]) / m, var = (sum of
+    (s[w+k] - mean)^2, left to right) / m, sd = sqrt(var), value k =
+    (s[w+k] - mean) / sd.  Returns the windows back to back, (n-m+1) * m
+    values.  Plain loops; for test-sized series."""
+    s = [float(x) for x in _f64(s)]
+    n = len(s)
+    nw = n - m + 1
+    out = np.empty(nw * m)
+    for w in range(nw):
+        acc = 0.0
+        for k in range(m):
+            acc = acc + s[w + k]
+        mean = acc / m
+        v = 0.0
+        for k in range(m):
+            d = s[w + k] - mean
+            v = v + d * d
+        sd = math.sqrt(v / m)
+        for k in range(m):
+            out[w * m + k] = (s[w + k] - mean) / sd if sd > 0.0 else 0.0
     return out

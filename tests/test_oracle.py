@@ -430,3 +430,41 @@ def test_ddtw_of_linear_series_closed_form(orc):
     d = orc.derivative(v, [0, 10, 17])
     for p in (dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.5)):
         assert orc.dp(p, d[:10], d[10:]) == 40.0
+
+
+# Sub-sequence search candidates: z-normalised windows (Section 5.3).
+
+def test_subseq_windows_closed_forms(orc):
+    # an arithmetic progression: every window of 3 is (-1, 0, 1) / sqrt(2/3)
+    w = orc.subseq_windows(np.arange(7.0) * 0.5 - 1.0, 3)
+    assert w.shape == (5 * 3,)
+    r = math.sqrt(1.5)
+    assert np.allclose(w, np.tile([-r, 0.0, r], 5), rtol=1e-15, atol=0)
+    assert np.array_equal(orc.subseq_windows(np.full(6, 4.5), 4), np.zeros(12))   # constant: zeros
+    assert np.array_equal(orc.subseq_windows(np.array([1.0, 2.0]), 2), np.array([-1.0, 1.0]))
+
+
+def test_subseq_windows_are_normalised_and_invariant(orc):
+    rng = np.random.default_rng(3)
+    s = np.cumsum(rng.standard_normal(300))
+    m = 40
+    w = orc.subseq_windows(s, m).reshape(-1, m)
+    assert w.shape == (261, m)
+    assert np.all(np.abs(w.mean(axis=1)) < 1e-12)
+    assert np.allclose((w * w).mean(axis=1), 1.0, rtol=1e-12, atol=0)
+    # a positive scale and a shift of the series leave the windows unchanged
+    w2 = orc.subseq_windows(3.0 * s + 11.0, m).reshape(-1, m)
+    assert np.allclose(w, w2, rtol=0, atol=1e-12)
+
+
+def test_subseq_search_finds_a_planted_match(orc):
+    # a scaled and shifted copy of a window is found at its position at ~0 cost
+    rng = np.random.default_rng(9)
+    s = np.cumsum(rng.standard_normal(400))
+    m = 32
+    q = orc.subseq_windows(2.5 * s[150:150 + m] - 4.0, m)
+    w = orc.subseq_windows(s, m)
+    off = np.arange(0, len(w) + 1, m, dtype=np.int64)
+    for p in (dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.1)):
+        idx, dist, _ = orc.nn1(p, q, np.array([0, m], dtype=np.int64), w, off, "dp")
+        assert idx[0] == 150 and dist[0] < 1e-20
