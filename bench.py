@@ -254,11 +254,11 @@ def main():
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 plain device copies of this many MiB (HBM counter calibration) and exit")
-    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5),
+    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5, 6),
                     help="2: the benchmark (500 x 500, length 512); 3: all-pairs matrix; 4: batched uneven "
-                         "lengths, graph launch; 5: served requests")
-    ap.add_argument("--refs", type=int, default=0, help="workloads 3-5: series / candidate count (0: the full workload)")
-    ap.add_argument("--queries", type=int, default=0, help="workloads 4/5: query count (0: the full workload)")
+                         "lengths, graph launch; 5: served requests; 6: sub-sequence search")
+    ap.add_argument("--refs", type=int, default=0, help="workloads 3-6: series / candidate / window count (0: the full workload)")
+    ap.add_argument("--queries", type=int, default=0, help="workloads 4-6: query count (0: the full workload)")
     args = ap.parse_args()
     if args.copy_mib > 0:
         import torch
@@ -286,6 +286,8 @@ def main():
         return run_batched(args, torch, eap, synth)
     if args.workload == 5:
         return run_served(args, torch, eap, synth)
+    if args.workload == 6:
+        return run_subseq(args, torch, eap, synth)
 
     dev = torch.device("cuda:0")
     if args.derivative and args.kinds == ap_default_kinds:
@@ -674,6 +676,100 @@ def run_batched(args, torch, eap, synth):
         step_ms_p50=float(np.percentile(step_ms, 50)), step_ms_p99=float(np.percentile(step_ms, 99)),
         graph_results_identical_to_eager=same, tuning=tuning, per_distance=per, plain_gpu_dp=plain,
         roofline=roofline, cpu_baseline=cpu)), flush=True)
+
+
+def run_subseq(args, torch, eap, synth):
+    """Workload 6: sub-sequence search (Section 5.3), the query slid along a
+    long reference series as NN search over its z-normalised windows.  A
+    random walk of 2^20 + 127 values (2^20 windows of 128), 16 queries of 128
+    values (8 noisy, scaled and shifted copies of windows, 8 random walks),
+    CDTW w = 5% (the usual UCR-suite window; --kinds dtw for full DTW), FP32
+    screen + FP64 recheck.  A step builds the z-normalised windows (a GB of
+    candidates, resident in HBM) and searches every query."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(6)
+    m, nw = 128, (args.refs or (1 << 20))
+    n = nw + m - 1
+    s = np.cumsum(rng.standard_normal(n))
+    nq = args.queries or 16
+    starts = rng.integers(0, nw, nq // 2)
+    qs = [1.5 * s[st:st + m] + 3.0 + 0.1 * rng.standard_normal(m) for st in starts]
+    qs += [np.cumsum(rng.standard_normal(m)) for _ in range(nq - len(qs))]
+    kinds = [k for k in args.kinds.split(",") if k in ("dtw", "cdtw")] if args.kinds != ap_default_kinds else ["cdtw"]
+    P = {"dtw": dict(kind="dtw"), "cdtw": dict(kind="cdtw", window_ratio=0.05)}
+    sd = torch.from_numpy(s).to(dev)
+    qv = torch.from_numpy(np.concatenate(qs)).to(dev)
+    q_off = np.arange(nq + 1, dtype=np.int64) * m
+    r_off = np.arange(nw + 1, dtype=np.int64) * m
+    w = torch.empty(nw * m, dtype=torch.float64, device=dev)
+    zq = torch.empty(nq * m, dtype=torch.float64, device=dev)
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(q_off, r_off, P[k], precision=args.precision), dev) for k in kinds}
+    outs = {k: (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev), None)
+            for k in kinds}
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        eap.subseq_windows(sd, m, out=w)
+        for i in range(nq):
+            eap.subseq_windows(qv[i * m:(i + 1) * m], m, out=zq[i * m:(i + 1) * m])
+        for k in kinds:
+            eap.nn1(zq, q_off, w, r_off, P[k], ws=ws[k], out=outs[k], precision=args.precision)
+
+    step()
+    if not args.no_tune:
+        for k in kinds:
+            eap.tune_nn1(zq, q_off, w, r_off, P[k], precision=args.precision, ws=ws[k])
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    eap.profile_take()
+    eap.profile_enable(True)
+    steps = max(1, min(args.steps, 5))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    eap.profile_enable(False)
+    prof = eap.profile_take()
+    dense = {k: dense_cells(k, P[k], q_off, r_off) for k in kinds}
+    found = {k: int(sum(1 for i, st in enumerate(starts) if int(outs[k][0][i].item()) == int(st))) for k in kinds}
+    per = {}
+    for k in kinds:
+        main = [x for x in prof if x["kind"] == k and x["stage"] == 2]
+        per[k] = dict(main_sweep_ms=(sum(x["ms"] for x in main) / len(main)) if main else None,
+                      main_kernel=(kernel_label(main[0]) if main else None), dense_cells=dense[k],
+                      planted_found=found[k], planted=len(starts))
+    # the oracle on the whole workload, timed like one step: the windows and
+    # the queries normalised, then the NN search; the GPU answers compared
+    cpu = None
+    if args.cpu_queries > 0:
+        from oracle import oracle as orc
+        same, cells, secs = True, 0.0, 0.0
+        for k in kinds:
+            t1 = time.perf_counter()
+            ow = orc.subseq_windows(s, m)
+            oq = np.concatenate([orc.subseq_windows(x, m) for x in qs])
+            oi, od, _ = orc.nn1(P[k], oq, q_off, ow, r_off, "eap")
+            secs += time.perf_counter() - t1
+            cells += dense[k]
+            same &= bool(np.array_equal(outs[k][0].cpu().numpy(), oi)
+                         and np.array_equal(outs[k][1].cpu().numpy(), od))
+            del ow
+        cpu = dict(value=cells / secs / 1e9, unit="GCUPS", cores=orc.num_threads(), kind="oracle",
+                   sample=f"the whole workload: {nw} windows normalised and the EAPruned NN of the {nq} queries "
+                          f"({secs:.1f} s)",
+                   nn_identical_to_gpu=same)
+    total = sum(dense.values())
+    print(json.dumps(dict(
+        metric=METRIC, value=total / (ms_per_step * 1e-3) / 1e9, unit="GCUPS", n_gpus=1, steps=steps, warmup=args.warmup,
+        ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=("f32+f64" if args.precision else "f64"), data="synthetic",
+        config=dict(workload=f"sub-sequence search: {nq} queries of {m} values in a random walk of {n} values "
+                             f"({nw} z-normalised windows), " + ", ".join(
+                                 f"{k}" + (" w=5%" if k == "cdtw" else "") for k in kinds),
+                    queries=nq, windows=nw, length=m, distances=kinds),
+        queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3), per_distance=per, cpu_baseline=cpu)), flush=True)
 
 
 def run_served(args, torch, eap, synth):

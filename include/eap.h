@@ -198,6 +198,20 @@ size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params*
 eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const eap_params* p, int32_t mode,
                         void* ws, size_t ws_bytes, double* out, void* stream);
 
+/* Sub-sequence search (Section 5.3: the closest match of a query within a
+ * long series) as NN search: every window of length m of the series,
+ * z-normalised on its own as the UCR suite does, is a candidate.
+ * out[w*m + k] = (s[w+k] - mean_w) / sd_w for w = 0..n-m, k < m, with
+ * mean_w = (sum of s[w..w+m-1], left to right) / m and sd_w = sqrt((sum of
+ * (s[w+k] - mean_w)^2, left to right) / m) in binary64 (population standard
+ * deviation; a constant window gives zeros).  The search is then eap_nn1 of
+ * the query, z-normalised the same way (this call with n = m), against the
+ * n-m+1 candidates with offsets k*m; the NN index is the window's start.
+ *  s, n, m     device double[n], 1 <= m <= 2048, m <= n, (n-m+1)*m < 2^31
+ *              (longer series: search them in overlapping parts).
+ *  out         device double[(n-m+1)*m], not overlapping s. */
+eap_status eap_subseq_windows(const double* s, int64_t n, int64_t m, double* out, void* stream);
+
 /* Derivative series, for the derivative variants DDTW, DCDTW and DWDTW
  * (Section 2.3 names them: the distance of the series' first derivatives,
  * with no formula given).  The estimate of Keogh and Pazzani: for 1 < i < m,

@@ -191,21 +191,22 @@ def subseq_windows(s, m: int) -> np.ndarray:
     mean = (sum over k, left to right, of s[w+k]) / m, var = (sum of
     (s[w+k] - mean)^2, left to right) / m, sd = sqrt(var), value k =
     (s[w+k] - mean) / sd.  Returns the windows back to back, (n-m+1) * m
-    values.  Plain loops; for test-sized series."""
-    s = [float(x) for x in _f64(s)]
-    n = len(s)
-    nw = n - m + 1
-    out = np.empty(nw * m)
-    for w in range(nw):
-        acc = 0.0
-        for k in range(m):
-            acc = acc + s[w + k]
-        mean = acc / m
-        v = 0.0
-        for k in range(m):
-            d = s[w + k] - mean
-            v = v + d * d
-        sd = math.sqrt(v / m)
-        for k in range(m):
-            out[w * m + k] = (s[w + k] - mean) / sd if sd > 0.0 else 0.0
-    return out
+    values.  The loops run over k, each step applied to all windows at once
+    (element-wise binary64 operations, so every window sees exactly the
+    sequence of operations written above)."""
+    s = _f64(s)
+    nw = len(s) - m + 1
+    acc = np.zeros(nw)
+    for k in range(m):
+        acc = acc + s[k:k + nw]
+    mean = acc / m
+    v = np.zeros(nw)
+    for k in range(m):
+        d = s[k:k + nw] - mean
+        v = v + d * d
+    sd = np.sqrt(v / m)
+    out = np.zeros((nw, m))
+    ok = sd > 0.0
+    for k in range(m):
+        out[ok, k] = (s[k:k + nw][ok] - mean[ok]) / sd[ok]
+    return out.reshape(-1)

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "derivative", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "derivative", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
@@ -111,6 +111,8 @@ def lib():
         L.eap_pairwise_workspace.argtypes = [_pi64, _i64, _pP]
         L.eap_pairwise.restype = ctypes.c_int
         L.eap_pairwise.argtypes = [_vp, _pi64, _i64, _pP, ctypes.c_int32, _vp, _sz, _vp, _vp]
+        L.eap_subseq_windows.restype = ctypes.c_int
+        L.eap_subseq_windows.argtypes = [_vp, _i64, _i64, _vp, _vp]
         L.eap_derivative_workspace.restype = _sz
         L.eap_derivative_workspace.argtypes = [_i64]
         L.eap_derivative.restype = ctypes.c_int
@@ -398,6 +400,34 @@ def capture_end(stream) -> Graph:
     h = ctypes.c_void_p(None)
     _check(lib().eap_capture_end(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
     return Graph(h)
+
+
+def subseq_windows(s, m: int, stream=None, out=None):
+    """Every window of length m of the device float64 series s, z-normalised
+    on its own (sub-sequence search candidates, eap_subseq_windows), back to
+    back: a device tensor of (len(s) - m + 1) * m values."""
+    import torch
+    _dev_f64(s, "series")
+    n = s.numel()
+    if out is None:
+        out = torch.empty(max(n - m + 1, 0) * m, dtype=torch.float64, device=s.device)
+    _check(lib().eap_subseq_windows(s.data_ptr(), n, int(m), out.data_ptr(), _stream(stream, s.device)))
+    return out
+
+
+def subseq_search(query, series, p, precision: int = 0, stream=None):
+    """Sub-sequence search (Section 5.3): the start of the window of `series`
+    closest to `query` (both device float64), every window and the query
+    z-normalised, as an NN search over the windows.  Returns (start, distance)
+    as 1-element device tensors, with the windows' offsets."""
+    import numpy as np
+    m = query.numel()
+    zq = subseq_windows(query, m, stream=stream)
+    w = subseq_windows(series, m, stream=stream)
+    nw = w.numel() // m
+    r_off = np.arange(nw + 1, dtype=np.int64) * m
+    idx, dist, _ = nn1(zq, np.array([0, m], dtype=np.int64), w, r_off, p, precision=precision, stream=stream)
+    return idx, dist
 
 
 def derivative(v, off, ws=None, stream=None, out=None):

@@ -852,6 +852,23 @@ static void pw_layout(const SetInfo& S, const eap_params* p, PWLayout& pl) {
     pl.edge = pl.L.take(edge_bytes(std::max<int64_t>(np, 1), S.maxlen, S.maxlen));
 }
 
+eap_status eap_subseq_windows(const double* s, int64_t n, int64_t m, double* out, void* stream) {
+    if (!s || !out) return fail(EAP_EINVAL, "NULL series or output");
+    if (m < 1 || m > kMaxLen) return fail(EAP_EINVAL, "window length %lld outside 1..%lld", (long long)m,
+                                          (long long)kMaxLen);
+    if (n < m) return fail(EAP_EINVAL, "series of %lld values is shorter than the window", (long long)n);
+    const int64_t nw = n - m + 1;
+    if (nw > (int64_t)INT32_MAX / m)
+        return fail(EAP_EINVAL, "%lld windows of %lld values exceed 2^31 - 1 values: search the series in parts",
+                    (long long)nw, (long long)m);
+    const char* sb = reinterpret_cast<const char*>(s);
+    const char* ob = reinterpret_cast<const char*>(out);
+    if (sb < ob + sizeof(double) * (size_t)(nw * m) && ob < sb + sizeof(double) * (size_t)n)
+        return fail(EAP_EINVAL, "out overlaps the series");
+    HIPCHK(launch_subseq_windows(s, nw, (int)m, out, (hipStream_t)stream));
+    return EAP_OK;
+}
+
 size_t eap_derivative_workspace(int64_t n) {
     if (n < 1) return 0;
     return (sizeof(int64_t) * (size_t)(n + 1) + kAlign - 1) / kAlign * kAlign;

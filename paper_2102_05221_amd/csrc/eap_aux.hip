@@ -50,6 +50,25 @@ __global__ void derivative_kernel(const double* v, const int64_t* off, int64_t n
     }
 }
 
+// Z-normalised windows of length m (sub-sequence search candidates): one
+// thread per window by grid stride, sums left to right as written.
+__global__ void subseq_windows_kernel(const double* s, int64_t nw, int m, double* out) {
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+        const double* x = s + w;
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) acc = acc + x[k];
+        const double mean = acc / (double)m;
+        double v = 0.0;
+        for (int k = 0; k < m; ++k) {
+            const double d = x[k] - mean;
+            v = v + d * d;
+        }
+        const double sd = sqrt(v / (double)m);
+        double* o = out + w * m;
+        for (int k = 0; k < m; ++k) o[k] = sd > 0.0 ? (x[k] - mean) / sd : 0.0;
+    }
+}
+
 __global__ void to_f32_kernel(const double* v, int64_t n, float* out) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
         out[x] = (float)v[x];
@@ -673,6 +692,11 @@ hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, dou
 hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(derivative_kernel, dim3((unsigned)std::min<int64_t>(n, 65535)), dim3(256), 0, s, v, off, n,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(subseq_windows_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, s, x, nw, m, out);
     return hipGetLastError();
 }
 

@@ -96,6 +96,7 @@ bool band_shape_ok(int diags, int g);
 hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s);
 hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
 hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s);
+hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s);
 // Path upper bounds of all NN pairs; rT: workspace of nB * lr_max doubles for
 // the interleaved candidates.  For CDTW with env_up/env_lo (nA * lr_max
 // doubles each) and lb (nA * nB doubles), also LB_Keogh of every pair.

@@ -137,6 +137,17 @@ def test_derivative_argument_errors(L):
     assert L.eap_derivative(FAKE, pi(so), 3, out, None, need, None) == eap.EAP_EWORKSPACE
 
 
+def test_subseq_windows_argument_errors(L):
+    out = ctypes.c_void_p(0x100000)
+    assert L.eap_subseq_windows(None, 100, 10, out, None) == eap.EAP_EINVAL
+    assert L.eap_subseq_windows(FAKE, 100, 10, None, None) == eap.EAP_EINVAL
+    assert L.eap_subseq_windows(FAKE, 100, 0, out, None) == eap.EAP_EINVAL          # empty window
+    assert L.eap_subseq_windows(FAKE, 100, 3000, out, None) == eap.EAP_EINVAL       # longer than supported
+    assert L.eap_subseq_windows(FAKE, 9, 10, out, None) == eap.EAP_EINVAL           # series shorter than the window
+    assert L.eap_subseq_windows(FAKE, 1 << 30, 2048, out, None) == eap.EAP_EINVAL   # over 2^31 - 1 values
+    assert L.eap_subseq_windows(FAKE, 100, 10, ctypes.c_void_p(0x1100), None) == eap.EAP_EINVAL  # overlap
+
+
 def test_workspace_sizes_grow_with_the_problem(L):
     p = _p("twe", nu=0.001, lam=1.0)
     o = eap.NNOpts(0, 1e-4, 0)

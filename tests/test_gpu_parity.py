@@ -437,6 +437,40 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert c["lb_pruned"] > 0
 
 
+@pytest.mark.parametrize("m", [1, 2, 37, 128])
+def test_subseq_windows_bit_equal_to_oracle(torch_dev, orc, m):
+    """Z-normalised windows of a long series (sums, square root and divisions
+    in the same order as the oracle's) equal the oracle's bit for bit."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(m)
+    s = np.cumsum(rng.standard_normal(1500)) * 2.0 + 5.0
+    s[100:130] = 3.25   # constant stretch: constant windows give zeros
+    log(f"subseq windows m={m}")
+    g = eap.subseq_windows(to_dev(torch, dev, s), m).cpu().numpy()
+    assert np.array_equal(g, orc.subseq_windows(s, m))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("p", [dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.1)], ids=pid)
+def test_subseq_search_parity(torch_dev, orc, p, precision):
+    """Sub-sequence search over a 4,000-value series with noisy, scaled and
+    shifted copies of windows planted as queries: the GPU's best window and
+    distance equal the oracle's."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(21 + precision)
+    s = np.cumsum(rng.standard_normal(4000))
+    m = 64
+    sd = to_dev(torch, dev, s)
+    w_or = orc.subseq_windows(s, m)
+    off = np.arange(0, len(w_or) + 1, m, dtype=np.int64)
+    for start in (0, 1234, 3936):
+        q = 1.7 * s[start:start + m] - 2.0 + 0.05 * rng.standard_normal(m)
+        log(f"subseq search {pid(p)} precision={precision} start={start}")
+        gi, gd = eap.subseq_search(to_dev(torch, dev, q), sd, p, precision=precision)
+        oi, od, _ = orc.nn1(p, orc.subseq_windows(q, m), np.array([0, m], dtype=np.int64), w_or, off, "dp")
+        assert int(gi.item()) == int(oi[0]) and float(gd.item()) == float(od[0])
+
+
 def test_derivative_series_bit_equal_to_oracle(torch_dev, orc):
     """The derivative series of ragged series (lengths 1 to 300, the short
     cases included) equal the oracle's bit for bit."""
