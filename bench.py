@@ -687,14 +687,10 @@ def run_subseq(args, torch, eap, synth):
     screen + FP64 recheck.  A step builds the z-normalised windows (a GB of
     candidates, resident in HBM) and searches every query."""
     dev = torch.device("cuda:0")
-    rng = np.random.default_rng(6)
-    m, nw = 128, (args.refs or (1 << 20))
+    m, nw, nq = 128, (args.refs or (1 << 20)), (args.queries or 16)
+    W = synth.subseq_workload(nw, m, nq)
+    s, qs, starts = W["series"], W["queries"], W["starts"]
     n = nw + m - 1
-    s = np.cumsum(rng.standard_normal(n))
-    nq = args.queries or 16
-    starts = rng.integers(0, nw, nq // 2)
-    qs = [1.5 * s[st:st + m] + 3.0 + 0.1 * rng.standard_normal(m) for st in starts]
-    qs += [np.cumsum(rng.standard_normal(m)) for _ in range(nq - len(qs))]
     kinds = [k for k in args.kinds.split(",") if k in ("dtw", "cdtw")] if args.kinds != ap_default_kinds else ["cdtw"]
     P = {"dtw": dict(kind="dtw"), "cdtw": dict(kind="cdtw", window_ratio=0.05)}
     sd = torch.from_numpy(s).to(dev)

@@ -21,7 +21,8 @@
  *    be reused as soon as the call returns.
  *  - The library never allocates device memory inside these calls: each driver
  *    takes a caller-provided device workspace sized by its *_workspace()
- *    function.  One workspace must not be used by two calls in flight.
+ *    function and aligned to 256 bytes (hipMalloc's and torch's allocations
+ *    are).  One workspace must not be used by two calls in flight.
  *  - Inputs must be finite; the library does not scan for NaN.
  *  - Errors: argument errors return EAP_EINVAL / EAP_EWORKSPACE synchronously,
  *    before anything is enqueued, and leave outputs untouched.  HIP failures
@@ -47,7 +48,7 @@ typedef enum {
     EAP_EINVAL = -1,     /* bad argument */
     EAP_ENOMEM = -2,     /* host staging memory could not be obtained */
     EAP_EDEVICE = -3,    /* a HIP call failed */
-    EAP_EWORKSPACE = -4  /* workspace missing or smaller than *_workspace() */
+    EAP_EWORKSPACE = -4  /* workspace missing, smaller than *_workspace() or not 256-byte aligned */
 } eap_status;
 
 /* Distance parameters (Section 2.3).

@@ -119,6 +119,15 @@ struct Header {
     unsigned long long absmax_r;
 };
 constexpr int kCounterWords = 32;
+// Workspace checks shared by the drivers: present, 256-byte aligned (kernels
+// read parts of it in aligned vectors), and at least `need` bytes.
+static eap_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (!ws || ws_bytes < need) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+        return fail(EAP_EWORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    return EAP_OK;
+}
+
 constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
 // header words cleared by every call: the queues, counts and absmax
 constexpr int kClearedWords = (int)(offsetof(Header, absmax_r) / 8) - kCounterWords;
@@ -556,7 +565,7 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
     Common c;
     size_t ovf, edge;
     distance_layout(lx, ly, p, L, c, &ovf, &edge);
-    if (!ws || ws_bytes < L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, L.off);
+    if (eap_status st_ws = check_ws(ws, ws_bytes, L.off)) return st_ws;
     Plan pl;
     if ((st = make_plan(p, lx, ly, std::llabs(lx - ly), false, &pl)) != EAP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -592,8 +601,8 @@ bool screen_useful(const eap_params* p, int64_t lmax) {
 struct NNLayout {
     Layout L;
     Common c;
-    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0, rT = 0;
-    size_t env_up = 0, env_lo = 0, lb = 0;   // CDTW: query envelopes and LB_Keogh per pair
+    size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0, rT = 0, part = 0;
+    size_t env = 0, lb = 0;   // CDTW: query envelopes (env_stride layout) and LB_Keogh per pair
     // FP32 screen
     size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
@@ -627,13 +636,13 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
         c.gtab = L.take(sizeof(double) * c.gtabv.size());
     }
     nl.best = nl.L.take(sizeof(unsigned long long) * (size_t)Q.n);
+    nl.part = nl.L.take(sizeof(double) * 2 * (size_t)scan_part_entries(Q.n));
     nl.seed = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
     if (effective_kind(p) == EAP_CDTW) {
-        nl.env_up = nl.L.take(sizeof(double) * (size_t)(Q.n * R.maxlen));
-        nl.env_lo = nl.L.take(sizeof(double) * (size_t)(Q.n * R.maxlen));
+        nl.env = nl.L.take(sizeof(double) * 3 * (size_t)env_stride(Q.n, R.maxlen));
         nl.lb = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     }
     nl.edge = nl.L.take(edge_bytes(Q.n * R.n, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)));
@@ -677,7 +686,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     const bool screen = prec1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
     NNLayout nl;
     nn_layout(Q, R, p, prec1, screen, nl);
-    if (!ws || ws_bytes < nl.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, nl.L.off);
+    if (eap_status st_ws = check_ws(ws, ws_bytes, nl.L.off)) return st_ws;
     Plan pl;
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     const bool plain = o && (o->flags & 2);
@@ -718,6 +727,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     int32_t* seed = reinterpret_cast<int32_t*>(at(ws, nl.seed));
     int32_t* seed_items = reinterpret_cast<int32_t*>(at(ws, nl.seed_items));
     double* res = reinterpret_cast<double*>(at(ws, nl.res));
+    double* part = reinterpret_cast<double*>(at(ws, nl.part));
     int32_t* ovf = reinterpret_cast<int32_t*>(at(ws, nl.ovf));
     a.mode = PM_NN_ALL;
     a.nA = nq;
@@ -737,17 +747,16 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK)
             return st;
         if (main_done) HIPCHK(hipEventRecord(main_done, s));
-        HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
+        HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, part, s));
         return EAP_OK;
     }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
     const bool lbk = effective_kind(p) == EAP_CDTW;
     double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
-                        lbk ? reinterpret_cast<double*>(at(ws, nl.env_up)) : nullptr,
-                        lbk ? reinterpret_cast<double*>(at(ws, nl.env_lo)) : nullptr, lb, s));
+                        lbk ? reinterpret_cast<double*>(at(ws, nl.env)) : nullptr, lb, s));
     a.lb = lb;
-    HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, s));
+    HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, part, s));
     const bool rerun = pl.rerun;
     // the seed and recheck sweeps have one or a few pairs per query
     Plan few = pl;
@@ -818,7 +827,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         //     result becomes +inf
         int32_t* items = reinterpret_cast<int32_t*>(at(ws, nl.recheck));
         HIPCHK(launch_screen_filter(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, o->margin_rel, res,
-                                    best, seeded ? seed : nullptr, items, &h->ovf_count[2], &h->counters[2], s));
+                                    best, seeded ? seed : nullptr, items, &h->ovf_count[2], &h->counters[2], part,
+                                    s));
         HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
         SweepArgs b = a;
         b.widen_abs = nullptr;
@@ -833,7 +843,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         }
     }
     // 4. lexicographic (distance, index) minimum per query
-    HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, s));
+    HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, part, s));
     return EAP_OK;
 }
 
@@ -881,7 +891,7 @@ eap_status eap_derivative(const double* v, const int64_t* off, int64_t n, double
     SetInfo S;
     if ((st = check_offsets(off, n, "series", &S)) != EAP_OK) return st;
     const size_t need = eap_derivative_workspace(n);
-    if (!ws || ws_bytes < need) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if (eap_status st_ws = check_ws(ws, ws_bytes, need)) return st_ws;
     const char* vb = reinterpret_cast<const char*>(v);
     const char* ob = reinterpret_cast<const char*>(out);
     const size_t bytes = sizeof(double) * (size_t)S.total;
@@ -913,7 +923,7 @@ eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const 
     if (np > (int64_t)INT32_MAX) return fail(EAP_EINVAL, "too many pairs");
     PWLayout pw;
     pw_layout(S, p, pw);
-    if (!ws || ws_bytes < pw.L.off) return fail(EAP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, pw.L.off);
+    if (eap_status st_ws = check_ws(ws, ws_bytes, pw.L.off)) return st_ws;
     Plan pl;
     if ((st = make_plan(p, S.maxlen, S.maxlen, S.maxlen - S.minlen, false, &pl)) != EAP_OK) return st;
     hipStream_t hs = (hipStream_t)stream;

@@ -52,20 +52,42 @@ __global__ void derivative_kernel(const double* v, const int64_t* off, int64_t n
 
 // Z-normalised windows of length m (sub-sequence search candidates): one
 // thread per window by grid stride, sums left to right as written.
-__global__ void subseq_windows_kernel(const double* s, int64_t nw, int m, double* out) {
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
-        const double* x = s + w;
-        double acc = 0.0;
-        for (int k = 0; k < m; ++k) acc = acc + x[k];
-        const double mean = acc / (double)m;
-        double v = 0.0;
-        for (int k = 0; k < m; ++k) {
-            const double d = x[k] - mean;
-            v = v + d * d;
+// z-normalised windows of a series, 256 windows per block: the block's
+// 256 + m - 1 values go to LDS, thread t takes the mean and standard deviation
+// of window t (sums in index order), then the block writes its windows, which
+// are contiguous in the output, with consecutive threads on consecutive
+// doubles.  sd == 0 gives a window of zeros.
+constexpr int kWinPerBlock = 256;
+__global__ __launch_bounds__(256) void subseq_windows_kernel(const double* s, int64_t nw, int m, double* out) {
+    extern __shared__ double xs[];   // kWinPerBlock + m - 1 values, then the means and deviations
+    double* mu = xs + kWinPerBlock + m - 1;
+    double* sdv = mu + kWinPerBlock;
+    for (int64_t w0 = (int64_t)blockIdx.x * kWinPerBlock; w0 < nw; w0 += (int64_t)gridDim.x * kWinPerBlock) {
+        const int nb = (int)(nw - w0 < kWinPerBlock ? nw - w0 : kWinPerBlock);
+        __syncthreads();   // the previous tile has been written out
+        for (int k = threadIdx.x; k < nb + m - 1; k += blockDim.x) xs[k] = s[w0 + k];
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            const double* x = xs + threadIdx.x;
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc = acc + x[k];
+            const double mean = acc / (double)m;
+            double v = 0.0;
+            for (int k = 0; k < m; ++k) {
+                const double d = x[k] - mean;
+                v = v + d * d;
+            }
+            mu[threadIdx.x] = mean;
+            sdv[threadIdx.x] = sqrt(v / (double)m);
         }
-        const double sd = sqrt(v / (double)m);
-        double* o = out + w * m;
-        for (int k = 0; k < m; ++k) o[k] = sd > 0.0 ? (x[k] - mean) / sd : 0.0;
+        __syncthreads();
+        double* o = out + w0 * m;
+        const int tot = nb * m;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int w = e / m, k = e - w * m;
+            const double sd = sdv[w];
+            o[e] = sd > 0.0 ? (xs[w + k] - mu[w]) / sd : 0.0;
+        }
     }
 }
 
@@ -254,8 +276,8 @@ __global__ void interleave_kernel(const double* rv, const int64_t* roff, int64_t
 // w = floor(ratio * max(L_q, longest candidate)), which only widens it (a
 // looser, still valid bound).  One block per query; columns with no row in
 // the window get (-inf, +inf) (such pairs are infeasible anyway).
-__global__ void envelope_kernel(const double* qv, const int64_t* qoff, int64_t nq, int lr_max, double ratio,
-                                double* up, double* lo) {
+__global__ void envelope_kernel(const double* qv, const int64_t* qoff, int64_t nq, int lr_max, int64_t ld,
+                                double ratio, double* up, double* lo, double* qx) {
     for (int64_t a = blockIdx.x; a < nq; a += gridDim.x) {
         const double* s = qv + qoff[a];
         const int lq = (int)(qoff[a + 1] - qoff[a]);
@@ -272,8 +294,9 @@ __global__ void envelope_kernel(const double* qv, const int64_t* qoff, int64_t n
                 u = __builtin_huge_val();
                 l = -__builtin_huge_val();
             }
-            up[a * (int64_t)lr_max + j - 1] = u;
-            lo[a * (int64_t)lr_max + j - 1] = l;
+            up[a * ld + j - 1] = u;
+            lo[a * ld + j - 1] = l;
+            qx[a * ld + j - 1] = s[(j < lq ? j : lq) - 1];
         }
     }
 }
@@ -303,87 +326,89 @@ __global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qof
 
 // CDTW: the path bound and LB_Keogh of QT queries against 256 candidates per
 // block, in one pass over each candidate's values (read once for all QT
-// queries; the queries in LDS, their envelopes by block-uniform loads).  Each
-// bound adds its terms in path order (the diagonal, then the longer series'
-// tail), like path_ub_acc; (a - b)^2 and (b - a)^2 are the same double.
+// queries; query values and envelopes by scalar loads).  Each bound adds its
+// terms in path order (the diagonal, then the longer series' tail), like
+// path_ub_acc; (a - b)^2 and (b - a)^2 are the same double.
 template <int QT>
-__global__ void ub_lb_cdtw_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rT,
-                                  const int64_t* roff, int lq_max, int lr_max, const double* env_up,
-                                  const double* env_lo, double* lb, double* ub) {
-    extern __shared__ double qs[];   // QT x lq_max
+__global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const double* qv, const int64_t* qoff,
+                                                         const double* rT, const int64_t* roff, int64_t ld,
+                                                         const double* env_up, const double* env_lo,
+                                                         const double* env_q, double* lb, double* ub) {
+    // Every lane of a wave reads the same query value and envelope entries:
+    // through the constant address space they arrive by scalar loads, one per
+    // wave, and enter the arithmetic as scalar operands.  Nothing this kernel
+    // writes is read through these pointers.
+    typedef double d8 __attribute__((ext_vector_type(8)));
+    typedef const __attribute__((address_space(4))) d8* cd8p;
+    typedef const __attribute__((address_space(4))) int64_t* cip;
     const int64_t nB = A.nB;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = b < nB;
+    const int64_t bb = live ? b : nB - 1;   // lanes past the end read the last candidate, store nothing
+    const int lr = (int)(roff[bb + 1] - roff[bb]);
+    int lw = lr;   // the wave's longest candidate: the column loop is uniform
+    for (int o = 32; o > 0; o >>= 1) lw = max(lw, __shfl_xor(lw, o));
+    lw = __builtin_amdgcn_readfirstlane(lw);
     const double ratio = A.window_ratio;
+    const cip qo = (cip)qoff;
     for (int64_t a0 = (int64_t)blockIdx.y * QT; a0 < A.nA; a0 += (int64_t)gridDim.y * QT) {
         const int nqt = (int)((A.nA - a0) < QT ? (A.nA - a0) : QT);
+        int64_t qb[QT];
         int lq[QT];
-#pragma unroll
-        for (int t = 0; t < QT; ++t) lq[t] = t < nqt ? (int)(qoff[a0 + t + 1] - qoff[a0 + t]) : 0;
-        __syncthreads();
-        for (int t = 0; t < nqt; ++t)
-            for (int k = threadIdx.x; k < lq[t]; k += blockDim.x) qs[t * lq_max + k] = qv[qoff[a0 + t] + k];
-        __syncthreads();
-        if (b >= nB) continue;
-        const int lr = (int)(roff[b + 1] - roff[b]);
-        auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
         double acc[QT], lbv[QT];
-        bool on[QT];
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
+            qb[t] = t < nqt ? qo[a0 + t] : 0;
+            lq[t] = t < nqt ? (int)(qo[a0 + t + 1] - qb[t]) : 1;
             const int L = lq[t] > lr ? lq[t] : lr, ld = lq[t] > lr ? lq[t] - lr : lr - lq[t];
-            on[t] = t < nqt && !(ratio < 1.0 && (int)floor(ratio * (double)L) < ld);
-            acc[t] = on[t] ? 0.0 : __builtin_huge_val();   // +inf: the window admits no path
+            acc[t] = (ratio < 1.0 && (int)floor(ratio * (double)L) < ld) ? __builtin_huge_val() : 0.0;   // +inf: no path
             lbv[t] = 0.0;
         }
-        // candidate values and envelope entries in chunks of CH (loads issued
-        // together; indexes clamped into the series), terms added in order
+        // candidate values in chunks of CH (loads issued together, indexes
+        // clamped into the series); the query extended by its last value and
+        // the envelopes come in aligned chunks of 8 from rows of ld >= lw
+        // entries, so their reads need no clamp; terms added in order
         constexpr int CH = 8;
-        for (int j0 = 0; j0 < lr; j0 += CH) {
+        for (int j0 = 0; j0 < lw; j0 += CH) {
             double xv[CH];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) xv[u] = R(j0 + u < lr ? j0 + u : lr - 1);
+            for (int u = 0; u < CH; ++u) xv[u] = rT[(int64_t)(j0 + u < lr ? j0 + u : lr - 1) * nB + bb];
 #pragma unroll
             for (int t = 0; t < QT; ++t) {
-                if (!on[t]) continue;
-                const double* eu = env_up + (a0 + t) * lr_max;
-                const double* el = env_lo + (a0 + t) * lr_max;
-                double uv[CH], lv[CH];
+                if (t >= nqt) continue;
+                const int64_t base = (a0 + t) * ld + j0;
+                const d8 Y = *(cd8p)(env_q + base), U = *(cd8p)(env_up + base), O = *(cd8p)(env_lo + base);
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
-                    const int jj = j0 + u < lr ? j0 + u : lr - 1;
-                    uv[u] = eu[jj];
-                    lv[u] = el[jj];
-                }
-#pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    const int j = j0 + u;
-                    if (j < lr) {
+                    const double y = Y[u], up = U[u], lo = O[u];
+                    if (j0 + u < lr) {
                         // the diagonal while both series last, then down the candidate
                         const double x = xv[u];
-                        const double y = j < lq[t] ? qs[t * lq_max + j] : qs[t * lq_max + lq[t] - 1];
                         const double d = x - y;
                         acc[t] = (d * d) + acc[t];
-                        const double e = x > uv[u] ? x - uv[u] : (x < lv[u] ? lv[u] - x : 0.0);
+                        const double e = fmax(fmax(x - up, lo - x), 0.0);   // at most one side is positive
                         lbv[t] = lbv[t] + e * e;
                     }
                 }
             }
         }
         // queries longer than the candidate: their tail against its last value
-        const double xl = R(lr - 1);
+        const double xl = rT[(int64_t)(lr - 1) * nB + bb];
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
-            if (!on[t]) continue;
+            if (t >= nqt) continue;
             for (int i = lr; i < lq[t]; ++i) {
-                const double d = qs[t * lq_max + i] - xl;
+                const double d = qv[qb[t] + i] - xl;
                 acc[t] = (d * d) + acc[t];
             }
         }
+        if (live) {
 #pragma unroll
-        for (int t = 0; t < QT; ++t) {
-            if (t < nqt) {
-                ub[(a0 + t) * nB + b] = acc[t];
-                lb[(a0 + t) * nB + b] = lbv[t];
+            for (int t = 0; t < QT; ++t) {
+                if (t < nqt) {
+                    ub[(a0 + t) * nB + b] = acc[t];
+                    lb[(a0 + t) * nB + b] = lbv[t];
+                }
             }
         }
     }
@@ -514,39 +539,106 @@ __global__ void argmin_kernel(const double* res, int64_t nq, int64_t nr, const i
     }
 }
 
+// A few queries with many candidates: each query's scan is split over S
+// blocks, block (c, q) reducing chunk c to a (value, index) minimum, and a
+// finishing pass (one wave per query) reduces the chunks.  MODE 0 is the seed
+// scan (lexicographic over every value, +inf included), MODE 1 the NN argmin
+// (finite values only); the result equals the single-pass kernels' since the
+// lexicographic minimum is associative.
+template <int MODE>
+__global__ __launch_bounds__(256) void scan_part_kernel(const double* v, int64_t nr, int S, double* pv,
+                                                        int64_t* pi) {
+    __shared__ double sv[4];
+    __shared__ int64_t si[4];
+    const int64_t q = blockIdx.y;
+    const int64_t per = (nr + S - 1) / S, r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < nr ? r0 + per : nr;
+    double bv = __builtin_huge_val();
+    int64_t bi = -1;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const double u = v[q * nr + r];
+        if (MODE == 0 ? lex_less(u, r, bv, bi) : u < bv) {
+            bv = u;
+            bi = r;
+        }
+    }
+    group_min<256>(bv, bi, sv, si);
+    if (threadIdx.x == 0) {
+        pv[q * S + blockIdx.x] = bv;
+        pi[q * S + blockIdx.x] = bi;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void scan_finish_kernel(const double* pv, const int64_t* pi, int64_t nq, int S,
+                                                          int64_t nr, int32_t* seed_b, int32_t* items,
+                                                          unsigned long long* best, const int32_t* labels,
+                                                          int64_t* out_idx, double* out_dist, int32_t* out_label) {
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double bv = __builtin_huge_val();
+    int64_t bi = -1;
+    if (q < nq)
+        for (int c = lane; c < S; c += 64)
+            if (lex_less(pv[q * S + c], pi[q * S + c], bv, bi)) {
+                bv = pv[q * S + c];
+                bi = pi[q * S + c];
+            }
+    group_min<64>(bv, bi, nullptr, nullptr);
+    if (lane != 0 || q >= nq) return;
+    if (MODE == 0) {
+        if (bi < 0) bi = 0;   // every bound +inf: any candidate, cut-off +inf
+        seed_b[q] = (int32_t)bi;
+        items[q] = (int32_t)(q * nr + bi);
+        best[q] = dbits(bv);
+    } else {
+        out_idx[q] = bi;
+        out_dist[q] = bv;
+        if (out_label) out_label[q] = (bi >= 0 && labels) ? labels[bi] : -1;
+    }
+}
+
+constexpr int kCompactPer = 2048;   // candidates per block of lb_compact_kernel
+
 // CDTW NN: the pairs whose lower bound does not exceed the query's cut-off
 // after the seed sweep (the seed itself excluded), listed for the main sweep;
 // the others are +inf without a sweep, as are the pairs whose window admits no
 // path (w = floor(ratio * max(L_q, L_r)) < |L_q - L_r|).  Wave-level
 // compaction: one atomic per wave of 64 pairs.  The cut-off can only fall
 // afterwards, so no NN is lost.
-__global__ void lb_compact_kernel(const double* lb, const unsigned long long* best, const int32_t* seed,
-                                  const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,
-                                  double* res, int32_t* items, unsigned int* count, unsigned long long* pruned) {
-    const int64_t total = nq * nr;
+__global__ __launch_bounds__(256) void lb_compact_kernel(const double* lb, const unsigned long long* best,
+                                                         const int32_t* seed, const int64_t* qoff,
+                                                         const int64_t* roff, double ratio, int64_t nq, int64_t nr,
+                                                         double* res, int32_t* items, unsigned int* count,
+                                                         unsigned long long* pruned) {
+    // block (c, q-stride): candidates [c * per, (c + 1) * per) of its queries
     const int lane = threadIdx.x & 63;
+    const int64_t per = (int64_t)kCompactPer, r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < nr ? r0 + per : nr;
     unsigned long long np = 0;
-    for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)); base < total;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = base + lane;
-        bool keep = false, drop = false;
-        if (p < total) {
-            const int64_t q = p / nr, r = p - q * nr;
-            if (!seed || seed[q] != (int32_t)r) {
-                const int lq = (int)(qoff[q + 1] - qoff[q]), lr = (int)(roff[r + 1] - roff[r]);
+    for (int64_t q = blockIdx.y; q < nq; q += gridDim.y) {
+        const int lq = (int)(qoff[q + 1] - qoff[q]);
+        const double cut = bitsd(best[q]);
+        const int64_t sb = seed ? (int64_t)seed[q] : -1;
+        for (int64_t base = r0 + (threadIdx.x & ~63); base < r1; base += blockDim.x) {
+            const int64_t r = base + lane;
+            bool keep = false, drop = false;
+            if (r < r1 && r != sb) {
+                const int64_t p = q * nr + r;
+                const int lr = (int)(roff[r + 1] - roff[r]);
                 const int L = lq > lr ? lq : lr, ld = lq > lr ? lq - lr : lr - lq;
                 const bool feasible = ratio >= 1.0 || (int)floor(ratio * (double)L) >= ld;
-                drop = feasible && lb[p] * (1.0 - 1e-11) > bitsd(best[q]);   // counted
+                drop = feasible && lb[p] * (1.0 - 1e-11) > cut;   // counted
                 keep = feasible && !drop;
                 if (!keep) res[p] = __builtin_huge_val();
             }
+            const unsigned long long m = __ballot(keep);
+            unsigned int off = 0;
+            if (lane == 0 && m) off = atomicAdd(count, (unsigned int)__popcll(m));
+            off = __shfl(off, 0);
+            if (keep) items[off + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)(q * nr + r);
+            np += drop ? 1 : 0;
         }
-        const unsigned long long m = __ballot(keep);
-        unsigned int off = 0;
-        if (lane == 0 && m) off = atomicAdd(count, (unsigned int)__popcll(m));
-        off = __shfl(off, 0);
-        if (keep) items[off + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)p;
-        np += drop ? 1 : 0;
     }
     for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
     if (lane == 0 && np) atomicAdd(pruned, np);
@@ -556,8 +648,13 @@ __global__ void lb_compact_kernel(const double* lb, const unsigned long long* be
 __global__ void absmax_kernel(const double* v, int64_t n, unsigned long long* out) {
     __shared__ double part[4];
     double m = 0.0;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
-        m = fmax(m, __builtin_fabs(v[x]));
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; x + 3 * st < n; x += 4 * st) {   // four independent loads in flight
+        const double a = v[x], b = v[x + st], c = v[x + 2 * st], d = v[x + 3 * st];
+        m = fmax(m, fmax(fmax(__builtin_fabs(a), __builtin_fabs(b)), fmax(__builtin_fabs(c), __builtin_fabs(d))));
+    }
+    for (; x < n; x += st) m = fmax(m, __builtin_fabs(v[x]));
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -617,6 +714,21 @@ __global__ void screen_widen_kernel(int kind, SweepArgs A, const int64_t* qoff, 
     }
 }
 
+// The screen's thresholds for one query from its FP32 cut-off b32: thr
+// (FP32 results above it cannot be the NN) and cut64 (an upper bound on the
+// FP64 NN distance); both +inf when b32 is.
+__device__ __forceinline__ void screen_cut(int kind, const int64_t* qoff, int64_t q, int64_t lr_max, double gap,
+                                           double Ab, double margin_rel, double b32, double& thr, double& cut64) {
+    thr = __builtin_huge_val();
+    cut64 = __builtin_huge_val();
+    if (!(b32 < __builtin_huge_val())) return;
+    const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
+    const double Amax = (kind == ERP) ? fmax(Ab, __builtin_fabs(gap)) : Ab;
+    const double b = b32 * (1.0 + margin_rel);
+    cut64 = screen_bound(kind, b, N, Amax);
+    thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);
+}
+
 // After the FP32 sweep: every candidate of query q whose FP32 distance is
 // <= b + 2 eps(screen_bound(b)) is listed for the FP64 recheck, where b is the
 // best-so-far (the least FP32 distance, or the seed's FP64 distance).  The
@@ -642,14 +754,7 @@ __global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff,
         int64_t sb = -1;
         unsigned long long n = 0;
         if (on) {
-            const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
-            const double Amax = (kind == ERP) ? fmax(Ab, __builtin_fabs(gap)) : Ab;
-            const double b32 = bitsd(best[q]);
-            if (b32 < __builtin_huge_val()) {
-                const double b = b32 * (1.0 + margin_rel);
-                cut64 = screen_bound(kind, b, N, Amax);
-                thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);
-            }
+            screen_cut(kind, qoff, q, lr_max, gap, Ab, margin_rel, bitsd(best[q]), thr, cut64);
             sb = seed ? (int64_t)seed[q] : -1;
             dseed = (sb >= 0) ? res[q * A.nB + sb] : __builtin_huge_val();
             for (int64_t r = tq; r < A.nB; r += TPQ) {
@@ -671,11 +776,67 @@ __global__ void screen_filter_kernel(int kind, SweepArgs A, const int64_t* qoff,
     }
 }
 
+// The screen filter split for a few queries with many candidates: first the
+// per-query thresholds (and the recheck's first cut-off into best[q], as
+// screen_filter_kernel sets it), then block (c, q) lists the pairs of chunk c
+// of query q at or below the threshold and resets every result slot but the
+// seed's; wave-level compaction of the list.
+__global__ void screen_prep_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
+                                   const unsigned long long* absmax, double margin_rel, const double* res,
+                                   unsigned long long* best, const int32_t* seed, double* thr_out) {
+    const double Ab = bitsd(*absmax);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < A.nA; q += (int64_t)gridDim.x * blockDim.x) {
+        double thr, cut64;
+        screen_cut(kind, qoff, q, lr_max, gap, Ab, margin_rel, bitsd(best[q]), thr, cut64);
+        const int64_t sb = seed ? (int64_t)seed[q] : -1;
+        const double dseed = (sb >= 0) ? res[q * A.nB + sb] : __builtin_huge_val();
+        thr_out[q] = thr;
+        best[q] = dbits(dseed < cut64 ? dseed : cut64);
+    }
+}
+
+__global__ __launch_bounds__(256) void screen_pick_kernel(const double* thr_in, int64_t nB, int S, double* res,
+                                                          const int32_t* seed, int32_t* items, unsigned int* count,
+                                                          unsigned long long* rechecks) {
+    const int64_t q = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t per = (nB + S - 1) / S, r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < nB ? r0 + per : nB;
+    const double thr = thr_in[q];
+    const int64_t sb = seed ? (int64_t)seed[q] : -1;
+    unsigned long long n = 0;
+    for (int64_t base = r0 + (threadIdx.x & ~63); base < r1; base += blockDim.x) {
+        const int64_t r = base + lane;
+        bool keep = false;
+        if (r < r1 && r != sb) {
+            const int64_t p = q * nB + r;
+            keep = res[p] <= thr;
+            res[p] = __builtin_huge_val();
+        }
+        const unsigned long long m = __ballot(keep);
+        unsigned int off = 0;
+        if (lane == 0 && m) off = atomicAdd(count, (unsigned int)__popcll(m));
+        off = __shfl(off, 0);
+        if (keep) items[off + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)(q * nB + r);
+        n += keep ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    if (lane == 0 && n) atomicAdd(rechecks, n);
+}
+
 // Threads per query for the per-query scans over nr candidates: one wave up
 // to 1024 candidates, a 256-thread block up to 4096, else a 1024-thread block
 // (with a few queries and many candidates a wave's chain of loads is the
 // whole kernel's time).
 static int scan_threads(int64_t nr) { return nr > 4096 ? 1024 : (nr > 1024 ? 256 : 64); }
+
+// Blocks per query for the split scans: one per 4096 candidates, at most
+// about 1024 blocks in all (so nq x S < scan_part_entries(nq)); 1 = no split.
+static int scan_split(int64_t nq, int64_t nr) {
+    if (nr <= 4096) return 1;
+    const int64_t s = std::min<int64_t>((nr + 4095) / 4096, (1024 + nq - 1) / nq);
+    return (int)std::max<int64_t>(s, 1);
+}
 
 static int blocks_for(int64_t n, int per) {
     int64_t b = (n + per - 1) / per;
@@ -696,7 +857,8 @@ hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, dou
 }
 
 hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(subseq_windows_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, s, x, nw, m, out);
+    const size_t lds = sizeof(double) * (size_t)(3 * kWinPerBlock + m - 1);
+    hipLaunchKernelGGL(subseq_windows_kernel, dim3(blocks_for(nw, kWinPerBlock)), dim3(256), lds, s, x, nw, m, out);
     return hipGetLastError();
 }
 
@@ -730,13 +892,16 @@ hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, c
                              const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,
                              double* res, int32_t* items, unsigned int* count, unsigned long long* pruned,
                              hipStream_t s) {
-    hipLaunchKernelGGL(lb_compact_kernel, dim3(std::min(blocks_for(nq * nr, 256), 4096)), dim3(256), 0, s, lb, best,
-                       seed, qoff, roff, ratio, nq, nr, res, items, count, pruned);
+    // about 4096 blocks: chunks of kCompactPer candidates times query groups
+    const int64_t gx = (nr + kCompactPer - 1) / kCompactPer;
+    const int64_t gy = std::min<int64_t>(nq, std::max<int64_t>(1, 4096 / gx));
+    hipLaunchKernelGGL(lb_compact_kernel, dim3((unsigned)gx, (unsigned)std::min<int64_t>(gy, 65535)), dim3(256), 0,
+                       s, lb, best, seed, qoff, roff, ratio, nq, nr, res, items, count, pruned);
     return hipGetLastError();
 }
 
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s) {
-    hipLaunchKernelGGL(absmax_kernel, dim3(std::min(blocks_for(n, 256 * 8), 256)), dim3(256), 0, s, v, n, out);
+    hipLaunchKernelGGL(absmax_kernel, dim3(std::min(blocks_for(n, 256 * 16), 2048)), dim3(256), 0, s, v, n, out);
     return hipGetLastError();
 }
 
@@ -750,7 +915,15 @@ hipError_t launch_screen_widen(int kind, const SweepArgs& a, const int64_t* qoff
 hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                 const unsigned long long* absmax, double margin_rel, double* res,
                                 unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,
-                                unsigned long long* rechecks, hipStream_t s) {
+                                unsigned long long* rechecks, double* part, hipStream_t s) {
+    const int S = scan_split(a.nA, a.nB);
+    if (S >= 2 && part) {
+        hipLaunchKernelGGL(screen_prep_kernel, dim3(blocks_for(a.nA, 256)), dim3(256), 0, s, kind, a, qoff, lr_max,
+                           gap, absmax, margin_rel, res, best, seed, part);
+        hipLaunchKernelGGL(screen_pick_kernel, dim3((unsigned)S, (unsigned)a.nA), dim3(256), 0, s, part, a.nB, S, res,
+                           seed, items, count, rechecks);
+        return hipGetLastError();
+    }
     switch (scan_threads(a.nB)) {
     case 1024: hipLaunchKernelGGL(screen_filter_kernel<1024>, dim3(blocks_for(a.nA, 1)), dim3(1024), 0, s, kind, a,
                                   qoff, lr_max, gap, absmax, margin_rel, res, best, seed, items, count, rechecks); break;
@@ -763,36 +936,39 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
 }
 
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const int64_t* roff,
-                        int lq_max, int lr_max, double* rT, double* ub, double* env_up, double* env_lo, double* lb,
-                        hipStream_t s) {
-    if (kind == CDTW && lb && env_up && env_lo) {
-        // CDTW: the query envelopes, then bound and LB_Keogh of up to 4 queries
-        // per pass over the candidates (at most 4 x 2048 doubles of LDS)
+                        int lq_max, int lr_max, double* rT, double* ub, double* env, double* lb, hipStream_t s) {
+    if (kind == CDTW && lb && env) {
+        // CDTW: the query envelopes (upper, lower, and the query extended by
+        // its last value: three arrays of env_stride doubles), then bound and
+        // LB_Keogh of up to 16 queries per pass over the candidates
+        const int64_t stride = env_stride(a.nA, lr_max), ld = env_ld(lr_max);
+        double *up = env, *lo = env + stride, *qx = env + 2 * stride;
         hipLaunchKernelGGL(envelope_kernel, dim3(std::min<int64_t>(a.nA, 65535)), dim3(256), 0, s, qv, qoff, a.nA,
-                           lr_max, a.window_ratio, env_up, env_lo);
-        // queries per block: 4 when the grid still has at least 2 blocks per CU
-        // (fewer reads of the candidates), else 2 or 1 (more blocks)
+                           lr_max, ld, a.window_ratio, up, lo, qx);
+        // queries per block: the most that still leaves at least 2 blocks per
+        // CU (fewer reads of the candidates)
         const int64_t bx = (a.nB + 255) / 256;
         int cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
         int qt = 1;
-        for (int c : {4, 2})
+        for (int c : {16, 8, 4, 2})
             if (bx * ((a.nA + c - 1) / c) >= 2 * (int64_t)cus) {
                 qt = c;
                 break;
             }
         const dim3 gq((unsigned)bx, (unsigned)std::min<int64_t>((a.nA + qt - 1) / qt, 65535));
-        const size_t lds = sizeof(double) * (size_t)qt * (size_t)lq_max;
+#define EAP_UBLB(QT) hipLaunchKernelGGL(ub_lb_cdtw_kernel<QT>, gq, dim3(256), 0, s, a, qv, qoff, rT, roff, ld, \
+                                        up, lo, qx, lb, ub)
         switch (qt) {
-        case 4: hipLaunchKernelGGL(ub_lb_cdtw_kernel<4>, gq, dim3(256), lds, s, a, qv, qoff, rT, roff, lq_max, lr_max,
-                                   env_up, env_lo, lb, ub); break;
-        case 2: hipLaunchKernelGGL(ub_lb_cdtw_kernel<2>, gq, dim3(256), lds, s, a, qv, qoff, rT, roff, lq_max, lr_max,
-                                   env_up, env_lo, lb, ub); break;
-        default: hipLaunchKernelGGL(ub_lb_cdtw_kernel<1>, gq, dim3(256), lds, s, a, qv, qoff, rT, roff, lq_max,
-                                    lr_max, env_up, env_lo, lb, ub); break;
+        case 16: EAP_UBLB(16); break;
+        case 8: EAP_UBLB(8); break;
+        case 4: EAP_UBLB(4); break;
+        case 2: EAP_UBLB(2); break;
+        default: EAP_UBLB(1); break;
         }
+#undef EAP_UBLB
         return hipGetLastError();
     }
     const dim3 g((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>(a.nA, 65535)), b(256);
@@ -825,7 +1001,15 @@ hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, co
 }
 
 hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* items,
-                       unsigned long long* best, hipStream_t s) {
+                       unsigned long long* best, double* part, hipStream_t s) {
+    const int S = scan_split(nq, nr);
+    if (S >= 2 && part) {
+        int64_t* pi = reinterpret_cast<int64_t*>(part + scan_part_entries(nq));
+        hipLaunchKernelGGL(scan_part_kernel<0>, dim3((unsigned)S, (unsigned)nq), dim3(256), 0, s, ub, nr, S, part, pi);
+        hipLaunchKernelGGL(scan_finish_kernel<0>, dim3(blocks_for(nq, 4)), dim3(256), 0, s, part, pi, nq, S, nr,
+                           seed_b, items, best, nullptr, nullptr, nullptr, nullptr);
+        return hipGetLastError();
+    }
     switch (scan_threads(nr)) {
     case 1024: hipLaunchKernelGGL(seed_kernel<1024>, dim3(blocks_for(nq, 1)), dim3(1024), 0, s, ub, nq, nr, seed_b,
                                   items, best); break;
@@ -838,7 +1022,16 @@ hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b
 }
 
 hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
-                         double* out_dist, int32_t* out_label, hipStream_t s) {
+                         double* out_dist, int32_t* out_label, double* part, hipStream_t s) {
+    const int S = scan_split(nq, nr);
+    if (S >= 2 && part) {
+        int64_t* pi = reinterpret_cast<int64_t*>(part + scan_part_entries(nq));
+        hipLaunchKernelGGL(scan_part_kernel<1>, dim3((unsigned)S, (unsigned)nq), dim3(256), 0, s, res, nr, S, part,
+                           pi);
+        hipLaunchKernelGGL(scan_finish_kernel<1>, dim3(blocks_for(nq, 4)), dim3(256), 0, s, part, pi, nq, S, nr,
+                           nullptr, nullptr, nullptr, labels, out_idx, out_dist, out_label);
+        return hipGetLastError();
+    }
     switch (scan_threads(nr)) {
     case 1024: hipLaunchKernelGGL(argmin_kernel<1024>, dim3(blocks_for(nq, 1)), dim3(1024), 0, s, res, nq, nr, labels,
                                   out_idx, out_dist, out_label); break;

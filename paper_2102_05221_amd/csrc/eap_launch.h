@@ -106,17 +106,28 @@ hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, 
                              hipStream_t s);
 // *dst = max(*dst, *src) (u64), one thread.
 hipError_t launch_max_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s);
+// CDTW envelope area: three arrays (upper envelope, lower envelope, query
+// extended by its last value), each nq rows of env_ld(lr_max) doubles, lr_max
+// of them used: rows of a multiple of 8 doubles, so the UB + LB kernel reads
+// them in aligned chunks of 8.
+inline int64_t env_ld(int64_t lr_max) { return (lr_max + 7) & ~(int64_t)7; }
+inline int64_t env_stride(int64_t nq, int64_t lr_max) { return nq * env_ld(lr_max); }
 // Path upper bound of every (query, candidate) pair from rT (launch_interleave);
-// for CDTW with env_up / env_lo / lb also the query envelopes and LB_Keogh.
+// for CDTW with env (3 x env_stride doubles) and lb also the query envelopes
+// and LB_Keogh.
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const int64_t* roff,
-                        int lq_max, int lr_max, double* rT, double* ub, double* env_up, double* env_lo, double* lb,
-                        hipStream_t s);
+                        int lq_max, int lr_max, double* rT, double* ub, double* env, double* lb, hipStream_t s);
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s);
+// Scratch of the split per-query scans (seed, argmin, screen filter) for a
+// few queries with many candidates: 2 x scan_part_entries(nq) doubles
+// (partial values, then partial indexes); part == nullptr runs the
+// single-pass kernels.
+inline int64_t scan_part_entries(int64_t nq) { return 1024 + nq; }
 hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b, int32_t* list_a,
-                       unsigned long long* best, hipStream_t s);
+                       unsigned long long* best, double* part, hipStream_t s);
 hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
-                         double* out_dist, int32_t* out_label, hipStream_t s);
+                         double* out_dist, int32_t* out_label, double* part, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed,
@@ -126,7 +137,7 @@ hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, c
 hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                 const unsigned long long* absmax, double margin_rel, double* res,
                                 unsigned long long* best, const int32_t* seed, int32_t* items, unsigned int* count,
-                                unsigned long long* rechecks, hipStream_t s);
+                                unsigned long long* rechecks, double* part, hipStream_t s);
 hipError_t launch_screen_widen(int kind, const SweepArgs& a, const int64_t* qoff, int64_t lr_max, double gap,
                                const unsigned long long* absmax, double* widen_abs, hipStream_t s);
 

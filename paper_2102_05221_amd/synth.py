@@ -184,3 +184,19 @@ def random_pairs(seed: int, n: int, lo: int, hi: int, kind: str = "walk"):
             xs.append(rng.standard_normal(int(lx)))
             ys.append(rng.standard_normal(int(ly)))
     return xs, ys
+
+
+def subseq_workload(n_windows: int = 1 << 20, m: int = 128, n_query: int = 16):
+    """Sub-sequence search input (Section 5.3's task on a synthetic recording):
+    a random walk of ``n_windows + m - 1`` values, so that it has ``n_windows``
+    windows of ``m``, and ``n_query`` raw queries of ``m`` values.  The first
+    half of the queries are windows of the walk at seeded ``starts``, scaled by
+    1.5, shifted by 3 and given N(0, 0.1) noise; the rest are fresh random
+    walks.  Nothing is normalised here: the search normalises every window and
+    query itself."""
+    rng = np.random.default_rng(BASE_SEED + 6)
+    s = np.cumsum(rng.standard_normal(n_windows + m - 1))
+    starts = rng.integers(0, n_windows, n_query // 2)
+    qs = [1.5 * s[st:st + m] + 3.0 + 0.1 * rng.standard_normal(m) for st in starts]
+    qs += [np.cumsum(rng.standard_normal(m)) for _ in range(n_query - len(qs))]
+    return dict(series=s, queries=qs, starts=starts, m=m)

@@ -92,8 +92,8 @@ def test_nn1_argument_errors(L):
     assert need > 0
     ws = ctypes.c_void_p(0x2000)
 
-    def call(q=FAKE, qo_=qo, nq=2, r=FAKE, ro_=ro, nr=3, pp=p, oo=o, nb=need, idx=FAKE, dist=FAKE):
-        return L.eap_nn1(q, pi(qo_), nq, r, pi(ro_), nr, None, ctypes.byref(pp), ctypes.byref(oo), ws, nb, idx,
+    def call(q=FAKE, qo_=qo, nq=2, r=FAKE, ro_=ro, nr=3, pp=p, oo=o, nb=need, idx=FAKE, dist=FAKE, w=ws):
+        return L.eap_nn1(q, pi(qo_), nq, r, pi(ro_), nr, None, ctypes.byref(pp), ctypes.byref(oo), w, nb, idx,
                          dist, None, None)
 
     assert call(q=None) == eap.EAP_EINVAL
@@ -104,6 +104,7 @@ def test_nn1_argument_errors(L):
     assert call(oo=eap.NNOpts(7, 1e-4, 0)) == eap.EAP_EINVAL
     assert call(oo=eap.NNOpts(1, float("nan"), 0)) == eap.EAP_EINVAL
     assert call(nb=need - 1) == eap.EAP_EWORKSPACE
+    assert call(w=ctypes.c_void_p(0x2008)) == eap.EAP_EWORKSPACE   # not 256-byte aligned
 
 
 def test_pairwise_argument_errors(L):
