@@ -720,6 +720,8 @@ def run_subseq(args, torch, eap, synth):
     torch.cuda.synchronize()
     eap.profile_take()
     eap.profile_enable(True)
+    for k in kinds:
+        eap.reset_counters(ws[k])
     steps = max(1, min(args.steps, 5))
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -729,12 +731,16 @@ def run_subseq(args, torch, eap, synth):
     eap.profile_enable(False)
     prof = eap.profile_take()
     dense = {k: dense_cells(k, P[k], q_off, r_off) for k in kinds}
+    cnt = {k: eap.read_counters(ws[k]) for k in kinds}
     found = {k: int(sum(1 for i, st in enumerate(starts) if int(outs[k][0][i].item()) == int(st))) for k in kinds}
     per = {}
     for k in kinds:
         main = [x for x in prof if x["kind"] == k and x["stage"] == 2]
         per[k] = dict(main_sweep_ms=(sum(x["ms"] for x in main) / len(main)) if main else None,
                       main_kernel=(kernel_label(main[0]) if main else None), dense_cells=dense[k],
+                      executed_fraction=cnt[k]["cells"] / steps / dense[k],
+                      lb_pruned_fraction=cnt[k]["lb_pruned"] / steps / (nq * nw),
+                      fp64_rechecks_per_step=cnt[k]["rechecks"] / steps,
                       planted_found=found[k], planted=len(starts))
     # the oracle on the whole workload, timed like one step: the windows and
     # the queries normalised, then the NN search; the GPU answers compared

@@ -234,10 +234,14 @@ size_t edge_bytes(int64_t items, int64_t lli_max, int64_t lco_max) {
     return (size_t)groups * (size_t)(lli_max + 1) * sizeof(double);
 }
 
-int band_group(int diags) { return diags <= 256 ? 16 : (diags == 512 ? 32 : 64); }
+// Default lanes per pair of the band sweep: 8 diagonals per parity and lane
+// for the narrow bands (32, 64), else 4 or 8 from the band's width.
+int band_group(int diags) {
+    return diags == 32 ? 2 : (diags == 64 ? 4 : (diags <= 256 ? 16 : (diags == 512 ? 32 : 64)));
+}
 
 int pick_diags(int64_t need) {
-    for (int d : {128, 256, 512, 1024, 2048})
+    for (int d : {32, 64, 128, 256, 512, 1024, 2048})
         if (need <= d) return d;
     return 0;
 }
@@ -978,7 +982,7 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
                                {32, 16}, {64, 8}, {64, 16}, {16, 32}, {32, 32}, {64, 32}};
     std::vector<RowsShape> shapes;   // band sweep: {lanes, columns per lane}
     if (band) {
-        for (int g : {4, 8, 16, 32, 64})
+        for (int g : {2, 4, 8, 16, 32, 64})
             if (band_shape_ok(pl.size, g)) shapes.push_back(RowsShape{g, pl.size / (2 * g)});
     } else {
         for (const RowsShape& x : all)

@@ -391,6 +391,10 @@ template <int KIND, typename T>
 static hipError_t gob_d(int diags, int g, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s,
                         int* occ) {
     switch (diags * 100 + g) {
+    case 3202: return gob<KIND, T, 2, 8>(a, SA, SB, grid, s, occ);
+    case 3204: return gob<KIND, T, 4, 4>(a, SA, SB, grid, s, occ);
+    case 6404: return gob<KIND, T, 4, 8>(a, SA, SB, grid, s, occ);
+    case 6408: return gob<KIND, T, 8, 4>(a, SA, SB, grid, s, occ);
     case 12808: return gob<KIND, T, 8, 8>(a, SA, SB, grid, s, occ);
     case 12816: return gob<KIND, T, 16, 4>(a, SA, SB, grid, s, occ);
     case 25616: return gob<KIND, T, 16, 8>(a, SA, SB, grid, s, occ);
@@ -408,6 +412,7 @@ static hipError_t gob_d(int diags, int g, const SweepArgs& a, SeriesPtrs SA, Ser
 // of the register file).
 bool band_shape_ok(int diags, int g) {
     switch (diags * 100 + g) {
+    case 3202: case 3204: case 6404: case 6408:
     case 12808: case 12816: case 25616: case 25632: case 51232: case 51264: case 102464: case 204864: return true;
     }
     return false;
