@@ -717,15 +717,15 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     if (!cand_ready) {
         // what the candidates alone determine, kept for calls with flags bit 3:
         // the interleaved copy, and for precision 1 the FP32 copies and |x| maximum
-        HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, rT, s));
-        if (prec1) {
-            HIPCHK(launch_to_f32(r, R.total, reinterpret_cast<float*>(at(ws, nl.r32)), s));
-            if (p->kind == EAP_ERP)
-                HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total,
-                                     reinterpret_cast<float*>(at(ws, nl.r32b)), s));
-            HIPCHK(launch_fill_u64(&h->absmax_r, 0ull, 1, s));
-            HIPCHK(launch_absmax(r, R.total, &h->absmax_r, s));
-        }
+        // (one pass over the candidates writes the interleaved and FP32 copies
+        // and takes the maximum)
+        if (prec1) HIPCHK(launch_fill_u64(&h->absmax_r, 0ull, 1, s));
+        HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, rT,
+                                 prec1 ? reinterpret_cast<float*>(at(ws, nl.r32)) : nullptr,
+                                 prec1 ? &h->absmax_r : nullptr, s));
+        if (prec1 && p->kind == EAP_ERP)
+            HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total,
+                                 reinterpret_cast<float*>(at(ws, nl.r32b)), s));
     }
     unsigned long long* best = reinterpret_cast<unsigned long long*>(at(ws, nl.best));
     int32_t* seed = reinterpret_cast<int32_t*>(at(ws, nl.seed));

@@ -247,25 +247,46 @@ __device__ double path_ub_acc(const SweepArgs& A, FR rowv, int Lli, FC colv, int
 // A tile of 64 series x 64 positions per block, through LDS: each wave reads
 // 64 consecutive values of one series and writes 64 consecutive series of one
 // position.  Grid: (ceil(nr / 64), ceil(lmax / 64)), 256 threads.
-__global__ void interleave_kernel(const double* rv, const int64_t* roff, int64_t nr, int lmax, double* rT) {
+__global__ __launch_bounds__(256) void interleave_kernel(const double* rv, const int64_t* roff, int64_t nr, int lmax,
+                                                         double* rT, float* r32, unsigned long long* absmax) {
     __shared__ double tile[64][65];
+    __shared__ double part[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t b0 = (int64_t)blockIdx.x * 64;
     const int k0 = blockIdx.y * 64;
-    for (int i = w; i < 64; i += 4) {
-        const int64_t b = b0 + i;
-        double v = 0.0;
-        if (b < nr) {
-            const int64_t o = roff[b], len = roff[b + 1] - o;
-            if (k0 + lane < len) v = rv[o + k0 + lane];
-        }
-        tile[i][lane] = v;
+    // wave w reads candidates b0 + w + 4 ii: offsets first, then all 16 loads
+    // in flight, then the tile (and, when asked, the FP32 copy in the input's
+    // own layout and the largest |x|)
+    int64_t o[16];
+    int len[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+        const int64_t b = b0 + w + 4 * ii;
+        o[ii] = b < nr ? roff[b] : 0;
+        len[ii] = b < nr ? (int)(roff[b + 1] - o[ii]) : 0;
+    }
+    double v[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) v[ii] = (k0 + lane < len[ii]) ? rv[o[ii] + k0 + lane] : 0.0;
+    double m = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+        tile[w + 4 * ii][lane] = v[ii];
+        if (r32 && k0 + lane < len[ii]) r32[o[ii] + k0 + lane] = (float)v[ii];
+        m = fmax(m, __builtin_fabs(v[ii]));
     }
     __syncthreads();
-    for (int kk = w; kk < 64; kk += 4) {
-        const int k = k0 + kk;
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+        const int k = k0 + w + 4 * ii;
         const int64_t b = b0 + lane;
-        if (k < lmax && b < nr) rT[(int64_t)k * nr + b] = tile[lane][kk];
+        if (k < lmax && b < nr) rT[(int64_t)k * nr + b] = tile[lane][w + 4 * ii];
+    }
+    if (absmax) {
+        for (int s = 32; s > 0; s >>= 1) m = fmax(m, __shfl_xor(m, s));
+        if (lane == 0) part[w] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(absmax, dbits(fmax(fmax(part[0], part[1]), fmax(part[2], part[3]))));
     }
 }
 
@@ -611,8 +632,10 @@ __global__ __launch_bounds__(256) void lb_compact_kernel(const double* lb, const
                                                          const int64_t* roff, double ratio, int64_t nq, int64_t nr,
                                                          double* res, int32_t* items, unsigned int* count,
                                                          unsigned long long* pruned) {
-    // block (c, q-stride): candidates [c * per, (c + 1) * per) of its queries
-    const int lane = threadIdx.x & 63;
+    // block (c, q-stride): candidates [c * per, (c + 1) * per) of its queries;
+    // a wave takes 512 at a time, 8 per lane (coalesced, lane-minor), and
+    // lists its kept pairs with one atomic: a scan of the lanes' counts
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t per = (int64_t)kCompactPer, r0 = (int64_t)blockIdx.x * per;
     const int64_t r1 = r0 + per < nr ? r0 + per : nr;
     unsigned long long np = 0;
@@ -620,24 +643,35 @@ __global__ __launch_bounds__(256) void lb_compact_kernel(const double* lb, const
         const int lq = (int)(qoff[q + 1] - qoff[q]);
         const double cut = bitsd(best[q]);
         const int64_t sb = seed ? (int64_t)seed[q] : -1;
-        for (int64_t base = r0 + (threadIdx.x & ~63); base < r1; base += blockDim.x) {
-            const int64_t r = base + lane;
-            bool keep = false, drop = false;
-            if (r < r1 && r != sb) {
-                const int64_t p = q * nr + r;
-                const int lr = (int)(roff[r + 1] - roff[r]);
-                const int L = lq > lr ? lq : lr, ld = lq > lr ? lq - lr : lr - lq;
-                const bool feasible = ratio >= 1.0 || (int)floor(ratio * (double)L) >= ld;
-                drop = feasible && lb[p] * (1.0 - 1e-11) > cut;   // counted
-                keep = feasible && !drop;
-                if (!keep) res[p] = __builtin_huge_val();
+        for (int64_t base = r0 + (int64_t)wv * 512; base < r1; base += 4 * 512) {
+            unsigned int keep = 0;   // bit u: candidate base + 64 u + lane kept
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t r = base + 64 * u + lane;
+                if (r < r1 && r != sb) {
+                    const int64_t p = q * nr + r;
+                    const int lr = (int)(roff[r + 1] - roff[r]);
+                    const int L = lq > lr ? lq : lr, ld = lq > lr ? lq - lr : lr - lq;
+                    const bool feasible = ratio >= 1.0 || (int)floor(ratio * (double)L) >= ld;
+                    const bool drop = feasible && lb[p] * (1.0 - 1e-11) > cut;   // counted
+                    if (feasible && !drop) keep |= 1u << u;
+                    else res[p] = __builtin_huge_val();
+                    np += drop ? 1 : 0;
+                }
             }
-            const unsigned long long m = __ballot(keep);
+            const unsigned int c = (unsigned int)__popc(keep);
+            unsigned int pre = c;   // inclusive scan of the counts over the wave
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned int y = __shfl_up(pre, o);
+                if (lane >= o) pre += y;
+            }
+            const unsigned int total = __shfl(pre, 63);
             unsigned int off = 0;
-            if (lane == 0 && m) off = atomicAdd(count, (unsigned int)__popcll(m));
-            off = __shfl(off, 0);
-            if (keep) items[off + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)(q * nr + r);
-            np += drop ? 1 : 0;
+            if (lane == 63 && total) off = atomicAdd(count, total);
+            off = __shfl(off, 63) + pre - c;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (keep & (1u << u)) items[off++] = (int32_t)(q * nr + base + 64 * u + lane);
         }
     }
     for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
@@ -872,10 +906,10 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT,
-                             hipStream_t s) {
+hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT, float* r32,
+                             unsigned long long* absmax, hipStream_t s) {
     hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((nr + 63) / 64), (unsigned)((lr_max + 63) / 64)), dim3(256),
-                       0, s, rv, roff, nr, lr_max, rT);
+                       0, s, rv, roff, nr, lr_max, rT, r32, absmax);
     return hipGetLastError();
 }
 

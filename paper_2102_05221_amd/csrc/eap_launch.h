@@ -97,13 +97,12 @@ hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, dou
 hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
 hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s);
-// Path upper bounds of all NN pairs; rT: workspace of nB * lr_max doubles for
-// the interleaved candidates.  For CDTW with env_up/env_lo (nA * lr_max
-// doubles each) and lb (nA * nB doubles), also LB_Keogh of every pair.
 // Candidates interleaved for coalesced reads: rT[k * nr + b] = value k of
-// candidate b (0 past its end), k < lr_max.
-hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT,
-                             hipStream_t s);
+// candidate b (0 past its end), k < lr_max.  With r32 also the FP32 copy
+// (same layout as rv), with absmax also the largest |x| (atomicMax on the
+// bit pattern of a non-negative double; clear it first).
+hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT, float* r32,
+                             unsigned long long* absmax, hipStream_t s);
 // *dst = max(*dst, *src) (u64), one thread.
 hipError_t launch_max_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s);
 // CDTW envelope area: three arrays (upper envelope, lower envelope, query
