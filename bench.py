@@ -230,6 +230,44 @@ def run_pairwise(args, torch, eap, synth):
 ap_default_kinds = "dtw,cdtw,wdtw,erp,msm,twe"
 
 
+def ablation(torch, eap, stream, q, q_off, r, r_off, params, ws, ref, dense, kinds):
+    """The search's parts switched off one at a time (Section 5's ranking of
+    the full DP, early abandoning with pruning, and lower bounds, on the GPU):
+    every variant is one nn1 call per distance, timed with HIP events on the
+    search's stream after an untimed run, its results checked against the
+    default path's.  Variants: plain FP64 DP (no cut-off), EAPruned FP64 with
+    the cut-off starting at each pair's path bound (no seed sweep), EAPruned
+    FP64, for CDTW EAPruned FP64 without LB_Keogh, and the default FP32 screen
+    + FP64 recheck."""
+    variants = [("plain_dp_fp64", 0, eap.FLAG_PLAIN), ("eapruned_fp64_no_seed", 0, eap.FLAG_NO_SEED),
+                ("eapruned_fp64", 0, 0), ("eapruned_fp64_no_lb", 0, eap.FLAG_NO_LB),
+                ("eapruned_fp32_screen", 1, 0)]
+    out = {}
+    for name, prec, flags in variants:
+        per, total, same = {}, 0.0, True
+        for k in kinds:
+            if flags == eap.FLAG_NO_LB and params[k]["kind"] != "cdtw":
+                continue
+            nq = len(q_off) - 1
+            o = (torch.empty(nq, dtype=torch.int64, device=q.device),
+                 torch.empty(nq, dtype=torch.float64, device=q.device), None)
+            for rep in range(2):
+                if rep:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                eap.nn1(q, q_off, r, r_off, params[k], ws=ws[k], out=o, precision=prec, flags=flags)
+                if rep:
+                    b.record(stream)
+                torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            total += ms
+            per[k] = dict(ms=ms, gcups=dense[k] / (ms * 1e-3) / 1e9)
+            same &= bool(np.array_equal(o[0].cpu().numpy(), ref[k][0]) and np.array_equal(o[1].cpu().numpy(), ref[k][1]))
+        if per:
+            out[name] = dict(ms=total, per_distance=per, nn_identical=same)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,7 +278,12 @@ def main():
                     help="queries in the CPU-oracle EAPruned sample (0: skip; about 5 s for all 500 of the "
                          "default workload on 16 threads)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
-    ap.add_argument("--precision", type=int, default=1, help="0: FP64 sweep; 1: FP32 screen + FP64 recheck")
+    ap.add_argument("--ablation", action="store_true",
+                    help="workloads 2 and 6: also time the search with its parts switched off one at a time "
+                         "(plain DP, no seed, FP64 only, no LB_Keogh), after the timed region")
+    ap.add_argument("--precision", type=int, default=None,
+                    help="0: FP64 sweep; 1: FP32 screen + FP64 recheck (default 1, and 0 for workload 6, where "
+                         "LB_Keogh leaves so few pairs that the screen's extra stages cost more than they save)")
     ap.add_argument("--no-tune", action="store_true", help="skip the row-sweep autotuner (default shapes)")
     ap.add_argument("--schedule", default="pipelined", choices=("pipelined", "serial", "concurrent"),
                     help="workload 2: how the six searches of a step share the GPU.  pipelined: three "
@@ -260,6 +303,8 @@ def main():
     ap.add_argument("--refs", type=int, default=0, help="workloads 3-6: series / candidate / window count (0: the full workload)")
     ap.add_argument("--queries", type=int, default=0, help="workloads 4-6: query count (0: the full workload)")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = 0 if args.workload == 6 else 1
     if args.copy_mib > 0:
         import torch
         n = args.copy_mib * (1 << 20) // 8
@@ -462,6 +507,11 @@ def main():
                      gcups=sum(dense.values()) / (total_plain_ms * 1e-3) / 1e9,
                      speedup_of_eapruned=total_plain_ms / ms_per_step, nn_identical=same)
 
+    abl = None
+    if args.ablation:
+        abl = ablation(torch, eap, stream, q, wl["query_off"], r, wl["ref_off"], wl["params"], ws,
+                       {k: (gpu_idx[k], gpu_dist[k]) for k in kinds}, dense, kinds)
+
     # the same step under the other schedules (secondary figures, after the
     # timed region; the kernel times above come from the timed schedule)
     schedules = {}
@@ -530,6 +580,7 @@ def main():
         step_ms_p99=float(np.percentile(step_ms, 99)),
         per_distance=per,
         plain_gpu_dp=plain,
+        ablation=abl,
         roofline=roofline,
         cpu_baseline=cpu,
     )
@@ -683,9 +734,10 @@ def run_subseq(args, torch, eap, synth):
     long reference series as NN search over its z-normalised windows.  A
     random walk of 2^20 + 127 values (2^20 windows of 128), 16 queries of 128
     values (8 noisy, scaled and shifted copies of windows, 8 random walks),
-    CDTW w = 5% (the usual UCR-suite window; --kinds dtw for full DTW), FP32
-    screen + FP64 recheck.  A step builds the z-normalised windows (a GB of
-    candidates, resident in HBM) and searches every query."""
+    CDTW w = 5% (the usual UCR-suite window; --kinds dtw for full DTW), FP64
+    sweeps unless --precision 1 asks for the FP32 screen.  A step builds the
+    z-normalised windows (a GB of candidates, resident in HBM) and searches
+    every query."""
     dev = torch.device("cuda:0")
     m, nw, nq = 128, (args.refs or (1 << 20)), (args.queries or 16)
     W = synth.subseq_workload(nw, m, nq)
@@ -699,7 +751,7 @@ def run_subseq(args, torch, eap, synth):
     r_off = np.arange(nw + 1, dtype=np.int64) * m
     w = torch.empty(nw * m, dtype=torch.float64, device=dev)
     zq = torch.empty(nq * m, dtype=torch.float64, device=dev)
-    ws = {k: eap.workspace(eap.nn1_workspace_bytes(q_off, r_off, P[k], precision=args.precision), dev) for k in kinds}
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(q_off, r_off, P[k], precision=1), dev) for k in kinds}   # fits both
     outs = {k: (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev), None)
             for k in kinds}
     stream = torch.cuda.current_stream(dev)
@@ -742,6 +794,10 @@ def run_subseq(args, torch, eap, synth):
                       lb_pruned_fraction=cnt[k]["lb_pruned"] / steps / (nq * nw),
                       fp64_rechecks_per_step=cnt[k]["rechecks"] / steps,
                       planted_found=found[k], planted=len(starts))
+    abl = None
+    if args.ablation:
+        abl = ablation(torch, eap, stream, zq, q_off, w, r_off, P, ws,
+                       {k: (outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()) for k in kinds}, dense, kinds)
     # the oracle on the whole workload, timed like one step: the windows and
     # the queries normalised, then the NN search; the GPU answers compared
     cpu = None
@@ -771,7 +827,8 @@ def run_subseq(args, torch, eap, synth):
                              f"({nw} z-normalised windows), " + ", ".join(
                                  f"{k}" + (" w=5%" if k == "cdtw" else "") for k in kinds),
                     queries=nq, windows=nw, length=m, distances=kinds),
-        queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3), per_distance=per, cpu_baseline=cpu)), flush=True)
+        queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3), per_distance=per, ablation=abl,
+        cpu_baseline=cpu)), flush=True)
 
 
 def run_served(args, torch, eap, synth):

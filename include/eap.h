@@ -103,6 +103,9 @@ typedef struct {
  *              interleaved and FP32 copies, |x| maximum), which sits at the
  *              workspace's start, is reused.  For a resident candidate set
  *              searched by batch after batch (the request server uses it).
+ *              bit 4: no lower bound: a CDTW search skips LB_Keogh and sweeps
+ *              every pair under the cut-off; for ablation only.  Same results.
+ *              Other bits: EAP_EINVAL.
  *  main_wait   hipEvent_t or NULL: the stream waits for it before the main
  *              sweep (after the bounds, the seed sweep and the screen set-up).
  *  main_done   hipEvent_t or NULL: recorded on the stream right after the main

@@ -19,13 +19,14 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "derivative", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "FLAG_NO_LB", "derivative", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
 FLAG_PLAIN = 2        # plain full DP for every pair: the baseline
 FLAG_PREPARED = 4     # offsets and tables already in the workspace: kernels only (graph capture)
 FLAG_CANDIDATES = 8   # the workspace holds what an earlier call derived from these same candidates
+FLAG_NO_LB = 16       # CDTW: no LB_Keogh in front of the sweep (ablation)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeap.so")

@@ -685,6 +685,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     if (o) {
         if (o->precision != 0 && o->precision != 1) return fail(EAP_EINVAL, "precision must be 0 or 1");
         if (!(std::isfinite(o->margin_rel) && o->margin_rel >= 0)) return fail(EAP_EINVAL, "margin_rel must be >= 0");
+        if (o->flags & ~31) return fail(EAP_EINVAL, "unknown flags 0x%x", (unsigned)o->flags);
     }
     const bool prec1 = o && o->precision == 1;
     const bool screen = prec1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
@@ -755,7 +756,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         return EAP_OK;
     }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
-    const bool lbk = effective_kind(p) == EAP_CDTW;
+    const bool lbk = effective_kind(p) == EAP_CDTW && !(o && (o->flags & 16));
     double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env)) : nullptr, lb, s));

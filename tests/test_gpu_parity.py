@@ -435,6 +435,12 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert np.array_equal(gi.cpu().numpy(), oi)
     assert np.array_equal(gd.cpu().numpy(), od)
     assert c["lb_pruned"] > 0
+    # with the bound switched off every pair is swept, with the same results
+    eap.reset_counters(ws)
+    gi, gd, _ = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, precision=precision, ws=ws, flags=eap.FLAG_NO_LB)
+    assert eap.read_counters(ws)["lb_pruned"] == 0
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
 
 
 @pytest.mark.parametrize("m", [1, 2, 37, 128])
