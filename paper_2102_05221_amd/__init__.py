@@ -184,6 +184,13 @@ def _offsets(off) -> np.ndarray:
     return a
 
 
+def _sized(t, off, name):
+    """The values tensor t must hold the off[-1] values its offsets address
+    (the library reads them through a raw pointer)."""
+    if len(off) and t.numel() < int(off[-1]):
+        raise ValueError(f"{name}: offsets address {int(off[-1])} values, the tensor holds {t.numel()}")
+
+
 def _stream(stream, device):
     import torch
     if stream is None:
@@ -196,6 +203,25 @@ def _dev_f64(t, name):
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous float64 CUDA/HIP tensor")
     return t
+
+
+def _dev_buf(t, n, dtype, name):
+    """A contiguous device tensor of `dtype` with at least n elements: the
+    library writes or reads n of them through a raw pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA/HIP tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} needed")
+    return t
+
+
+def _ws(ws):
+    """A workspace: a contiguous device byte tensor (its size in bytes is passed)."""
+    import torch
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.element_size() != 1 or not ws.is_contiguous():
+        raise TypeError("ws must be a contiguous uint8 CUDA/HIP tensor (see workspace())")
+    return ws
 
 
 def workspace(nbytes: int, device):
@@ -211,8 +237,7 @@ def distance(x, y, p, cutoff: float = math.inf, ws=None, stream=None):
     _dev_f64(y, "y")
     p = _as_params(p)
     need = lib().eap_distance_workspace(x.numel(), y.numel(), ctypes.byref(p))
-    if ws is None:
-        ws = workspace(need, x.device)
+    ws = workspace(need, x.device) if ws is None else _ws(ws)
     out = torch.empty(1, dtype=torch.float64, device=x.device)
     _check(lib().eap_distance(x.data_ptr(), x.numel(), y.data_ptr(), y.numel(), ctypes.byref(p), float(cutoff),
                               out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, x.device)))
@@ -250,22 +275,25 @@ def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: 
     _dev_f64(r, "candidates")
     q_off, r_off = _offsets(q_off), _offsets(r_off)
     nq, nr = len(q_off) - 1, len(r_off) - 1
+    _sized(q, q_off, "queries")
+    _sized(r, r_off, "candidates")
     p = _as_params(p)
     o = NNOpts(int(precision), float(margin_rel), int(flags), _event_handle(main_wait, stream, q.device),
                _event_handle(main_done, stream, q.device))
-    if ws is None:
-        ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device)
+    ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device) if ws is None else _ws(ws)
     if out is None:
         idx = torch.empty(nq, dtype=torch.int64, device=q.device)
         dist = torch.empty(nq, dtype=torch.float64, device=q.device)
         lab = torch.empty(nq, dtype=torch.int32, device=q.device) if ref_labels is not None else None
     else:
         idx, dist, lab = out
+        _dev_buf(idx, nq, torch.int64, "out[0]")
+        _dev_buf(dist, nq, torch.float64, "out[1]")
+        if lab is not None:
+            _dev_buf(lab, nq, torch.int32, "out[2]")
     lab_in = 0
     if ref_labels is not None:
-        if ref_labels.dtype != torch.int32 or not ref_labels.is_cuda:
-            raise TypeError("ref_labels must be an int32 device tensor")
-        lab_in = ref_labels.data_ptr()
+        lab_in = _dev_buf(ref_labels, nr, torch.int32, "ref_labels").data_ptr()
     _check(lib().eap_nn1(q.data_ptr(), q_off.ctypes.data_as(_pi64), nq, r.data_ptr(), r_off.ctypes.data_as(_pi64),
                          nr, lab_in or None, ctypes.byref(p), ctypes.byref(o), ws.data_ptr(), ws.numel(),
                          idx.data_ptr(), dist.data_ptr(), lab.data_ptr() if lab is not None else None,
@@ -283,10 +311,11 @@ def tune_nn1(q, q_off, r, r_off, p, precision: int = 0, margin_rel: float = 1e-4
     _dev_f64(r, "candidates")
     q_off, r_off = _offsets(q_off), _offsets(r_off)
     nq, nr = len(q_off) - 1, len(r_off) - 1
+    _sized(q, q_off, "queries")
+    _sized(r, r_off, "candidates")
     p = _as_params(p)
     o = NNOpts(int(precision), float(margin_rel), 0)
-    if ws is None:
-        ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device)
+    ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device) if ws is None else _ws(ws)
     idx = torch.empty(nq, dtype=torch.int64, device=q.device)
     dist = torch.empty(nq, dtype=torch.float64, device=q.device)
     recs = (TuneRec * 16)()
@@ -349,14 +378,13 @@ class Server:
         self._refs = refs
         self._labels = ref_labels
         self._r_off = _offsets(r_off)
+        _sized(refs, self._r_off, "candidates")
         self._p = _as_params(p)
         o = ServerOpts(int(slots), int(max_batch), int(max_query_len), int(mem_budget), int(precision),
                        float(margin_rel))
         lab = None
         if ref_labels is not None:
-            if ref_labels.dtype != torch.int32 or not ref_labels.is_cuda:
-                raise TypeError("ref_labels must be an int32 device tensor")
-            lab = ref_labels.data_ptr()
+            lab = _dev_buf(ref_labels, len(self._r_off) - 1, torch.int32, "ref_labels").data_ptr()
         h = ctypes.c_void_p(None)
         _scheck(lib().eap_server_create(refs.data_ptr(), self._r_off.ctypes.data_as(_pi64), len(self._r_off) - 1,
                                         lab, ctypes.byref(self._p), ctypes.byref(o), ctypes.byref(h)))
@@ -410,24 +438,33 @@ def subseq_windows(s, m: int, stream=None, out=None):
     import torch
     _dev_f64(s, "series")
     n = s.numel()
+    need = max(n - int(m) + 1, 0) * int(m)
     if out is None:
-        out = torch.empty(max(n - m + 1, 0) * m, dtype=torch.float64, device=s.device)
+        out = torch.empty(need, dtype=torch.float64, device=s.device)
+    _dev_buf(out, need, torch.float64, "out")
     _check(lib().eap_subseq_windows(s.data_ptr(), n, int(m), out.data_ptr(), _stream(stream, s.device)))
     return out
 
 
-def subseq_search(query, series, p, precision: int = 0, stream=None):
-    """Sub-sequence search (Section 5.3): the start of the window of `series`
-    closest to `query` (both device float64), every window and the query
-    z-normalised, as an NN search over the windows.  Returns (start, distance)
-    as 1-element device tensors, with the windows' offsets."""
+def subseq_search(query, series, p, precision: int = 0, stream=None, m: int = 0):
+    """Sub-sequence search (Section 5.3): for each query, the start of the
+    window of `series` closest to it (both device float64), every window and
+    every query z-normalised, as one NN search over the windows.  `query` is
+    one query, or with m > 0 the concatenation of queries of m values each.
+    Returns (starts int64, distances float64) device tensors, one entry per
+    query."""
     import numpy as np
-    m = query.numel()
-    zq = subseq_windows(query, m, stream=stream)
+    import torch
+    m = int(m) if m else query.numel()
+    if m < 1 or query.numel() % m:
+        raise EapError(f"query length {query.numel()} is not a multiple of m = {m}")
+    nq = query.numel() // m
+    zq = torch.empty_like(query)
+    for i in range(nq):
+        subseq_windows(query[i * m:(i + 1) * m], m, stream=stream, out=zq[i * m:(i + 1) * m])
     w = subseq_windows(series, m, stream=stream)
-    nw = w.numel() // m
-    r_off = np.arange(nw + 1, dtype=np.int64) * m
-    idx, dist, _ = nn1(zq, np.array([0, m], dtype=np.int64), w, r_off, p, precision=precision, stream=stream)
+    r_off = np.arange(w.numel() // m + 1, dtype=np.int64) * m
+    idx, dist, _ = nn1(zq, np.arange(nq + 1, dtype=np.int64) * m, w, r_off, p, precision=precision, stream=stream)
     return idx, dist
 
 
@@ -439,10 +476,11 @@ def derivative(v, off, ws=None, stream=None, out=None):
     _dev_f64(v, "series")
     off = _offsets(off)
     n = len(off) - 1
-    if ws is None:
-        ws = workspace(int(lib().eap_derivative_workspace(n)), v.device)
+    _sized(v, off, "series")
+    ws = workspace(int(lib().eap_derivative_workspace(n)), v.device) if ws is None else _ws(ws)
     if out is None:
         out = torch.empty_like(v)
+    _dev_buf(out, int(off[-1]) if len(off) else 0, torch.float64, "out")
     _check(lib().eap_derivative(v.data_ptr(), off.ctypes.data_as(_pi64), n, out.data_ptr(), ws.data_ptr(),
                                 ws.numel(), _stream(stream, v.device)))
     return out
@@ -461,11 +499,12 @@ def pairwise(s, s_off, p, mode: str = "prune", ws=None, stream=None, out=None):
     _dev_f64(s, "series")
     s_off = _offsets(s_off)
     n = len(s_off) - 1
+    _sized(s, s_off, "series")
     p = _as_params(p)
-    if ws is None:
-        ws = workspace(pairwise_workspace_bytes(s_off, p), s.device)
+    ws = workspace(pairwise_workspace_bytes(s_off, p), s.device) if ws is None else _ws(ws)
     if out is None:
         out = torch.empty(max(n * (n - 1) // 2, 1), dtype=torch.float64, device=s.device)
+    _dev_buf(out, n * (n - 1) // 2, torch.float64, "out")
     m = {"prune": 0, "full": 1}[mode]
     _check(lib().eap_pairwise(s.data_ptr(), s_off.ctypes.data_as(_pi64), n, ctypes.byref(p), m, ws.data_ptr(),
                               ws.numel(), out.data_ptr(), _stream(stream, s.device)))

@@ -175,3 +175,38 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(eap, "LIB_PATH", str(tmp_path / "libeap.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         eap.lib()
+
+
+def test_binding_checks_tensor_sizes_before_any_call():
+    """The binding refuses device tensors smaller than the offsets or outputs
+    address (the library reads and writes them through raw pointers).  Fake
+    "device" tensors: the checks run before anything reaches the library."""
+    import torch
+
+    class Fake(torch.Tensor):
+        pass
+
+    def dev(n, dtype=torch.float64):
+        t = torch.empty(n, dtype=dtype).as_subclass(Fake)
+        t.__class__.is_cuda = property(lambda self: True)
+        return t
+
+    q, r = dev(10), dev(11)
+    with pytest.raises(ValueError, match="offsets address"):
+        eap.nn1(q, [0, 5, 12], r, [0, 11], dict(kind="dtw"))
+    with pytest.raises(ValueError, match="offsets address"):
+        eap.nn1(q, [0, 10], r, [0, 6, 12], dict(kind="dtw"))
+    with pytest.raises(ValueError, match="needed"):
+        eap.nn1(q, [0, 5, 10], r, [0, 11], dict(kind="dtw"), ws=dev(4096, torch.uint8),
+                out=(dev(1, torch.int64), dev(2), None))
+    with pytest.raises(TypeError, match="out\\[1\\]"):
+        eap.nn1(q, [0, 10], r, [0, 11], dict(kind="dtw"), ws=dev(4096, torch.uint8),
+                out=(dev(1, torch.int64), dev(1, torch.float32), None))
+    with pytest.raises(TypeError, match="ws must be"):
+        eap.nn1(q, [0, 10], r, [0, 11], dict(kind="dtw"), ws=dev(4096))
+    with pytest.raises(ValueError, match="needed"):
+        eap.subseq_windows(dev(100), 10, out=dev(90 * 10))
+    with pytest.raises(ValueError, match="needed"):
+        eap.pairwise(dev(30), [0, 10, 20, 30], dict(kind="dtw"), ws=dev(1 << 20, torch.uint8), out=dev(2))
+    with pytest.raises(ValueError, match="offsets address"):
+        eap.derivative(dev(10), [0, 4, 11], ws=dev(4096, torch.uint8))

@@ -477,6 +477,28 @@ def test_subseq_search_parity(torch_dev, orc, p, precision):
         assert int(gi.item()) == int(oi[0]) and float(gd.item()) == float(od[0])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_subseq_search_many_windows(torch_dev, orc, precision):
+    """Sixteen queries over the 70,000 windows of 64 of a random walk (the
+    scans split over blocks, several queries per bound pass), half of them
+    planted copies: the GPU's windows and distances equal the oracle's."""
+    torch, dev = torch_dev
+    W = synth.subseq_workload(70_000, 64, 16)
+    s, m = W["series"], W["m"]
+    qv = np.concatenate(W["queries"])
+    log(f"subseq search many windows precision={precision}")
+    gi, gd = eap.subseq_search(to_dev(torch, dev, qv), to_dev(torch, dev, s), dict(kind="cdtw", window_ratio=0.05),
+                               precision=precision, m=m)
+    w_or = orc.subseq_windows(s, m)
+    zq = np.concatenate([orc.subseq_windows(x, m) for x in W["queries"]])
+    q_off = np.arange(17, dtype=np.int64) * m
+    oi, od, _ = orc.nn1(dict(kind="cdtw", window_ratio=0.05), zq, q_off, w_or,
+                        np.arange(len(w_or) // m + 1, dtype=np.int64) * m, "eap")
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    assert np.array_equal(oi[:8], W["starts"])
+
+
 def test_derivative_series_bit_equal_to_oracle(torch_dev, orc):
     """The derivative series of ragged series (lengths 1 to 300, the short
     cases included) equal the oracle's bit for bit."""
@@ -580,6 +602,31 @@ def test_nn1_many_candidates(torch_dev, orc, kind, precision, nr):
     gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=precision)
     oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
     assert oi[1] == nr - 3 and od[1] == 0.0
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(gd.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("nq,nr", [(256, 4096), (64, 8192), (16, 16384)])
+def test_cdtw_nn_bound_and_scan_shapes(torch_dev, orc, nq, nr, precision):
+    """CDTW NN at shapes that take the bound + LB_Keogh kernel through 8, 4
+    and 2 queries per pass over the candidates (on a 256-CU device) and split
+    the per-query scans over 2 to 4 blocks; ragged lengths 20..40.  Exact
+    copies of query 0 sit at candidates 5 and nr - 1, in different chunks of
+    the split scans: the lower index must win."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(nq + nr + precision)
+    rs = synth.random_walks(rng, nr, (20, 40))
+    qs = synth.random_walks(rng, nq, (20, 40))
+    rs[5] = qs[0].copy()
+    rs[nr - 1] = qs[0].copy()
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(kind="cdtw", window_ratio=0.2)
+    log(f"cdtw bound and scan shapes nq={nq} nr={nr} precision={precision}")
+    gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=precision)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "eap")
+    assert oi[0] == 5 and od[0] == 0.0
     assert np.array_equal(gi.cpu().numpy(), oi)
     assert np.array_equal(gd.cpu().numpy(), od)
 
