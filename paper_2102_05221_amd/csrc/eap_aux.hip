@@ -367,9 +367,13 @@ __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const doub
     const bool live = b < nB;
     const int64_t bb = live ? b : nB - 1;   // lanes past the end read the last candidate, store nothing
     const int lr = (int)(roff[bb + 1] - roff[bb]);
-    int lw = lr;   // the wave's longest candidate: the column loop is uniform
-    for (int o = 32; o > 0; o >>= 1) lw = max(lw, __shfl_xor(lw, o));
+    int lw = lr, ln = lr;   // the wave's longest and shortest candidates: the column loops are uniform
+    for (int o = 32; o > 0; o >>= 1) {
+        lw = max(lw, __shfl_xor(lw, o));
+        ln = min(ln, __shfl_xor(ln, o));
+    }
     lw = __builtin_amdgcn_readfirstlane(lw);
+    ln = __builtin_amdgcn_readfirstlane(ln);
     const double ratio = A.window_ratio;
     const cip qo = (cip)qoff;
     for (int64_t a0 = (int64_t)blockIdx.y * QT; a0 < A.nA; a0 += (int64_t)gridDim.y * QT) {
@@ -388,31 +392,50 @@ __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const doub
         // candidate values in chunks of CH (loads issued together, indexes
         // clamped into the series); the query extended by its last value and
         // the envelopes come in aligned chunks of 8 from rows of ld >= lw
-        // entries, so their reads need no clamp; terms added in order
+        // entries, so their reads need no clamp; terms added in order.  Chunks
+        // inside every lane's candidate (j0 + CH <= ln) need no mask; in the
+        // others a column past a candidate's end adds +0 (the sums are >= 0,
+        // so they do not change), by selects rather than per-lane branches.  A
+        // full group of QT queries runs without a per-query guard, so the
+        // compiler can issue the next queries' scalar loads while it computes.
         constexpr int CH = 8;
-        for (int j0 = 0; j0 < lw; j0 += CH) {
+        auto chunk = [&](int j0, auto full_tag, auto mask_tag) {
+            constexpr bool FULL = decltype(full_tag)::value, MASK = decltype(mask_tag)::value;
             double xv[CH];
+            bool in[CH];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) xv[u] = rT[(int64_t)(j0 + u < lr ? j0 + u : lr - 1) * nB + bb];
+            for (int u = 0; u < CH; ++u) {
+                in[u] = !MASK || j0 + u < lr;
+                xv[u] = rT[(int64_t)(in[u] ? j0 + u : lr - 1) * nB + bb];
+            }
 #pragma unroll
             for (int t = 0; t < QT; ++t) {
-                if (t >= nqt) continue;
+                if (!FULL && t >= nqt) continue;
                 const int64_t base = (a0 + t) * ld + j0;
                 const d8 Y = *(cd8p)(env_q + base), U = *(cd8p)(env_up + base), O = *(cd8p)(env_lo + base);
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
-                    const double y = Y[u], up = U[u], lo = O[u];
-                    if (j0 + u < lr) {
-                        // the diagonal while both series last, then down the candidate
-                        const double x = xv[u];
-                        const double d = x - y;
+                    // the diagonal while both series last, then down the candidate
+                    const double x = xv[u];
+                    const double d = x - Y[u];
+                    const double e = fmax(fmax(x - U[u], O[u] - x), 0.0);   // at most one side is positive
+                    if (MASK) {
+                        acc[t] = (in[u] ? d * d : 0.0) + acc[t];
+                        lbv[t] = lbv[t] + (in[u] ? e * e : 0.0);
+                    } else {
                         acc[t] = (d * d) + acc[t];
-                        const double e = fmax(fmax(x - up, lo - x), 0.0);   // at most one side is positive
                         lbv[t] = lbv[t] + e * e;
                     }
                 }
             }
-        }
+        };
+        auto sweep = [&](auto full_tag) {
+            int j0 = 0;
+            for (; j0 + CH <= ln; j0 += CH) chunk(j0, full_tag, std::false_type{});
+            for (; j0 < lw; j0 += CH) chunk(j0, full_tag, std::true_type{});
+        };
+        if (nqt == QT) sweep(std::true_type{});
+        else sweep(std::false_type{});
         // queries longer than the candidate: their tail against its last value
         const double xl = rT[(int64_t)(lr - 1) * nB + bb];
 #pragma unroll
