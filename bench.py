@@ -756,12 +756,18 @@ def run_subseq(args, torch, eap, synth):
             for k in kinds}
     stream = torch.cuda.current_stream(dev)
 
+    zws = eap.workspace(eap.lib().eap_znorm_workspace(nq), dev)
+    flags = {k: 0 for k in kinds}
+
     def step():
+        # the windows and queries are rebuilt every step; their offsets (2^20 + 1
+        # of them) are the same each time, so after the first search they stay
+        # on the device (flags bit 2) instead of being checked and uploaded again
         eap.subseq_windows(sd, m, out=w)
-        for i in range(nq):
-            eap.subseq_windows(qv[i * m:(i + 1) * m], m, out=zq[i * m:(i + 1) * m])
+        eap.znorm(qv, q_off, ws=zws, out=zq)
         for k in kinds:
-            eap.nn1(zq, q_off, w, r_off, P[k], ws=ws[k], out=outs[k], precision=args.precision)
+            eap.nn1(zq, q_off, w, r_off, P[k], ws=ws[k], out=outs[k], precision=args.precision, flags=flags[k])
+            flags[k] = eap.FLAG_PREPARED
 
     step()
     if not args.no_tune:

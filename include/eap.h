@@ -216,6 +216,21 @@ eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const 
  *  out         device double[(n-m+1)*m], not overlapping s. */
 eap_status eap_subseq_windows(const double* s, int64_t n, int64_t m, double* out, void* stream);
 
+/* Z-normalisation of every series of a ragged set: the normalisation that
+ * sub-sequence search (Section 5.3) applies to its queries.  For each series,
+ * out = (v - mean) / sd with mean and sd as in eap_subseq_windows (sums left
+ * to right in binary64, population standard deviation; a constant series
+ * gives zeros), so a series of length m comes out equal to its single
+ * window from eap_subseq_windows.  One launch for the whole set.
+ *  v, off, n   device values, host offsets (n >= 1 series, lengths 1..2048
+ *              as for every set).
+ *  out         device double[off[n]], not overlapping v.
+ *  ws          device workspace of eap_znorm_workspace(n) bytes.
+ * Errors as for eap_derivative. */
+size_t eap_znorm_workspace(int64_t n);
+eap_status eap_znorm(const double* v, const int64_t* off, int64_t n, double* out, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* Derivative series, for the derivative variants DDTW, DCDTW and DWDTW
  * (Section 2.3 names them: the distance of the series' first derivatives,
  * with no formula given).  The estimate of Keogh and Pazzani: for 1 < i < m,

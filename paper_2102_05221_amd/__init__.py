@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "FLAG_NO_LB", "derivative", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "FLAG_NO_LB", "derivative", "znorm", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
@@ -114,6 +114,10 @@ def lib():
         L.eap_pairwise.argtypes = [_vp, _pi64, _i64, _pP, ctypes.c_int32, _vp, _sz, _vp, _vp]
         L.eap_subseq_windows.restype = ctypes.c_int
         L.eap_subseq_windows.argtypes = [_vp, _i64, _i64, _vp, _vp]
+        L.eap_znorm_workspace.restype = _sz
+        L.eap_znorm_workspace.argtypes = [_i64]
+        L.eap_znorm.restype = ctypes.c_int
+        L.eap_znorm.argtypes = [_vp, _pi64, _i64, _vp, _vp, _sz, _vp]
         L.eap_derivative_workspace.restype = _sz
         L.eap_derivative_workspace.argtypes = [_i64]
         L.eap_derivative.restype = ctypes.c_int
@@ -459,13 +463,30 @@ def subseq_search(query, series, p, precision: int = 0, stream=None, m: int = 0)
     if m < 1 or query.numel() % m:
         raise EapError(f"query length {query.numel()} is not a multiple of m = {m}")
     nq = query.numel() // m
-    zq = torch.empty_like(query)
-    for i in range(nq):
-        subseq_windows(query[i * m:(i + 1) * m], m, stream=stream, out=zq[i * m:(i + 1) * m])
+    q_off = np.arange(nq + 1, dtype=np.int64) * m
+    zq = znorm(query, q_off, stream=stream)
     w = subseq_windows(series, m, stream=stream)
     r_off = np.arange(w.numel() // m + 1, dtype=np.int64) * m
-    idx, dist, _ = nn1(zq, np.arange(nq + 1, dtype=np.int64) * m, w, r_off, p, precision=precision, stream=stream)
+    idx, dist, _ = nn1(zq, q_off, w, r_off, p, precision=precision, stream=stream)
     return idx, dist
+
+
+def znorm(v, off, ws=None, stream=None, out=None):
+    """Every series of the concatenated set v (device float64, host offsets
+    off) z-normalised on its own, in one launch (eap_znorm): the queries of a
+    sub-sequence search.  Returns a device tensor."""
+    import torch
+    _dev_f64(v, "series")
+    off = _offsets(off)
+    n = len(off) - 1
+    _sized(v, off, "series")
+    ws = workspace(int(lib().eap_znorm_workspace(n)), v.device) if ws is None else _ws(ws)
+    if out is None:
+        out = torch.empty_like(v)
+    _dev_buf(out, int(off[-1]) if len(off) else 0, torch.float64, "out")
+    _check(lib().eap_znorm(v.data_ptr(), off.ctypes.data_as(_pi64), n, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                           _stream(stream, v.device)))
+    return out
 
 
 def derivative(v, off, ws=None, stream=None, out=None):

@@ -907,6 +907,25 @@ eap_status eap_derivative(const double* v, const int64_t* off, int64_t n, double
     return EAP_OK;
 }
 
+size_t eap_znorm_workspace(int64_t n) { return eap_derivative_workspace(n); }
+
+eap_status eap_znorm(const double* v, const int64_t* off, int64_t n, double* out, void* ws, size_t ws_bytes,
+                     void* stream) {
+    eap_status st;
+    if (!v || !out) return fail(EAP_EINVAL, "NULL series or output");
+    SetInfo S;
+    if ((st = check_offsets(off, n, "series", &S)) != EAP_OK) return st;
+    if (eap_status st_ws = check_ws(ws, ws_bytes, eap_znorm_workspace(n))) return st_ws;
+    const char* vb = reinterpret_cast<const char*>(v);
+    const char* ob = reinterpret_cast<const char*>(out);
+    const size_t bytes = sizeof(double) * (size_t)S.total;
+    if (vb < ob + bytes && ob < vb + bytes) return fail(EAP_EINVAL, "out overlaps the input values");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload(ws, off, sizeof(int64_t) * (size_t)(n + 1), s)) != EAP_OK) return st;
+    HIPCHK(launch_znorm(v, reinterpret_cast<const int64_t*>(ws), n, out, s));
+    return EAP_OK;
+}
+
 size_t eap_pairwise_workspace(const int64_t* s_off, int64_t n, const eap_params* p) {
     SetInfo S;
     if (check_params(p) != EAP_OK || check_offsets(s_off, n, "series", &S) != EAP_OK) return 0;

@@ -91,6 +91,35 @@ __global__ __launch_bounds__(256) void subseq_windows_kernel(const double* s, in
     }
 }
 
+// z-normalisation of each series of a ragged set, one block per series (grid
+// stride): thread 0 takes the sums in index order (the order is part of the
+// result: it matches subseq_windows_kernel for a window covering the whole
+// series), then the block writes the series.
+__global__ __launch_bounds__(256) void znorm_kernel(const double* v, const int64_t* off, int64_t n, double* out) {
+    __shared__ double stat[2];
+    for (int64_t a = blockIdx.x; a < n; a += gridDim.x) {
+        const int64_t o = off[a];
+        const int64_t L = off[a + 1] - o;
+        const double* x = v + o;
+        __syncthreads();   // the previous series' statistics have been used
+        if (threadIdx.x == 0) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < L; ++k) acc = acc + x[k];
+            const double mean = acc / (double)L;
+            double s2 = 0.0;
+            for (int64_t k = 0; k < L; ++k) {
+                const double d = x[k] - mean;
+                s2 = s2 + d * d;
+            }
+            stat[0] = mean;
+            stat[1] = sqrt(s2 / (double)L);
+        }
+        __syncthreads();
+        const double mean = stat[0], sd = stat[1];
+        for (int64_t k = threadIdx.x; k < L; k += blockDim.x) out[o + k] = sd > 0.0 ? (x[k] - mean) / sd : 0.0;
+    }
+}
+
 __global__ void to_f32_kernel(const double* v, int64_t n, float* out) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
         out[x] = (float)v[x];
@@ -642,7 +671,7 @@ __global__ __launch_bounds__(256) void scan_finish_kernel(const double* pv, cons
     }
 }
 
-constexpr int kCompactPer = 2048;   // candidates per block of lb_compact_kernel
+constexpr int kCompactPer = 8192;   // candidates per block of lb_compact_kernel (4 waves x 64 lanes x 32)
 
 // CDTW NN: the pairs whose lower bound does not exceed the query's cut-off
 // after the seed sweep (the seed itself excluded), listed for the main sweep;
@@ -656,8 +685,9 @@ __global__ __launch_bounds__(256) void lb_compact_kernel(const double* lb, const
                                                          double* res, int32_t* items, unsigned int* count,
                                                          unsigned long long* pruned) {
     // block (c, q-stride): candidates [c * per, (c + 1) * per) of its queries;
-    // a wave takes 512 at a time, 8 per lane (coalesced, lane-minor), and
-    // lists its kept pairs with one atomic: a scan of the lanes' counts
+    // a wave takes 2048 at a time, 32 per lane (coalesced, lane-minor), and
+    // lists its kept pairs with one atomic on the shared list counter (a scan
+    // of the lanes' counts gives each lane its place)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t per = (int64_t)kCompactPer, r0 = (int64_t)blockIdx.x * per;
     const int64_t r1 = r0 + per < nr ? r0 + per : nr;
@@ -666,10 +696,10 @@ __global__ __launch_bounds__(256) void lb_compact_kernel(const double* lb, const
         const int lq = (int)(qoff[q + 1] - qoff[q]);
         const double cut = bitsd(best[q]);
         const int64_t sb = seed ? (int64_t)seed[q] : -1;
-        for (int64_t base = r0 + (int64_t)wv * 512; base < r1; base += 4 * 512) {
+        for (int64_t base = r0 + (int64_t)wv * 2048; base < r1; base += 4 * 2048) {
             unsigned int keep = 0;   // bit u: candidate base + 64 u + lane kept
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
+#pragma unroll 8
+            for (int u = 0; u < 32; ++u) {
                 const int64_t r = base + 64 * u + lane;
                 if (r < r1 && r != sb) {
                     const int64_t p = q * nr + r;
@@ -692,9 +722,8 @@ __global__ __launch_bounds__(256) void lb_compact_kernel(const double* lb, const
             unsigned int off = 0;
             if (lane == 63 && total) off = atomicAdd(count, total);
             off = __shfl(off, 63) + pre - c;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (keep & (1u << u)) items[off++] = (int32_t)(q * nr + base + 64 * u + lane);
+            for (unsigned int km = keep; km; km &= km - 1u)
+                items[off++] = (int32_t)(q * nr + base + 64 * (__ffs(km) - 1) + lane);
         }
     }
     for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
@@ -916,6 +945,11 @@ hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, dou
 hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s) {
     const size_t lds = sizeof(double) * (size_t)(3 * kWinPerBlock + m - 1);
     hipLaunchKernelGGL(subseq_windows_kernel, dim3(blocks_for(nw, kWinPerBlock)), dim3(256), lds, s, x, nw, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_znorm(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(znorm_kernel, dim3(blocks_for(n, 1)), dim3(256), 0, s, v, off, n, out);
     return hipGetLastError();
 }
 

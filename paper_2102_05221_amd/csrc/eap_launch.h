@@ -95,6 +95,8 @@ bool band_shape_ok(int diags, int g);
 // Auxiliary kernels.
 hipError_t launch_erp_border(const double* v, const int64_t* off, int64_t n, double gap, double* out, hipStream_t s);
 hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s);
+// z-normalise each series of a ragged set (device offsets), see eap_znorm.
+hipError_t launch_znorm(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s);
 // Candidates interleaved for coalesced reads: rT[k * nr + b] = value k of

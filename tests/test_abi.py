@@ -139,6 +139,20 @@ def test_derivative_argument_errors(L):
     assert L.eap_derivative(FAKE, pi(so), 3, out, None, need, None) == eap.EAP_EWORKSPACE
 
 
+def test_znorm_argument_errors(L):
+    so = np.array([0, 4, 4, 9], dtype=np.int64)      # a zero-length series
+    pi = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    ok = np.array([0, 4, 9], dtype=np.int64)
+    need = L.eap_znorm_workspace(2)
+    assert need > 0
+    ws = ctypes.c_void_p(0x4000)
+    out = ctypes.c_void_p(0x100000)
+    assert L.eap_znorm(FAKE, pi(so), 3, out, ws, need, None) == eap.EAP_EINVAL
+    assert L.eap_znorm(None, pi(ok), 2, out, ws, need, None) == eap.EAP_EINVAL
+    assert L.eap_znorm(FAKE, pi(ok), 2, out, ws, need - 1, None) == eap.EAP_EWORKSPACE
+    assert L.eap_znorm(FAKE, pi(ok), 2, FAKE, ws, need, None) == eap.EAP_EINVAL      # out overlaps the input
+
+
 def test_subseq_windows_argument_errors(L):
     out = ctypes.c_void_p(0x100000)
     assert L.eap_subseq_windows(None, 100, 10, out, None) == eap.EAP_EINVAL

@@ -477,6 +477,23 @@ def test_subseq_search_parity(torch_dev, orc, p, precision):
         assert int(gi.item()) == int(oi[0]) and float(gd.item()) == float(od[0])
 
 
+def test_znorm_bit_equal_to_oracle(torch_dev, orc):
+    """Ragged z-normalisation in one launch (lengths 1 to 2048, a constant
+    series, more series than the grid covers in one pass): each series equals
+    the oracle's single window over it, bit for bit."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(77)
+    lens = [1, 2, 37, 128, 1000, 2048, 5] + list(rng.integers(1, 9, 70_000))
+    xs = [np.cumsum(rng.standard_normal(int(L))) * 3.0 + 7.0 for L in lens]
+    xs[4] = np.full(1000, 2.5)
+    v, off = synth.pack(xs)
+    log("znorm ragged")
+    g = eap.znorm(to_dev(torch, dev, v), off).cpu().numpy()
+    want = np.concatenate([orc.subseq_windows(x, len(x)) for x in xs])
+    assert np.array_equal(g, want)
+    assert np.array_equal(g[off[4]:off[5]], np.zeros(1000))
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_subseq_search_many_windows(torch_dev, orc, precision):
     """Sixteen queries over the 70,000 windows of 64 of a random walk (the
