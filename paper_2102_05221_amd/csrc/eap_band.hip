@@ -54,8 +54,16 @@ __device__ __forceinline__ double shl1(double v) {
     return __builtin_bit_cast(double, r);
 }
 
+// Blocks per CU the register budget is sized for: the band sweep waits on a
+// chain of dependent steps, so FP32 bands of up to 8 diagonals per parity and
+// lane are held to 168 VGPRs (3 blocks of 256, 3 waves per SIMD); wider lanes
+// and FP64 keep 2.
+template <typename T, int C>
+constexpr int band_min_blocks() { return (sizeof(T) == 4 && C <= 8) ? 3 : 2; }
+
 template <int KIND, typename T, int G, int C>
-__global__ __launch_bounds__(256) void band_kernel(SweepArgs A, Series<T> SA, Series<T> SB) {
+__global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(SweepArgs A, Series<T> SA,
+                                                                             Series<T> SB) {
     constexpr bool WIN = (KIND == CDTW || KIND == ERP);
     constexpr int CB = C;        // ring length
     constexpr int M2 = 2 * C;    // diagonals per lane
