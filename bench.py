@@ -795,11 +795,26 @@ def run_subseq(args, torch, eap, synth):
     for k in kinds:
         main = [x for x in prof if x["kind"] == k and x["stage"] == 2]
         per[k] = dict(main_sweep_ms=(sum(x["ms"] for x in main) / len(main)) if main else None,
-                      main_kernel=(kernel_label(main[0]) if main else None), dense_cells=dense[k],
+                      main_kernel=(kernel_label(main[0]) if main else None),
+                      main_fp32=bool(main[0]["fp32"]) if main else False,
+                      main_cells_per_launch=cnt[k]["stage_cells"][2] / steps, dense_cells=dense[k],
                       executed_fraction=cnt[k]["cells"] / steps / dense[k],
                       lb_pruned_fraction=cnt[k]["lb_pruned"] / steps / (nq * nw),
                       fp64_rechecks_per_step=cnt[k]["rechecks"] / steps,
                       planted_found=found[k], planted=len(starts))
+    # dominant kernel: the main sweep, executed cells per launch over its launch time
+    dom = max(kinds, key=lambda k: per[k]["main_sweep_ms"] or 0.0)
+    d = per[dom]
+    roofline = None
+    if d["main_sweep_ms"]:
+        ops = (OPS_PER_CELL_F32 if d["main_fp32"] else OPS_PER_CELL)[dom]
+        peak = (LANE_OPS_PER_S_F32 if d["main_fp32"] else LANE_OPS_PER_S) / ops / 1e9
+        achieved = d["main_cells_per_launch"] / (d["main_sweep_ms"] * 1e-3) / 1e9
+        kernel = f"{d['main_kernel']} sweep, {dom.upper()} main stage, {'fp32' if d['main_fp32'] else 'fp64'}"
+        roofline = dict(bound="alu", achieved=achieved, peak=peak, unit="GCUPS", frac=achieved / peak,
+                        traffic=None, kernel=kernel, ops_per_cell=ops, launch_ms=d["main_sweep_ms"],
+                        cells_per_launch=d["main_cells_per_launch"])
+        roofline["traffic"], roofline["traffic_note"] = hbm_traffic(kernel)
     abl = None
     if args.ablation:
         abl = ablation(torch, eap, stream, zq, q_off, w, r_off, P, ws,
@@ -834,7 +849,7 @@ def run_subseq(args, torch, eap, synth):
                                  f"{k}" + (" w=5%" if k == "cdtw" else "") for k in kinds),
                     queries=nq, windows=nw, length=m, distances=kinds),
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3), per_distance=per, ablation=abl,
-        cpu_baseline=cpu)), flush=True)
+        roofline=roofline, cpu_baseline=cpu)), flush=True)
 
 
 def run_served(args, torch, eap, synth):

@@ -56,10 +56,10 @@ __device__ __forceinline__ double shl1(double v) {
 
 // Blocks per CU the register budget is sized for: the band sweep waits on a
 // chain of dependent steps, so FP32 bands of up to 8 diagonals per parity and
-// lane are held to 168 VGPRs (3 blocks of 256, 3 waves per SIMD); wider lanes
-// and FP64 keep 2.
+// lane are held to 168 VGPRs (3 blocks of 256, 3 waves per SIMD).  Wider FP32
+// lanes and FP64 take the registers they need (a tighter budget spills).
 template <typename T, int C>
-constexpr int band_min_blocks() { return (sizeof(T) == 4 && C <= 8) ? 3 : 2; }
+constexpr int band_min_blocks() { return (sizeof(T) == 4 && C <= 8) ? 3 : 1; }
 
 template <int KIND, typename T, int G, int C>
 __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(SweepArgs A, Series<T> SA,
