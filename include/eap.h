@@ -101,7 +101,9 @@ typedef struct {
  *              precision, with any queries; what it derived from the
  *              candidates alone (their device offsets, ERP borders,
  *              interleaved and FP32 copies, |x| maximum), which sits at the
- *              workspace's start, is reused.  For a resident candidate set
+ *              workspace's start, is reused (a CDTW search without LB_Keogh
+ *              over 2^18 or more candidates rebuilds the interleaved copy,
+ *              which searches with the bound over such sets do not make).  For a resident candidate set
  *              searched by batch after batch (the request server uses it).
  *              bit 4: no lower bound: a CDTW search skips LB_Keogh and sweeps
  *              every pair under the cut-off; for ablation only.  Same results.

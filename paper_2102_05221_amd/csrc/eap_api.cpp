@@ -128,6 +128,10 @@ static eap_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
     return EAP_OK;
 }
 
+// Candidate sets from this size on are read in their own layout by the CDTW
+// bound + LB_Keogh kernel (no interleaved copy).
+constexpr int64_t kDirectReadMinCandidates = int64_t(1) << 18;
+
 constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
 // header words cleared by every call: the queues, counts and absmax
 constexpr int kClearedWords = (int)(offsetof(Header, absmax_r) / 8) - kCounterWords;
@@ -715,18 +719,29 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         return st;
     Header* h = hdr_of(ws, nl.c);
     double* rT = reinterpret_cast<double*>(at(ws, nl.rT));
+    // The bound kernels read the interleaved copy of the candidates, except
+    // CDTW with LB_Keogh over a very large candidate set, whose kernel reads
+    // them in their own layout (building the copy would cost a full extra read
+    // and write of the set).  The choice depends on the candidates and the
+    // flags only, so calls with flags bit 3 find the copy when they need it.
+    const bool lbk = effective_kind(p) == EAP_CDTW && !(o && (o->flags & 16));
+    const bool direct = lbk && nr >= kDirectReadMinCandidates;
+    const bool need_rT = !direct;
     if (!cand_ready) {
         // what the candidates alone determine, kept for calls with flags bit 3:
-        // the interleaved copy, and for precision 1 the FP32 copies and |x| maximum
-        // (one pass over the candidates writes the interleaved and FP32 copies
-        // and takes the maximum)
+        // the interleaved copy (when a bound kernel reads it), and for precision
+        // 1 the FP32 copies and |x| maximum, all in one pass over the candidates
         if (prec1) HIPCHK(launch_fill_u64(&h->absmax_r, 0ull, 1, s));
-        HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, rT,
-                                 prec1 ? reinterpret_cast<float*>(at(ws, nl.r32)) : nullptr,
-                                 prec1 ? &h->absmax_r : nullptr, s));
+        if (need_rT || prec1)
+            HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, need_rT ? rT : nullptr,
+                                     prec1 ? reinterpret_cast<float*>(at(ws, nl.r32)) : nullptr,
+                                     prec1 ? &h->absmax_r : nullptr, s));
         if (prec1 && p->kind == EAP_ERP)
             HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total,
                                  reinterpret_cast<float*>(at(ws, nl.r32b)), s));
+    } else if (need_rT && effective_kind(p) == EAP_CDTW && nr >= kDirectReadMinCandidates) {
+        // an earlier call with LB_Keogh over this large set made no interleaved copy
+        HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, rT, nullptr, nullptr, s));
     }
     unsigned long long* best = reinterpret_cast<unsigned long long*>(at(ws, nl.best));
     int32_t* seed = reinterpret_cast<int32_t*>(at(ws, nl.seed));
@@ -756,9 +771,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         return EAP_OK;
     }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
-    const bool lbk = effective_kind(p) == EAP_CDTW && !(o && (o->flags & 16));
     double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
-    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
+    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, direct ? r : nullptr, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env)) : nullptr, lb, s));
     a.lb = lb;
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, part, s));

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void interleave_kernel(const double* rv, const
     for (int ii = 0; ii < 16; ++ii) {
         const int k = k0 + w + 4 * ii;
         const int64_t b = b0 + lane;
-        if (k < lmax && b < nr) rT[(int64_t)k * nr + b] = tile[lane][w + 4 * ii];
+        if (rT && k < lmax && b < nr) rT[(int64_t)k * nr + b] = tile[lane][w + 4 * ii];
     }
     if (absmax) {
         for (int s = 32; s > 0; s >>= 1) m = fmax(m, __shfl_xor(m, s));
@@ -376,12 +376,16 @@ __global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qof
 
 // CDTW: the path bound and LB_Keogh of QT queries against 256 candidates per
 // block, in one pass over each candidate's values (read once for all QT
-// queries; query values and envelopes by scalar loads).  Each bound adds its
+// queries; query values and envelopes by scalar loads).  The candidates come
+// from the interleaved copy rT (coalesced), or with rv != NULL from their own
+// layout: a lane takes 8 consecutive values of its candidate per chunk, which
+// for very large candidate sets costs less than building the copy.  Each bound adds its
 // terms in path order (the diagonal, then the longer series' tail), like
 // path_ub_acc; (a - b)^2 and (b - a)^2 are the same double.
 template <int QT>
 __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const double* qv, const int64_t* qoff,
-                                                         const double* rT, const int64_t* roff, int64_t ld,
+                                                         const double* rv, const double* rT, const int64_t* roff,
+                                                         int64_t ld,
                                                          const double* env_up, const double* env_lo,
                                                          const double* env_q, double* lb, double* ub) {
     // Every lane of a wave reads the same query value and envelope entries:
@@ -395,7 +399,8 @@ __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const doub
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = b < nB;
     const int64_t bb = live ? b : nB - 1;   // lanes past the end read the last candidate, store nothing
-    const int lr = (int)(roff[bb + 1] - roff[bb]);
+    const int64_t ro = roff[bb];
+    const int lr = (int)(roff[bb + 1] - ro);
     int lw = lr, ln = lr;   // the wave's longest and shortest candidates: the column loops are uniform
     for (int o = 32; o > 0; o >>= 1) {
         lw = max(lw, __shfl_xor(lw, o));
@@ -435,7 +440,8 @@ __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const doub
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 in[u] = !MASK || j0 + u < lr;
-                xv[u] = rT[(int64_t)(in[u] ? j0 + u : lr - 1) * nB + bb];
+                const int jj = in[u] ? j0 + u : lr - 1;
+                xv[u] = rv ? rv[ro + jj] : rT[(int64_t)jj * nB + bb];
             }
 #pragma unroll
             for (int t = 0; t < QT; ++t) {
@@ -466,7 +472,7 @@ __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const doub
         if (nqt == QT) sweep(std::true_type{});
         else sweep(std::false_type{});
         // queries longer than the candidate: their tail against its last value
-        const double xl = rT[(int64_t)(lr - 1) * nB + bb];
+        const double xl = rv ? rv[ro + lr - 1] : rT[(int64_t)(lr - 1) * nB + bb];
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
             if (t >= nqt) continue;
@@ -1026,8 +1032,9 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
     return hipGetLastError();
 }
 
-hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const int64_t* roff,
-                        int lq_max, int lr_max, double* rT, double* ub, double* env, double* lb, hipStream_t s) {
+hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
+                        const int64_t* roff, int lq_max, int lr_max, const double* rT, double* ub, double* env,
+                        double* lb, hipStream_t s) {
     if (kind == CDTW && lb && env) {
         // CDTW: the query envelopes (upper, lower, and the query extended by
         // its last value: three arrays of env_stride doubles), then bound and
@@ -1050,7 +1057,7 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
                 break;
             }
         const dim3 gq((unsigned)bx, (unsigned)std::min<int64_t>((a.nA + qt - 1) / qt, 65535));
-#define EAP_UBLB(QT) hipLaunchKernelGGL(ub_lb_cdtw_kernel<QT>, gq, dim3(256), 0, s, a, qv, qoff, rT, roff, ld, \
+#define EAP_UBLB(QT) hipLaunchKernelGGL(ub_lb_cdtw_kernel<QT>, gq, dim3(256), 0, s, a, qv, qoff, rv, rT, roff, ld, \
                                         up, lo, qx, lb, ub)
         switch (qt) {
         case 16: EAP_UBLB(16); break;

@@ -100,7 +100,8 @@ hipError_t launch_znorm(const double* v, const int64_t* off, int64_t n, double* 
 hipError_t launch_derivative(const double* v, const int64_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_subseq_windows(const double* x, int64_t nw, int m, double* out, hipStream_t s);
 // Candidates interleaved for coalesced reads: rT[k * nr + b] = value k of
-// candidate b (0 past its end), k < lr_max.  With r32 also the FP32 copy
+// candidate b (0 past its end), k < lr_max (rT may be NULL when only the
+// following are wanted).  With r32 also the FP32 copy
 // (same layout as rv), with absmax also the largest |x| (atomicMax on the
 // bit pattern of a non-negative double; clear it first).
 hipError_t launch_interleave(const double* rv, const int64_t* roff, int64_t nr, int lr_max, double* rT, float* r32,
@@ -115,9 +116,11 @@ inline int64_t env_ld(int64_t lr_max) { return (lr_max + 7) & ~(int64_t)7; }
 inline int64_t env_stride(int64_t nq, int64_t lr_max) { return nq * env_ld(lr_max); }
 // Path upper bound of every (query, candidate) pair from rT (launch_interleave);
 // for CDTW with env (3 x env_stride doubles) and lb also the query envelopes
-// and LB_Keogh.
-hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const int64_t* roff,
-                        int lq_max, int lr_max, double* rT, double* ub, double* env, double* lb, hipStream_t s);
+// and LB_Keogh, reading the candidates from rT, or with rv != NULL from rv /
+// roff in their own layout (rT unused).
+hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
+                        const int64_t* roff, int lq_max, int lr_max, const double* rT, double* ub, double* env,
+                        double* lb, hipStream_t s);
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s);
 // Scratch of the split per-query scans (seed, argmin, screen filter) for a

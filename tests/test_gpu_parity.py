@@ -575,6 +575,44 @@ def test_candidates_prepared_flag(torch_dev, orc, kind, precision):
         oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
         assert np.array_equal(gi.cpu().numpy(), oi), i
         assert np.array_equal(gd.cpu().numpy(), od), i
+    if kind == "cdtw":
+        # the LB_Keogh calls above left no interleaved copy of the candidates;
+        # a call without the bound that reuses the candidates rebuilds it
+        qv, qo = packed[1]
+        log(f"candidates prepared {kind} precision={precision} without LB_Keogh")
+        gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, r, ro, p, precision=precision, ws=ws,
+                            flags=eap.FLAG_CANDIDATES | eap.FLAG_NO_LB)
+        oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+        assert np.array_equal(gi.cpu().numpy(), oi)
+        assert np.array_equal(gd.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cdtw_very_many_candidates_read_in_place(torch_dev, orc, precision):
+    """2^18 + 5 short ragged candidates (lengths 8..16): the CDTW bound + LB
+    kernel reads them in their own layout; then, on the same workspace with
+    the candidates prepared, a search without LB_Keogh (which rebuilds the
+    interleaved copy) and one with it.  Every result is the oracle's."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(123 + precision)
+    nr = (1 << 18) + 5
+    lens = rng.integers(8, 17, nr)
+    ro = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    rv = rng.standard_normal(int(ro[-1]))
+    qs = [rng.standard_normal(int(L)) for L in (12, 9, 16)]
+    qs[1] = rv[ro[nr - 2]:ro[nr - 1]].copy()        # an exact match near the end
+    qv, qo = synth.pack(qs)
+    p = dict(kind="cdtw", window_ratio=0.25)
+    r = to_dev(torch, dev, rv)
+    q = to_dev(torch, dev, qv)
+    ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, p, precision=1), dev)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "eap")
+    assert oi[1] == nr - 2 and od[1] == 0.0
+    for flags in (0, eap.FLAG_CANDIDATES | eap.FLAG_NO_LB, eap.FLAG_CANDIDATES):
+        log(f"cdtw very many candidates precision={precision} flags={flags}")
+        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, ws=ws, flags=flags)
+        assert np.array_equal(gi.cpu().numpy(), oi), flags
+        assert np.array_equal(gd.cpu().numpy(), od), flags
 
 
 @pytest.mark.parametrize("precision", [0, 1])
