@@ -1,27 +1,28 @@
 """Benchmark: 1-NN search with the six elastic distances on one MI355X.
 
-One step is the whole hot path over one batch: for each of DTW, CDTW, WDTW,
-ERP, MSM and TWE, the 1-NN of 500 queries among 500 candidates (length 512,
-five time-warped sine classes, z-normalised; the paper's NN-classification
-workload at UCR scale, synthetic and seeded).  Inputs are resident in HBM
-before the timed region.  By default the six searches run pipelined: each on
-one of three streams (round-robin), their main sweeps one at a time (each
-waits for the previous search's main sweep through an event), their bound,
-seed, recheck and argmin stages overlapping the neighbouring main sweeps
-(--schedule serial: one after the other on one stream).
+One step is the whole hot path over one batch.  The default workload (4) is
+batched 1-NN search with uneven lengths: for each of DTW, CDTW, WDTW, ERP, MSM
+and TWE, the 1-NN of 1,000 queries among 10,000 candidates whose lengths are
+uniform in 64..2048 (five time-warped sine classes, z-normalised; synthetic,
+seeded stand-ins for the paper's NN classification over UCR-shaped data),
+each search an FP32 screening sweep with an FP64 recheck of its near-ties
+(margin 1e-4 relative plus a certified rounding bound), the six searches
+captured in one HIP graph: a step is one graph launch.  Inputs are resident
+in HBM before the timed region.  --workload 2 runs 500 x 500 series of length
+512 (six pipelined searches per step), 3 all-pairs matrices, 5 a request
+server, 6 sub-sequence search.
 
 Reported (one JSON line on stdout):
-  value        effective GCUPS: DP cells of the plain full programme (band
-               cells for CDTW) of all six searches, divided by the step time.
-               By default each search is the FP32 screen + FP64 recheck, whose
-               NN answers equal the FP64 sweep's bit for bit (--precision 0:
-               FP64 sweep only)
-  queries_per_s  1-NN searches per second (500 queries x 6 distances per step)
-  plain_gpu_dp   the same searches with the plain full DP on the GPU
+  value        effective GCUPS: DP cells of the plain full programme (cells in
+               the window for CDTW, none for pairs the window forbids) of all
+               six searches, divided by the step time
+  queries_per_s  1-NN searches per second (queries x six distances per step)
+  plain_gpu_dp   the same searches with the plain full FP64 DP on the GPU
   roofline     the dominant sweep kernel: executed cells per launch over its
-               mean launch time (HIP events), against the VALU cell-update
-               peak for that distance
-  cpu_baseline the CPU oracle (EAPruned NN) on a bounded sample, host threads
+               mean launch time (HIP events on its stream), against the VALU
+               cell-update peak for that distance and precision
+  cpu_baseline the CPU oracle on bounded samples (EAPruned NN on all host
+               threads, its full DP, one thread), NN answers compared
 """
 import argparse
 import json
@@ -47,6 +48,10 @@ LANE_OPS_PER_S_F32 = 2 * LANE_OPS_PER_S
 OPS_PER_CELL = {"dtw": 5, "cdtw": 5, "wdtw": 6, "erp": 6, "msm": 16, "twe": 8}
 OPS_PER_CELL_F32 = {"dtw": 4, "cdtw": 4, "wdtw": 5, "erp": 5, "msm": 9, "twe": 7}
 HBM_PEAK_GBS = 8000.0
+ROOFLINE_CONVENTION = ("achieved = executed cells of the dominant kernel's launch / its launch time; peak = VALU "
+                       "lane-op rate / minimal lane-ops per cell of its distance and precision, with the lane-op "
+                       "rate 39.3e12/s for FP64 (78.6 TFLOP/s / 2: min-plus cells have no FMA) and 78.6e12/s for "
+                       "FP32 (157.3 TFLOP/s / 2)")
 
 
 def band_cells(li, co, w):
@@ -114,18 +119,31 @@ def swept_kind(kind, p):
     return kind
 
 
-def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist, derivative=False):
-    """The CPU oracle's EAPruned NN (Alg. 1 + Alg. 5) on the first nq_sample
-    queries against all candidates, every host thread; beside it the oracle's
-    full DP on at most 64 of those queries (every thread) and EAPruned on the
-    first query, one thread.  derivative: on the oracle's derivative series
-    of the same inputs (the transform itself untimed)."""
+def cpu_baseline(wl, kinds, gpu_idx, gpu_dist, eap_q, dp_q, dp_r=None, one_q=1, one_r=None, derivative=False):
+    """The CPU oracle timed on the host, on bounded samples of the workload:
+      value          EAPruned NN (Alg. 1 + Alg. 5) of the first eap_q queries
+                     against every candidate, all host threads, as effective
+                     GCUPS (dense cells of the sample / seconds); its NN
+                     answers compared with the GPU's (nn_identical_to_gpu)
+      full_dp_gcups  the oracle's full DP of the first dp_q queries against the
+                     first dp_r candidates (all of them when None), all threads
+      one_core_gcups EAPruned NN of the first one_q queries against the first
+                     one_r candidates, one thread
+    derivative: on the oracle's derivative series of the same inputs (the
+    transform itself untimed)."""
     from oracle import oracle as orc
     if derivative:
         wl = dict(wl, queries=orc.derivative(wl["queries"], wl["query_off"]),
                   refs=orc.derivative(wl["refs"], wl["ref_off"]))
-    qo = wl["query_off"][: nq_sample + 1]
-    qv = wl["queries"][: qo[-1]]
+    nr = len(wl["ref_off"]) - 1
+    dp_r = nr if dp_r is None else min(dp_r, nr)
+    one_r = nr if one_r is None else min(one_r, nr)
+
+    def head(off, vals, n):
+        o = off[: n + 1]
+        return vals[: o[-1]], o
+
+    qv, qo = head(wl["query_off"], wl["queries"], eap_q)
     cells = 0
     secs = 0.0
     match = True
@@ -135,26 +153,23 @@ def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist, derivative=False):
         idx, dist, _ = orc.nn1(p, qv, qo, wl["refs"], wl["ref_off"], "eap")
         secs += time.perf_counter() - t0
         cells += dense_cells(kind, p, qo, wl["ref_off"])
-        match &= bool(np.array_equal(idx, gpu_idx[kind][:nq_sample]) and np.array_equal(dist, gpu_dist[kind][:nq_sample]))
-    # up to 64 queries by the oracle's full DP (every thread), and the first
-    # query by EAPruned on one thread
-    nd = min(nq_sample, 64)
-    do = wl["query_off"][: nd + 1]
-    dv = wl["queries"][: do[-1]]
+        match &= bool(np.array_equal(idx, gpu_idx[kind][:eap_q]) and np.array_equal(dist, gpu_dist[kind][:eap_q]))
+    dv, do = head(wl["query_off"], wl["queries"], dp_q)
+    rv, ro = head(wl["ref_off"], wl["refs"], dp_r)
+    v1, o1 = head(wl["query_off"], wl["queries"], one_q)
+    r1, ro1 = head(wl["ref_off"], wl["refs"], one_r)
     sd = dcells = 0.0
-    q1o = wl["query_off"][:2]
-    q1 = wl["queries"][: q1o[-1]]
     c1 = s1 = 0.0
     for kind in kinds:
         p = wl["params"][kind]
         t0 = time.perf_counter()
-        orc.nn1(p, dv, do, wl["refs"], wl["ref_off"], "dp")
+        orc.nn1(p, dv, do, rv, ro, "dp")
         sd += time.perf_counter() - t0
-        dcells += dense_cells(kind, p, do, wl["ref_off"])
+        dcells += dense_cells(kind, p, do, ro)
         t0 = time.perf_counter()
-        orc.nn1(p, q1, q1o, wl["refs"], wl["ref_off"], "eap", nthreads=1)
+        orc.nn1(p, v1, o1, r1, ro1, "eap", nthreads=1)
         s1 += time.perf_counter() - t0
-        c1 += dense_cells(kind, p, q1o, wl["ref_off"])
+        c1 += dense_cells(kind, p, o1, ro1)
     model = ""
     try:
         model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
@@ -162,13 +177,16 @@ def cpu_baseline(wl, kinds, nq_sample, gpu_idx, gpu_dist, derivative=False):
         pass
     return dict(value=cells / secs / 1e9, unit="GCUPS", cores=orc.num_threads(), kind="oracle",
                 host=dict(cpu_model=model, logical_cpus=os.cpu_count()),
-                sample=f"EAPruned NN of the first {nq_sample} queries against all {len(wl['ref_off']) - 1} "
-                       f"candidates, {len(kinds)} distances, {secs:.1f} s",
+                sample=f"EAPruned NN of the first {eap_q} queries against all {nr} candidates, {len(kinds)} "
+                       f"distances, {secs:.1f} s on {orc.num_threads()} threads",
+                seconds=secs,
                 nn_identical_to_gpu=match,
                 full_dp_gcups=dcells / sd / 1e9,
-                full_dp_sample=f"full DP of the first {nd} queries against all candidates",
+                full_dp_sample=f"full DP of the first {dp_q} queries against the first {dp_r} candidates, "
+                               f"{len(kinds)} distances, {sd:.1f} s",
                 one_core_gcups=c1 / s1 / 1e9,
-                one_core_sample="EAPruned NN of the first query, one thread")
+                one_core_sample=f"EAPruned NN of the first {one_q} queries against the first {one_r} "
+                                f"candidates, {len(kinds)} distances, one thread, {s1:.1f} s")
 
 
 def run_pairwise(args, torch, eap, synth):
@@ -274,9 +292,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kinds", default=ap_default_kinds)
-    ap.add_argument("--cpu-queries", type=int, default=500,
-                    help="queries in the CPU-oracle EAPruned sample (0: skip; about 5 s for all 500 of the "
-                         "default workload on 16 threads)")
+    ap.add_argument("--cpu-queries", type=int, default=None,
+                    help="queries in the CPU-oracle EAPruned sample, each against every candidate (0: skip; "
+                         "default 16 for workload 4, 500 for workload 2)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
     ap.add_argument("--ablation", action="store_true",
                     help="workloads 2 and 6: also time the search with its parts switched off one at a time "
@@ -297,12 +315,16 @@ def main():
                     help="also time the other precision's step (outside the timed region)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 3 plain device copies of this many MiB (HBM counter calibration) and exit")
-    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5, 6),
-                    help="2: the benchmark (500 x 500, length 512); 3: all-pairs matrix; 4: batched uneven "
-                         "lengths, graph launch; 5: served requests; 6: sub-sequence search")
+    ap.add_argument("--workload", type=int, default=4, choices=(2, 3, 4, 5, 6),
+                    help="4 (default): 1-NN of 1,000 queries among 10,000 candidates of uneven lengths "
+                         "(64..2048), six distances, FP32 screen + FP64 recheck, one graph launch per step; "
+                         "2: 500 x 500, length 512; 3: all-pairs matrix; 5: served requests; 6: sub-sequence "
+                         "search")
     ap.add_argument("--refs", type=int, default=0, help="workloads 3-6: series / candidate / window count (0: the full workload)")
     ap.add_argument("--queries", type=int, default=0, help="workloads 4-6: query count (0: the full workload)")
     args = ap.parse_args()
+    if args.cpu_queries is None:
+        args.cpu_queries = 16 if args.workload == 4 else 500
     if args.precision is None:
         args.precision = 0 if args.workload == 6 else 1
     if args.copy_mib > 0:
@@ -549,7 +571,8 @@ def main():
 
     cpu = None
     if args.cpu_queries > 0:
-        cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, nq), gpu_idx, gpu_dist, derivative=args.derivative)
+        cpu = cpu_baseline(wl, kinds, gpu_idx, gpu_dist, eap_q=min(args.cpu_queries, nq), dp_q=min(args.cpu_queries, nq, 64),
+                           derivative=args.derivative)
 
     total_dense = sum(dense.values())
     line = dict(
@@ -651,12 +674,17 @@ def run_batched(args, torch, eap, synth):
     same = all(torch.equal(outs[k][i], want[k][i]) for k in kinds for i in range(3))
     graph.close()
 
-    # per-distance breakdown and the dominant kernel: one eager profiled step
+    # per-distance breakdown and the dominant kernel: eager steps right after the
+    # timed graph launches, every sweep launch bracketed by HIP events on the
+    # stream it runs on (the same kernels, inputs and launch shapes the graph
+    # replays; the graph itself cannot carry timing events)
+    prof_steps = 2
     for k in kinds:
         eap.reset_counters(ws[k], stream=s)
     eap.profile_take()
     eap.profile_enable(True)
-    eager()
+    for _ in range(prof_steps):
+        eager()
     s.synchronize()
     eap.profile_enable(False)
     prof = eap.profile_take()
@@ -665,23 +693,34 @@ def run_batched(args, torch, eap, synth):
     for k in kinds:
         sk = swept_kind(k, P[k])
         main = [x for x in prof if x["kind"] == sk and x["stage"] == 2]
-        per[k] = dict(sweep_ms=sum(x["ms"] for x in prof if x["kind"] == sk),
-                      main_sweep_ms=sum(x["ms"] for x in main),
-                      main_kernel=(kernel_label(main[0]) if main else None),
-                      main_fp32=bool(main[0]["fp32"]) if main else False,
-                      main_cells=counters[k]["stage_cells"][2], dense_cells=dense[k],
-                      executed_fraction=counters[k]["cells"] / dense[k] if dense[k] else None,
-                      fp64_rechecks=counters[k]["rechecks"],
+        mc = counters[k]["stage_cells"][2] / prof_steps
+        mms = sum(x["ms"] for x in main) / prof_steps
+        fp32 = bool(main[0]["fp32"]) if main else False
+        ops = (OPS_PER_CELL_F32 if fp32 else OPS_PER_CELL)[sk]
+        peak = (LANE_OPS_PER_S_F32 if fp32 else LANE_OPS_PER_S) / ops / 1e9
+        per[k] = dict(sweep_ms=sum(x["ms"] for x in prof if x["kind"] == sk) / prof_steps,
+                      main_sweep_ms=mms, main_launches=len(main) // prof_steps,
+                      main_kernel=(kernel_label(main[0]) if main else None), main_fp32=fp32,
+                      main_cells=mc, dense_cells=dense[k],
+                      main_gcups=(mc / (mms * 1e-3) / 1e9) if mms else None, main_peak_gcups=peak,
+                      main_frac=(mc / (mms * 1e-3) / 1e9 / peak) if mms else None,
+                      executed_fraction=counters[k]["cells"] / prof_steps / dense[k] if dense[k] else None,
+                      fp64_rechecks=counters[k]["rechecks"] / prof_steps,
+                      lb_pruned=counters[k]["lb_pruned"] / prof_steps,
                       nn_accuracy=float(np.mean(outs[k][2].cpu().numpy() == wl["query_labels"])))
     dom = max(kinds, key=lambda k: per[k]["main_sweep_ms"])
     d = per[dom]
-    ops = (OPS_PER_CELL_F32 if d["main_fp32"] else OPS_PER_CELL)[dom]
-    peak = (LANE_OPS_PER_S_F32 if d["main_fp32"] else LANE_OPS_PER_S) / ops / 1e9
-    achieved = d["main_cells"] / (d["main_sweep_ms"] * 1e-3) / 1e9
-    roofline = dict(bound="alu", achieved=achieved, peak=peak, unit="GCUPS", frac=achieved / peak, traffic=None,
-                    kernel=f"{d['main_kernel']} sweep, {dom.upper()} main stage, "
-                           f"{'fp32' if d['main_fp32'] else 'fp64'}", ops_per_cell=ops,
-                    launch_ms=d["main_sweep_ms"], note="from one eager profiled step after the timed graph launches")
+    ops = (OPS_PER_CELL_F32 if d["main_fp32"] else OPS_PER_CELL)[swept_kind(dom, P[dom])]
+    kernel = f"{d['main_kernel']} sweep, {swept_kind(dom, P[dom]).upper()} main stage, " \
+             f"{'fp32' if d['main_fp32'] else 'fp64'}"
+    launch_ms = d["main_sweep_ms"] / max(d["main_launches"], 1)
+    roofline = dict(bound="alu", achieved=d["main_gcups"], peak=d["main_peak_gcups"], unit="GCUPS",
+                    frac=d["main_frac"], traffic=None, kernel=kernel, ops_per_cell=ops, launch_ms=launch_ms,
+                    cells_per_launch=d["main_cells"] / max(d["main_launches"], 1),
+                    convention=ROOFLINE_CONVENTION,
+                    note=f"kernel time: mean of {prof_steps} eager steps right after the timed graph launches, "
+                         "HIP events on the launch stream")
+    roofline["traffic"], roofline["traffic_note"] = hbm_traffic(kernel)
 
     # plain FP64 DP on the GPU for the first queries against every candidate,
     # scaled to the whole workload by dense cells
@@ -712,7 +751,8 @@ def run_batched(args, torch, eap, synth):
     if args.cpu_queries > 0:
         gi = {k: outs[k][0].cpu().numpy() for k in kinds}
         gd = {k: outs[k][1].cpu().numpy() for k in kinds}
-        cpu = cpu_baseline(wl, kinds, min(args.cpu_queries, 2, nq), gi, gd)
+        cpu = cpu_baseline(wl, kinds, gi, gd, eap_q=min(args.cpu_queries, nq), dp_q=min(2, nq), dp_r=1000,
+                           one_q=1, one_r=2000)
 
     total = sum(dense.values())
     print(json.dumps(dict(
@@ -720,9 +760,10 @@ def run_batched(args, torch, eap, synth):
         warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f32+f64", data="synthetic",
         config=dict(workload=f"batched uneven lengths: 1-NN of {nq} queries among {nr} candidates, lengths "
-                             "uniform in [64, 2048], 5 warped-sine classes, six distances, FP32 screen + FP64 "
-                             "recheck, one HIP graph launch per step", queries=nq, candidates=nr,
-                    distances=kinds),
+                             "uniform in [64, 2048], 5 warped-sine classes, six distances (CDTW w=10%, WDTW "
+                             "g=0.05, ERP gap=0, MSM c=0.5, TWE nu=0.001 lambda=1), FP32 screen + FP64 recheck "
+                             "(margin 1e-4 relative), one HIP graph launch per step", queries=nq, candidates=nr,
+                    lengths=[64, 2048], distances=kinds, precision="fp32 screen + fp64 recheck"),
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)), step_ms_p99=float(np.percentile(step_ms, 99)),
         graph_results_identical_to_eager=same, tuning=tuning, per_distance=per, plain_gpu_dp=plain,
@@ -918,13 +959,10 @@ def run_served(args, torch, eap, synth):
 
 
 def _source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2102_05221_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
+    """Hash of the library sources the committed counter summaries must match
+    (the one the build embeds in libeap.so)."""
+    from paper_2102_05221_amd import srchash
+    return srchash.source_hash()
 
 
 if __name__ == "__main__":

@@ -360,6 +360,11 @@ const char* eap_last_error(void);
 /* Library version string. */
 const char* eap_version(void);
 
+/* Content hash (16 hex digits) of the sources the library was built from;
+ * the Python binding refuses a library whose hash differs from the sources
+ * beside it, so a stale build is never used silently. */
+const char* eap_source_hash(void);
+
 #ifdef __cplusplus
 }
 #endif

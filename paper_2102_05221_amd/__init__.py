@@ -98,6 +98,13 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2102_05221_amd.build` "
                                "(there is no CPU fallback)")
         L = ctypes.CDLL(LIB_PATH)
+        L.eap_source_hash.restype = ctypes.c_char_p
+        L.eap_source_hash.argtypes = []
+        from . import srchash
+        built, here = L.eap_source_hash().decode(), srchash.source_hash()
+        if built != here:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, sources {here}): "
+                               "rebuild it with `python -m paper_2102_05221_amd.build`")
         L.eap_last_error.restype = ctypes.c_char_p
         L.eap_version.restype = ctypes.c_char_p
         L.eap_distance_workspace.restype = _sz
@@ -461,7 +468,7 @@ def subseq_search(query, series, p, precision: int = 0, stream=None, m: int = 0)
     import torch
     m = int(m) if m else query.numel()
     if m < 1 or query.numel() % m:
-        raise EapError(f"query length {query.numel()} is not a multiple of m = {m}")
+        raise ValueError(f"query length {query.numel()} is not a multiple of m = {m}")
     nq = query.numel() // m
     q_off = np.arange(nq + 1, dtype=np.int64) * m
     zq = znorm(query, q_off, stream=stream)

@@ -9,6 +9,12 @@ import os
 import subprocess
 import sys
 
+try:
+    from . import srchash
+except ImportError:   # run as a script
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_2102_05221_amd import srchash
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
@@ -28,10 +34,12 @@ SOURCES = ["eap_rows.hip", "eap_band.hip", "eap_aux.hip", "eap_api.cpp", "eap_se
 NO_NANS = {"eap_rows.hip", "eap_band.hip"}
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, digest: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
     extra = ["-fno-honor-nans"] if src in NO_NANS else []
+    if src == "eap_api.cpp":   # eap_source_hash(): the sources this library was built from
+        extra.append(f'-DEAP_SOURCE_HASH="{digest}"')
     cmd = ["hipcc", *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -45,9 +53,10 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    digest = srchash.source_hash()
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, digest), SOURCES))
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

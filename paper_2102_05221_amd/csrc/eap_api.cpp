@@ -140,10 +140,14 @@ constexpr int kClearedWords = (int)(offsetof(Header, absmax_r) / 8) - kCounterWo
 // WDTW: G[m] = 1 / (1 + exp(-g * (m / 2))) for m = 2k - L in [-Lmax, 2 Lmax]; the
 // weight of |i-j| = k for longer length L is G[2k - L] (eq. WDTW with w_max = 1:
 // (double)k - (double)L / 2 equals m / 2 exactly).
+int64_t wdtw_table_len(int64_t lmax) { return 3 * lmax + 1; }
+void wdtw_fill(double g, int64_t lmax, double* t) {
+    for (int64_t m = -lmax; m <= 2 * lmax; ++m) t[(size_t)(m + lmax)] = 1.0 / (1.0 + std::exp(-g * ((double)m / 2.0)));
+}
 void wdtw_table(double g, int64_t lmax, std::vector<double>& t, int& off) {
     off = (int)lmax;
-    t.resize((size_t)(3 * lmax + 1));
-    for (int64_t m = -lmax; m <= 2 * lmax; ++m) t[(size_t)(m + lmax)] = 1.0 / (1.0 + std::exp(-g * ((double)m / 2.0)));
+    t.resize((size_t)wdtw_table_len(lmax));
+    wdtw_fill(g, lmax, t.data());
 }
 
 // TWE: nu * (2|k|) for k = j - i in [-Lmax, Lmax + 1024] (eq. TWECost with tau_i = i).
@@ -153,12 +157,13 @@ void wdtw_table(double g, int64_t lmax, std::vector<double>& t, int& off) {
 // L + G + 2K and first columns up to L + W, d stays within
 // [-(lmax + G + 3K), lmax + W + G + K + C] = [-(lmax + 160), lmax + 1136] for
 // G <= 64, K <= 32, C <= 16, W <= 1024, inside the table's range.
+constexpr int64_t kTweLo = 256, kTweHi = 1280;
+int64_t twe_table_len(int64_t lmax) { return 2 * lmax + kTweLo + kTweHi + 1; }
 void twe_table(double nu, int64_t lmax, std::vector<double>& t, int& off) {
-    constexpr int64_t lo = 256, hi = 1280;
-    off = (int)(lmax + lo);
-    t.resize((size_t)(2 * lmax + lo + hi + 1));
-    for (int64_t k = -(lmax + lo); k <= lmax + hi; ++k)
-        t[(size_t)(k + lmax + lo)] = nu * (double)(2 * (k < 0 ? -k : k));
+    off = (int)(lmax + kTweLo);
+    t.resize((size_t)twe_table_len(lmax));
+    for (int64_t k = -(lmax + kTweLo); k <= lmax + kTweHi; ++k)
+        t[(size_t)(k + lmax + kTweLo)] = nu * (double)(2 * (k < 0 ? -k : k));
 }
 
 // Pinned staging for host-to-device copies: a ring of buffers, each reused
@@ -357,26 +362,35 @@ SweepArgs base_args(const eap_params* p) {
 // Device regions shared by the drivers for one (set A, set B) problem.
 struct Common {
     size_t hdr = 0, offA = 0, offB = 0, bordA = 0, bordB = 0, tab = 0, gtab = 0;
-    std::vector<double> tabv, gtabv;
-    int tab_off = 0, gtab_off = 0;
+    std::vector<double> tabv, gtabv;   // host copies (empty when the tables are not built on the host)
+    int tab_off = 0, gtab_off = 0, tab_len = 0, gtab_len = 0;
+    int64_t lmax = 0;
 };
 
-void plan_common(Layout& L, Common& c, const eap_params* p, const SetInfo& A, const SetInfo* B) {
+// Region offsets of the common part; with build_tables the TWE / WDTW tables
+// are also built on the host (for upload), else only their places are taken.
+void plan_common(Layout& L, Common& c, const eap_params* p, const SetInfo& A, const SetInfo* B,
+                 bool build_tables = true) {
     c.hdr = L.take(kHeaderBytes);
     c.offA = L.take(sizeof(int64_t) * (size_t)(A.n + 1));
     if (B) c.offB = L.take(sizeof(int64_t) * (size_t)(B->n + 1));
     const int64_t lmax = std::max(A.maxlen, B ? B->maxlen : 0);
+    c.lmax = lmax;
     if (p->kind == EAP_ERP) {
         c.bordA = L.take(sizeof(double) * (size_t)A.total);
         if (B) c.bordB = L.take(sizeof(double) * (size_t)B->total);
     }
     if (p->kind == EAP_TWE) {
-        twe_table(p->nu, lmax, c.tabv, c.tab_off);
-        c.tab = L.take(sizeof(double) * c.tabv.size());
+        if (build_tables) twe_table(p->nu, lmax, c.tabv, c.tab_off);
+        c.tab_off = (int)(lmax + kTweLo);
+        c.tab_len = (int)twe_table_len(lmax);
+        c.tab = L.take(sizeof(double) * (size_t)c.tab_len);
     }
     if (p->kind == EAP_WDTW) {
-        wdtw_table(p->g, lmax, c.gtabv, c.gtab_off);
-        c.gtab = L.take(sizeof(double) * c.gtabv.size());
+        if (build_tables) wdtw_table(p->g, lmax, c.gtabv, c.gtab_off);
+        c.gtab_off = (int)lmax;
+        c.gtab_len = (int)wdtw_table_len(lmax);
+        c.gtab = L.take(sizeof(double) * (size_t)c.gtab_len);
     }
 }
 
@@ -421,14 +435,14 @@ eap_status setup_common(void* ws, const Common& c, const eap_params* p, const do
             return st;
         a.tab = reinterpret_cast<const double*>(at(ws, c.tab));
         a.tab_off = c.tab_off;
-        a.tab_len = (int)c.tabv.size();
+        a.tab_len = c.tab_len;
     }
     if (p->kind == EAP_WDTW) {
         if (!prepared && (st = upload(at(ws, c.gtab), c.gtabv.data(), sizeof(double) * c.gtabv.size(), s)) != EAP_OK)
             return st;
         a.gtab = reinterpret_cast<const double*>(at(ws, c.gtab));
         a.gtab_off = c.gtab_off;
-        a.gtab_len = (int)c.gtabv.size();
+        a.gtab_len = c.gtab_len;
     }
     Header* h = reinterpret_cast<Header*>(at(ws, c.hdr));
     a.counters = h->counters;
@@ -461,9 +475,11 @@ struct Profiler {
 Profiler g_prof;
 
 // One sweep launch (kernel A or B) over `n` work slots, counted under `stage`.
+// timed = false: never bracketed by profiling events (the call that makes no
+// allocation of any kind may not create them).
 eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, Header* h, int stage,
                  unsigned int* queue, const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s,
-                 bool fp32 = false) {
+                 bool fp32 = false, bool timed = true) {
     a.queue = queue;
     a.items = items;
     a.npairs = n;
@@ -477,7 +493,7 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
-    if (cap == hipStreamCaptureStatusNone) {
+    if (cap == hipStreamCaptureStatusNone && timed) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (g_prof.on) {
             e0 = g_prof.get();
@@ -539,15 +555,20 @@ extern "C" {
 
 const char* eap_last_error(void) { return g_err.c_str(); }
 
-const char* eap_version(void) { return "eap-mi355x 0.1 (gfx950)"; }
+const char* eap_version(void) { return "eap-mi355x 0.2 (gfx950)"; }
+
+#ifndef EAP_SOURCE_HASH
+#define EAP_SOURCE_HASH "unknown"
+#endif
+const char* eap_source_hash(void) { return EAP_SOURCE_HASH; }
 
 // ------------------------------------------------------------------ distance
 static void distance_layout(int64_t lx, int64_t ly, const eap_params* p, Layout& L, Common& c, size_t* ovf,
-                            size_t* edge) {
+                            size_t* edge, bool build_tables = true) {
     SetInfo A, B;
     A.n = 1; A.total = lx; A.maxlen = A.minlen = lx;
     B.n = 1; B.total = ly; B.maxlen = B.minlen = ly;
-    plan_common(L, c, p, A, &B);
+    plan_common(L, c, p, A, &B, build_tables);
     *ovf = L.take(sizeof(int32_t) * 8);
     *edge = L.take(edge_bytes(1, std::max(lx, ly), std::min(lx, ly)));
 }
@@ -635,12 +656,15 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
     c.offA = L.take(sizeof(int64_t) * (size_t)(Q.n + 1));
     if (p->kind == EAP_ERP) c.bordA = L.take(sizeof(double) * (size_t)Q.total);
     const int64_t lmax = std::max(Q.maxlen, R.maxlen);
+    c.lmax = lmax;
     if (p->kind == EAP_TWE) {
         twe_table(p->nu, lmax, c.tabv, c.tab_off);
+        c.tab_len = (int)c.tabv.size();
         c.tab = L.take(sizeof(double) * c.tabv.size());
     }
     if (p->kind == EAP_WDTW) {
         wdtw_table(p->g, lmax, c.gtabv, c.gtab_off);
+        c.gtab_len = (int)c.gtabv.size();
         c.gtab = L.take(sizeof(double) * c.gtabv.size());
     }
     nl.best = nl.L.take(sizeof(unsigned long long) * (size_t)Q.n);
