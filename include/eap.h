@@ -173,6 +173,22 @@ size_t eap_distance_workspace(int64_t lx, int64_t ly, const eap_params* p);
 eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly, const eap_params* p,
                         double cutoff, double* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Distance with cut-off that allocates nothing, for callers that cannot
+ * allocate device or pinned memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, result and
+ * errors as eap_distance, without the workspace: the scratch lives in a
+ * static device array of the library (2 MiB, one copy per GPU, held until the
+ * process ends; its device address is taken once per device, on the first
+ * call there).  The offsets, the TWE / WDTW table and the cut-off reach the
+ * device through kernel arguments, so no staging buffer or copy call is used,
+ * and no event is created.  Every call on one GPU shares that GPU's scratch,
+ * which keeps the last call's contents (the call clears what must start at
+ * zero): calls that overlap on one GPU - on two streams, or from two
+ * threads - race and must not be issued.  A layout larger than the scratch
+ * (impossible for lengths up to 2048) is EAP_EWORKSPACE. */
+eap_status eap_distance_noalloc(const double* x, int64_t lx, const double* y, int64_t ly, const eap_params* p,
+                                double cutoff, double* out, void* stream);
+
 /* 1-NN search (Alg. 1): for each query, the candidate with the smallest
  * distance, lowest index on ties (the strict '<' of Alg. 1).
  *  q, q_off, nq        queries (device values, host offsets), nq >= 1.

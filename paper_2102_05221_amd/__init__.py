@@ -17,7 +17,7 @@ import os
 
 import numpy as np
 
-__all__ = ["params", "distance", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
+__all__ = ["params", "distance", "distance_noalloc", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
            "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "FLAG_NO_LB", "derivative", "znorm", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
@@ -111,6 +111,8 @@ def lib():
         L.eap_distance_workspace.argtypes = [_i64, _i64, _pP]
         L.eap_distance.restype = ctypes.c_int
         L.eap_distance.argtypes = [_vp, _i64, _vp, _i64, _pP, _d, _vp, _vp, _sz, _vp]
+        L.eap_distance_noalloc.restype = ctypes.c_int
+        L.eap_distance_noalloc.argtypes = [_vp, _i64, _vp, _i64, _pP, _d, _vp, _vp]
         L.eap_nn1_workspace.restype = _sz
         L.eap_nn1_workspace.argtypes = [_pi64, _i64, _pi64, _i64, _pP, _pO]
         L.eap_nn1.restype = ctypes.c_int
@@ -252,6 +254,20 @@ def distance(x, y, p, cutoff: float = math.inf, ws=None, stream=None):
     out = torch.empty(1, dtype=torch.float64, device=x.device)
     _check(lib().eap_distance(x.data_ptr(), x.numel(), y.data_ptr(), y.numel(), ctypes.byref(p), float(cutoff),
                               out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, x.device)))
+    return out
+
+
+def distance_noalloc(x, y, p, cutoff: float = math.inf, out=None, stream=None):
+    """As distance(), through eap_distance_noalloc: the library's static
+    scratch instead of a workspace (calls on one GPU must not overlap)."""
+    import torch
+    _dev_f64(x, "x")
+    _dev_f64(y, "y")
+    p = _as_params(p)
+    out = torch.empty(1, dtype=torch.float64, device=x.device) if out is None else _dev_buf(out, 1, torch.float64,
+                                                                                              "out")
+    _check(lib().eap_distance_noalloc(x.data_ptr(), x.numel(), y.data_ptr(), y.numel(), ctypes.byref(p),
+                                      float(cutoff), out.data_ptr(), _stream(stream, x.device)))
     return out
 
 

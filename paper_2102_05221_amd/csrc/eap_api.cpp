@@ -550,6 +550,71 @@ eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, Head
 
 }  // namespace
 
+// ------------------------------------------- distance without allocation
+// Scratch of eap_distance_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Its largest layout
+// (two series of 2048 values: header, offsets, ERP borders or a distance
+// table, and the row sweep's strip edges for one block of 64 groups) is
+// about 1.2 MB.
+constexpr size_t kNoAllocScratchBytes = size_t(2) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+// Device address of `scratch` per device, taken once with that device current
+// (the array's name is only a host-side stand-in, not a device address).
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+
+eap_status scratch_ptr(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(EAP_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(EAP_EDEVICE, "no device address for the static scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return EAP_OK;
+}
+
+// n host words to dst through kernel arguments, kPutWords per launch.
+eap_status put_words(void* dst, const unsigned long long* src, int64_t n, hipStream_t s) {
+    for (int64_t o = 0; o < n; o += kPutWords) {
+        const int m = (int)std::min<int64_t>(kPutWords, n - o);
+        HIPCHK(launch_put_u64(static_cast<unsigned long long*>(dst) + o, src + o, m, s));
+    }
+    return EAP_OK;
+}
+
+// A per-diagonal table (TWE: nu * 2|k|; WDTW: the weights), built on the host
+// with the same expressions eap_distance uploads, a chunk at a time on the
+// stack, and delivered through kernel arguments.
+eap_status put_table(int kind, const eap_params* p, int64_t lmax, double* dst, hipStream_t s) {
+    const int64_t len = (kind == EAP_TWE) ? twe_table_len(lmax) : wdtw_table_len(lmax);
+    double buf[kPutWords];
+    for (int64_t o = 0; o < len; o += kPutWords) {
+        const int m = (int)std::min<int64_t>(kPutWords, len - o);
+        for (int x = 0; x < m; ++x) {
+            const int64_t e = o + x;
+            if (kind == EAP_TWE) {
+                const int64_t k = e - (lmax + kTweLo);
+                buf[x] = p->nu * (double)(2 * (k < 0 ? -k : k));
+            } else {
+                const int64_t mm = e - lmax;
+                buf[x] = 1.0 / (1.0 + std::exp(-p->g * ((double)mm / 2.0)));
+            }
+        }
+        unsigned long long w[kPutWords];
+        std::memcpy(w, buf, sizeof(double) * (size_t)m);
+        HIPCHK(launch_put_u64(reinterpret_cast<unsigned long long*>(dst + o), w, m, s));
+    }
+    return EAP_OK;
+}
+}  // namespace
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -614,6 +679,58 @@ eap_status eap_distance(const double* x, int64_t lx, const double* y, int64_t ly
     a.edge = edge_bytes(1, std::max(lx, ly), std::min(lx, ly)) ? at(ws, edge) : nullptr;
     a.edge_stride = std::max(lx, ly) + 1;
     return sweep(p, pl, pl.band, a, hdr_of(ws, c), 2, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s);
+}
+
+
+// ------------------------------------------- distance without allocation
+eap_status eap_distance_noalloc(const double* x, int64_t lx, const double* y, int64_t ly, const eap_params* p,
+                                double cutoff, double* out, void* stream) {
+    eap_status st;
+    if ((st = check_params(p)) != EAP_OK) return st;
+    if (!x || !y || !out) return fail(EAP_EINVAL, "NULL series or output");
+    if (lx < 1 || ly < 1) return fail(EAP_EINVAL, "series lengths must be >= 1");
+    if (lx > kMaxLen || ly > kMaxLen) return fail(EAP_EINVAL, "series longer than %lld are not supported", (long long)kMaxLen);
+    if (std::isnan(cutoff) || cutoff < 0) return fail(EAP_EINVAL, "cutoff must be >= 0 or +inf");
+    Layout L;
+    Common c;
+    size_t ovf, edge;
+    distance_layout(lx, ly, p, L, c, &ovf, &edge, /*build_tables=*/false);
+    if (L.off > kNoAllocScratchBytes)
+        return fail(EAP_EWORKSPACE, "eap_distance_noalloc needs %zu bytes of scratch; its static area holds %zu",
+                    L.off, kNoAllocScratchBytes);
+    void* ws = nullptr;
+    if ((st = scratch_ptr(&ws)) != EAP_OK) return st;
+    Plan pl;
+    if ((st = make_plan(p, lx, ly, std::llabs(lx - ly), false, &pl)) != EAP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // what eap_distance uploads from staging memory arrives here through
+    // kernel arguments: the offsets, the per-diagonal table and the cut-off
+    const unsigned long long offw[2][2] = {{0ull, (unsigned long long)lx}, {0ull, (unsigned long long)ly}};
+    if ((st = put_words(at(ws, c.offA), offw[0], 2, s)) != EAP_OK) return st;
+    if ((st = put_words(at(ws, c.offB), offw[1], 2, s)) != EAP_OK) return st;
+    if (p->kind == EAP_TWE || p->kind == EAP_WDTW) {
+        double* tab = reinterpret_cast<double*>(at(ws, p->kind == EAP_TWE ? c.tab : c.gtab));
+        if ((st = put_table(p->kind, p, c.lmax, tab, s)) != EAP_OK) return st;
+    }
+    const int64_t offa[2] = {0, lx}, offb[2] = {0, ly};
+    SweepArgs a = base_args(p);
+    SeriesPtrs SA, SB;
+    // prepared: nothing left to upload (queues are cleared by a fill kernel)
+    if ((st = setup_common(ws, c, p, x, offa, 1, y, offb, 1, s, a, SA, SB, /*prepared=*/true)) != EAP_OK) return st;
+    unsigned long long cw;
+    std::memcpy(&cw, &cutoff, sizeof cw);
+    if ((st = put_words(out, &cw, 1, s)) != EAP_OK) return st;
+    a.mode = PM_SINGLE;
+    a.nA = a.nB = 1;
+    a.pcut = out;
+    a.res = out;
+    a.band_half = pl.band_half;
+    a.ovf_items = reinterpret_cast<int32_t*>(at(ws, ovf));
+    a.ovf_count = &hdr_of(ws, c)->ovf_count[0];
+    a.edge = edge_bytes(1, std::max(lx, ly), std::min(lx, ly)) ? at(ws, edge) : nullptr;
+    a.edge_stride = std::max(lx, ly) + 1;
+    return sweep(p, pl, pl.band, a, hdr_of(ws, c), 2, &hdr_of(ws, c)->queues[0], nullptr, 1, SA, SB, s,
+                 /*fp32=*/false, /*timed=*/false);
 }
 
 // ---------------------------------------------------------------------- NN

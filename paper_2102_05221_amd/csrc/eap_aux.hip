@@ -130,6 +130,13 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, int
         p[x] = v;
 }
 
+// Host words delivered through the kernel's argument block (no staging
+// buffer, no copy call): dst[x] = w.w[x] for x < n <= kPutWords.
+__global__ void put_u64_kernel(unsigned long long* dst, int n, PutWords w) {
+    const int x = threadIdx.x;
+    if (x < n) dst[x] = w.w[x];
+}
+
 // Cost of the warping path (1,1), (2,2), .., (m,m) followed by straight moves
 // along the longer series (Section 4: any path bounds the optimum).  Every step
 // adds its term exactly as the recurrence would, so the value is >= the
@@ -966,6 +973,14 @@ hipError_t launch_to_f32(const double* v, int64_t n, float* out, hipStream_t s) 
 
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_u64(unsigned long long* dst, const unsigned long long* src, int n, hipStream_t s) {
+    if (n < 0 || n > kPutWords) return hipErrorInvalidValue;
+    PutWords w;
+    for (int x = 0; x < n; ++x) w.w[x] = src[x];
+    hipLaunchKernelGGL(put_u64_kernel, dim3(1), dim3(kPutWords), 0, s, dst, n, w);
     return hipGetLastError();
 }
 

@@ -133,6 +133,14 @@ hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b
 hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
                          double* out_dist, int32_t* out_label, double* part, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+// Up to kPutWords host words written to dst by one kernel whose argument
+// block carries them: a host-to-device transfer that needs no staging memory
+// and no copy call (the call that allocates nothing uses it).
+constexpr int kPutWords = 448;
+struct PutWords {
+    unsigned long long w[kPutWords];
+};
+hipError_t launch_put_u64(unsigned long long* dst, const unsigned long long* src, int n, hipStream_t s);
 hipError_t launch_absmax(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_lb_compact(const double* lb, const unsigned long long* best, const int32_t* seed,
                              const int64_t* qoff, const int64_t* roff, double ratio, int64_t nq, int64_t nr,

@@ -83,6 +83,25 @@ def test_distance_argument_errors(L):
     assert L.eap_distance(FAKE, 10, FAKE, 12, ctypes.byref(p), 1.0, FAKE, None, need, None) == eap.EAP_EWORKSPACE
 
 
+def test_distance_noalloc_argument_errors(L):
+    """The call without a workspace rejects the same arguments before it
+    touches the device."""
+    p = _p()
+    cases = [
+        (None, 10, FAKE, 12, p, 1.0, FAKE),
+        (FAKE, 10, FAKE, 12, p, 1.0, None),                    # NULL output
+        (FAKE, 0, FAKE, 12, p, 1.0, FAKE),
+        (FAKE, 10, FAKE, 12, p, float("nan"), FAKE),
+        (FAKE, 10, FAKE, 12, p, -1.0, FAKE),
+        (FAKE, 10, FAKE, 12, _p("cdtw", window_ratio=-0.1), 1.0, FAKE),
+        (FAKE, 10, FAKE, 12, _p("twe", lam=-1.0), 1.0, FAKE),
+        (FAKE, 10, FAKE, 2049, p, 1.0, FAKE),                  # longer than supported
+    ]
+    for x, lx, y, ly, pp, cut, out in cases:
+        assert L.eap_distance_noalloc(x, lx, y, ly, ctypes.byref(pp), cut, out, None) == eap.EAP_EINVAL, (lx, ly)
+        assert len(L.eap_last_error()) > 0
+
+
 def test_nn1_argument_errors(L):
     p = _p("msm", c=0.5)
     qo, ro = _off(5, 7), _off(4, 4, 9)
