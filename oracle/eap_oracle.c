@@ -19,9 +19,10 @@
  *                 the plain definition, O(L_S * L_T) memory.
  *   orc_brute     minimum over every monotone lattice path, enumerated
  *                 explicitly (the guarantees listed after eq. Common).
- *   orc_eap       EAPruned, Alg. 5 (Section 4.3), in the paper's stage order,
- *                 with a cell counter; the three readings this file takes
- *                 where the printed algorithm is incomplete are marked READING.
+ *   orc_eap       EAPruned (Section 4), each row evaluated over the interval
+ *                 of columns that the pruning rules of Sections 4.1-4.2 leave
+ *                 live, with a cell counter.
+ *   orc_eabase    EABase, Alg. 4: full rows, abandoned on a dead row.
  *   orc_ub        cost of the diagonal-then-straight warping path, an upper
  *                 bound usable as a prune-only cut-off (Section 4, intro).
  *   orc_nn1       NN search, Alg. 1 (strict '<', lowest index wins ties).
@@ -330,135 +331,201 @@ static void terms(const eap_ctx* e, int64_t i, int64_t j, double* canon, double*
     }
 }
 
-/* EAPruned (Alg. 5).  The shorter series goes on the columns ("co"), the
- * longer on the rows ("li").  Returns D(S,T) when D <= cutoff, else +inf.
- * A cell is alive when its value is <= cutoff; abandoning needs a value
- * > cutoff, so a pair whose distance equals the cut-off is returned exactly.
+/* Orientation shared by the cut-off variants: the shorter series on the
+ * columns, the longer on the rows (Section 2.4); the window; the WDTW
+ * weights.  Returns 0, or 1 when the window admits no path (result +inf),
+ * or -1 on a bad argument. */
+static int eap_setup(eap_ctx* e, int kind, const double* S, int64_t ls, const double* T, int64_t lt,
+                     const double* prm, double** W)
+{
+    e->kind = kind;
+    e->prm = prm;
+    if (ls >= lt) {
+        e->R = S; e->lr = ls; e->C = T; e->lc = lt;
+    } else {
+        e->R = T; e->lr = lt; e->C = S; e->lc = ls;
+    }
+    e->w = orc_window(kind, prm[P_WR], ls, lt);
+    *W = NULL;
+    e->W = NULL;
+    if (e->w < 0) return -1;
+    if (e->w < e->lr - e->lc) return 1;
+    if (kind == ORC_WDTW) {
+        *W = (double*)malloc(sizeof(double) * (size_t)e->lr);
+        orc_wdtw_weights(prm[P_G], e->lr, *W);
+        e->W = *W;
+    }
+    return 0;
+}
+
+/* One interior cell from whichever dependencies are given (+inf for the
+ * others), in the operation order of cell_dp. */
+static double cell_from(const eap_ctx* e, int64_t i, int64_t j, double diag, double top, double left)
+{
+    double canon, arow, acol;
+    terms(e, i, j, &canon, &arow, &acol);
+    return dmin3(diag + canon, top + arow, left + acol);
+}
+
+/* EAPruned (Section 4).  Returns D(S,T) when D <= cutoff, else +inf.
  *
- * Per row: stage 1 sets the left border (computed while the row starts at
- * column 1, +inf otherwise); stage 2 computes discard points (top and
- * diagonal dependencies) while the left neighbour is dead; stage 3 computes
- * full cells up to the previous row's pruning point; stage 4 handles the cell
- * at the pruning point (diagonal and, unless the left is dead, left); stage 5
- * continues from the left while cells stay alive.  next_start marks the first
- * non-discarded column, pruning_point the previous row's pruning point and
- * next_pruning_point the one being built (Section 4.1-4.3).
+ * Written from the definitions of Sections 4.1 and 4.2 rather than from the
+ * staged loop of Alg. 5.  A cell is alive when its value is <= cutoff.
+ * Costs are non-negative and rounded addition is monotone, so a cell's value
+ * is never below its smallest dependency: a cell whose dependencies are all
+ * dead is dead, and a dead cell never leads to an alive one.  Hence the only
+ * cells worth evaluating in row i are those that have an alive dependency:
  *
- * READING (final value): the printed algorithm returns curr[L_co] after the
- * last row; when that row stops before column L_co the entry is stale.  The
- * result is curr[L_co] only if the last row's pruning point is L_co + 1 and
- * curr[L_co] <= cutoff, else +inf.
- * READING (initial pruning point): with a computed top border the first
- * pruning point is 1 + the last border column whose value is <= cutoff
- * (Section 4.1 describes computed borders; for +inf borders this is 1).
- * READING (stage 4): "j == next_start" means the left neighbour is a discard
- * point; with a computed left border still alive it is not, so the test also
- * asks that curr[j-1] > cutoff.
- * next_pruning_point starts at the initial pruning point.
+ *  - pruning from the left (Section 4.1): left of the previous row's first
+ *    alive cell, every top and diagonal dependency is dead (a discard zone or
+ *    a run of discard points above), so row i starts at that column - or at
+ *    column 1 when its own left border is computed and alive (ERP);
+ *  - pruning on the right (Section 4.2): past the previous row's last alive
+ *    cell p-1 (p is that row's pruning point), only the cell at p still has
+ *    an alive (diagonal) dependency; beyond it a cell can only be alive
+ *    through its left neighbour, so the row goes on while its last cell is
+ *    alive;
+ *  - early abandoning: when no cell of a row (left border included) is
+ *    alive, no path to (L_li, L_co) stays under the cut-off.
  *
- * cells (nullable) counts the interior cells evaluated in stages 2-5;
- * ab_i/ab_j (nullable) receive the cell at which the pair was abandoned
+ * Every row is then the interval [lo, hi] of columns it evaluates, read from
+ * the previous row's alive extent; dependencies outside the previous row's
+ * evaluated interval are dead and read as +inf.  Alive cells come out exact
+ * (their smallest dependency is alive, hence exact, by induction); dead cells
+ * come out > cutoff, though not necessarily with their exact value.
+ * Borders (eq. Common): M(0,0) = 0; the top border M(0,j) and the left
+ * border M(i,0) are computed for ERP on 1..w+1 (Alg. 4's initialisation,
+ * reading R5) and +inf otherwise; the left border of row i is evaluated only
+ * while the one above it was alive (a dead border stays dead).  The result is
+ * M(L_li, L_co) when the last row evaluated column L_co and it is alive.
+ *
+ * These intervals evaluate the same cells as the staged loop of Alg. 5 for
+ * the distances with +inf borders (the worked example's counts of Section 4.2
+ * follow: 5 and 16 cells saved, abandoned at (5,3)); with a live computed
+ * left border (ERP) a row without an alive interior cell gets the pruning
+ * point its definition gives, 1, where the printed loop keeps the previous
+ * row's.
+ *
+ * cells (nullable) counts the interior cells evaluated; ab_i/ab_j (nullable)
+ * receive the last cell evaluated in the row where the pair was abandoned
  * (0,0 when it was not). */
 double orc_eap(int kind, const double* S, int64_t ls, const double* T, int64_t lt, const double* prm,
                double cutoff, int64_t* cells, int64_t* ab_i, int64_t* ab_j)
 {
     if (ls < 1 || lt < 1 || isnan(cutoff)) return NAN;
-    eap_ctx e;
-    e.kind = kind;
-    e.prm = prm;
-    if (ls >= lt) {
-        e.R = S; e.lr = ls; e.C = T; e.lc = lt;
-    } else {
-        e.R = T; e.lr = lt; e.C = S; e.lc = ls;
-    }
-    e.w = orc_window(kind, prm[P_WR], ls, lt);
-    if (e.w < 0) return NAN;
-    int64_t n_cells = 0;
     if (cells) *cells = 0;
     if (ab_i) *ab_i = 0;
     if (ab_j) *ab_j = 0;
-    if (e.w < e.lr - e.lc) return INF;
-    double* W = NULL;
-    if (kind == ORC_WDTW) {
-        W = (double*)malloc(sizeof(double) * (size_t)e.lr);
-        orc_wdtw_weights(prm[P_G], e.lr, W);
+    eap_ctx e;
+    double* W;
+    int st = eap_setup(&e, kind, S, ls, T, lt, prm, &W);
+    if (st < 0) return NAN;
+    if (st > 0) return INF;
+    const int64_t Lco = e.lc, Lli = e.lr, w = e.w;
+    const double gap = prm[P_GAP];
+    double* prev = (double*)malloc(sizeof(double) * (size_t)(Lco + 1));
+    double* curr = (double*)malloc(sizeof(double) * (size_t)(Lco + 1));
+    int64_t n_cells = 0;
+
+    /* row 0, the top border: evaluated on [0, hb] */
+    int64_t hb = (kind == ORC_ERP) ? imin(w + 1, Lco) : 0;
+    prev[0] = 0.0;
+    for (int64_t j = 1; j <= hb; ++j) prev[j] = prev[j - 1] + fabs(e.C[j - 1] - gap);
+    int64_t plo = 0, phi = hb;             /* evaluated interval of the previous row */
+    int64_t first = 0, last = 0;           /* its first and last alive columns */
+    for (int64_t j = 0; j <= hb; ++j)
+        if (prev[j] <= cutoff) last = j;   /* M(0,0) = 0 is alive: cutoff >= 0 */
+
+    double result = INF;
+    int abandoned = 0;
+    for (int64_t i = 1; i <= Lli; ++i) {
+        /* left border of row i, evaluated while the border above is alive */
+        double border = INF;
+        if (kind == ORC_ERP && i <= w + 1 && plo == 0 && prev[0] <= cutoff)
+            border = prev[0] + fabs(e.R[i - 1] - gap);
+        const int64_t jmax = imin(i + w, Lco);
+        int64_t lo = (border <= cutoff) ? 1 : imax(first, 1);
+        lo = imax(lo, i - w);
+        const int64_t reach = imin(last + 1, jmax);   /* last column with an alive top or diagonal */
+        curr[lo - 1] = (lo == 1) ? border : INF;
+        int64_t hi = lo - 1, nfirst = -1, nlast = -1;
+        if (lo == 1 && border <= cutoff) nfirst = nlast = 0;
+        for (int64_t j = lo; j <= jmax; ++j) {
+            if (j > reach && curr[j - 1] > cutoff) break;   /* right of the pruning point, left dead */
+            double diag = (j - 1 >= plo && j - 1 <= phi) ? prev[j - 1] : INF;
+            double top = (j >= plo && j <= phi) ? prev[j] : INF;
+            curr[j] = cell_from(&e, i, j, diag, top, curr[j - 1]);
+            ++n_cells;
+            hi = j;
+            if (curr[j] <= cutoff) {
+                if (nfirst < 0) nfirst = j;
+                nlast = j;
+            }
+        }
+        if (nfirst < 0) {                   /* no alive cell: abandon */
+            abandoned = 1;
+            if (ab_i) *ab_i = i;
+            if (ab_j) *ab_j = hi;
+            break;
+        }
+        double* t = prev; prev = curr; curr = t;
+        plo = lo - 1;
+        phi = hi;
+        first = nfirst;
+        last = nlast;
     }
-    e.W = W;
+    if (!abandoned && phi == Lco && prev[Lco] <= cutoff) result = prev[Lco];
+    free(prev);
+    free(curr);
+    free(W);
+    if (cells) *cells = n_cells;
+    return result;
+}
+
+/* EABase (Alg. 4): the usual early abandoning, no pruning.  Every row is
+ * evaluated in full within the window, with all three dependencies; the pair
+ * is abandoned after the first row whose smallest value (left border
+ * included, as Alg. 4 stores it in the row) exceeds the cut-off.  Returns
+ * M(L_li, L_co) when no row is abandoned (which may exceed the cut-off: the
+ * last row's minimum need not be its last cell), else +inf.  cells
+ * (nullable) counts the interior cells evaluated. */
+double orc_eabase(int kind, const double* S, int64_t ls, const double* T, int64_t lt, const double* prm,
+                  double cutoff, int64_t* cells)
+{
+    if (ls < 1 || lt < 1 || isnan(cutoff)) return NAN;
+    if (cells) *cells = 0;
+    eap_ctx e;
+    double* W;
+    int st = eap_setup(&e, kind, S, ls, T, lt, prm, &W);
+    if (st < 0) return NAN;
+    if (st > 0) return INF;
     const int64_t Lco = e.lc, Lli = e.lr, w = e.w;
     const double gap = prm[P_GAP];
     double* prev = (double*)malloc(sizeof(double) * (size_t)(Lco + 1));
     double* curr = (double*)malloc(sizeof(double) * (size_t)(Lco + 1));
     for (int64_t j = 0; j <= Lco; ++j) prev[j] = curr[j] = INF;
     curr[0] = 0.0;
-    int64_t hb = imin(w + 1, Lco);
-    for (int64_t j = 1; j <= hb; ++j) curr[j] = (kind == ORC_ERP) ? curr[j - 1] + fabs(e.C[j - 1] - gap) : INF;
-    int64_t next_start = 1;
-    int64_t pruning_point = 1;
-    for (int64_t j = 0; j <= hb; ++j)
-        if (curr[j] <= cutoff) pruning_point = j + 1;
-    int64_t next_pruning_point = pruning_point;
+    for (int64_t j = 1; j <= imin(w + 1, Lco); ++j)
+        curr[j] = (kind == ORC_ERP) ? curr[j - 1] + fabs(e.C[j - 1] - gap) : INF;
+    int64_t n_cells = 0;
     double result = INF;
     int abandoned = 0;
-    double canon, arow, acol;
-
-    for (int64_t i = 1; i <= Lli && !abandoned; ++i) {
+    for (int64_t i = 1; i <= Lli; ++i) {
         double* t = prev; prev = curr; curr = t;
-        int64_t jStart = imax(i - w, next_start);
-        int64_t jStop = imin(i + w, Lco);
-        int64_t j = jStart;
-        /* stage 1: left border */
-        curr[jStart - 1] = (jStart == 1 && kind == ORC_ERP) ? prev[0] + fabs(e.R[i - 1] - gap) : INF;
-        /* stage 2: discard points, up to (excluding) the pruning point */
-        if (curr[jStart - 1] > cutoff) {
-            for (; j < pruning_point && j == next_start; ++j) {
-                terms(&e, i, j, &canon, &arow, &acol);
-                curr[j] = dmin2(prev[j - 1] + canon, prev[j] + arow);
-                ++n_cells;
-                if (curr[j] <= cutoff) next_pruning_point = j + 1;
-                else ++next_start;
-            }
-        }
-        /* stage 3: full cells up to (excluding) the pruning point */
-        for (; j < pruning_point; ++j) {
-            terms(&e, i, j, &canon, &arow, &acol);
-            curr[j] = dmin3(prev[j - 1] + canon, prev[j] + arow, curr[j - 1] + acol);
+        const int64_t js = imax(1, i - w), je = imin(i + w, Lco);
+        curr[js - 1] = (js == 1 && kind == ORC_ERP) ? prev[0] + fabs(e.R[i - 1] - gap) : INF;
+        double mn = curr[js - 1];
+        for (int64_t j = js; j <= je; ++j) {
+            curr[j] = cell_from(&e, i, j, prev[j - 1], prev[j], curr[j - 1]);
             ++n_cells;
-            if (curr[j] <= cutoff) next_pruning_point = j + 1;
+            mn = dmin2(mn, curr[j]);
         }
-        /* stage 4: the cell at the pruning point */
-        if (j <= jStop) {
-            terms(&e, i, j, &canon, &arow, &acol);
-            ++n_cells;
-            if (j == next_start && curr[j - 1] > cutoff) {
-                curr[j] = prev[j - 1] + canon;
-                if (curr[j] <= cutoff) next_pruning_point = j + 1;
-                else {
-                    abandoned = 1;
-                    if (ab_i) *ab_i = i;
-                    if (ab_j) *ab_j = j;
-                    break;
-                }
-            } else {
-                curr[j] = dmin2(prev[j - 1] + canon, curr[j - 1] + acol);
-                if (curr[j] <= cutoff) next_pruning_point = j + 1;
-            }
-            ++j;
-        } else if (j == next_start) {
+        if (mn > cutoff) {
             abandoned = 1;
-            if (ab_i) *ab_i = i;
-            if (ab_j) *ab_j = j;
             break;
         }
-        /* stage 5: after the pruning point, left dependency only */
-        for (; j <= jStop && j == next_pruning_point; ++j) {
-            terms(&e, i, j, &canon, &arow, &acol);
-            curr[j] = curr[j - 1] + acol;
-            ++n_cells;
-            if (curr[j] <= cutoff) next_pruning_point = j + 1;
-        }
-        pruning_point = next_pruning_point;
     }
-    if (!abandoned && pruning_point == Lco + 1 && curr[Lco] <= cutoff) result = curr[Lco];
+    if (!abandoned) result = curr[Lco];
     free(prev);
     free(curr);
     free(W);

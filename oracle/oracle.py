@@ -46,6 +46,8 @@ def lib():
         L.orc_brute.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _pi64]
         L.orc_eap.restype = _d
         L.orc_eap.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _d, _pi64, _pi64, _pi64]
+        L.orc_eabase.restype = _d
+        L.orc_eabase.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _d, _pi64]
         L.orc_ub.restype = _d
         L.orc_ub.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd]
         L.orc_nn1.restype = None
@@ -117,6 +119,15 @@ def eap(p: dict, x, y, cutoff: float = float("inf")):
     d = lib().orc_eap(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), float(cutoff), ctypes.byref(c),
                       ctypes.byref(ai), ctypes.byref(aj))
     return d, c.value, (ai.value, aj.value)
+
+
+def eabase(p: dict, x, y, cutoff: float = float("inf")):
+    """EABase (Alg. 4): (value, cells evaluated); +inf when a row is dead."""
+    x, y = _f64(x), _f64(y)
+    prm = _prm(p)
+    c = ctypes.c_int64(0)
+    d = lib().orc_eabase(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), float(cutoff), ctypes.byref(c))
+    return d, c.value
 
 
 def ub(p: dict, x, y) -> float:

@@ -92,6 +92,17 @@ def test_worked_example_cell_claims(orc):
     assert d == INF and cells == 1 and ab == (1, 1)
 
 
+def test_worked_example_eabase(orc):
+    """EABase (Alg. 4) on the worked example: at cut-off 6 it computes full
+    rows until the first dead one and saves only the last row (Section 4.2);
+    at cut-off 9 it computes all 36 cells and returns D."""
+    g = read_golden()
+    d, cells = orc.eabase(dict(kind="dtw"), g["S"], g["T"], 6.0)
+    assert d == INF and 36 - cells == g["EABASE_SAVED"][6.0]
+    d, cells = orc.eabase(dict(kind="dtw"), g["S"], g["T"], 9.0)
+    assert d == g["D"] and cells == 36
+
+
 # --- closed forms and limit cases -------------------------------------------
 
 def test_length_one_closed_forms(orc):
@@ -302,6 +313,14 @@ def test_eapruned_is_exact_or_abandoned(orc, p):
             assert same(e, want), (p, lx, ly, c, e, want)
             if c == INF and d < INF:
                 assert cells <= lx * ly
+            # EABase (Alg. 4) returns D or +inf, D whenever D <= cut-off, and
+            # evaluates every cell EAPruned evaluates (it prunes nothing and
+            # abandons no earlier)
+            b, bcells = orc.eabase(p, x, y, c)
+            assert same(b, d) or b == INF, (p, lx, ly, c, b, d)
+            if d <= c:
+                assert same(b, d)
+            assert cells <= bcells, (p, lx, ly, c, cells, bcells)
 
 
 def test_eapruned_prunes_on_long_series(orc):
