@@ -54,6 +54,11 @@ ROOFLINE_CONVENTION = ("achieved = executed cells of the dominant kernel's launc
                        "FP32 (157.3 TFLOP/s / 2)")
 
 
+def say(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def band_cells(li, co, w):
     """Cells (i, j), 1 <= i <= li, 1 <= j <= co, with |i - j| <= w, for arrays
     li >= co with w >= li - co (closed form of the row-by-row count)."""
@@ -303,6 +308,10 @@ def main():
                     help="0: FP64 sweep; 1: FP32 screen + FP64 recheck (default 1, and 0 for workload 6, where "
                          "LB_Keogh leaves so few pairs that the screen's extra stages cost more than they save)")
     ap.add_argument("--no-tune", action="store_true", help="skip the row-sweep autotuner (default shapes)")
+    ap.add_argument("--shapes", default="",
+                    help="workload 4: row-sweep shapes pinned instead of tuned, e.g. wdtw=4x16,msm=8x16 (the other "
+                         "distances keep their defaults); lets a profiled run launch exactly the shapes of a timed "
+                         "one without the tuner's own launches")
     ap.add_argument("--schedule", default="pipelined", choices=("pipelined", "serial", "concurrent"),
                     help="workload 2: how the six searches of a step share the GPU.  pipelined: three "
                          "streams (round-robin), main sweeps one at a time (chained by events), the "
@@ -629,11 +638,20 @@ def run_batched(args, torch, eap, synth):
                 torch.empty(nq, dtype=torch.int32, device=dev)) for k in kinds}
     dense = {k: dense_cells(k, P[k], qo, ro) for k in kinds}
 
+    say(f"workload 4: {nq} queries x {nr} candidates resident; shapes")
     # shapes tuned on a sample (100 queries x every candidate), untimed
     sq, sr = min(100, nq), nr
     tq, tr = q[: qo[sq]], r[: ro[sr]]
     tuning = {}
-    if not args.no_tune:
+    if args.shapes:
+        lco_max = int(min(np.diff(qo).max(), np.diff(ro).max()))
+        for item in args.shapes.split(","):
+            k, shp = item.split("=")
+            g, c = (int(x) for x in shp.split("x"))
+            for prec in (0, 1):
+                eap.tune_set(swept_kind(k, P[k]), prec, lco_max, g, c)
+            tuning[k] = f"{g}x{c} (pinned)"
+    elif not args.no_tune:
         for k in kinds:
             recs = eap.tune_nn1(tq, qo[: sq + 1], tr, ro[: sr + 1], P[k], precision=1)
             if recs:
@@ -645,6 +663,7 @@ def run_batched(args, torch, eap, synth):
         for k in kinds:
             eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, ws=ws[k], out=outs[k], stream=s)
 
+    say("eager run and graph capture")
     eager()   # uploads offsets and tables into the workspaces
     s.synchronize()
     want = {k: (outs[k][0].clone(), outs[k][1].clone(), outs[k][2].clone()) for k in kinds}
@@ -656,6 +675,7 @@ def run_batched(args, torch, eap, synth):
     for _ in range(args.warmup):
         graph.launch(stream=s)
     s.synchronize()
+    say(f"{args.steps} timed graph launches")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     step_ev = []
     t0 = time.perf_counter()
@@ -679,6 +699,7 @@ def run_batched(args, torch, eap, synth):
     # stream it runs on (the same kernels, inputs and launch shapes the graph
     # replays; the graph itself cannot carry timing events)
     prof_steps = 2
+    say("per-kernel timing steps")
     for k in kinds:
         eap.reset_counters(ws[k], stream=s)
     eap.profile_take()
@@ -726,6 +747,7 @@ def run_batched(args, torch, eap, synth):
     # scaled to the whole workload by dense cells
     plain = None
     if not args.no_plain:
+        say("plain FP64 DP sample")
         pq = min(50, nq)
         pqv = q[: qo[pq]]
         pms = 0.0
@@ -749,9 +771,10 @@ def run_batched(args, torch, eap, synth):
 
     cpu = None
     if args.cpu_queries > 0:
+        say("CPU oracle baseline")
         gi = {k: outs[k][0].cpu().numpy() for k in kinds}
         gd = {k: outs[k][1].cpu().numpy() for k in kinds}
-        cpu = cpu_baseline(wl, kinds, gi, gd, eap_q=min(args.cpu_queries, nq), dp_q=min(2, nq), dp_r=1000,
+        cpu = cpu_baseline(wl, kinds, gi, gd, eap_q=min(args.cpu_queries, nq), dp_q=min(16, nq), dp_r=250,
                            one_q=1, one_r=2000)
 
     total = sum(dense.values())
