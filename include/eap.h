@@ -370,6 +370,17 @@ const char* eap_server_last_error(void);
  * library's weights against another implementation bit for bit. */
 eap_status eap_wdtw_weights(double g, int64_t L, double* out);
 
+/* Host utilities: the certified error bound of the FP32 screen (precision 1).
+ * eap_screen_eps(kind, exact_diff, B, N, A) bounds |V32 - B| for any warping
+ * path of exact cost B with at most N steps over values of magnitude <= A
+ * (ERP: also >= |gap|), V32 being the path's cost evaluated in FP32 as the
+ * recurrence adds it; exact_diff != 0 when each difference is formed in
+ * float64 and rounded once (no input rounding).  eap_screen_bound(kind,
+ * exact_diff, b, N, A) is the largest exact cost C with C <= b + eps(C).
+ * The derivation is in the library's eap_screen.h.  NaN for an unknown kind. */
+double eap_screen_eps(int32_t kind, int32_t exact_diff, double B, double N, double A);
+double eap_screen_bound(int32_t kind, int32_t exact_diff, double b, double N, double A);
+
 /* Thread-local text of the last error on this thread; valid until the next call. */
 const char* eap_last_error(void);
 

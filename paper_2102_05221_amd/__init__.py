@@ -111,6 +111,10 @@ def lib():
         L.eap_distance_workspace.argtypes = [_i64, _i64, _pP]
         L.eap_distance.restype = ctypes.c_int
         L.eap_distance.argtypes = [_vp, _i64, _vp, _i64, _pP, _d, _vp, _vp, _sz, _vp]
+        L.eap_screen_eps.restype = _d
+        L.eap_screen_eps.argtypes = [ctypes.c_int32, ctypes.c_int32, _d, _d, _d]
+        L.eap_screen_bound.restype = _d
+        L.eap_screen_bound.argtypes = [ctypes.c_int32, ctypes.c_int32, _d, _d, _d]
         L.eap_distance_noalloc.restype = ctypes.c_int
         L.eap_distance_noalloc.argtypes = [_vp, _i64, _vp, _i64, _pP, _d, _vp, _vp]
         L.eap_nn1_workspace.restype = _sz
@@ -581,6 +585,16 @@ def profile_take(cap: int = 4096) -> list:
     inv = {v: k for k, v in KINDS.items()}
     return [dict(stage=r.stage, kernel=("band" if r.kernel else "rows"), kind=inv.get(r.kind, r.kind), size=r.size,
                  group=r.group, fp32=int(r.fp32), ms=float(r.ms)) for r in buf[:n.value]]
+
+
+def screen_eps(kind: str, B: float, N: float, A: float, exact_diff: bool = False) -> float:
+    """The FP32 screen's certified bound on |V32 - B| (eap_screen_eps)."""
+    return lib().eap_screen_eps(KINDS[kind], int(exact_diff), float(B), float(N), float(A))
+
+
+def screen_bound(kind: str, b: float, N: float, A: float, exact_diff: bool = False) -> float:
+    """Largest exact path cost whose FP32 value can be <= b (eap_screen_bound)."""
+    return lib().eap_screen_bound(KINDS[kind], int(exact_diff), float(b), float(N), float(A))
 
 
 def wdtw_weights(g: float, L: int) -> np.ndarray:

@@ -17,6 +17,7 @@
 
 #include "eap.h"
 #include "eap_launch.h"
+#include "eap_screen.h"
 
 using namespace eap;
 
@@ -1295,6 +1296,16 @@ eap_status eap_tune_reset(void) {
     g_tuned.clear();
     g_tuned_band.clear();
     return EAP_OK;
+}
+
+double eap_screen_eps(int32_t kind, int32_t exact_diff, double B, double N, double A) {
+    if (kind < EAP_DTW || kind > EAP_TWE) return NAN;
+    return screen_eps(kind | (exact_diff ? kScreenExactDiff : 0), B, N, A);
+}
+
+double eap_screen_bound(int32_t kind, int32_t exact_diff, double b, double N, double A) {
+    if (kind < EAP_DTW || kind > EAP_TWE) return NAN;
+    return screen_bound(kind | (exact_diff ? kScreenExactDiff : 0), b, N, A);
 }
 
 eap_status eap_wdtw_weights(double g, int64_t L, double* out) {

@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "eap_pairs.h"
+#include "eap_screen.h"
 
 namespace eap {
 
@@ -763,40 +764,6 @@ __global__ void absmax_kernel(const double* v, int64_t n, unsigned long long* ou
     }
 }
 
-// Certified bound on |D32 - D64| for any warping path whose exact cost is at
-// most B, with at most N steps, over values of magnitude <= A, in FP32 (unit
-// roundoff u = 2^-24): each term carries the rounding of its inputs
-// (u|a| + u|b|), of its own operations, and the running sum adds gamma_N on the
-// total.  Squared costs: |fl(d)^2 - d^2| <= 4uA|d| + 3u d^2 per term and
-// sum|d| <= sqrt(N sum d^2) (Cauchy-Schwarz; WDTW's weights are <= 1 and add
-// one more rounding).  L1 costs (ERP, MSM, TWE): <= u(4A + 3|term|) per term.
-// The FP64 reference carries the same error with 2^-53, covered by the factor
-// 1.01; the last term covers FP32 underflow of tiny squares.
-__device__ double screen_eps(int kind, double B, double N, double A) {
-    const double u = 0x1p-24;
-    double e;
-    if (kind == DTW || kind == CDTW || kind == WDTW) e = u * ((N + 5.0) * B + 4.0 * A * sqrt(N * B));
-    else e = u * ((N + 3.0) * B + 4.0 * N * A);
-    return 1.01 * e + N * 4e-38;
-}
-
-// Largest exact cost C that can still satisfy C <= b + eps(C), i.e. a bound on
-// the exact cost of any path whose FP32 evaluation is <= b.  eps grows like
-// sqrt(C) for the squared costs, so for b near 0 this is about (4uA)^2 N, not 0.
-__device__ double screen_bound(int kind, double b, double N, double A) {
-    const double u = 1.01 * 0x1p-24;
-    const double e0 = b + N * 4e-38;
-    double B;
-    if (kind == DTW || kind == CDTW || kind == WDTW) {
-        const double a = u * (N + 5.0), c = u * 4.0 * A * sqrt(N);
-        const double r = (c + sqrt(c * c + 4.0 * (1.0 - a) * e0)) / (2.0 * (1.0 - a));
-        B = r * r;
-    } else {
-        B = (e0 + u * 4.0 * N * A) / (1.0 - u * (N + 3.0));
-    }
-    return B * (1.0 + 1e-9);
-}
-
 // Widening of each query's FP32 cut-off during the screening sweep.  The
 // best-so-far b is an FP32 distance (or the FP64 path bound UB >= b), so the
 // exact NN distance is <= screen_bound(b) and any prefix of its path evaluates
@@ -804,7 +771,7 @@ __device__ double screen_bound(int kind, double b, double N, double A) {
 __global__ void screen_widen_kernel(int kind, SweepArgs A, const int64_t* qoff, int64_t lr_max, double gap,
                                     const unsigned long long* absmax, double* widen_abs) {
     double Amax = bitsd(*absmax);
-    if (kind == ERP) Amax = fmax(Amax, __builtin_fabs(gap));
+    if ((kind & 7) == ERP) Amax = fmax(Amax, __builtin_fabs(gap));
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < A.nA; q += (int64_t)gridDim.x * blockDim.x) {
         const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
         const double ub = bitsd(A.best[q]);
@@ -822,7 +789,7 @@ __device__ __forceinline__ void screen_cut(int kind, const int64_t* qoff, int64_
     cut64 = __builtin_huge_val();
     if (!(b32 < __builtin_huge_val())) return;
     const double N = (double)(qoff[q + 1] - qoff[q] + lr_max);
-    const double Amax = (kind == ERP) ? fmax(Ab, __builtin_fabs(gap)) : Ab;
+    const double Amax = ((kind & 7) == ERP) ? fmax(Ab, __builtin_fabs(gap)) : Ab;
     const double b = b32 * (1.0 + margin_rel);
     cut64 = screen_bound(kind, b, N, Amax);
     thr = b + 2.0 * screen_eps(kind, cut64, N, Amax);

@@ -799,10 +799,12 @@ def test_plain_dp_mode_gives_the_same_nn(torch_dev, kind):
         assert torch.equal(a[0], x[0]) and torch.equal(a[1], x[1])
 
 
+@pytest.mark.parametrize("margin", [1e-4, 0.0])
 @pytest.mark.parametrize("kind", synth.SIX)
-def test_fp32_screen_gives_fp64_results(torch_dev, orc, kind):
+def test_fp32_screen_gives_fp64_results(torch_dev, orc, kind, margin):
     """Precision 1 (FP32 screen + FP64 recheck) returns the FP64 NN bit for bit,
-    also when candidates differ by far less than FP32 can resolve."""
+    also when candidates differ by far less than FP32 can resolve; with margin
+    0 only the certified rounding bound keeps the FP64 NN in the recheck."""
     torch, dev = torch_dev
     wl = synth.make_workload(2, n_ref=80, n_query=12, length=200)
     rs = synth.unpack(wl["refs"], wl["ref_off"])
@@ -817,10 +819,10 @@ def test_fp32_screen_gives_fp64_results(torch_dev, orc, kind):
     rv, ro = synth.pack(rs)
     p = wl["params"][kind]
     q, r = to_dev(torch, dev, wl["queries"]), to_dev(torch, dev, rv)
-    log(f"fp32 screen {kind}")
+    log(f"fp32 screen {kind} margin {margin}")
     ws = eap.workspace(eap.nn1_workspace_bytes(wl["query_off"], ro, p, precision=1), dev)
     eap.reset_counters(ws)
-    a = eap.nn1(q, wl["query_off"], r, ro, p, precision=1, ws=ws)
+    a = eap.nn1(q, wl["query_off"], r, ro, p, precision=1, margin_rel=margin, ws=ws)
     c = eap.read_counters(ws)
     torch.cuda.synchronize()
     oi, od, _ = orc.nn1(p, wl["queries"], wl["query_off"], rv, ro, "dp")
