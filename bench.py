@@ -47,11 +47,15 @@ LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 LANE_OPS_PER_S_F32 = 2 * LANE_OPS_PER_S
 OPS_PER_CELL = {"dtw": 5, "cdtw": 5, "wdtw": 6, "erp": 6, "msm": 16, "twe": 8}
 OPS_PER_CELL_F32 = {"dtw": 4, "cdtw": 4, "wdtw": 5, "erp": 5, "msm": 9, "twe": 7}
+# FP32 WDTW with exact differences: the float64 subtraction, at half the FP32
+# lane-op rate, counts as two FP32 operations, plus its conversion to FP32
+OPS_PER_CELL_F32_XD = {"wdtw": 7}
 HBM_PEAK_GBS = 8000.0
 ROOFLINE_CONVENTION = ("achieved = executed cells of the dominant kernel's launch / its launch time; peak = VALU "
                        "lane-op rate / minimal lane-ops per cell of its distance and precision, with the lane-op "
                        "rate 39.3e12/s for FP64 (78.6 TFLOP/s / 2: min-plus cells have no FMA) and 78.6e12/s for "
-                       "FP32 (157.3 TFLOP/s / 2)")
+                       "FP32 (157.3 TFLOP/s / 2); an FP32 sweep with exact differences counts its float64 "
+                       "subtraction as two FP32 operations")
 
 
 def say(msg):
@@ -91,10 +95,17 @@ def dense_cells(kind, p, q_off, r_off):
 
 def kernel_label(rec):
     """Name of a sweep launch: kernel, width (strip columns or band diagonals),
-    lanes per pair x columns per lane."""
+    lanes per pair x columns per lane (xd: exact differences)."""
     g = rec["group"]
     c = rec["size"] // g if rec["kernel"] == "rows" else rec["size"] // (2 * g)
-    return f"{rec['kernel']}{rec['size']} {g}x{c}"
+    return f"{rec['kernel']}{rec['size']} {g}x{c}" + (" xd" if rec.get("exact_diff") else "")
+
+
+def ops_per_cell(kind, fp32, xd=False):
+    """Minimal lane-ops per cell of a sweep, in FP32 operations for FP32 sweeps."""
+    if fp32 and xd:
+        return OPS_PER_CELL_F32_XD[kind]
+    return (OPS_PER_CELL_F32 if fp32 else OPS_PER_CELL)[kind]
 
 
 def hbm_traffic(kernel):
@@ -717,11 +728,12 @@ def run_batched(args, torch, eap, synth):
         mc = counters[k]["stage_cells"][2] / prof_steps
         mms = sum(x["ms"] for x in main) / prof_steps
         fp32 = bool(main[0]["fp32"]) if main else False
-        ops = (OPS_PER_CELL_F32 if fp32 else OPS_PER_CELL)[sk]
+        xd = bool(main[0].get("exact_diff")) if main else False
+        ops = ops_per_cell(sk, fp32, xd)
         peak = (LANE_OPS_PER_S_F32 if fp32 else LANE_OPS_PER_S) / ops / 1e9
         per[k] = dict(sweep_ms=sum(x["ms"] for x in prof if x["kind"] == sk) / prof_steps,
                       main_sweep_ms=mms, main_launches=len(main) // prof_steps,
-                      main_kernel=(kernel_label(main[0]) if main else None), main_fp32=fp32,
+                      main_kernel=(kernel_label(main[0]) if main else None), main_fp32=fp32, main_xd=xd,
                       main_cells=mc, dense_cells=dense[k],
                       main_gcups=(mc / (mms * 1e-3) / 1e9) if mms else None, main_peak_gcups=peak,
                       main_frac=(mc / (mms * 1e-3) / 1e9 / peak) if mms else None,
@@ -731,7 +743,7 @@ def run_batched(args, torch, eap, synth):
                       nn_accuracy=float(np.mean(outs[k][2].cpu().numpy() == wl["query_labels"])))
     dom = max(kinds, key=lambda k: per[k]["main_sweep_ms"])
     d = per[dom]
-    ops = (OPS_PER_CELL_F32 if d["main_fp32"] else OPS_PER_CELL)[swept_kind(dom, P[dom])]
+    ops = ops_per_cell(swept_kind(dom, P[dom]), d["main_fp32"], d["main_xd"])
     kernel = f"{d['main_kernel']} sweep, {swept_kind(dom, P[dom]).upper()} main stage, " \
              f"{'fp32' if d['main_fp32'] else 'fp64'}"
     launch_ms = d["main_sweep_ms"] / max(d["main_launches"], 1)

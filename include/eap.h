@@ -82,9 +82,12 @@ typedef struct {
  *              rounding error of any warping path (input rounding, per-term
  *              rounding and the running sum), so the FP64 nearest neighbour is
  *              always among the candidates rechecked.  WDTW whose diagonal
- *              weight 1/(1+exp(g*L/2)) is below 1e-8 (L the longest length) is
- *              swept in FP64 directly: its distances are too small for an FP32
- *              screen to separate candidates.
+ *              weight 1/(1+exp(g*L/2)) is below 1e-8 (L the longest length)
+ *              screens with exact differences: the FP32 sweep reads the
+ *              float64 series and rounds each difference once, so the bound
+ *              has no input-rounding term (its distances, scaled by such
+ *              weights, lie far below the rounding of the inputs); below a
+ *              diagonal weight of 1e-30 it sweeps in FP64 throughout.
  *  margin_rel  relative part of the screen margin for precision 1 (>= 0,
  *              finite; 1e-4 by default in the binding).
  *  flags       bit 0: skip the seeding pass (every candidate starts from the
@@ -150,7 +153,8 @@ typedef struct {
  * eap_profile_take() waits for the recorded launches, copies up to `cap`
  * records into `out` (host memory), returns their number in *n and forgets
  * them.  kernel: 0 row sweep, 1 band sweep; size: strip width (row sweep) or
- * band diagonals; group: lanes per pair; kind: eap_kind swept. */
+ * band diagonals; group: lanes per pair; kind: eap_kind swept; exact_diff: 1
+ * for an FP32 sweep that forms its differences from float64 values. */
 typedef struct {
     int32_t stage;
     int32_t kernel;
@@ -159,6 +163,7 @@ typedef struct {
     int32_t fp32;
     float ms;
     int32_t group;
+    int32_t exact_diff;
 } eap_profile_rec;
 eap_status eap_profile_enable(int32_t on);
 eap_status eap_profile_take(eap_profile_rec* out, int32_t cap, int32_t* n);

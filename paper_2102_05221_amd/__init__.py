@@ -61,7 +61,7 @@ class Counters(ctypes.Structure):
 class ProfileRec(ctypes.Structure):
     _fields_ = [("stage", ctypes.c_int32), ("kernel", ctypes.c_int32), ("kind", ctypes.c_int32),
                 ("size", ctypes.c_int32), ("fp32", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("group", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("exact_diff", ctypes.c_int32)]
 
 
 class TuneRec(ctypes.Structure):
@@ -578,13 +578,14 @@ def profile_enable(on: bool = True):
 def profile_take(cap: int = 4096) -> list:
     """Wait for the timed launches and return them as dicts (stage, kernel
     'rows'/'band', kind, size = strip width or band diagonals, group = lanes
-    per pair, fp32, ms)."""
+    per pair, fp32, exact_diff, ms)."""
     buf = (ProfileRec * cap)()
     n = ctypes.c_int32(0)
     _check(lib().eap_profile_take(buf, cap, ctypes.byref(n)))
     inv = {v: k for k, v in KINDS.items()}
     return [dict(stage=r.stage, kernel=("band" if r.kernel else "rows"), kind=inv.get(r.kind, r.kind), size=r.size,
-                 group=r.group, fp32=int(r.fp32), ms=float(r.ms)) for r in buf[:n.value]]
+                 group=r.group, fp32=int(r.fp32), exact_diff=int(r.exact_diff), ms=float(r.ms))
+            for r in buf[:n.value]]
 
 
 def screen_eps(kind: str, B: float, N: float, A: float, exact_diff: bool = False) -> float:

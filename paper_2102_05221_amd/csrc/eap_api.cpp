@@ -480,7 +480,8 @@ Profiler g_prof;
 // allocation of any kind may not create them).
 eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, Header* h, int stage,
                  unsigned int* queue, const int32_t* items, int64_t n, SeriesPtrs SA, SeriesPtrs SB, hipStream_t s,
-                 bool fp32 = false, bool timed = true) {
+                 bool fp32 = false, bool timed = true, bool xd = false) {
+    if (xd && band) return fail(EAP_EINVAL, "exact-difference FP32 sweeps run on the row sweep only");
     a.queue = queue;
     a.items = items;
     a.npairs = n;
@@ -512,7 +513,7 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
         // measurably slow the sweep (up to a quarter for the band sweep)
         int occ = 0;
         const hipError_t oe = band ? launch_band(kind, fp32, pl.size, lanes, a, SA, SB, grid, s, &occ)
-                                   : launch_rows(kind, fp32, sh, a, SA, SB, grid, s, &occ);
+                                   : launch_rows(kind, fp32, sh, a, SA, SB, grid, s, &occ, xd);
         if (oe == hipSuccess && occ > 0) grid = std::min(grid, device_cus() * occ);
     }
     // slots per queue atomic: about 8 chunks per group, so that short items
@@ -521,14 +522,14 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     const int64_t groups = (int64_t)grid * (256 / lanes);
     a.chunk = a.npairs_dev ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(32, n / (groups * 8)));
     if (band) e = launch_band(kind, fp32, pl.size, lanes, a, SA, SB, grid, s);
-    else e = launch_rows(kind, fp32, sh, a, SA, SB, grid, s);
+    else e = launch_rows(kind, fp32, sh, a, SA, SB, grid, s, nullptr, xd);
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     if (e0 && e1) {
         HIPCHK(hipEventRecord(e1, s));
         std::lock_guard<std::mutex> lk(g_prof.mu);
         ProfRec pr;
         pr.r = eap_profile_rec{stage, band ? 1 : 0, kind, band ? pl.size : sh.g * sh.c, fp32 ? 1 : 0, 0.0f,
-                               lanes};
+                               lanes, xd ? 1 : 0};
         pr.e0 = e0;
         pr.e1 = e1;
         g_prof.pending.push_back(pr);
@@ -541,12 +542,12 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
 // the count at run time, so nothing synchronises the host.
 eap_status rerun_overflow(const eap_params* p, const Plan& pl, SweepArgs a, Header* h, int stage,
                           unsigned int* ovf_count, const int32_t* ovf_items, int64_t max_items, unsigned int* queue,
-                          SeriesPtrs SA, SeriesPtrs SB, hipStream_t s, bool fp32 = false) {
+                          SeriesPtrs SA, SeriesPtrs SB, hipStream_t s, bool fp32 = false, bool xd = false) {
     a.ovf_items = nullptr;
     a.ovf_count = nullptr;
     a.npairs_dev = ovf_count;
     a.skip_b = nullptr;
-    return sweep(p, pl, false, a, h, stage, queue, ovf_items, max_items, SA, SB, s, fp32);
+    return sweep(p, pl, false, a, h, stage, queue, ovf_items, max_items, SA, SB, s, fp32, true, xd);
 }
 
 }  // namespace
@@ -735,14 +736,21 @@ eap_status eap_distance_noalloc(const double* x, int64_t lx, const double* y, in
 }
 
 // ---------------------------------------------------------------------- NN
-// Whether an FP32 screen can separate candidates.  Its certified error bound
-// carries the rounding of the inputs, about u * max|x| per difference, at any
+// How the FP32 screen forms its differences.  Its certified error bound with
+// FP32 inputs carries their rounding, about u * max|x| per difference, at any
 // weight; WDTW's weights near the diagonal, 1 / (1 + exp(g L / 2)), make its
 // distances so small for long series that this bound would list most
-// candidates for the recheck, so WDTW then runs in FP64 throughout.
-bool screen_useful(const eap_params* p, int64_t lmax) {
-    if (p->kind != EAP_WDTW) return true;
-    return 1.0 / (1.0 + std::exp(p->g * (double)lmax / 2.0)) >= 1e-8;
+// candidates for the recheck.  Such WDTW searches sweep in FP32 with exact
+// differences instead (float64 series, each difference rounded once), whose
+// bound is relative.  WDTW keeps a weight of at least 1e-30 there, far inside
+// the FP32 normal range, so the relative bound holds for the weights too.
+bool screen_exact_diff(const eap_params* p, int64_t lmax) {
+    if (p->kind != EAP_WDTW) return false;
+    return 1.0 / (1.0 + std::exp(p->g * (double)lmax / 2.0)) < 1e-8;
+}
+bool screen_possible(const eap_params* p, int64_t lmax) {
+    if (p->kind != EAP_WDTW || !screen_exact_diff(p, lmax)) return true;
+    return 1.0 / (1.0 + std::exp(p->g * (double)lmax / 2.0)) >= 1e-30;
 }
 
 struct NNLayout {
@@ -814,7 +822,7 @@ size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off,
         return 0;
     NNLayout nl;
     const bool prec1 = o && o->precision == 1;
-    nn_layout(Q, R, p, prec1, prec1 && screen_useful(p, std::max(Q.maxlen, R.maxlen)), nl);
+    nn_layout(Q, R, p, prec1, prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen)), nl);
     return nl.L.off;
 }
 
@@ -834,7 +842,9 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         if (o->flags & ~31) return fail(EAP_EINVAL, "unknown flags 0x%x", (unsigned)o->flags);
     }
     const bool prec1 = o && o->precision == 1;
-    const bool screen = prec1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
+    const bool screen = prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen));
+    const bool xd = screen && screen_exact_diff(p, std::max(Q.maxlen, R.maxlen));
+    const int skind = effective_kind(p) | (xd ? kScreenExactDiff : 0);   // the screen bound's mode
     NNLayout nl;
     nn_layout(Q, R, p, prec1, screen, nl);
     if (eap_status st_ws = check_ws(ws, ws_bytes, nl.L.off)) return st_ws;
@@ -844,7 +854,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     const bool seeded = !plain && !(o && (o->flags & 1));
     const bool prepared = o && (o->flags & 4);
     const bool cand_ready = o && (o->flags & 8);
-    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
+    // exact-difference sweeps run on the row sweep only (no narrow WDTW band)
+    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain && !xd, &pl)) != EAP_OK) return st;
 
     hipStream_t s = (hipStream_t)stream;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -936,8 +947,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         a.skip_b = seed;
     }
     // FP32 screen: sweep single-precision copies under a widened cut-off
-    SeriesPtrs XQ = SQ, XR = SR;
-    if (screen) {
+    SeriesPtrs XQ = SQ, XR = SR;   // exact differences: the sweep reads the float64 series
+    if (screen && !xd) {
         float* q32 = reinterpret_cast<float*>(at(ws, nl.q32));
         float* r32 = reinterpret_cast<float*>(at(ws, nl.r32));
         HIPCHK(launch_to_f32(q, Q.total, q32, s));
@@ -950,6 +961,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
             XQ.border = qb;
             XR.border = rb;
         }
+    }
+    if (screen) {
         // |x| maximum over queries and candidates (theirs computed above or kept)
         HIPCHK(launch_fill_u64(&h->absmax, 0ull, 1, s));
         HIPCHK(launch_absmax(q, Q.total, &h->absmax, s));
@@ -957,7 +970,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         double* widen = reinterpret_cast<double*>(at(ws, nl.widen));
         // best[q] is now the seed's FP64 distance or the path bound: the widening
         // at it bounds every best-so-far of the FP32 pass
-        HIPCHK(launch_screen_widen(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, widen, s));
+        HIPCHK(launch_screen_widen(skind, a, SQ.off, R.maxlen, p->gap, &h->absmax, widen, s));
         a.widen_abs = widen;
         a.widen_rel = o->margin_rel;
     }
@@ -974,11 +987,12 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         m.skip_b = nullptr;
     }
     if (main_wait) HIPCHK(hipStreamWaitEvent(s, main_wait, 0));
-    if ((st = sweep(p, pl, pl.band, m, h, 2, &h->queues[2], main_items, nq * nr, XQ, XR, s, screen)) != EAP_OK)
+    if ((st = sweep(p, pl, pl.band, m, h, 2, &h->queues[2], main_items, nq * nr, XQ, XR, s, screen, true, xd)) !=
+        EAP_OK)
         return st;
     if (rerun) {
-        if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], XQ, XR, s, screen)) !=
-            EAP_OK)
+        if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], XQ, XR, s, screen,
+                                 xd)) != EAP_OK)
             return st;
     }
     if (main_done) HIPCHK(hipEventRecord(main_done, s));
@@ -987,7 +1001,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         //     recomputed in FP64 (the seed keeps its FP64 distance); every other
         //     result becomes +inf
         int32_t* items = reinterpret_cast<int32_t*>(at(ws, nl.recheck));
-        HIPCHK(launch_screen_filter(effective_kind(p), a, SQ.off, R.maxlen, p->gap, &h->absmax, o->margin_rel, res,
+        HIPCHK(launch_screen_filter(skind, a, SQ.off, R.maxlen, p->gap, &h->absmax, o->margin_rel, res,
                                     best, seeded ? seed : nullptr, items, &h->ovf_count[2], &h->counters[2], part,
                                     s));
         HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(&h->ovf_count[0]), 0ull, 1, s));
@@ -1147,11 +1161,12 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
         own.main_wait = own.main_done = nullptr;
         o = &own;
     }
-    const bool fp32 = o && o->precision == 1 && screen_useful(p, std::max(Q.maxlen, R.maxlen));
+    const bool fp32 = o && o->precision == 1 && screen_possible(p, std::max(Q.maxlen, R.maxlen));
+    const bool xd = fp32 && screen_exact_diff(p, std::max(Q.maxlen, R.maxlen));
     const bool plain = o && (o->flags & 2);
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     Plan pl;
-    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain, &pl)) != EAP_OK) return st;
+    if ((st = make_plan(p, Q.maxlen, R.maxlen, ldiff, !plain && !xd, &pl)) != EAP_OK) return st;
     const bool band = pl.band;
     hipStream_t s = (hipStream_t)stream;
     const RowsShape all[13] = {{4, 8},  {4, 16},  {8, 8},   {8, 16},  {16, 8},  {16, 16}, {32, 8},

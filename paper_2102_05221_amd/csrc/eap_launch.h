@@ -81,8 +81,9 @@ struct SeriesPtrs {
 // without a window, MSM, TWE).  Returns the launch error.  Pairs wider than
 // one strip need a.edge with room for grid * 256 / G groups.  With `occ` set
 // nothing is launched: *occ = blocks of this kernel one CU holds at once.
+// xd: exact differences (FP32 WDTW only; A and B hold float64 values).
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s, int* occ = nullptr);
+                       hipStream_t s, int* occ = nullptr, bool xd = false);
 int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a);
 bool rows_shape_ok(int kind, RowsShape sh, bool fp32);
 

@@ -36,6 +36,14 @@
 // Per-diagonal terms (TWE's nu * 2|i-j|, WDTW's weight of |i-j|) come from an
 // LDS table; each lane reads the C + K - 1 entries its next K steps need into
 // registers at the start of every block.
+//
+// Exact differences (XD, FP32 WDTW only): the series stay in float64 (type V)
+// and each cell rounds its difference s_i - t_j once to FP32 after forming it
+// in float64, so the FP32 screen's error bound carries no input rounding (it
+// is then relative: for long series WDTW's distances, scaled by weights near
+// 1e-22, are far below the rounding of the inputs themselves).
+#include <type_traits>
+
 #include "eap_pairs.h"
 
 namespace eap {
@@ -44,14 +52,17 @@ namespace eap {
 // except TWE and ERP lanes of 16 or more columns, which spill heavily at that
 // budget and run faster with 256 VGPRs at 2 blocks per CU (measured on the
 // 500 x 500, length-512 NN workload: TWE 8x16 3.49 against 4.87 ms); FP64: 2.
-template <int KIND, typename T, int C>
+template <int KIND, typename T, int C, bool XD>
 constexpr int rows_min_blocks() {
-    return (sizeof(T) == 4 && !(C >= 16 && (KIND == TWE || KIND == ERP))) ? 3 : 2;
+    return (sizeof(T) == 4 && !(C >= 16 && (KIND == TWE || KIND == ERP || XD))) ? 3 : 2;
 }
 
-template <int KIND, typename T, int G, int C>
-__global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_kernel(SweepArgs A, Series<T> SA,
-                                                                                     Series<T> SB) {
+template <typename T, bool XD> using RowValue = typename std::conditional<XD, double, T>::type;
+
+template <int KIND, typename T, int G, int C, bool XD>
+__global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows_kernel(
+    SweepArgs A, Series<RowValue<T, XD>> SA, Series<RowValue<T, XD>> SB) {
+    using V = RowValue<T, XD>;   // type of the series values
     constexpr bool DTAB = (KIND == TWE || KIND == WDTW);
     // steps between group decisions: long blocks share the block-end work
     // (ballots, cut-off, strip and pair bookkeeping) among more steps, and
@@ -89,29 +100,34 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
     // Every lane loads its row inputs at every step, also in groups without a
     // pair: until a group fetches one, li and bp point at a valid one-value
     // range (the first value of set A), so those loads stay in bounds.
-    const T* li = SA.v;
-    const T* lib = nullptr;
-    const T* co = nullptr;
-    const T* cob = nullptr;
+    const V* li = SA.v;
+    const V* lib = nullptr;
+    const V* co = nullptr;
+    const V* cob = nullptr;
     int Lli = 1, Lco = 0, kend = 0, uend = 0, row = 0;
     int nstrip = 1, si = 0, cb = 0, c0 = 1, r_start = 1;
     int e_lo = 0, e_hi = -1;       // rows of the incoming edge that can be <= cut-off
     int rec_lo = 0, rec_hi = -1;   // the same for the edge this strip writes (last lane)
     bool last = true, full_top = true;
     T cut = 0;
-    T val[C], vb[C], tv[C], aux[C];
+    T val[C], vb[C], aux[C];
+    V tv[C];
     T adv[KIND == TWE ? C : 1];   // TWE: |s_{i-1} - t_j| of the previous row
     T dwin[NW];                   // per-diagonal terms of this block
-    T dg = 0, lout = 0, sout = 0, sp = 0, tpm = 0, brd0 = 0, s0 = 0;
+    T dg = 0, lout = 0, brd0 = 0;
+    V sout = 0, sp = 0, tpm = 0, s0 = 0;
     // Lane 0's inputs of a block's K rows (s_i and M(i, cb)) are staged across
     // the group: lane j holds rows R0 + 1 + j + G*i (i < RS; R0 = lane 0's row
     // before the block), loaded one block ahead, and lane 0 reads the one for
     // each step with a cross-lane permute.
     constexpr int RS = (K + G - 1) / G;
-    T st_s[RS], st_b[RS], nx_s[RS], nx_b[RS];
+    V st_s[RS], nx_s[RS];
+    T st_b[RS], nx_b[RS];
 #pragma unroll
     for (int i = 0; i < RS; ++i) st_s[i] = st_b[i] = nx_s[i] = nx_b[i] = 0;
-    const T* bp = SA.v - 1;  // left inputs: bp[i] = M(i, cb) for e_lo <= i <= e_hi
+    // left inputs: bp[i] = M(i, cb) for e_lo <= i <= e_hi (until a pair is
+    // fetched, and in the first strip of +inf borders, a valid dummy range)
+    const T* bp = reinterpret_cast<const T*>(SA.v) - 1;
     unsigned long long ncells = 0, npairs = 0;
 #pragma unroll
     for (int u = 0; u < C; ++u) val[u] = vb[u] = tv[u] = aux[u] = 0;
@@ -124,7 +140,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
     // strip) or the previous strip's edge, +inf outside its live rows.  Every
     // lane loads (rows clamped into 1..L_li, so every address is in bounds) and
     // only lane 0's values are used: no branch in the step.
-    auto load_row = [&](int r, T& sv, T& bv) {
+    auto load_row = [&](int r, V& sv, T& bv) {
         const unsigned rc = (unsigned)__builtin_elementwise_min(__builtin_elementwise_max(r, 1), Lli);
         sv = li[rc - 1u];
         const T x = load_nc(bp + rc);
@@ -138,7 +154,8 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
             // the left border M(i, 0): computed for ERP, +inf otherwise
             e_lo = 1;
             e_hi = (KIND == ERP) ? Lli : 0;
-            bp = (KIND == ERP) ? lib - 1 : li - 1;
+            if constexpr (KIND == ERP) bp = lib - 1;
+            else bp = reinterpret_cast<const T*>(li) - 1;
         } else {
             bp = eb;
         }
@@ -155,8 +172,8 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
         full_top = (r_start == 1);
         // column values t_j of the strip (+inf beyond L_co) and t_{c0-1} (t_0 = 0)
 #pragma unroll
-        for (int u = 0; u < C; ++u) tv[u] = (c0 + u <= Lco) ? co[c0 + u - 1] : INF;
-        tpm = (c0 >= 2 && c0 - 1 <= Lco) ? co[c0 - 2] : (T)0;
+        for (int u = 0; u < C; ++u) tv[u] = (c0 + u <= Lco) ? co[c0 + u - 1] : inf_v<V>();
+        tpm = (c0 >= 2 && c0 - 1 <= Lco) ? co[c0 - 2] : (V)0;
 #pragma unroll
         for (int u = 0; u < C; ++u) {
             const T tprev = (u == 0) ? tpm : tv[u - 1];
@@ -181,7 +198,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
         // ERP's border M(0, c0-1), which makes the lane recompute its own top
         // border exactly, or +inf, which keeps +inf borders at +inf
         brd0 = (KIND == ERP) ? topl : INF;
-        s0 = (KIND == ERP) ? gap : (T)0;
+        s0 = (KIND == ERP) ? (V)gap : (V)0;
         // the last strip starts late enough that the last cell, (L_li, L_co) in
         // lane kend, is computed by the last step of a block: the result is then
         // read once, at the block end, from the buffer that step wrote
@@ -279,13 +296,14 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
         // +inf inputs, which reproduces their top border bit for bit; lanes past
         // the last row compute values nobody reads.
         auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t) {
-            T lin, sin;
+            T lin;
+            V sin;
             row += 1;
             {
                 // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G
                 const int src = lane - k + (t % G);
                 const T bv = __shfl(st_b[t / G], src);   // M(row, cb)
-                const T sv = __shfl(st_s[t / G], src);   // s_row
+                const V sv = __shfl(st_s[t / G], src);   // s_row
                 if constexpr (G == 16) {
                     // a group is one DPP row: shift and feed lane 0 at once
                     lin = row_shr1_or(lout, bv);
@@ -315,7 +333,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
 #pragma unroll
             for (int u = 0; u < C; ++u) {
                 const T top = src[u];
-                const T d = sin - tv[u];
+                const T d = (T)(sin - tv[u]);   // XD: formed in float64, rounded once
                 T v;
                 if constexpr (KIND == DTW || KIND == CDTW) {
                     v = (d * d) + vmin(vmin(diag, top), left);
@@ -460,38 +478,39 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C>())) void rows_ker
     wave_add_u64(&A.stage[8], npairs);
 }
 
-template <int KIND, typename T, int G, int C>
+template <int KIND, typename T, int G, int C, bool XD>
 static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s, int* occ) {
+    using V = RowValue<T, XD>;
     const int lds = rows_lds_bytes(KIND, sizeof(T) == 4, a);
     if (occ)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, reinterpret_cast<const void*>(&rows_kernel<KIND, T, G, C>),
-                                                            256, (size_t)lds);
-    Series<T> A{(const T*)SA.v, SA.off, (const T*)SA.border};
-    Series<T> B{(const T*)SB.v, SB.off, (const T*)SB.border};
-    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C>), dim3(grid), dim3(256), lds, s, a, A, B);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ, reinterpret_cast<const void*>(&rows_kernel<KIND, T, G, C, XD>), 256, (size_t)lds);
+    Series<V> A{(const V*)SA.v, SA.off, (const V*)SA.border};
+    Series<V> B{(const V*)SB.v, SB.off, (const V*)SB.border};
+    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C, XD>), dim3(grid), dim3(256), lds, s, a, A, B);
     return hipGetLastError();
 }
 
-template <int KIND, typename T>
+template <int KIND, typename T, bool XD = false>
 static hipError_t go_w(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s,
                        int* occ) {
     switch (sh.g * 1000 + sh.c) {
-    case 4008: return go<KIND, T, 4, 8>(a, SA, SB, grid, s, occ);
-    case 4016: return go<KIND, T, 4, 16>(a, SA, SB, grid, s, occ);
-    case 8008: return go<KIND, T, 8, 8>(a, SA, SB, grid, s, occ);
-    case 8016: return go<KIND, T, 8, 16>(a, SA, SB, grid, s, occ);
-    case 16008: return go<KIND, T, 16, 8>(a, SA, SB, grid, s, occ);
-    case 16016: return go<KIND, T, 16, 16>(a, SA, SB, grid, s, occ);
-    case 32008: return go<KIND, T, 32, 8>(a, SA, SB, grid, s, occ);
-    case 32016: return go<KIND, T, 32, 16>(a, SA, SB, grid, s, occ);
-    case 64008: return go<KIND, T, 64, 8>(a, SA, SB, grid, s, occ);
-    case 64016: return go<KIND, T, 64, 16>(a, SA, SB, grid, s, occ);
+    case 4008: return go<KIND, T, 4, 8, XD>(a, SA, SB, grid, s, occ);
+    case 4016: return go<KIND, T, 4, 16, XD>(a, SA, SB, grid, s, occ);
+    case 8008: return go<KIND, T, 8, 8, XD>(a, SA, SB, grid, s, occ);
+    case 8016: return go<KIND, T, 8, 16, XD>(a, SA, SB, grid, s, occ);
+    case 16008: return go<KIND, T, 16, 8, XD>(a, SA, SB, grid, s, occ);
+    case 16016: return go<KIND, T, 16, 16, XD>(a, SA, SB, grid, s, occ);
+    case 32008: return go<KIND, T, 32, 8, XD>(a, SA, SB, grid, s, occ);
+    case 32016: return go<KIND, T, 32, 16, XD>(a, SA, SB, grid, s, occ);
+    case 64008: return go<KIND, T, 64, 8, XD>(a, SA, SB, grid, s, occ);
+    case 64016: return go<KIND, T, 64, 16, XD>(a, SA, SB, grid, s, occ);
     }
     if constexpr (sizeof(T) == 4 && (KIND == DTW || KIND == WDTW)) {   // 32 columns per lane: registers
         switch (sh.g * 1000 + sh.c) {
-        case 16032: return go<KIND, T, 16, 32>(a, SA, SB, grid, s, occ);
-        case 32032: return go<KIND, T, 32, 32>(a, SA, SB, grid, s, occ);
-        case 64032: return go<KIND, T, 64, 32>(a, SA, SB, grid, s, occ);
+        case 16032: return go<KIND, T, 16, 32, XD>(a, SA, SB, grid, s, occ);
+        case 32032: return go<KIND, T, 32, 32, XD>(a, SA, SB, grid, s, occ);
+        case 64032: return go<KIND, T, 64, 32, XD>(a, SA, SB, grid, s, occ);
         }
     }
     return hipErrorInvalidValue;
@@ -511,7 +530,11 @@ bool rows_shape_ok(int kind, RowsShape sh, bool fp32) {
 }
 
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s, int* occ) {
+                       hipStream_t s, int* occ, bool xd) {
+    if (xd) {   // exact differences: FP32 WDTW on float64 series only
+        if (fp32 && kind == WDTW) return go_w<WDTW, float, true>(sh, a, A, B, grid, s, occ);
+        return hipErrorInvalidValue;
+    }
     if (fp32) {
         switch (kind) {
         case DTW: case CDTW: return go_w<DTW, float>(sh, a, A, B, grid, s, occ);

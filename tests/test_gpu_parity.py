@@ -837,6 +837,41 @@ def test_fp32_screen_gives_fp64_results(torch_dev, orc, kind, margin):
     assert c["stage_pairs"][4] + c["stage_pairs"][5] == c["rechecks"]
 
 
+@pytest.mark.parametrize("margin", [1e-4, 0.0])
+def test_fp32_screen_exact_differences_wdtw_long(torch_dev, orc, margin):
+    """WDTW of long series (weights near the diagonal around 1e-22): the FP32
+    screen forms its differences from the float64 values, and the NN must
+    equal the FP64 oracle's bit for bit, near-ties included."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(31)
+    qs = synth.random_walks(rng, 5, (1500, 2048))
+    rs = synth.random_walks(rng, 36, (64, 2048))
+    rs[3] = qs[0].copy()
+    rs[4] = qs[0].copy()
+    rs[4][100] += 1e-9
+    rs[7] = qs[2] + rng.normal(0, 1e-9, size=len(qs[2]))
+    rs[8] = qs[2] + rng.normal(0, 1e-9, size=len(qs[2]))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(kind="wdtw", g=0.05)
+    log(f"fp32 screen, exact differences, WDTW, margin {margin}")
+    ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, p, precision=1), dev)
+    eap.reset_counters(ws)
+    eap.profile_take()
+    eap.profile_enable(True)
+    g = eap.nn1(to_dev(torch, dev, qv), qo, to_dev(torch, dev, rv), ro, p, precision=1, margin_rel=margin, ws=ws)
+    torch.cuda.synchronize()
+    eap.profile_enable(False)
+    prof = eap.profile_take()
+    c = eap.read_counters(ws)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    assert np.array_equal(g[0].cpu().numpy(), oi) and np.array_equal(g[1].cpu().numpy(), od)
+    # the main sweep ran in FP32 with exact differences; the near-ties were rechecked
+    main = [x for x in prof if x["stage"] == 2]
+    assert main and all(x["fp32"] and x["exact_diff"] for x in main)
+    assert c["rechecks"] >= 2
+
+
 def test_fp32_screen_ragged_windows(torch_dev, orc):
     torch, dev = torch_dev
     rng = np.random.default_rng(8)
