@@ -25,7 +25,11 @@
  *   orc_eabase    EABase, Alg. 4: full rows, abandoned on a dead row.
  *   orc_ub        cost of the diagonal-then-straight warping path, an upper
  *                 bound usable as a prune-only cut-off (Section 4, intro).
- *   orc_nn1       NN search, Alg. 1 (strict '<', lowest index wins ties).
+ *   orc_envelope, orc_lb_keogh, orc_lb_kim
+ *                 the lower bounds of Section 2.1 (definitions).
+ *   orc_nn1       NN search, Alg. 1 (strict '<', lowest index wins ties); with
+ *                 the full DP, EAPruned, EABase, or EAPruned behind the lower
+ *                 bounds (Alg. 2).
  *   orc_pairwise  all pairs i<j, plain DP or prune-only EAPruned.
  *
  * Parity status: DTW, CDTW, ERP and MSM are pinned by the paper's worked
@@ -574,6 +578,69 @@ double orc_ub(int kind, const double* x, int64_t lx, const double* y, int64_t ly
  * cells_total (nullable) sums EAPruned's evaluated cells.  Queries run in
  * parallel over nthreads OpenMP threads (<= 0: the OpenMP default); the
  * count applies to this call only. */
+/* ------------------------------------------------------------------------- */
+/* Lower bounds for DTW and CDTW (Section 2.1: LB_Kim and LB_Keogh, used by
+ * the lower-bounded NN search, Alg. 2; Section 5.2 runs LB_Keogh and a
+ * second LB_Keogh with the arguments reversed, "lb-keogh2").  Both distances
+ * use the squared difference, and every warping path starts at (1,1), ends at
+ * (L_Q, L_C) and, under a window w, visits each column j of C only at rows i
+ * with |i - j| <= w. */
+
+/* Envelope of x (length L) under window w, at positions j = 1..n:
+ * up[j-1] = max and lo[j-1] = min of x_i over i in [j-w, j+w] and [1, L];
+ * an empty range (j > L + w) gives up = -inf, lo = +inf. */
+void orc_envelope(const double* x, int64_t L, int64_t w, int64_t n, double* up, double* lo)
+{
+    for (int64_t j = 1; j <= n; ++j) {
+        double u = -INF, l = INF;
+        for (int64_t i = imax(1, j - w); i <= imin(L, j + w); ++i) {
+            if (x[i - 1] > u) u = x[i - 1];
+            if (x[i - 1] < l) l = x[i - 1];
+        }
+        up[j - 1] = u;
+        lo[j - 1] = l;
+    }
+}
+
+/* Squared distance of v to the range [lo, up] (0 inside it). */
+static double dist_to_range(double v, double lo, double up)
+{
+    if (v > up) return (v - up) * (v - up);
+    if (v < lo) return (lo - v) * (lo - v);
+    return 0.0;
+}
+
+/* LB_Keogh(Q, C) under window w: the sum over the columns j = 1..L_C of C,
+ * left to right, of the squared distance of c_j to the envelope of Q at j.
+ * A path pays at least that much in column j.  +inf when the window admits
+ * no path (w < |L_Q - L_C|). */
+double orc_lb_keogh(const double* q, int64_t lq, const double* c, int64_t lc, int64_t w)
+{
+    if (w < (lq > lc ? lq - lc : lc - lq)) return INF;
+    double* up = (double*)malloc(sizeof(double) * (size_t)lc);
+    double* lo = (double*)malloc(sizeof(double) * (size_t)lc);
+    orc_envelope(q, lq, w, lc, up, lo);
+    double s = 0.0;
+    for (int64_t j = 0; j < lc; ++j) s = s + dist_to_range(c[j], lo[j], up[j]);
+    free(up);
+    free(lo);
+    return s;
+}
+
+/* LB_Kim in its first-and-last-points form: the costs of the cells (1,1)
+ * and (L_Q, L_C), which every path contains (one cell when both series have
+ * length 1). */
+double orc_lb_kim(const double* q, int64_t lq, const double* c, int64_t lc)
+{
+    double a = q[0] - c[0];
+    double s = a * a;
+    if (lq > 1 || lc > 1) {
+        double b = q[lq - 1] - c[lc - 1];
+        s = s + b * b;
+    }
+    return s;
+}
+
 void orc_nn1(int kind, const double* prm, const double* q, const int64_t* q_off, int64_t nq, const double* r,
              const int64_t* r_off, int64_t nr, int mode, int64_t* out_idx, double* out_dist, int nthreads,
              int64_t* cells_total)
@@ -596,6 +663,29 @@ void orc_nn1(int kind, const double* prm, const double* q, const int64_t* q_off,
                 int64_t c = 0;
                 d = orc_eap(kind, qa, la, rb, lb, prm, best, &c, NULL, NULL);
                 cells_sum += c;
+            } else if (mode == 2) {
+                int64_t c = 0;
+                d = orc_eabase(kind, qa, la, rb, lb, prm, best, &c);
+                cells_sum += c;
+            } else if (mode == 3) {
+                /* Alg. 2: a candidate is computed only while its lower bounds
+                 * stay below the best-so-far (DTW and CDTW): LB_Kim, then
+                 * LB_Keogh(Q, C), then LB_Keogh(C, Q), then EAPruned.  A bound
+                 * is compared after scaling by 1 - 1e-11, which covers its own
+                 * rounding and the distance's (sums of at most 2 x 2048 terms). */
+                d = INF;
+                int go = 1;
+                if (kind == ORC_DTW || kind == ORC_CDTW) {
+                    int64_t w = orc_window(kind, prm[P_WR], la, lb);
+                    go = orc_lb_kim(qa, la, rb, lb) * (1.0 - 1e-11) < best &&
+                         orc_lb_keogh(qa, la, rb, lb, w) * (1.0 - 1e-11) < best &&
+                         orc_lb_keogh(rb, lb, qa, la, w) * (1.0 - 1e-11) < best;
+                }
+                if (go) {
+                    int64_t c = 0;
+                    d = orc_eap(kind, qa, la, rb, lb, prm, best, &c, NULL, NULL);
+                    cells_sum += c;
+                }
             } else {
                 d = orc_dp(kind, qa, la, rb, lb, prm, NULL);
             }

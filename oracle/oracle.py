@@ -48,6 +48,12 @@ def lib():
         L.orc_eap.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _d, _pi64, _pi64, _pi64]
         L.orc_eabase.restype = _d
         L.orc_eabase.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd, _d, _pi64]
+        L.orc_envelope.restype = None
+        L.orc_envelope.argtypes = [_pd, _i64, _i64, _i64, _pd, _pd]
+        L.orc_lb_keogh.restype = _d
+        L.orc_lb_keogh.argtypes = [_pd, _i64, _pd, _i64, _i64]
+        L.orc_lb_kim.restype = _d
+        L.orc_lb_kim.argtypes = [_pd, _i64, _pd, _i64]
         L.orc_ub.restype = _d
         L.orc_ub.argtypes = [ctypes.c_int, _pd, _i64, _pd, _i64, _pd]
         L.orc_nn1.restype = None
@@ -130,14 +136,40 @@ def eabase(p: dict, x, y, cutoff: float = float("inf")):
     return d, c.value
 
 
+def envelope(x, w: int, n: int = 0):
+    """(up, lo) of x under window w at positions 1..n (default len(x))."""
+    x = _f64(x)
+    n = n or len(x)
+    up, lo = np.empty(n), np.empty(n)
+    lib().orc_envelope(_ptr(x), len(x), int(w), n, _ptr(up), _ptr(lo))
+    return up, lo
+
+
+def lb_keogh(q, c, w: int) -> float:
+    """LB_Keogh(Q, C): envelope of q under window w against the values of c."""
+    q, c = _f64(q), _f64(c)
+    return lib().orc_lb_keogh(_ptr(q), len(q), _ptr(c), len(c), int(w))
+
+
+def lb_kim(q, c) -> float:
+    """LB_Kim, first and last points."""
+    q, c = _f64(q), _f64(c)
+    return lib().orc_lb_kim(_ptr(q), len(q), _ptr(c), len(c))
+
+
 def ub(p: dict, x, y) -> float:
     x, y = _f64(x), _f64(y)
     prm = _prm(p)
     return lib().orc_ub(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm))
 
 
+NN_MODES = {"dp": 0, "eap": 1, "eabase": 2, "eap_lb": 3}
+
+
 def nn1(p: dict, q, q_off, r, r_off, mode: str = "eap", nthreads: int = 0):
-    """Alg. 1 over ragged sets; mode 'dp' (full DP) or 'eap' (EAPruned).
+    """Alg. 1 over ragged sets; mode 'dp' (full DP), 'eap' (EAPruned), 'eabase'
+    (Alg. 4) or 'eap_lb' (EAPruned behind LB_Kim, LB_Keogh and the reversed
+    LB_Keogh, Alg. 2; DTW and CDTW).
     Returns (idx int64[nq], dist float64[nq], cells evaluated)."""
     q, r = _f64(q), _f64(r)
     q_off = np.ascontiguousarray(q_off, dtype=np.int64)
@@ -148,7 +180,7 @@ def nn1(p: dict, q, q_off, r, r_off, mode: str = "eap", nthreads: int = 0):
     cells = ctypes.c_int64(0)
     prm = _prm(p)
     lib().orc_nn1(kind_id(p), _ptr(prm), _ptr(q), _iptr(q_off), nq, _ptr(r), _iptr(r_off), nr,
-                  1 if mode == "eap" else 0, _iptr(idx), _ptr(dist), int(nthreads), ctypes.byref(cells))
+                  NN_MODES[mode], _iptr(idx), _ptr(dist), int(nthreads), ctypes.byref(cells))
     return idx, dist, cells.value
 
 

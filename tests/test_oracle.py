@@ -487,3 +487,80 @@ def test_subseq_search_finds_a_planted_match(orc):
     for p in (dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.1)):
         idx, dist, _ = orc.nn1(p, q, np.array([0, m], dtype=np.int64), w, off, "dp")
         assert idx[0] == 150 and dist[0] < 1e-20
+
+
+# --- lower bounds (Section 2.1: LB_Kim, LB_Keogh; Section 5.2: reversed) -----
+
+def test_envelope_closed_forms(orc):
+    rng = np.random.default_rng(61)
+    x = rng.normal(size=37)
+    up, lo = orc.envelope(x, 0)
+    assert np.array_equal(up, x) and np.array_equal(lo, x)        # window 0: the series
+    up, lo = orc.envelope(x, 40)
+    assert (up == x.max()).all() and (lo == x.min()).all()          # window >= L: global range
+    inc = np.cumsum(np.abs(rng.normal(size=30)) + 0.1)              # increasing: range ends
+    for w in (1, 3, 7):
+        up, lo = orc.envelope(inc, w)
+        for j in range(1, 31):
+            assert up[j - 1] == inc[min(j + w, 30) - 1] and lo[j - 1] == inc[max(j - w, 1) - 1]
+    up, lo = orc.envelope(x, 2, n=45)                               # past L + w: empty range
+    assert up[-1] == -INF and lo[-1] == INF and up[38] == x[-1]
+
+
+def test_lb_keogh_window_zero_is_squared_euclidean(orc):
+    """Window 0: the envelope is the query itself, so LB_Keogh is the squared
+    Euclidean distance, which CDTW with window 0 also is (bitwise: the same
+    left-to-right sum)."""
+    rng = np.random.default_rng(62)
+    for L in (1, 5, 64, 300):
+        q, c = rng.normal(size=L), rng.normal(size=L)
+        assert orc.lb_keogh(q, c, 0) == orc.dp(dict(kind="cdtw", window_ratio=0.0), q, c)
+
+
+def test_lb_kim_hand_values(orc):
+    assert orc.lb_kim([1.0, 2.0, 3.0], [0.0, 5.0]) == 1.0 + 4.0
+    assert orc.lb_kim([2.0], [-1.0]) == 9.0                          # one shared cell
+    assert orc.lb_kim([2.0], [-1.0, 4.0]) == 9.0 + 4.0
+
+
+def test_lb_keogh_hand_value(orc):
+    # q = (0, 4, 1), w = 1: envelope ranges [0,4], [0,4], [1,4]; c = (5, -1, 2)
+    # adds (5-4)^2 + (0-(-1))^2 + 0 = 2
+    assert orc.lb_keogh([0.0, 4.0, 1.0], [5.0, -1.0, 2.0], 1) == 2.0
+
+
+@pytest.mark.parametrize("p", [dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.1),
+                               dict(kind="cdtw", window_ratio=0.3), dict(kind="cdtw", window_ratio=0.0)])
+def test_lower_bounds_below_distance(orc, p):
+    """LB_Kim, LB_Keogh both ways, and LB_Keogh under a wider window than the
+    pair's own are all <= D, on random pairs of equal and unequal lengths."""
+    rng = np.random.default_rng(63)
+    for it in range(300):
+        lq, lc = rng.integers(1, 40, size=2)
+        if it % 2:
+            lc = lq
+        q = synth.znorm(np.cumsum(rng.normal(size=lq))) if lq > 1 else rng.normal(size=1)
+        c = synth.znorm(np.cumsum(rng.normal(size=lc))) if lc > 1 else rng.normal(size=1)
+        d = orc.dp(p, q, c)
+        w = orc.window(p, lq, lc)
+        if d == INF:
+            assert orc.lb_keogh(q, c, w) == INF
+            continue
+        for lb in (orc.lb_kim(q, c), orc.lb_keogh(q, c, w), orc.lb_keogh(c, q, w),
+                   orc.lb_keogh(q, c, w + 3), orc.lb_keogh(c, q, max(lq, lc))):
+            assert lb <= d * (1 + 1e-12), (p, lq, lc, lb, d)
+
+
+@pytest.mark.parametrize("kind", ["dtw", "cdtw"])
+def test_nn_lower_bounded_and_eabase_match_full_dp(orc, kind):
+    """Alg. 2 (EAPruned behind LB_Kim, LB_Keogh and the reversed LB_Keogh) and
+    Alg. 4 (EABase) return the full DP's nearest neighbours."""
+    wl = synth.make_workload(2, n_ref=60, n_query=12, length=96)
+    p = wl["params"][kind]
+    ref = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "dp")
+    for mode in ("eap_lb", "eabase"):
+        got = orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], mode)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), mode
+    # the bounds skip work: fewer cells than EAPruned alone
+    assert orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "eap_lb")[2] < \
+        orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "eap")[2]
