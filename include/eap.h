@@ -108,9 +108,33 @@ typedef struct {
  *              over 2^18 or more candidates rebuilds the interleaved copy,
  *              which searches with the bound over such sets do not make).  For a resident candidate set
  *              searched by batch after batch (the request server uses it).
- *              bit 4: no lower bound: a CDTW search skips LB_Keogh and sweeps
- *              every pair under the cut-off; for ablation only.  Same results.
+ *              bit 4: prune only (Section 5's "Prune"): every pair is swept
+ *              under its own cut-off, one ulp above the cost of its
+ *              diagonal-then-straight warping path (an upper bound), with no
+ *              best-so-far shared between pairs: cells are pruned, nothing
+ *              is abandoned, every pair's value is exact.  Precision 0 only
+ *              (EAP_EINVAL otherwise); no seed sweep, no lower bounds.  For
+ *              ablation.  Same results.
+ *              bit 5: no pruning (EABase, Alg. 4): the row sweep computes
+ *              every row of every strip of a pair, abandoning the pair only
+ *              once nothing on its sweep boundary is <= cut-off.  (The band
+ *              sweep prunes nothing beyond the window anyway.)  For ablation.
+ *              Same results.
  *              Other bits: EAP_EINVAL.
+ *  lb          lower bounds in front of the sweep (DTW and CDTW only; the
+ *              other distances ignore it), eap_lb_mode:
+ *              EAP_LB_DEFAULT  CDTW: EAP_LB_KEOGH; DTW: EAP_LB_NONE.
+ *              EAP_LB_NONE     every pair is swept under the cut-off.
+ *              EAP_LB_KEOGH    LB_Keogh of the query's envelope against the
+ *                              candidate, its first and last columns taking
+ *                              the exact costs of the corner cells (LB_Kim).
+ *              EAP_LB_KEOGH2   then, for the pairs it keeps, the reversed
+ *                              LB_Keogh (the candidate's envelope against the
+ *                              query, Section 5.2's "lb-keogh2").
+ *              A pair whose bound exceeds the best-so-far is +inf without a
+ *              sweep; envelopes use the widest window any pair of the series
+ *              has (for DTW the series' range).  Results do not depend on it.
+ *              Other values: EAP_EINVAL.
  *  main_wait   hipEvent_t or NULL: the stream waits for it before the main
  *              sweep (after the bounds, the seed sweep and the screen set-up).
  *  main_done   hipEvent_t or NULL: recorded on the stream right after the main
@@ -121,12 +145,14 @@ typedef struct {
  *              latency-bound stages of the neighbouring searches overlap
  *              them.  Both must be NULL while the stream is being captured.
  *              The caller owns the events; results do not depend on them. */
+typedef enum { EAP_LB_DEFAULT = 0, EAP_LB_NONE = 1, EAP_LB_KEOGH = 2, EAP_LB_KEOGH2 = 3 } eap_lb_mode;
 typedef struct {
     int32_t precision;
     double margin_rel;
     int32_t flags;
     void* main_wait;
     void* main_done;
+    int32_t lb;
 } eap_nn_opts;
 
 /* Counters accumulated in a workspace by the calls that use it (zero them with
@@ -203,11 +229,10 @@ eap_status eap_distance_noalloc(const double* x, int64_t lx, const double* y, in
  *                      finite distance (window too small for every one).
  *  out_dist            device double[nq]: the distance, or +inf.
  *  out_label           device int32[nq] or NULL: r_labels[idx], -1 when idx < 0.
- * For CDTW (window ratio < 1) the search puts LB_Keogh in front of the DP
- * (the lower-bounded search of Section 2.1, Alg. 2): a pair whose bound exceeds the
- * cut-off is +inf without a sweep.  The bound uses the query's envelope over
- * the widest window any of its pairs has; results are those of the search
- * without it. */
+ * DTW and CDTW searches can put lower bounds in front of the DP (the
+ * lower-bounded search of Section 2.1, Alg. 2; eap_nn_opts.lb): a pair whose
+ * bound exceeds the cut-off is +inf without a sweep; results are those of the
+ * search without them. */
 size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off, int64_t nr, const eap_params* p,
                          const eap_nn_opts* o);
 eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const double* r, const int64_t* r_off,
@@ -267,6 +292,21 @@ eap_status eap_znorm(const double* v, const int64_t* off, int64_t n, double* out
 size_t eap_derivative_workspace(int64_t n);
 eap_status eap_derivative(const double* v, const int64_t* off, int64_t n, double* out, void* ws, size_t ws_bytes,
                           void* stream);
+
+/* Envelopes for LB_Keogh (Section 2.1), as the NN search builds them: for
+ * every series s of a ragged set and positions j = 1..npos,
+ * up[s*npos + j-1] / lo[s*npos + j-1] = max / min of s_i over i in [j-w, j+w]
+ * and [1, L_s], with w = floor(window_ratio * max(L_s, other_max)) (the widest
+ * window of any pair of s with series of length <= other_max; window_ratio
+ * >= 1: the whole series); an empty range gives (+inf, -inf).  O(L) per
+ * series (van Herk / Gil-Werman; the values are copies of inputs).
+ *  v, off, n          device values, host offsets (n >= 1 series, lengths 1..2048).
+ *  npos               1..2048; other_max 0..2048; window_ratio >= 0.
+ *  up, lo             device double[n * npos] each.
+ *  ws                 device workspace of eap_envelopes_workspace(n) bytes. */
+size_t eap_envelopes_workspace(int64_t n);
+eap_status eap_envelopes(const double* v, const int64_t* off, int64_t n, int64_t npos, int64_t other_max,
+                         double window_ratio, double* up, double* lo, void* ws, size_t ws_bytes, void* stream);
 
 /* Copies the counters accumulated in `ws` to host memory (synchronises `stream`).
  * eap_reset_counters() zeroes them (asynchronously, on `stream`). */

@@ -19,14 +19,16 @@ import numpy as np
 
 __all__ = ["params", "distance", "distance_noalloc", "nn1", "pairwise", "workspace", "read_counters", "reset_counters",
            "profile_enable", "profile_take", "wdtw_weights", "EapError", "lib", "KINDS", "FLAG_NO_SEED",
-           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "FLAG_NO_LB", "derivative", "znorm", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
+           "FLAG_PLAIN", "FLAG_PREPARED", "FLAG_CANDIDATES", "FLAG_PRUNE_ONLY", "FLAG_NO_PRUNE", "LB_MODES", "derivative", "envelopes", "znorm", "subseq_windows", "subseq_search", "tune_nn1", "tune_set", "tune_reset", "capture_begin", "capture_end", "Graph",
            "Server"]
 
 FLAG_NO_SEED = 1   # skip the seeding sweep (ablation)
 FLAG_PLAIN = 2        # plain full DP for every pair: the baseline
 FLAG_PREPARED = 4     # offsets and tables already in the workspace: kernels only (graph capture)
 FLAG_CANDIDATES = 8   # the workspace holds what an earlier call derived from these same candidates
-FLAG_NO_LB = 16       # CDTW: no LB_Keogh in front of the sweep (ablation)
+FLAG_PRUNE_ONLY = 16  # each pair under its own path bound, no shared best-so-far (Section 5's Prune)
+FLAG_NO_PRUNE = 32    # early abandoning without pruning (EABase, Alg. 4)
+LB_MODES = {"default": 0, "none": 1, "keogh": 2, "keogh2": 3}   # eap_nn_opts.lb (DTW and CDTW)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeap.so")
@@ -49,7 +51,7 @@ class Params(ctypes.Structure):
 
 class NNOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("margin_rel", ctypes.c_double), ("flags", ctypes.c_int32),
-                ("main_wait", ctypes.c_void_p), ("main_done", ctypes.c_void_p)]
+                ("main_wait", ctypes.c_void_p), ("main_done", ctypes.c_void_p), ("lb", ctypes.c_int32)]
 
 
 class Counters(ctypes.Structure):
@@ -111,6 +113,10 @@ def lib():
         L.eap_distance_workspace.argtypes = [_i64, _i64, _pP]
         L.eap_distance.restype = ctypes.c_int
         L.eap_distance.argtypes = [_vp, _i64, _vp, _i64, _pP, _d, _vp, _vp, _sz, _vp]
+        L.eap_envelopes_workspace.restype = _sz
+        L.eap_envelopes_workspace.argtypes = [_i64]
+        L.eap_envelopes.restype = ctypes.c_int
+        L.eap_envelopes.argtypes = [_vp, _pi64, _i64, _i64, _i64, _d, _vp, _vp, _vp, _sz, _vp]
         L.eap_screen_eps.restype = _d
         L.eap_screen_eps.argtypes = [ctypes.c_int32, ctypes.c_int32, _d, _d, _d]
         L.eap_screen_bound.restype = _d
@@ -275,10 +281,16 @@ def distance_noalloc(x, y, p, cutoff: float = math.inf, out=None, stream=None):
     return out
 
 
-def nn1_workspace_bytes(q_off, r_off, p, precision: int = 0) -> int:
+def _lb_mode(lb) -> int:
+    if lb not in LB_MODES:
+        raise ValueError(f"lb must be one of {sorted(LB_MODES)}")
+    return LB_MODES[lb]
+
+
+def nn1_workspace_bytes(q_off, r_off, p, precision: int = 0, lb: str = "default") -> int:
     q_off, r_off = _offsets(q_off), _offsets(r_off)
     p = _as_params(p)
-    o = NNOpts(precision, 1e-4, 0)
+    o = NNOpts(precision, 1e-4, 0, None, None, _lb_mode(lb))
     return int(lib().eap_nn1_workspace(q_off.ctypes.data_as(_pi64), len(q_off) - 1, r_off.ctypes.data_as(_pi64),
                                        len(r_off) - 1, ctypes.byref(p), ctypes.byref(o)))
 
@@ -295,12 +307,14 @@ def _event_handle(ev, stream, device):
 
 
 def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: float = 1e-4, flags: int = 0,
-        ws=None, stream=None, out=None, main_wait=None, main_done=None):
+        ws=None, stream=None, out=None, main_wait=None, main_done=None, lb: str = "default"):
     """1-NN search (Alg. 1).  q, r: float64 device tensors of concatenated
     series; q_off, r_off: host int64 offsets.  Returns (idx int64, dist float64,
     label int32 or None) device tensors.  main_wait / main_done: optional
     torch.cuda.Event the main sweep waits for / that is recorded after it, to
-    chain several searches on several streams."""
+    chain several searches on several streams.  lb: lower bounds in front of
+    the sweep for DTW and CDTW, one of LB_MODES ('default': LB_Keogh for
+    CDTW, none for DTW; 'keogh2' adds the reversed LB_Keogh)."""
     import torch
     _dev_f64(q, "queries")
     _dev_f64(r, "candidates")
@@ -310,8 +324,8 @@ def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: 
     _sized(r, r_off, "candidates")
     p = _as_params(p)
     o = NNOpts(int(precision), float(margin_rel), int(flags), _event_handle(main_wait, stream, q.device),
-               _event_handle(main_done, stream, q.device))
-    ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision), q.device) if ws is None else _ws(ws)
+               _event_handle(main_done, stream, q.device), _lb_mode(lb))
+    ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision, lb), q.device) if ws is None else _ws(ws)
     if out is None:
         idx = torch.empty(nq, dtype=torch.int64, device=q.device)
         dist = torch.empty(nq, dtype=torch.float64, device=q.device)
@@ -532,6 +546,23 @@ def derivative(v, off, ws=None, stream=None, out=None):
     _check(lib().eap_derivative(v.data_ptr(), off.ctypes.data_as(_pi64), n, out.data_ptr(), ws.data_ptr(),
                                 ws.numel(), _stream(stream, v.device)))
     return out
+
+
+def envelopes(v, off, npos: int, window_ratio: float, other_max: int = 0, ws=None, stream=None):
+    """LB_Keogh envelopes (eap_envelopes): (up, lo), device tensors of shape
+    (n, npos) for the series of v (device float64) with host offsets off."""
+    import torch
+    _dev_f64(v, "series")
+    off = _offsets(off)
+    n = len(off) - 1
+    _sized(v, off, "series")
+    ws = workspace(int(lib().eap_envelopes_workspace(n)), v.device) if ws is None else _ws(ws)
+    up = torch.empty((n, npos), dtype=torch.float64, device=v.device)
+    lo = torch.empty((n, npos), dtype=torch.float64, device=v.device)
+    _check(lib().eap_envelopes(v.data_ptr(), off.ctypes.data_as(_pi64), n, int(npos), int(other_max),
+                               float(window_ratio), up.data_ptr(), lo.data_ptr(), ws.data_ptr(), ws.numel(),
+                               _stream(stream, v.device)))
+    return up, lo
 
 
 def pairwise_workspace_bytes(s_off, p) -> int:

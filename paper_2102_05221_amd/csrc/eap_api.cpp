@@ -753,11 +753,21 @@ bool screen_possible(const eap_params* p, int64_t lmax) {
     return 1.0 / (1.0 + std::exp(p->g * (double)lmax / 2.0)) >= 1e-30;
 }
 
+// Lower bounds a search uses (eap_nn_opts.lb resolved for the distance swept).
+int lb_mode(const eap_params* p, const eap_nn_opts* o) {
+    const int k = effective_kind(p);
+    if (k != EAP_DTW && k != EAP_CDTW) return EAP_LB_NONE;
+    const int m = o ? o->lb : EAP_LB_DEFAULT;
+    if (m == EAP_LB_DEFAULT) return k == EAP_CDTW ? EAP_LB_KEOGH : EAP_LB_NONE;
+    return m;
+}
+
 struct NNLayout {
     Layout L;
     Common c;
     size_t best = 0, seed = 0, seed_items = 0, res = 0, ovf = 0, edge = 0, rT = 0, part = 0;
-    size_t env = 0, lb = 0;   // CDTW: query envelopes (env_stride layout) and LB_Keogh per pair
+    size_t env = 0, lb = 0;     // lower bounds: query envelopes (env_stride layout) and the bound per pair
+    size_t cenv = 0;            // reversed LB_Keogh: candidate envelopes, [position][nr], upper then lower
     // FP32 screen
     size_t q32 = 0, r32 = 0, q32b = 0, r32b = 0, widen = 0, recheck = 0;
 };
@@ -768,7 +778,7 @@ struct NNLayout {
 // other queries and the candidates-prepared flag finds what an earlier call
 // derived.  Then the query side and the per-pair arrays.
 static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params* p, bool prec1, bool screen,
-                            NNLayout& nl) {
+                            int lbm, NNLayout& nl) {
     Layout& L = nl.L;
     Common& c = nl.c;
     c.hdr = L.take(kHeaderBytes);
@@ -799,10 +809,11 @@ static eap_status nn_layout(const SetInfo& Q, const SetInfo& R, const eap_params
     nl.seed_items = nl.L.take(sizeof(int32_t) * (size_t)Q.n);
     nl.res = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     nl.ovf = nl.L.take(sizeof(int32_t) * (size_t)(Q.n * R.n));
-    if (effective_kind(p) == EAP_CDTW) {
+    if (lbm >= EAP_LB_KEOGH) {
         nl.env = nl.L.take(sizeof(double) * 3 * (size_t)env_stride(Q.n, R.maxlen));
         nl.lb = nl.L.take(sizeof(double) * (size_t)(Q.n * R.n));
     }
+    if (lbm == EAP_LB_KEOGH2) nl.cenv = nl.L.take(sizeof(double) * 2 * (size_t)(Q.maxlen * R.n));
     nl.edge = nl.L.take(edge_bytes(Q.n * R.n, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)));
     if (screen) {
         nl.q32 = nl.L.take(sizeof(float) * (size_t)Q.total);
@@ -822,7 +833,7 @@ size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off,
         return 0;
     NNLayout nl;
     const bool prec1 = o && o->precision == 1;
-    nn_layout(Q, R, p, prec1, prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen)), nl);
+    nn_layout(Q, R, p, prec1, prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen)), lb_mode(p, o), nl);
     return nl.L.off;
 }
 
@@ -839,19 +850,23 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     if (o) {
         if (o->precision != 0 && o->precision != 1) return fail(EAP_EINVAL, "precision must be 0 or 1");
         if (!(std::isfinite(o->margin_rel) && o->margin_rel >= 0)) return fail(EAP_EINVAL, "margin_rel must be >= 0");
-        if (o->flags & ~31) return fail(EAP_EINVAL, "unknown flags 0x%x", (unsigned)o->flags);
+        if (o->flags & ~63) return fail(EAP_EINVAL, "unknown flags 0x%x", (unsigned)o->flags);
+        if ((o->flags & 16) && o->precision != 0) return fail(EAP_EINVAL, "prune-only search runs in FP64 (precision 0)");
+        if (o->lb < EAP_LB_DEFAULT || o->lb > EAP_LB_KEOGH2) return fail(EAP_EINVAL, "unknown lb mode %d", o->lb);
     }
     const bool prec1 = o && o->precision == 1;
     const bool screen = prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen));
     const bool xd = screen && screen_exact_diff(p, std::max(Q.maxlen, R.maxlen));
     const int skind = effective_kind(p) | (xd ? kScreenExactDiff : 0);   // the screen bound's mode
+    const int lbm = lb_mode(p, o);
     NNLayout nl;
-    nn_layout(Q, R, p, prec1, screen, nl);
+    nn_layout(Q, R, p, prec1, screen, lbm, nl);
     if (eap_status st_ws = check_ws(ws, ws_bytes, nl.L.off)) return st_ws;
     Plan pl;
     const int64_t ldiff = std::max(std::llabs(Q.maxlen - R.minlen), std::llabs(R.maxlen - Q.minlen));
     const bool plain = o && (o->flags & 2);
-    const bool seeded = !plain && !(o && (o->flags & 1));
+    const bool prune_only = !plain && o && (o->flags & 16);
+    const bool seeded = !plain && !prune_only && !(o && (o->flags & 1));
     const bool prepared = o && (o->flags & 4);
     const bool cand_ready = o && (o->flags & 8);
     // exact-difference sweeps run on the row sweep only (no narrow WDTW band)
@@ -877,7 +892,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     // them in their own layout (building the copy would cost a full extra read
     // and write of the set).  The choice depends on the candidates and the
     // flags only, so calls with flags bit 3 find the copy when they need it.
-    const bool lbk = effective_kind(p) == EAP_CDTW && !(o && (o->flags & 16));
+    const bool lbk = lbm >= EAP_LB_KEOGH && !plain && !prune_only;
     const bool direct = lbk && nr >= kDirectReadMinCandidates;
     const bool need_rT = !direct;
     if (!cand_ready) {
@@ -892,7 +907,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         if (prec1 && p->kind == EAP_ERP)
             HIPCHK(launch_to_f32(static_cast<const double*>(SR.border), R.total,
                                  reinterpret_cast<float*>(at(ws, nl.r32b)), s));
-    } else if (need_rT && effective_kind(p) == EAP_CDTW && nr >= kDirectReadMinCandidates) {
+    } else if (need_rT && (effective_kind(p) == EAP_CDTW || effective_kind(p) == EAP_DTW) &&
+               nr >= kDirectReadMinCandidates) {
         // an earlier call with LB_Keogh over this large set made no interleaved copy
         HIPCHK(launch_interleave(r, SR.off, nr, (int)R.maxlen, rT, nullptr, nullptr, s));
     }
@@ -913,6 +929,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     a.edge = edge_bytes(nq * nr, std::max(Q.maxlen, R.maxlen), std::min(Q.maxlen, R.maxlen)) ? at(ws, nl.edge)
                                                                                              : nullptr;
     a.edge_stride = std::max(Q.maxlen, R.maxlen) + 1;
+    a.no_prune = (o && (o->flags & 32)) ? 1 : 0;
     if (plain) {
         // baseline: every pair by the full dynamic programme
         a.plain = 1;
@@ -928,6 +945,24 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, direct ? r : nullptr, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
                         lbk ? reinterpret_cast<double*>(at(ws, nl.env)) : nullptr, lb, s));
     a.lb = lb;
+    if (prune_only) {
+        // Section 5's "Prune": each pair under its own path bound (one ulp
+        // above it), no best-so-far shared between pairs, so nothing is
+        // abandoned and every result is exact
+        HIPCHK(launch_next_up(res, nq * nr, s));
+        a.prune_only = 1;
+        a.pcut = res;
+        if (main_wait) HIPCHK(hipStreamWaitEvent(s, main_wait, 0));
+        if ((st = sweep(p, pl, pl.band, a, h, 2, &h->queues[2], nullptr, nq * nr, SQ, SR, s)) != EAP_OK) return st;
+        if (pl.rerun) {
+            if ((st = rerun_overflow(p, pl, a, h, 3, &h->ovf_count[0], ovf, nq * nr, &h->queues[3], SQ, SR, s)) !=
+                EAP_OK)
+                return st;
+        }
+        if (main_done) HIPCHK(hipEventRecord(main_done, s));
+        HIPCHK(launch_argmin(res, nq, nr, r_labels, out_idx, out_dist, out_label, part, s));
+        return EAP_OK;
+    }
     HIPCHK(launch_seed(res, nq, nr, seed, seed_items, best, part, s));
     const bool rerun = pl.rerun;
     // the seed and recheck sweeps have one or a few pairs per query
@@ -985,6 +1020,16 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         main_items = ovf;
         m.npairs_dev = &h->ovf_count[3];
         m.skip_b = nullptr;
+        if (lbm == EAP_LB_KEOGH2) {
+            // the reversed LB_Keogh for the pairs kept: the candidates' envelopes
+            // at the queries' positions, then each kept pair's larger bound; the
+            // sweep drops a pair whose bound exceeds its query's cut-off
+            double* cup = reinterpret_cast<double*>(at(ws, nl.cenv));
+            double* clo = cup + (size_t)(Q.maxlen * nr);
+            HIPCHK(launch_envelope(r, SR.off, nr, (int)R.maxlen, (int)Q.maxlen, (int)Q.maxlen, a.window_ratio, cup, clo,
+                                   nullptr, 1, nr, s));
+            HIPCHK(launch_lb_reverse(q, SQ.off, r, SR.off, nr, cup, clo, ovf, &h->ovf_count[3], nq * nr, lb, s));
+        }
     }
     if (main_wait) HIPCHK(hipStreamWaitEvent(s, main_wait, 0));
     if ((st = sweep(p, pl, pl.band, m, h, 2, &h->queues[2], main_items, nq * nr, XQ, XR, s, screen, true, xd)) !=
@@ -1074,6 +1119,26 @@ eap_status eap_derivative(const double* v, const int64_t* off, int64_t n, double
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload(ws, off, sizeof(int64_t) * (size_t)(n + 1), s)) != EAP_OK) return st;
     HIPCHK(launch_derivative(v, reinterpret_cast<const int64_t*>(ws), n, out, s));
+    return EAP_OK;
+}
+
+size_t eap_envelopes_workspace(int64_t n) { return eap_derivative_workspace(n); }
+
+eap_status eap_envelopes(const double* v, const int64_t* off, int64_t n, int64_t npos, int64_t other_max,
+                         double window_ratio, double* up, double* lo, void* ws, size_t ws_bytes, void* stream) {
+    eap_status st;
+    if (!v || !up || !lo) return fail(EAP_EINVAL, "NULL series or output");
+    SetInfo S;
+    if ((st = check_offsets(off, n, "series", &S)) != EAP_OK) return st;
+    if (npos < 1 || npos > kMaxLen) return fail(EAP_EINVAL, "npos %lld outside 1..%lld", (long long)npos,
+                                                (long long)kMaxLen);
+    if (other_max < 0 || other_max > kMaxLen) return fail(EAP_EINVAL, "other_max outside 0..%lld", (long long)kMaxLen);
+    if (std::isnan(window_ratio) || window_ratio < 0) return fail(EAP_EINVAL, "window_ratio must be >= 0");
+    if (eap_status st_ws = check_ws(ws, ws_bytes, eap_envelopes_workspace(n))) return st_ws;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload(ws, off, sizeof(int64_t) * (size_t)(n + 1), s)) != EAP_OK) return st;
+    HIPCHK(launch_envelope(v, reinterpret_cast<const int64_t*>(ws), n, (int)S.maxlen, (int)other_max, (int)npos,
+                           window_ratio, up, lo, nullptr, npos, 1, s));
     return EAP_OK;
 }
 

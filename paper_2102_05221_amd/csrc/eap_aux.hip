@@ -131,6 +131,15 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, int
         p[x] = v;
 }
 
+// x[i] = the next double above x[i] (+inf stays +inf): prune-only cut-offs
+// from path bounds, in place.
+__global__ void next_up_kernel(double* x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u = x[i];
+        if (u < __builtin_huge_val()) x[i] = bitsd(dbits(u) + 1ull);
+    }
+}
+
 // Host words delivered through the kernel's argument block (no staging
 // buffer, no copy call): dst[x] = w.w[x] for x < n <= kPutWords.
 __global__ void put_u64_kernel(unsigned long long* dst, int n, PutWords w) {
@@ -327,35 +336,170 @@ __global__ __launch_bounds__(256) void interleave_kernel(const double* rv, const
     }
 }
 
-// CDTW lower bound (LB_Keogh): for candidate column j the query values within
-// the window, rows max(1, j-w)..min(L_q, j+w), span [lo_j, up_j]; every warping
-// path visits column j at such a row, so D >= sum_j dist(t_j, [lo_j, up_j])^2.
-// The envelope uses the widest window any pair of the query can have,
-// w = floor(ratio * max(L_q, longest candidate)), which only widens it (a
-// looser, still valid bound).  One block per query; columns with no row in
-// the window get (-inf, +inf) (such pairs are infeasible anyway).
-__global__ void envelope_kernel(const double* qv, const int64_t* qoff, int64_t nq, int lr_max, int64_t ld,
-                                double ratio, double* up, double* lo, double* qx) {
-    for (int64_t a = blockIdx.x; a < nq; a += gridDim.x) {
-        const double* s = qv + qoff[a];
-        const int lq = (int)(qoff[a + 1] - qoff[a]);
-        const int L = lq > lr_max ? lq : lr_max;
-        const int w = (int)floor(ratio * (double)L);
-        for (int j = threadIdx.x + 1; j <= lr_max; j += blockDim.x) {
-            const int i0 = j - w < 1 ? 1 : j - w, i1 = j + w < lq ? j + w : lq;
-            double u = -__builtin_huge_val(), l = __builtin_huge_val();
-            for (int i = i0; i <= i1; ++i) {
-                u = fmax(u, s[i - 1]);
-                l = fmin(l, s[i - 1]);
-            }
-            if (i0 > i1) {
-                u = __builtin_huge_val();
-                l = -__builtin_huge_val();
-            }
-            up[a * ld + j - 1] = u;
-            lo[a * ld + j - 1] = l;
-            qx[a * ld + j - 1] = s[(j < lq ? j : lq) - 1];
+// Envelopes for LB_Keogh (Section 2.1; Section 5.2 computes them in O(L) with
+// Lemire's streaming algorithm).  For series s of a ragged set and positions
+// j = 1..npos: up_j / lo_j = max / min of s_i over i in [j-w, j+w] and
+// [1, L_s], with w = floor(ratio * max(L_s, other_max)), the widest window of
+// any pair of s (a wider window only loosens the bound); a position whose
+// range is empty (j > L_s + w) gets (+inf, -inf), which adds nothing.
+//
+// O(L) on the GPU without a sequential deque: the van Herk / Gil-Werman
+// decomposition.  Padded with the operation's identity to P[0 .. M), M =
+// npos + 2w, every window is the k = 2w + 1 entries P[j-1 .. j-1+2w]; with
+// P cut into blocks of k, g[p] = max of P from p's block start to p and
+// h[p] = max from p to its block end, the window's max is max(h[j-1],
+// g[j-1+2w]) (one block boundary inside).  Both are segmented scans: 256
+// threads take consecutive chunks, scan them, pass the carries across
+// chunks with a segmented Hillis-Steele scan in LDS, and rescan.  Three
+// comparisons per entry for each of max and min.  One block per series; w
+// at or above max(L_s, npos) is clamped there (the window then covers the
+// whole series).  Results are copies of input values, so the layout of the
+// arithmetic cannot change them.
+//
+// Layout: out[s * s_stride + (j-1) * p_stride]; with qx != NULL also the
+// series extended by its last value, qx[..] = s_{min(j, L_s)}.
+template <bool MAX>
+__device__ __forceinline__ double env_op(double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); }
+
+template <bool MAX>
+__device__ void env_pass(const double* v, int L, int w, int npos, int M, double* g, double* h, double* out,
+                         int64_t p_stride, double* carry, unsigned char* head) {
+    const double ID = MAX ? -__builtin_huge_val() : __builtin_huge_val();
+    const int k = 2 * w + 1;
+    const int T = blockDim.x, t = threadIdx.x;
+    const int E = (M + T - 1) / T, p0 = t * E, p1 = p0 + E < M ? p0 + E : M;
+    auto P = [&](int p) { return (p >= w && p - w < L) ? v[p - w] : ID; };
+    // forward: prefix within blocks of k (heads at p % k == 0)
+    double run = ID;
+    bool hd = false;
+    for (int p = p0; p < p1; ++p) {
+        const double x = P(p);
+        if (p % k == 0) {
+            run = x;
+            hd = true;
+        } else {
+            run = env_op<MAX>(run, x);
         }
+        g[p] = run;
+    }
+    carry[t] = run;
+    head[t] = hd ? 1 : 0;
+    __syncthreads();
+    for (int o = 1; o < T; o <<= 1) {   // inclusive segmented scan of (head, value) over the chunks
+        const double cv = t >= o ? carry[t - o] : ID;
+        const unsigned char ch = t >= o ? head[t - o] : 1;
+        __syncthreads();
+        if (t >= o && !head[t]) {
+            carry[t] = env_op<MAX>(cv, carry[t]);
+            head[t] = ch;
+        }
+        __syncthreads();
+    }
+    const double cin = t > 0 ? carry[t - 1] : ID;   // the block's part before this chunk
+    for (int p = p0; p < p1 && p % k != 0; ++p) g[p] = env_op<MAX>(cin, g[p]);
+    __syncthreads();
+    // backward: suffix within blocks (heads at block ends: p % k == k - 1 or p == M - 1)
+    run = ID;
+    hd = false;
+    for (int p = p1 - 1; p >= p0; --p) {
+        const double x = P(p);
+        if (p % k == k - 1 || p == M - 1) {
+            run = x;
+            hd = true;
+        } else {
+            run = env_op<MAX>(run, x);
+        }
+        h[p] = run;
+    }
+    carry[t] = run;
+    head[t] = hd ? 1 : 0;
+    __syncthreads();
+    for (int o = 1; o < T; o <<= 1) {   // the same scan from the right
+        const double cv = t + o < T ? carry[t + o] : ID;
+        const unsigned char ch = t + o < T ? head[t + o] : 1;
+        __syncthreads();
+        if (t + o < T && !head[t]) {
+            carry[t] = env_op<MAX>(cv, carry[t]);
+            head[t] = ch;
+        }
+        __syncthreads();
+    }
+    const double cout = t + 1 < T ? carry[t + 1] : ID;
+    for (int p = p1 - 1; p >= p0 && !(p % k == k - 1 || p == M - 1); --p) h[p] = env_op<MAX>(cout, h[p]);
+    __syncthreads();
+    for (int j = t; j < npos; j += T) {
+        const int e = j + k - 1 < M ? j + k - 1 : M - 1;
+        double r = env_op<MAX>(h[j], g[e]);
+        if (j + 1 - w > L) r = -ID;   // empty range: up = +inf, lo = -inf
+        out[(int64_t)j * p_stride] = r;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void envelope_kernel(const double* v, const int64_t* off, int64_t n, int npos,
+                                                       int other_max, double ratio, double* up, double* lo,
+                                                       double* qx, int64_t s_stride, int64_t p_stride) {
+    extern __shared__ double env_lds[];
+    __shared__ double carry[256];
+    __shared__ unsigned char head[256];
+    for (int64_t a = blockIdx.x; a < n; a += gridDim.x) {
+        const double* x = v + off[a];
+        const int L = (int)(off[a + 1] - off[a]);
+        const int Lw = L > other_max ? L : other_max;
+        const int cap = L > npos ? L : npos;
+        int w = ratio >= 1.0 ? cap : (int)floor(ratio * (double)Lw);
+        w = w > cap ? cap : w;
+        const int M = npos + 2 * w;
+        double* g = env_lds;
+        double* h = env_lds + M;
+        env_pass<true>(x, L, w, npos, M, g, h, up + a * s_stride, p_stride, carry, head);
+        env_pass<false>(x, L, w, npos, M, g, h, lo + a * s_stride, p_stride, carry, head);
+        if (qx)
+            for (int j = threadIdx.x; j < npos; j += blockDim.x)
+                qx[a * s_stride + (int64_t)j * p_stride] = x[(j + 1 < L ? j + 1 : L) - 1];
+    }
+}
+
+// Reversed LB_Keogh ("lb-keogh2", Section 5.2): for the pairs listed by the
+// first bound, the candidate's envelope against the query's values.  Every
+// path visits each row i of the query at a column within the candidate's
+// window of i, so D >= sum_i dist(q_i, [clo_i, cup_i])^2; as in the first
+// bound, the first and last rows take the exact costs of the corner cells
+// (1,1) and (L_q, L_r), which every path contains (LB_Kim).  The pair keeps
+// the larger of its two bounds.  Candidate envelopes are interleaved
+// (cup[i * nr + b]), so lanes on consecutive candidates read consecutive
+// addresses.  One lane per listed pair, grid-stride up to the device count.
+__global__ __launch_bounds__(256) void lb_reverse_kernel(const double* qv, const int64_t* qoff, const double* rv,
+                                                         const int64_t* roff, int64_t nr, const double* cup,
+                                                         const double* clo, const int32_t* items,
+                                                         const unsigned int* count, double* lb) {
+    const int64_t n = (int64_t)*count;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = items[x];
+        const int64_t a = p / nr, b = p - a * nr;
+        const double* q = qv + qoff[a];
+        const int lq = (int)(qoff[a + 1] - qoff[a]);
+        const double* r = rv + roff[b];
+        const int lr = (int)(roff[b + 1] - roff[b]);
+        double s = 0.0;
+        for (int i = 0; i < lq; ++i) {
+            const double y = q[i];
+            const double e = fmax(fmax(y - cup[(int64_t)i * nr + b], clo[(int64_t)i * nr + b] - y), 0.0);
+            s = s + e * e;
+        }
+        // corners: row 1 holds (1,1), row L_q holds (L_q, L_r)
+        const double d1 = q[0] - r[0], dL = q[lq - 1] - r[lr - 1];
+        const double e1 = fmax(fmax(q[0] - cup[b], clo[b] - q[0]), 0.0);
+        s = s + (d1 * d1 - e1 * e1);
+        if (lq >= 2) {
+            const double eL = fmax(fmax(q[lq - 1] - cup[(int64_t)(lq - 1) * nr + b], clo[(int64_t)(lq - 1) * nr + b] -
+                                                                                          q[lq - 1]),
+                                   0.0);
+            s = s + (dL * dL - eL * eL);
+        } else if (lr >= 2) {
+            s = s + dL * dL;   // row 1 also holds (1, L_r)
+        }
+        lb[p] = fmax(lb[p], s);
     }
 }
 
@@ -382,16 +526,17 @@ __global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qof
     }
 }
 
-// CDTW: the path bound and LB_Keogh of QT queries against 256 candidates per
-// block, in one pass over each candidate's values (read once for all QT
-// queries; query values and envelopes by scalar loads).  The candidates come
+// DTW and CDTW: the path bound and LB_Keogh (with LB_Kim's exact corner
+// cells) of QT queries against 256 candidates per block, in one pass over each
+// candidate's values (read once for all QT queries; query values and
+// envelopes by scalar loads).  For DTW the envelope is the query's range.  The candidates come
 // from the interleaved copy rT (coalesced), or with rv != NULL from their own
 // layout: a lane takes 8 consecutive values of its candidate per chunk, which
 // for very large candidate sets costs less than building the copy.  Each bound adds its
 // terms in path order (the diagonal, then the longer series' tail), like
 // path_ub_acc; (a - b)^2 and (b - a)^2 are the same double.
 template <int QT>
-__global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const double* qv, const int64_t* qoff,
+__global__ __launch_bounds__(256) void ub_lb_kernel(SweepArgs A, const double* qv, const int64_t* qoff,
                                                          const double* rv, const double* rT, const int64_t* roff,
                                                          int64_t ld,
                                                          const double* env_up, const double* env_lo,
@@ -488,6 +633,27 @@ __global__ __launch_bounds__(256) void ub_lb_cdtw_kernel(SweepArgs A, const doub
                 const double d = qv[qb[t] + i] - xl;
                 acc[t] = (d * d) + acc[t];
             }
+        }
+        // LB_Kim (first and last points): the first and last columns take the
+        // exact costs of the cells (1,1) and (L_q, L_r) that every path holds,
+        // in place of their envelope terms (which are no larger: for a
+        // feasible pair q_1 and q_{L_q} lie in those columns' ranges)
+        const double x1 = rv ? rv[ro] : rT[bb];
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+            if (t >= nqt) continue;
+            const int64_t eb = (a0 + t) * ld;
+            const double q1 = qv[qb[t]], qL = qv[qb[t] + lq[t] - 1];
+            const double e1 = fmax(fmax(x1 - env_up[eb], env_lo[eb] - x1), 0.0);
+            const double d1 = x1 - q1, dL = xl - qL;
+            double c = d1 * d1 - e1 * e1;
+            if (lr >= 2) {
+                const double eL = fmax(fmax(xl - env_up[eb + lr - 1], env_lo[eb + lr - 1] - xl), 0.0);
+                c = c + (dL * dL - eL * eL);
+            } else if (lq[t] >= 2) {
+                c = c + dL * dL;   // column 1 also holds (L_q, 1)
+            }
+            lbv[t] = lbv[t] + c;
         }
         if (live) {
 #pragma unroll
@@ -943,6 +1109,11 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
+hipError_t launch_next_up(double* x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(next_up_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_put_u64(unsigned long long* dst, const unsigned long long* src, int n, hipStream_t s) {
     if (n < 0 || n > kPutWords) return hipErrorInvalidValue;
     PutWords w;
@@ -1014,17 +1185,45 @@ hipError_t launch_screen_filter(int kind, const SweepArgs& a, const int64_t* qof
     return hipGetLastError();
 }
 
+hipError_t launch_envelope(const double* v, const int64_t* off, int64_t n, int set_max, int other_max, int npos,
+                           double ratio, double* up, double* lo, double* qx, int64_t s_stride, int64_t p_stride,
+                           hipStream_t s) {
+    const int cap = std::max(set_max, npos);
+    int w = ratio >= 1.0 ? cap : (int)std::floor(ratio * (double)std::max(set_max, other_max));
+    w = std::min(w, cap);
+    const size_t lds = sizeof(double) * 2 * (size_t)(npos + 2 * w);
+    static bool attr_set = false;
+    if (!attr_set && lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&envelope_kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(envelope_kernel, dim3((unsigned)std::min<int64_t>(n, 65535)), dim3(256), lds, s, v, off, n, npos,
+                       other_max, ratio, up, lo, qx, s_stride, p_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_reverse(const double* qv, const int64_t* qoff, const double* rv, const int64_t* roff, int64_t nr,
+                             const double* cup, const double* clo, const int32_t* items, const unsigned int* count,
+                             int64_t max_items, double* lb, hipStream_t s) {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((max_items + 255) / 256, 256 * 16));
+    hipLaunchKernelGGL(lb_reverse_kernel, dim3((unsigned)blocks), dim3(256), 0, s, qv, qoff, rv, roff, nr, cup, clo,
+                       items, count, lb);
+    return hipGetLastError();
+}
+
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
                         const int64_t* roff, int lq_max, int lr_max, const double* rT, double* ub, double* env,
                         double* lb, hipStream_t s) {
-    if (kind == CDTW && lb && env) {
-        // CDTW: the query envelopes (upper, lower, and the query extended by
-        // its last value: three arrays of env_stride doubles), then bound and
+    if ((kind == CDTW || kind == DTW) && lb && env) {
+        // the query envelopes (upper, lower, and the query extended by its
+        // last value: three arrays of env_stride doubles), then bound and
         // LB_Keogh of up to 16 queries per pass over the candidates
         const int64_t stride = env_stride(a.nA, lr_max), ld = env_ld(lr_max);
         double *up = env, *lo = env + stride, *qx = env + 2 * stride;
-        hipLaunchKernelGGL(envelope_kernel, dim3(std::min<int64_t>(a.nA, 65535)), dim3(256), 0, s, qv, qoff, a.nA,
-                           lr_max, ld, a.window_ratio, up, lo, qx);
+        hipError_t e = launch_envelope(qv, qoff, a.nA, lq_max, lr_max, lr_max, a.window_ratio, up, lo, qx, ld, 1, s);
+        if (e != hipSuccess) return e;
         // queries per block: the most that still leaves at least 2 blocks per
         // CU (fewer reads of the candidates)
         const int64_t bx = (a.nB + 255) / 256;
@@ -1039,7 +1238,7 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
                 break;
             }
         const dim3 gq((unsigned)bx, (unsigned)std::min<int64_t>((a.nA + qt - 1) / qt, 65535));
-#define EAP_UBLB(QT) hipLaunchKernelGGL(ub_lb_cdtw_kernel<QT>, gq, dim3(256), 0, s, a, qv, qoff, rv, rT, roff, ld, \
+#define EAP_UBLB(QT) hipLaunchKernelGGL(ub_lb_kernel<QT>, gq, dim3(256), 0, s, a, qv, qoff, rv, rT, roff, ld, \
                                         up, lo, qx, lb, ub)
         switch (qt) {
         case 16: EAP_UBLB(16); break;

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
     const int lane = threadIdx.x & 63;
     const int k = lane & (G - 1);
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane - k));
-    const bool nn = is_nn_mode(A.mode) && !A.plain;
+    // NN search with a shared best-so-far (not the plain DP, not prune-only)
+    const bool nn = is_nn_mode(A.mode) && !A.plain && !A.prune_only;
     const T gap = (T)A.gap;
 
     bool have = false, done = false, fin = false, ovf = false, lo_open = false, hi_open = false;

@@ -32,6 +32,13 @@ struct SweepArgs {
     unsigned long long* stage;       // [0] cells of this launch's stage, [8] its pairs
     // plain DP: cut-off +inf for every item, no best-so-far, no abandoning
     int plain;
+    // NN items under a per-item cut-off pcut[p] instead of the best-so-far
+    // (prune-only: one ulp above the pair's path bound, so nothing is abandoned)
+    int prune_only;
+    // no pruning (EABase, Alg. 4): every strip of the row sweep starts at row 1
+    // and runs to the last row; a pair is still abandoned once nothing on the
+    // sweep's boundary is <= cut-off
+    int no_prune;
     // distance parameters
     double gap, c, nu, lam;
     // Per-diagonal tables, indexed by (j - i) + tab_off:
@@ -115,9 +122,22 @@ hipError_t launch_max_u64(unsigned long long* dst, const unsigned long long* src
 // them in aligned chunks of 8.
 inline int64_t env_ld(int64_t lr_max) { return (lr_max + 7) & ~(int64_t)7; }
 inline int64_t env_stride(int64_t nq, int64_t lr_max) { return nq * env_ld(lr_max); }
+// Envelopes of a ragged set (device offsets) for LB_Keogh: positions 1..npos,
+// window floor(ratio * max(L_s, other_max)) per series (ratio >= 1: the whole
+// series), out[s * s_stride + (j-1) * p_stride]; qx (nullable): the series
+// extended by its last value.  set_max: the set's longest series.
+hipError_t launch_envelope(const double* v, const int64_t* off, int64_t n, int set_max, int other_max, int npos,
+                           double ratio, double* up, double* lo, double* qx, int64_t s_stride, int64_t p_stride,
+                           hipStream_t s);
+// Reversed LB_Keogh over the listed pairs (items[0 .. *count)): the candidate
+// envelopes cup / clo (interleaved, [position][nr]) against the query values;
+// lb[p] becomes the larger of its two bounds.
+hipError_t launch_lb_reverse(const double* qv, const int64_t* qoff, const double* rv, const int64_t* roff, int64_t nr,
+                             const double* cup, const double* clo, const int32_t* items, const unsigned int* count,
+                             int64_t max_items, double* lb, hipStream_t s);
 // Path upper bound of every (query, candidate) pair from rT (launch_interleave);
-// for CDTW with env (3 x env_stride doubles) and lb also the query envelopes
-// and LB_Keogh, reading the candidates from rT, or with rv != NULL from rv /
+// for DTW and CDTW with env (3 x env_stride doubles) and lb also the query
+// envelopes and LB_Keogh with LB_Kim's corners, reading the candidates from rT, or with rv != NULL from rv /
 // roff in their own layout (rT unused).
 hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const int64_t* qoff, const double* rv,
                         const int64_t* roff, int lq_max, int lr_max, const double* rT, double* ub, double* env,
@@ -134,6 +154,8 @@ hipError_t launch_seed(const double* ub, int64_t nq, int64_t nr, int32_t* seed_b
 hipError_t launch_argmin(const double* res, int64_t nq, int64_t nr, const int32_t* labels, int64_t* out_idx,
                          double* out_dist, int32_t* out_label, double* part, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+// x[i] = the next double above x[i], in place (+inf unchanged).
+hipError_t launch_next_up(double* x, int64_t n, hipStream_t s);
 // Up to kPutWords host words written to dst by one kernel whose argument
 // block carries them: a host-to-device transfer that needs no staging memory
 // and no copy call (the call that allocates nothing uses it).

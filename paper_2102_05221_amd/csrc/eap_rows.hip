@@ -87,7 +87,8 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     const int lane = threadIdx.x & 63;
     const int k = lane & (G - 1);
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane - k));
-    const bool nn = is_nn_mode(A.mode) && !A.plain;
+    // NN search with a shared best-so-far (not the plain DP, not prune-only)
+    const bool nn = is_nn_mode(A.mode) && !A.plain && !A.prune_only;
     const T gap = (T)A.gap, cc = (T)A.c, nu = (T)A.nu, lam = (T)A.lam;
     // this group's edge buffer: M(i, cb) of the previous strip, i = 0..L_li
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     // left inputs: bp[i] = M(i, cb) for e_lo <= i <= e_hi (until a pair is
     // fetched, and in the first strip of +inf borders, a valid dummy range)
     const T* bp = reinterpret_cast<const T*>(SA.v) - 1;
-    unsigned long long ncells = 0, npairs = 0;
+    unsigned long long ncells = 0, npairs = 0, nlb = 0;
 #pragma unroll
     for (int u = 0; u < C; ++u) val[u] = vb[u] = tv[u] = aux[u] = 0;
 #pragma unroll
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         // the first row: 1, unless the strip's top border and the incoming edge
         // are > cut-off down to some row (only for strips after the first)
         r_start = 1;
-        if (si > 0) {
+        if (si > 0 && !A.no_prune) {
             bool top_live = (e_lo <= 1);
             if constexpr (KIND == ERP) top_live = top_live || (cob[cb] <= cut);   // M(0, cb+1)
             if (!top_live) r_start = e_lo;
@@ -251,6 +252,17 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
                 }
                 if (nn) cut = nn_cut<T>(A, it.a);
                 else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
+                // a lower bound above the cut-off (DTW searches with lower
+                // bounds): D > cut-off, +inf without a sweep (the factor covers
+                // the rounding of the bound and of the DP)
+                if (nn && A.lb && A.lb[out] * (1.0 - 1e-11) > (double)cut) {
+                    if (k == 0) {
+                        A.res[out] = __builtin_huge_val();
+                        ++npairs;
+                        ++nlb;
+                    }
+                    continue;
+                }
                 si = 0;
                 start_strip();
                 have = true;
@@ -451,7 +463,8 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
                 drop = true;
             } else if (!last && (send || !alive)) {
                 if (nhi < nlo) drop = true;   // no edge row <= cut-off: no path goes on
-                else next_strip = true;
+                else if (send || !A.no_prune) next_strip = true;
+                // without pruning the strip goes on to its last row
             } else if (!alive) {
                 drop = true;
             }
@@ -476,6 +489,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     wave_add_u64(&A.counters[1], npairs);
     wave_add_u64(&A.stage[0], ncells);
     wave_add_u64(&A.stage[8], npairs);
+    wave_add_u64(&A.counters[4], nlb);
 }
 
 template <int KIND, typename T, int G, int C, bool XD>

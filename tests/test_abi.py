@@ -122,7 +122,10 @@ def test_nn1_argument_errors(L):
     assert call(ro_=np.array([0, 4, 4, 13], dtype=np.int64)) == eap.EAP_EINVAL   # a zero-length series
     assert call(oo=eap.NNOpts(7, 1e-4, 0)) == eap.EAP_EINVAL
     assert call(oo=eap.NNOpts(1, float("nan"), 0)) == eap.EAP_EINVAL
-    assert call(oo=eap.NNOpts(0, 1e-4, 32)) == eap.EAP_EINVAL   # unknown flag bit
+    assert call(oo=eap.NNOpts(0, 1e-4, 64)) == eap.EAP_EINVAL   # unknown flag bit
+    assert call(oo=eap.NNOpts(1, 1e-4, eap.FLAG_PRUNE_ONLY)) == eap.EAP_EINVAL   # prune-only is FP64
+    assert call(oo=eap.NNOpts(0, 1e-4, 0, None, None, 4)) == eap.EAP_EINVAL      # unknown lb mode
+    assert call(oo=eap.NNOpts(0, 1e-4, 0, None, None, -1)) == eap.EAP_EINVAL
     assert call(nb=need - 1) == eap.EAP_EWORKSPACE
     assert call(w=ctypes.c_void_p(0x2008)) == eap.EAP_EWORKSPACE   # not 256-byte aligned
 

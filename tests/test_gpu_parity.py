@@ -437,7 +437,7 @@ def test_cdtw_lower_bound_prunes_and_keeps_the_nn(torch_dev, orc, precision):
     assert c["lb_pruned"] > 0
     # with the bound switched off every pair is swept, with the same results
     eap.reset_counters(ws)
-    gi, gd, _ = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, precision=precision, ws=ws, flags=eap.FLAG_NO_LB)
+    gi, gd, _ = eap.nn1(q, wl["query_off"], r, wl["ref_off"], p, precision=precision, ws=ws, lb="none")
     assert eap.read_counters(ws)["lb_pruned"] == 0
     assert np.array_equal(gi.cpu().numpy(), oi)
     assert np.array_equal(gd.cpu().numpy(), od)
@@ -581,7 +581,7 @@ def test_candidates_prepared_flag(torch_dev, orc, kind, precision):
         qv, qo = packed[1]
         log(f"candidates prepared {kind} precision={precision} without LB_Keogh")
         gi, gd, _ = eap.nn1(to_dev(torch, dev, qv), qo, r, ro, p, precision=precision, ws=ws,
-                            flags=eap.FLAG_CANDIDATES | eap.FLAG_NO_LB)
+                            flags=eap.FLAG_CANDIDATES, lb="none")
         oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
         assert np.array_equal(gi.cpu().numpy(), oi)
         assert np.array_equal(gd.cpu().numpy(), od)
@@ -608,9 +608,9 @@ def test_cdtw_very_many_candidates_read_in_place(torch_dev, orc, precision):
     ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, p, precision=1), dev)
     oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "eap")
     assert oi[1] == nr - 2 and od[1] == 0.0
-    for flags in (0, eap.FLAG_CANDIDATES | eap.FLAG_NO_LB, eap.FLAG_CANDIDATES):
-        log(f"cdtw very many candidates precision={precision} flags={flags}")
-        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, ws=ws, flags=flags)
+    for flags, lb in ((0, "default"), (eap.FLAG_CANDIDATES, "none"), (eap.FLAG_CANDIDATES, "default")):
+        log(f"cdtw very many candidates precision={precision} flags={flags} lb={lb}")
+        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, ws=ws, flags=flags, lb=lb)
         assert np.array_equal(gi.cpu().numpy(), oi), flags
         assert np.array_equal(gd.cpu().numpy(), od), flags
 
@@ -915,3 +915,74 @@ def test_counters_accumulate(torch_dev):
     c2 = eap.read_counters(ws)
     assert c1["pairs"] > 0 and c1["cells"] > 0
     assert c2["pairs"] == 2 * c1["pairs"]
+
+
+@pytest.mark.parametrize("ratio", [0.0, 0.05, 0.3, 0.99, 1.0, 2.0])
+def test_envelopes_match_oracle(torch_dev, orc, ratio):
+    """The O(L) envelope kernel (segmented scans) against the definition."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(int(ratio * 100) + 3)
+    series = synth.random_walks(rng, 23, (1, 700)) + [rng.normal(size=1), rng.normal(size=2048)]
+    v, off = synth.pack(series)
+    vd = to_dev(torch, dev, v)
+    for npos, other in ((700, 0), (2048, 2048), (64, 900), (1, 5)):
+        log(f"envelopes ratio={ratio} npos={npos} other_max={other}")
+        up, lo = eap.envelopes(vd, off, npos, ratio, other)
+        torch.cuda.synchronize()
+        up, lo = up.cpu().numpy(), lo.cpu().numpy()
+        for i, x in enumerate(series):
+            L = len(x)
+            cap = max(L, npos)
+            w = cap if ratio >= 1 else min(int(math.floor(ratio * max(L, other))), cap)
+            ou, ol = orc.envelope(x, w, npos)
+            empty = np.arange(1, npos + 1) > L + w
+            assert np.array_equal(up[i][~empty], ou[~empty]) and np.array_equal(lo[i][~empty], ol[~empty]), (i, L)
+            assert (up[i][empty] == INF).all() and (lo[i][empty] == -INF).all()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("p", [dict(kind="dtw"), dict(kind="cdtw", window_ratio=0.1),
+                               dict(kind="cdtw", window_ratio=0.3)], ids=pid)
+def test_nn_lower_bound_modes(torch_dev, orc, p, precision):
+    """lb-none, lb-keogh (with LB_Kim's corners) and lb-keogh2 (plus the
+    reversed LB_Keogh) give the oracle's NN, for DTW and CDTW, ragged lengths."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(77)
+    qs = synth.random_walks(rng, 9, (20, 400))
+    rs = synth.random_walks(rng, 150, (10, 420))
+    rs[4] = qs[3].copy()                               # an exact match
+    rs[9] = qs[5] + rng.normal(0, 1e-9, size=len(qs[5]))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    for lb in ("none", "keogh", "keogh2", "default"):
+        log(f"nn lower bounds {pid(p)} lb={lb} precision={precision}")
+        ws = eap.workspace(eap.nn1_workspace_bytes(qo, ro, p, precision=precision, lb=lb), dev)
+        eap.reset_counters(ws)
+        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, ws=ws, lb=lb)
+        c = eap.read_counters(ws)
+        assert np.array_equal(gi.cpu().numpy(), oi) and np.array_equal(gd.cpu().numpy(), od), lb
+        if lb == "none":
+            assert c["lb_pruned"] == 0
+        elif lb in ("keogh", "keogh2"):
+            assert c["lb_pruned"] > 0, lb
+
+
+@pytest.mark.parametrize("p", ALL, ids=pid)
+def test_nn_prune_only_and_no_pruning(torch_dev, orc, p):
+    """Ablation modes: prune-only (each pair under its own path bound, FP64)
+    and early abandoning without pruning (EABase), FP64 and FP32 screen."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(78)
+    qs = synth.random_walks(rng, 7, (30, 700))
+    rs = synth.random_walks(rng, 60, (20, 700))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    for flags, precision in ((eap.FLAG_PRUNE_ONLY, 0), (eap.FLAG_NO_PRUNE, 0), (eap.FLAG_NO_PRUNE, 1)):
+        log(f"nn ablation mode {pid(p)} flags={flags} precision={precision}")
+        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, flags=flags)
+        torch.cuda.synchronize()
+        assert np.array_equal(gi.cpu().numpy(), oi) and np.array_equal(gd.cpu().numpy(), od), (flags, precision)
