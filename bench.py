@@ -264,32 +264,60 @@ def run_pairwise(args, torch, eap, synth):
 ap_default_kinds = "dtw,cdtw,wdtw,erp,msm,twe"
 
 
-def ablation(torch, eap, stream, q, q_off, r, r_off, params, ws, ref, dense, kinds):
-    """The search's parts switched off one at a time (Section 5's ranking of
-    the full DP, early abandoning with pruning, and lower bounds, on the GPU):
-    every variant is one nn1 call per distance, timed with HIP events on the
-    search's stream after an untimed run, its results checked against the
-    default path's.  Variants: plain FP64 DP (no cut-off), EAPruned FP64 with
-    the cut-off starting at each pair's path bound (no seed sweep), EAPruned
-    FP64, for CDTW EAPruned FP64 without LB_Keogh, and the default FP32 screen
-    + FP64 recheck."""
-    variants = [("plain_dp_fp64", 0, eap.FLAG_PLAIN), ("eapruned_fp64_no_seed", 0, eap.FLAG_NO_SEED),
-                ("eapruned_fp64", 0, 0), ("eapruned_fp64_no_lb", 0, eap.FLAG_NO_LB),
-                ("eapruned_fp32_screen", 1, 0)]
+ABLATION = [
+    # name, precision, flags, lower bounds, distances it applies to (None: all)
+    ("base_plain_dp_fp64", 0, "plain", "none", None),
+    ("pruned_fp64", 0, "prune_only", "none", None),
+    ("eabase_fp64", 0, "no_prune", "none", None),
+    ("eapruned_fp64_no_seed", 0, "no_seed", "none", None),
+    ("eapruned_fp64", 0, "", "none", None),
+    ("eabase_fp64_lb_keogh2", 0, "no_prune", "keogh2", ("dtw", "cdtw")),
+    ("eapruned_fp64_lb_keogh", 0, "", "keogh", ("dtw", "cdtw")),
+    ("eapruned_fp64_lb_keogh2", 0, "", "keogh2", ("dtw", "cdtw")),
+    ("eapruned_fp32_screen_default", 1, "", "default", None),
+]
+
+
+def ablation(torch, eap, stream, q, q_off, r, r_off, params, ref, dense, kinds):
+    """The search with its parts switched off one at a time, on the GPU
+    (Section 5.1's Base, Prune, EABase and EAPruned; Section 5.2's lower
+    bounds lb-none, lb-keogh, lb-keogh2 for DTW and CDTW): every variant is
+    one nn1 call per distance, timed with HIP events on the search's stream
+    after an untimed run, its results checked against the default path's
+    (`ref`, which the CPU-baseline leg checks against the oracle).
+      base_plain_dp_fp64         Base: the full DP, no cut-off
+      pruned_fp64                Prune: each pair under its own path bound (nothing
+                                 abandoned), no shared best-so-far; at the GPU's strip
+                                 granularity PrunedDTW's pruning is this too
+      eabase_fp64                EABase: best-so-far cut-off, early abandoning, no
+                                 pruning (every strip row is computed)
+      eapruned_fp64_no_seed      EAPruned without the seed sweep
+      eapruned_fp64              EAPruned, no lower bound (at strip granularity
+                                 PrunedDTW+EA coincides with it)
+      eabase_fp64_lb_keogh2      EABase behind LB_Keogh both ways
+      eapruned_fp64_lb_keogh     EAPruned behind LB_Keogh (with LB_Kim's corners)
+      eapruned_fp64_lb_keogh2    and the reversed LB_Keogh
+      eapruned_fp32_screen_default  the default search (FP32 screen + FP64 recheck,
+                                 LB_Keogh for CDTW)"""
+    flag = {"": 0, "plain": eap.FLAG_PLAIN, "prune_only": eap.FLAG_PRUNE_ONLY, "no_prune": eap.FLAG_NO_PRUNE,
+            "no_seed": eap.FLAG_NO_SEED}
+    nq = len(q_off) - 1
+    ws = {k: eap.workspace(eap.nn1_workspace_bytes(q_off, r_off, params[k], precision=1, lb="keogh2"), q.device)
+          for k in kinds}
     out = {}
-    for name, prec, flags in variants:
+    for name, prec, fl, lb, only in ABLATION:
         per, total, same = {}, 0.0, True
         for k in kinds:
-            if flags == eap.FLAG_NO_LB and params[k]["kind"] != "cdtw":
+            if only is not None and params[k]["kind"] not in only:
                 continue
-            nq = len(q_off) - 1
             o = (torch.empty(nq, dtype=torch.int64, device=q.device),
                  torch.empty(nq, dtype=torch.float64, device=q.device), None)
             for rep in range(2):
                 if rep:
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     a.record(stream)
-                eap.nn1(q, q_off, r, r_off, params[k], ws=ws[k], out=o, precision=prec, flags=flags)
+                eap.nn1(q, q_off, r, r_off, params[k], ws=ws[k], out=o, precision=prec, flags=flag[fl], lb=lb,
+                        stream=stream)
                 if rep:
                     b.record(stream)
                 torch.cuda.synchronize()
@@ -299,6 +327,7 @@ def ablation(torch, eap, stream, q, q_off, r, r_off, params, ws, ref, dense, kin
             same &= bool(np.array_equal(o[0].cpu().numpy(), ref[k][0]) and np.array_equal(o[1].cpu().numpy(), ref[k][1]))
         if per:
             out[name] = dict(ms=total, per_distance=per, nn_identical=same)
+    del ws
     return out
 
 
@@ -313,8 +342,10 @@ def main():
                          "default 16 for workload 4, 500 for workload 2)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-DP comparison")
     ap.add_argument("--ablation", action="store_true",
-                    help="workloads 2 and 6: also time the search with its parts switched off one at a time "
-                         "(plain DP, no seed, FP64 only, no LB_Keogh), after the timed region")
+                    help="workloads 2, 4 and 6: also time the search with its parts switched off one at a time "
+                         "(Base, Prune, EABase, EAPruned, lower bounds lb-none / lb-keogh / lb-keogh2), after the "
+                         "timed region; workload 4 on its first --ablation-queries queries")
+    ap.add_argument("--ablation-queries", type=int, default=100)
     ap.add_argument("--precision", type=int, default=None,
                     help="0: FP64 sweep; 1: FP32 screen + FP64 recheck (default 1, and 0 for workload 6, where "
                          "LB_Keogh leaves so few pairs that the screen's extra stages cost more than they save)")
@@ -551,7 +582,7 @@ def main():
 
     abl = None
     if args.ablation:
-        abl = ablation(torch, eap, stream, q, wl["query_off"], r, wl["ref_off"], wl["params"], ws,
+        abl = ablation(torch, eap, stream, q, wl["query_off"], r, wl["ref_off"], wl["params"],
                        {k: (gpu_idx[k], gpu_dist[k]) for k in kinds}, dense, kinds)
 
     # the same step under the other schedules (secondary figures, after the
@@ -781,6 +812,16 @@ def run_batched(args, torch, eap, synth):
                      ms_per_step_estimate=est, speedup_of_eapruned=est / ms_per_step)
         del pws
 
+    abl = None
+    if args.ablation:
+        say("ablation")
+        aq = min(args.ablation_queries, nq)
+        aqo = qo[: aq + 1]
+        abl = ablation(torch, eap, s, q[: qo[aq]], aqo, r, ro, P,
+                       {k: (outs[k][0][:aq].cpu().numpy(), outs[k][1][:aq].cpu().numpy()) for k in kinds},
+                       {k: dense_cells(k, P[k], aqo, ro) for k in kinds}, kinds)
+        abl = dict(sample=f"first {aq} queries x all {nr} candidates", variants=abl)
+
     cpu = None
     if args.cpu_queries > 0:
         say("CPU oracle baseline")
@@ -802,7 +843,7 @@ def run_batched(args, torch, eap, synth):
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)), step_ms_p99=float(np.percentile(step_ms, 99)),
         graph_results_identical_to_eager=same, tuning=tuning, per_distance=per, plain_gpu_dp=plain,
-        roofline=roofline, cpu_baseline=cpu)), flush=True)
+        ablation=abl, roofline=roofline, cpu_baseline=cpu)), flush=True)
 
 
 def run_subseq(args, torch, eap, synth):
@@ -893,7 +934,7 @@ def run_subseq(args, torch, eap, synth):
         roofline["traffic"], roofline["traffic_note"] = hbm_traffic(kernel)
     abl = None
     if args.ablation:
-        abl = ablation(torch, eap, stream, zq, q_off, w, r_off, P, ws,
+        abl = ablation(torch, eap, stream, zq, q_off, w, r_off, P,
                        {k: (outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()) for k in kinds}, dense, kinds)
     # the oracle on the whole workload, timed like one step: the windows and
     # the queries normalised, then the NN search; the GPU answers compared

@@ -52,6 +52,19 @@ __device__ __forceinline__ double row_shr1_or(double v, double first) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// Value of the lane whose byte address (lane * 4) is `addr`, from every lane
+// (ds_bpermute).  With a loop-invariant base and a constant added to it, the
+// constant lands in the instruction's offset field.
+__device__ __forceinline__ float bperm(int addr, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double bperm(int addr, double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
 // Non-negative doubles order like their bit patterns, +inf above every finite.

@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     const T INF = inf_v<T>();
     const int lane = threadIdx.x & 63;
     const int k = lane & (G - 1);
+    const int gaddr = (lane - k) * 4;   // byte address of the group's first lane (ds_bpermute)
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane - k));
     // NN search with a shared best-so-far (not the plain DP, not prune-only)
     const bool nn = is_nn_mode(A.mode) && !A.plain && !A.prune_only;
@@ -313,9 +314,8 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
             row += 1;
             {
                 // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G
-                const int src = lane - k + (t % G);
-                const T bv = __shfl(st_b[t / G], src);   // M(row, cb)
-                const V sv = __shfl(st_s[t / G], src);   // s_row
+                const T bv = bperm(gaddr + 4 * (t % G), st_b[t / G]);   // M(row, cb)
+                const V sv = bperm(gaddr + 4 * (t % G), st_s[t / G]);   // s_row
                 if constexpr (G == 16) {
                     // a group is one DPP row: shift and feed lane 0 at once
                     lin = row_shr1_or(lout, bv);
