@@ -48,8 +48,33 @@
 
 enum { ORC_DTW = 0, ORC_CDTW = 1, ORC_WDTW = 2, ORC_ERP = 3, ORC_MSM = 4, ORC_TWE = 5 };
 
-/* prm[] layout used by every entry point: window_ratio, g, gap, c, nu, lambda */
-enum { P_WR = 0, P_G = 1, P_GAP = 2, P_C = 3, P_NU = 4, P_LAMBDA = 5 };
+/* prm[] layout used by every entry point: window_ratio, g, gap, c, nu, lambda,
+ * dims.  dims > 1 (DTW and CDTW only) makes every series point a vector of
+ * dims values, stored point after point; lengths and offsets count points. */
+enum { P_WR = 0, P_G = 1, P_GAP = 2, P_C = 3, P_NU = 4, P_LAMBDA = 5, P_DIMS = 6 };
+
+static int dims_of(const double* prm)
+{
+    int d = (int)prm[P_DIMS];
+    return d < 1 ? 1 : d;
+}
+
+/* Squared Euclidean cost of two points of dims channels (Section 2.3: the
+ * cost is "usually the squared Euclidean distance"; for multivariate series
+ * it runs over the channels), added channel by channel from the first; one
+ * channel gives d*d exactly as the univariate cost. */
+static double sqcost(const double* x, int64_t i, const double* y, int64_t j, int dims)
+{
+    const double* a = x + (i - 1) * dims;
+    const double* b = y + (j - 1) * dims;
+    double d = a[0] - b[0];
+    double s = d * d;
+    for (int c = 1; c < dims; ++c) {
+        double e = a[c] - b[c];
+        s = s + e * e;
+    }
+    return s;
+}
 
 #define INF HUGE_VAL
 
@@ -125,7 +150,7 @@ static double cell_dp(int kind, const double* prm, const double* W, const double
     switch (kind) {
     case ORC_DTW:
     case ORC_CDTW: {
-        double cost = d * d;
+        double cost = sqcost(x, i, y, j, dims_of(prm));
         return cost + dmin3(diag, top, left);
     }
     case ORC_WDTW: {
@@ -218,7 +243,7 @@ static double bf_step(const bf_ctx* b, int m, int64_t a, int64_t c, double acc)
     double si = b->x[a - 1], tj = b->y[c - 1], d = si - tj;
     switch (b->kind) {
     case ORC_DTW:
-    case ORC_CDTW: return (d * d) + acc;
+    case ORC_CDTW: return sqcost(b->x, a, b->y, c, dims_of(b->prm)) + acc;
     case ORC_WDTW: return (b->W[iabs(a - c)] * (d * d)) + acc;
     case ORC_ERP:
         if (m == 0) return acc + fabs(d);
@@ -300,7 +325,7 @@ static void terms(const eap_ctx* e, int64_t i, int64_t j, double* canon, double*
     switch (e->kind) {
     case ORC_DTW:
     case ORC_CDTW: {
-        double cost = d * d;
+        double cost = sqcost(e->R, i, e->C, j, dims_of(e->prm));
         *canon = *arow = *acol = cost;
         return;
     }
@@ -651,12 +676,13 @@ void orc_nn1(int kind, const double* prm, const double* q, const int64_t* q_off,
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : cells_sum) num_threads(nt)
 #endif
     for (int64_t a = 0; a < nq; ++a) {
-        const double* qa = q + q_off[a];
+        const int dims = dims_of(prm);
+        const double* qa = q + q_off[a] * dims;
         int64_t la = q_off[a + 1] - q_off[a];
         double best = INF;
         int64_t bi = -1;
         for (int64_t b = 0; b < nr; ++b) {
-            const double* rb = r + r_off[b];
+            const double* rb = r + r_off[b] * dims;
             int64_t lb = r_off[b + 1] - r_off[b];
             double d;
             if (mode == 1) {
@@ -675,7 +701,7 @@ void orc_nn1(int kind, const double* prm, const double* q, const int64_t* q_off,
                  * rounding and the distance's (sums of at most 2 x 2048 terms). */
                 d = INF;
                 int go = 1;
-                if (kind == ORC_DTW || kind == ORC_CDTW) {
+                if ((kind == ORC_DTW || kind == ORC_CDTW) && dims == 1) {
                     int64_t w = orc_window(kind, prm[P_WR], la, lb);
                     go = orc_lb_kim(qa, la, rb, lb) * (1.0 - 1e-11) < best &&
                          orc_lb_keogh(qa, la, rb, lb, w) * (1.0 - 1e-11) < best &&
@@ -712,8 +738,8 @@ void orc_pairwise(int kind, const double* prm, const double* s, const int64_t* s
 #endif
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i + 1; j < n; ++j) {
-            const double* a = s + s_off[i];
-            const double* b = s + s_off[j];
+            const double* a = s + s_off[i] * dims_of(prm);
+            const double* b = s + s_off[j] * dims_of(prm);
             int64_t la = s_off[i + 1] - s_off[i], lb = s_off[j + 1] - s_off[j];
             double d;
             if (mode == 1) d = orc_dp(kind, a, la, b, lb, prm, NULL);

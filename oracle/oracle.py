@@ -69,8 +69,22 @@ def lib():
 
 def _prm(p: dict) -> np.ndarray:
     return np.array([float(p.get("window_ratio", float("inf"))), float(p.get("g", 0.0)), float(p.get("gap", 0.0)),
-                     float(p.get("c", 0.0)), float(p.get("nu", 0.0)), float(p.get("lam", p.get("lambda", 0.0)))],
-                    dtype=np.float64)
+                     float(p.get("c", 0.0)), float(p.get("nu", 0.0)), float(p.get("lam", p.get("lambda", 0.0))),
+                     float(p.get("dims", 1))], dtype=np.float64)
+
+
+def _pts(x: np.ndarray, p: dict) -> int:
+    """Points in a series of values (one value per channel per point)."""
+    d = dims(p)
+    if len(x) % d:
+        raise ValueError(f"{len(x)} values do not make whole points of {d} channels")
+    return len(x) // d
+
+
+def dims(p: dict) -> int:
+    """Channels per series point (multivariate DTW / CDTW); values are stored
+    point after point, so a series of L points holds L * dims values."""
+    return max(1, int(p.get("dims", 1)))
 
 
 def _f64(a) -> np.ndarray:
@@ -103,17 +117,17 @@ def dp(p: dict, x, y, return_matrix: bool = False):
     x, y = _f64(x), _f64(y)
     prm = _prm(p)
     if return_matrix:
-        M = np.empty((len(x) + 1, len(y) + 1), dtype=np.float64)
-        d = lib().orc_dp(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), _ptr(M))
+        M = np.empty((_pts(x, p) + 1, _pts(y, p) + 1), dtype=np.float64)
+        d = lib().orc_dp(kind_id(p), _ptr(x), _pts(x, p), _ptr(y), _pts(y, p), _ptr(prm), _ptr(M))
         return d, M
-    return lib().orc_dp(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), None)
+    return lib().orc_dp(kind_id(p), _ptr(x), _pts(x, p), _ptr(y), _pts(y, p), _ptr(prm), None)
 
 
 def brute(p: dict, x, y):
     x, y = _f64(x), _f64(y)
     prm = _prm(p)
     n = ctypes.c_int64(0)
-    d = lib().orc_brute(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), ctypes.byref(n))
+    d = lib().orc_brute(kind_id(p), _ptr(x), _pts(x, p), _ptr(y), _pts(y, p), _ptr(prm), ctypes.byref(n))
     return d, n.value
 
 
@@ -122,7 +136,7 @@ def eap(p: dict, x, y, cutoff: float = float("inf")):
     x, y = _f64(x), _f64(y)
     prm = _prm(p)
     c, ai, aj = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
-    d = lib().orc_eap(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), float(cutoff), ctypes.byref(c),
+    d = lib().orc_eap(kind_id(p), _ptr(x), _pts(x, p), _ptr(y), _pts(y, p), _ptr(prm), float(cutoff), ctypes.byref(c),
                       ctypes.byref(ai), ctypes.byref(aj))
     return d, c.value, (ai.value, aj.value)
 
@@ -132,7 +146,7 @@ def eabase(p: dict, x, y, cutoff: float = float("inf")):
     x, y = _f64(x), _f64(y)
     prm = _prm(p)
     c = ctypes.c_int64(0)
-    d = lib().orc_eabase(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm), float(cutoff), ctypes.byref(c))
+    d = lib().orc_eabase(kind_id(p), _ptr(x), _pts(x, p), _ptr(y), _pts(y, p), _ptr(prm), float(cutoff), ctypes.byref(c))
     return d, c.value
 
 
@@ -160,7 +174,7 @@ def lb_kim(q, c) -> float:
 def ub(p: dict, x, y) -> float:
     x, y = _f64(x), _f64(y)
     prm = _prm(p)
-    return lib().orc_ub(kind_id(p), _ptr(x), len(x), _ptr(y), len(y), _ptr(prm))
+    return lib().orc_ub(kind_id(p), _ptr(x), _pts(x, p), _ptr(y), _pts(y, p), _ptr(prm))
 
 
 NN_MODES = {"dp": 0, "eap": 1, "eabase": 2, "eap_lb": 3}

@@ -564,3 +564,81 @@ def test_nn_lower_bounded_and_eabase_match_full_dp(orc, kind):
     # the bounds skip work: fewer cells than EAPruned alone
     assert orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "eap_lb")[2] < \
         orc.nn1(p, wl["queries"], wl["query_off"], wl["refs"], wl["ref_off"], "eap")[2]
+
+
+# --- multivariate series (Section 2.3's squared Euclidean cost over channels) --
+
+def mv(rng, L, D):
+    """A random-walk multivariate series, L points of D channels, point-major."""
+    return np.cumsum(rng.normal(size=(L, D)), axis=0).ravel()
+
+
+@pytest.mark.parametrize("kind", ["dtw", "cdtw"])
+def test_multivariate_one_channel_is_univariate(orc, kind):
+    rng = np.random.default_rng(81)
+    p1 = dict(kind=kind, window_ratio=0.2)
+    for lx, ly in [(1, 1), (9, 6), (40, 44)]:
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        d = orc.dp(p1, x, y)
+        assert orc.dp(dict(p1, dims=1), x, y) == d
+        assert orc.eap(dict(p1, dims=1), x, y)[0] == d
+
+
+@pytest.mark.parametrize("kind", ["dtw", "cdtw"])
+def test_multivariate_duplicated_channel_doubles(orc, kind):
+    """Two identical channels: every cost is 2 d^2, exactly twice the
+    univariate one, so the whole DP doubles bit for bit (scaling by 2 commutes
+    with rounding)."""
+    rng = np.random.default_rng(82)
+    p = dict(kind=kind, window_ratio=0.25)
+    for lx, ly in [(5, 5), (17, 12), (60, 64)]:
+        x, y = rng.normal(size=lx), rng.normal(size=ly)
+        x2, y2 = np.repeat(x, 2), np.repeat(y, 2)
+        assert orc.dp(dict(p, dims=2), x2, y2) == 2.0 * orc.dp(p, x, y)
+
+
+@pytest.mark.parametrize("D", [2, 3, 5])
+def test_multivariate_brute_force_and_eapruned(orc, D):
+    rng = np.random.default_rng(83 + D)
+    for kind in ("dtw", "cdtw"):
+        p = dict(kind=kind, window_ratio=0.4, dims=D)
+        for _ in range(25):
+            lx, ly = rng.integers(1, 8, size=2)
+            x, y = mv(rng, lx, D), mv(rng, ly, D)
+            d = orc.dp(p, x, y)
+            b, _ = orc.brute(p, x, y)
+            assert same(d, b), (kind, D, lx, ly, d, b)
+            if d < INF:
+                for c in (INF, d, np.nextafter(d, -INF), 0.5 * d):
+                    assert same(orc.eap(p, x, y, c)[0], d if d <= c else INF)
+
+
+def test_multivariate_dependent_at_least_independent(orc):
+    """One warping path shared by all channels costs at least the sum of each
+    channel's own best path (dependent >= independent multivariate DTW)."""
+    rng = np.random.default_rng(84)
+    for _ in range(30):
+        lx, ly, D = rng.integers(2, 30), rng.integers(2, 30), 3
+        x, y = mv(rng, lx, D), mv(rng, ly, D)
+        dep = orc.dp(dict(kind="dtw", dims=D), x, y)
+        ind = sum(orc.dp(dict(kind="dtw"), x[c::D], y[c::D]) for c in range(D))
+        assert dep >= ind * (1 - 1e-12)
+
+
+def test_multivariate_nn_matches_full_dp(orc):
+    rng = np.random.default_rng(85)
+    D = 3
+    qs = [mv(rng, int(L), D) for L in rng.integers(20, 60, size=5)]
+    rs = [mv(rng, int(L), D) for L in rng.integers(20, 60, size=30)]
+    qv, rv = np.concatenate(qs), np.concatenate(rs)
+    qo = np.concatenate([[0], np.cumsum([len(x) // D for x in qs])]).astype(np.int64)
+    ro = np.concatenate([[0], np.cumsum([len(x) // D for x in rs])]).astype(np.int64)
+    for kind in ("dtw", "cdtw"):
+        p = dict(kind=kind, window_ratio=0.3, dims=D)
+        a = orc.nn1(p, qv, qo, rv, ro, "dp")
+        for mode in ("eap", "eabase", "eap_lb"):
+            b = orc.nn1(p, qv, qo, rv, ro, mode)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        # the first query's NN by direct evaluation
+        d = [orc.dp(p, qs[0], r) for r in rs]
+        assert a[0][0] == int(np.argmin(d)) and a[1][0] == min(d)
