@@ -61,6 +61,17 @@ typedef enum {
  *  c             MSM split/merge cost of eq. MSMCost, finite, >= 0.
  *  nu, lambda    TWE stiffness and delete penalty of eq. TWECost, finite, >= 0;
  *                timestamps are the indices (tau_i = i).
+ *  dims          channels per series point, 0 or 1 for univariate series.
+ *                2..4: multivariate DTW and CDTW (EAP_EINVAL for the other
+ *                distances): values are stored point after point (point i of
+ *                a series is values[(off + i) * dims .. + dims)), lengths and
+ *                offsets count points, and the cost of two points is their
+ *                squared Euclidean distance, the channels' squared differences
+ *                added in channel order (Section 2.3 names the squared
+ *                Euclidean distance as the usual cost; the paper's conclusion
+ *                names the multivariate case).  Multivariate searches run in
+ *                FP64 without lower bounds (precision and lb are ignored) and
+ *                are not taken by the request server.
  * Costs: DTW, CDTW, WDTW use the squared difference; ERP, MSM, TWE the
  * absolute difference. */
 typedef struct {
@@ -71,6 +82,7 @@ typedef struct {
     double c;
     double nu;
     double lambda;
+    int32_t dims;
 } eap_params;
 
 /* NN search options.

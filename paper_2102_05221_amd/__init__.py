@@ -46,7 +46,7 @@ class EapError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("window_ratio", ctypes.c_double), ("g", ctypes.c_double),
                 ("gap", ctypes.c_double), ("c", ctypes.c_double), ("nu", ctypes.c_double),
-                ("lam", ctypes.c_double)]
+                ("lam", ctypes.c_double), ("dims", ctypes.c_int32)]
 
 
 class NNOpts(ctypes.Structure):
@@ -188,14 +188,16 @@ def _check(status: int):
 
 
 def params(kind: str, window_ratio: float = math.inf, g: float = 0.0, gap: float = 0.0, c: float = 0.0,
-           nu: float = 0.0, lam: float = 0.0) -> Params:
-    """Distance parameters (eap_params); `kind` is one of KINDS."""
-    return Params(KINDS[kind], float(window_ratio), float(g), float(gap), float(c), float(nu), float(lam))
+           nu: float = 0.0, lam: float = 0.0, dims: int = 1) -> Params:
+    """Distance parameters (eap_params); `kind` is one of KINDS; dims > 1:
+    multivariate DTW / CDTW series of points of `dims` channels, stored point
+    after point (offsets count points)."""
+    return Params(KINDS[kind], float(window_ratio), float(g), float(gap), float(c), float(nu), float(lam), int(dims))
 
 
 def params_from_dict(d: dict) -> Params:
     return params(d["kind"], d.get("window_ratio", math.inf), d.get("g", 0.0), d.get("gap", 0.0), d.get("c", 0.0),
-                  d.get("nu", 0.0), d.get("lam", d.get("lambda", 0.0)))
+                  d.get("nu", 0.0), d.get("lam", d.get("lambda", 0.0)), d.get("dims", 1))
 
 
 def _as_params(p) -> Params:
@@ -207,11 +209,15 @@ def _offsets(off) -> np.ndarray:
     return a
 
 
-def _sized(t, off, name):
-    """The values tensor t must hold the off[-1] values its offsets address
-    (the library reads them through a raw pointer)."""
-    if len(off) and t.numel() < int(off[-1]):
-        raise ValueError(f"{name}: offsets address {int(off[-1])} values, the tensor holds {t.numel()}")
+def _sized(t, off, name, dims: int = 1):
+    """The values tensor t must hold the off[-1] points (of `dims` values
+    each) its offsets address (the library reads them through a raw pointer)."""
+    if len(off) and t.numel() < int(off[-1]) * dims:
+        raise ValueError(f"{name}: offsets address {int(off[-1]) * dims} values, the tensor holds {t.numel()}")
+
+
+def _dims(p) -> int:
+    return max(1, int(p.dims))
 
 
 def _stream(stream, device):
@@ -259,10 +265,14 @@ def distance(x, y, p, cutoff: float = math.inf, ws=None, stream=None):
     _dev_f64(x, "x")
     _dev_f64(y, "y")
     p = _as_params(p)
-    need = lib().eap_distance_workspace(x.numel(), y.numel(), ctypes.byref(p))
+    d = _dims(p)
+    if x.numel() % d or y.numel() % d:
+        raise ValueError(f"series of {x.numel()} and {y.numel()} values are not whole points of {d} channels")
+    lx, ly = x.numel() // d, y.numel() // d
+    need = lib().eap_distance_workspace(lx, ly, ctypes.byref(p))
     ws = workspace(need, x.device) if ws is None else _ws(ws)
     out = torch.empty(1, dtype=torch.float64, device=x.device)
-    _check(lib().eap_distance(x.data_ptr(), x.numel(), y.data_ptr(), y.numel(), ctypes.byref(p), float(cutoff),
+    _check(lib().eap_distance(x.data_ptr(), lx, y.data_ptr(), ly, ctypes.byref(p), float(cutoff),
                               out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, x.device)))
     return out
 
@@ -320,9 +330,9 @@ def nn1(q, q_off, r, r_off, p, ref_labels=None, precision: int = 0, margin_rel: 
     _dev_f64(r, "candidates")
     q_off, r_off = _offsets(q_off), _offsets(r_off)
     nq, nr = len(q_off) - 1, len(r_off) - 1
-    _sized(q, q_off, "queries")
-    _sized(r, r_off, "candidates")
     p = _as_params(p)
+    _sized(q, q_off, "queries", _dims(p))
+    _sized(r, r_off, "candidates", _dims(p))
     o = NNOpts(int(precision), float(margin_rel), int(flags), _event_handle(main_wait, stream, q.device),
                _event_handle(main_done, stream, q.device), _lb_mode(lb))
     ws = workspace(nn1_workspace_bytes(q_off, r_off, p, precision, lb), q.device) if ws is None else _ws(ws)
@@ -578,8 +588,8 @@ def pairwise(s, s_off, p, mode: str = "prune", ws=None, stream=None, out=None):
     _dev_f64(s, "series")
     s_off = _offsets(s_off)
     n = len(s_off) - 1
-    _sized(s, s_off, "series")
     p = _as_params(p)
+    _sized(s, s_off, "series", _dims(p))
     ws = workspace(pairwise_workspace_bytes(s_off, p), s.device) if ws is None else _ws(ws)
     if out is None:
         out = torch.empty(max(n * (n - 1) // 2, 1), dtype=torch.float64, device=s.device)

@@ -59,8 +59,14 @@ eap_status check_params(const eap_params* p) {
     if (p->kind == EAP_MSM && !(std::isfinite(p->c) && p->c >= 0)) return fail(EAP_EINVAL, "MSM c must be >= 0");
     if (p->kind == EAP_TWE && !(std::isfinite(p->nu) && p->nu >= 0 && std::isfinite(p->lambda) && p->lambda >= 0))
         return fail(EAP_EINVAL, "TWE nu and lambda must be finite and >= 0");
+    if (p->dims < 0 || p->dims > 4) return fail(EAP_EINVAL, "dims must be 0..4 (got %d)", p->dims);
+    if (p->dims > 1 && p->kind != EAP_DTW && p->kind != EAP_CDTW)
+        return fail(EAP_EINVAL, "multivariate series (dims > 1) are supported for DTW and CDTW only");
     return EAP_OK;
 }
+
+// Channels per series point (1: univariate).
+int dims_of(const eap_params* p) { return p->dims > 1 ? p->dims : 1; }
 
 bool windowed(const eap_params* p) {
     return (p->kind == EAP_CDTW || p->kind == EAP_ERP) && p->window_ratio < 1.0;
@@ -326,6 +332,18 @@ eap_status make_plan(const eap_params* p, int64_t la_max, int64_t lb_max, int64_
     pl->r32 = rows_shape(kind, true, lco_max);
     pl->band = false;
     pl->rerun = false;
+    if (dims_of(p) > 1) {
+        // multivariate DTW and CDTW: the row sweep, 8 columns per lane, the
+        // narrowest group whose strip holds the shorter series
+        int g = 64;
+        for (int c : {8, 16, 32})
+            if ((int64_t)c * 8 >= lco_max) {
+                g = c;
+                break;
+            }
+        pl->r64 = pl->r32 = RowsShape{g, 8};
+        return EAP_OK;
+    }
     if (kind == EAP_CDTW || (kind == EAP_ERP && windowed(p))) {
         pl->band = true;
         int64_t w = (int64_t)std::floor(p->window_ratio * (double)lmax);
@@ -513,7 +531,7 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
         // measurably slow the sweep (up to a quarter for the band sweep)
         int occ = 0;
         const hipError_t oe = band ? launch_band(kind, fp32, pl.size, lanes, a, SA, SB, grid, s, &occ)
-                                   : launch_rows(kind, fp32, sh, a, SA, SB, grid, s, &occ, xd);
+                                   : launch_rows(kind, fp32, sh, a, SA, SB, grid, s, &occ, xd, dims_of(p));
         if (oe == hipSuccess && occ > 0) grid = std::min(grid, device_cus() * occ);
     }
     // slots per queue atomic: about 8 chunks per group, so that short items
@@ -522,7 +540,7 @@ eap_status sweep(const eap_params* p, const Plan& pl, bool band, SweepArgs a, He
     const int64_t groups = (int64_t)grid * (256 / lanes);
     a.chunk = a.npairs_dev ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(32, n / (groups * 8)));
     if (band) e = launch_band(kind, fp32, pl.size, lanes, a, SA, SB, grid, s);
-    else e = launch_rows(kind, fp32, sh, a, SA, SB, grid, s, nullptr, xd);
+    else e = launch_rows(kind, fp32, sh, a, SA, SB, grid, s, nullptr, xd, dims_of(p));
     if (e != hipSuccess) return fail(EAP_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     if (e0 && e1) {
         HIPCHK(hipEventRecord(e1, s));
@@ -756,7 +774,7 @@ bool screen_possible(const eap_params* p, int64_t lmax) {
 // Lower bounds a search uses (eap_nn_opts.lb resolved for the distance swept).
 int lb_mode(const eap_params* p, const eap_nn_opts* o) {
     const int k = effective_kind(p);
-    if (k != EAP_DTW && k != EAP_CDTW) return EAP_LB_NONE;
+    if ((k != EAP_DTW && k != EAP_CDTW) || dims_of(p) > 1) return EAP_LB_NONE;
     const int m = o ? o->lb : EAP_LB_DEFAULT;
     if (m == EAP_LB_DEFAULT) return k == EAP_CDTW ? EAP_LB_KEOGH : EAP_LB_NONE;
     return m;
@@ -832,7 +850,7 @@ size_t eap_nn1_workspace(const int64_t* q_off, int64_t nq, const int64_t* r_off,
         check_offsets(r_off, nr, "candidates", &R) != EAP_OK)
         return 0;
     NNLayout nl;
-    const bool prec1 = o && o->precision == 1;
+    const bool prec1 = o && o->precision == 1 && dims_of(p) == 1;
     nn_layout(Q, R, p, prec1, prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen)), lb_mode(p, o), nl);
     return nl.L.off;
 }
@@ -854,7 +872,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
         if ((o->flags & 16) && o->precision != 0) return fail(EAP_EINVAL, "prune-only search runs in FP64 (precision 0)");
         if (o->lb < EAP_LB_DEFAULT || o->lb > EAP_LB_KEOGH2) return fail(EAP_EINVAL, "unknown lb mode %d", o->lb);
     }
-    const bool prec1 = o && o->precision == 1;
+    const bool prec1 = o && o->precision == 1 && dims_of(p) == 1;   // multivariate: FP64
     const bool screen = prec1 && screen_possible(p, std::max(Q.maxlen, R.maxlen));
     const bool xd = screen && screen_exact_diff(p, std::max(Q.maxlen, R.maxlen));
     const int skind = effective_kind(p) | (xd ? kScreenExactDiff : 0);   // the screen bound's mode
@@ -894,7 +912,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     // flags only, so calls with flags bit 3 find the copy when they need it.
     const bool lbk = lbm >= EAP_LB_KEOGH && !plain && !prune_only;
     const bool direct = lbk && nr >= kDirectReadMinCandidates;
-    const bool need_rT = !direct;
+    const bool need_rT = !direct && dims_of(p) == 1;
     if (!cand_ready) {
         // what the candidates alone determine, kept for calls with flags bit 3:
         // the interleaved copy (when a bound kernel reads it), and for precision
@@ -942,8 +960,12 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     }
     // 1. upper bounds from the diagonal path, the best of them seeds each query
     double* lb = lbk ? reinterpret_cast<double*>(at(ws, nl.lb)) : nullptr;
-    HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, direct ? r : nullptr, SR.off, (int)Q.maxlen, (int)R.maxlen, rT, res,
-                        lbk ? reinterpret_cast<double*>(at(ws, nl.env)) : nullptr, lb, s));
+    if (dims_of(p) > 1)
+        HIPCHK(launch_ub_mv(effective_kind(p), dims_of(p), false, a, q, SQ.off, r, SR.off, 0, res, s));
+    else
+        HIPCHK(launch_ub_nn(effective_kind(p), a, q, SQ.off, direct ? r : nullptr, SR.off, (int)Q.maxlen,
+                            (int)R.maxlen, rT, res, lbk ? reinterpret_cast<double*>(at(ws, nl.env)) : nullptr, lb,
+                            s));
     a.lb = lb;
     if (prune_only) {
         // Section 5's "Prune": each pair under its own path bound (one ulp
@@ -967,7 +989,7 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     const bool rerun = pl.rerun;
     // the seed and recheck sweeps have one or a few pairs per query
     Plan few = pl;
-    few.r64 = few.r32 = latency_shape(std::min(Q.maxlen, R.maxlen));
+    few.r64 = few.r32 = dims_of(p) > 1 ? RowsShape{64, 8} : latency_shape(std::min(Q.maxlen, R.maxlen));
     if (seeded) {
         // 2. sweep the seed candidate of every query under its bound, in FP64
         //    also when screening: its exact distance is the tightest start for
@@ -1200,7 +1222,9 @@ eap_status eap_pairwise(const double* s, const int64_t* s_off, int64_t n, const 
     a.edge_stride = S.maxlen + 1;
     if (mode == 0) {
         double* cut = reinterpret_cast<double*>(at(ws, pw.cut));
-        HIPCHK(launch_ub_condensed(effective_kind(p), a, s, SA.off, n, cut, hs));
+        if (dims_of(p) > 1) HIPCHK(launch_ub_mv(effective_kind(p), dims_of(p), true, a, s, SA.off, nullptr, nullptr, n,
+                                               cut, hs));
+        else HIPCHK(launch_ub_condensed(effective_kind(p), a, s, SA.off, n, cut, hs));
         a.pcut = cut;
     }
     if (mode == 1) a.plain = 1;
@@ -1226,6 +1250,7 @@ eap_status eap_tune_nn1(const double* q, const int64_t* q_off, int64_t nq, const
         own.main_wait = own.main_done = nullptr;
         o = &own;
     }
+    if (dims_of(p) > 1) return EAP_OK;   // multivariate searches have one shape per length: nothing to tune
     const bool fp32 = o && o->precision == 1 && screen_possible(p, std::max(Q.maxlen, R.maxlen));
     const bool xd = fp32 && screen_exact_diff(p, std::max(Q.maxlen, R.maxlen));
     const bool plain = o && (o->flags & 2);

@@ -693,6 +693,61 @@ __global__ void ub_condensed_kernel(SweepArgs A, const double* v, const int64_t*
     }
 }
 
+// Multivariate DTW and CDTW (points of ND channels, stored point after
+// point): the same diagonal-then-straight path, each step's cost the
+// channels' squared differences added in channel order, as the sweep adds
+// them.  One thread per pair.
+template <int KIND, int ND>
+__device__ double path_ub_mv(const SweepArgs& A, const double* li, int Lli, const double* co, int Lco) {
+    if (KIND == CDTW && A.window_ratio < 1.0) {
+        const int w = (int)floor(A.window_ratio * (double)Lli);
+        if (w < Lli - Lco) return __builtin_huge_val();
+    }
+    auto cost = [&](int i, int j) {
+        const double* a = li + (int64_t)i * ND;
+        const double* b = co + (int64_t)j * ND;
+        double d = a[0] - b[0];
+        double c = d * d;
+#pragma unroll
+        for (int ch = 1; ch < ND; ++ch) {
+            const double e = a[ch] - b[ch];
+            c = c + e * e;
+        }
+        return c;
+    };
+    double acc = 0.0;
+    for (int k = 0; k < Lco; ++k) acc = cost(k, k) + acc;
+    for (int i = Lco; i < Lli; ++i) acc = cost(i, Lco - 1) + acc;
+    return acc;
+}
+
+template <int KIND, int ND>
+__device__ __forceinline__ double pair_ub_mv(const SweepArgs& A, const double* x, int lx, const double* y, int ly) {
+    return (lx >= ly) ? path_ub_mv<KIND, ND>(A, x, lx, y, ly) : path_ub_mv<KIND, ND>(A, y, ly, x, lx);
+}
+
+template <int KIND, int ND>
+__global__ void ub_nn_mv_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rv,
+                                const int64_t* roff, double* ub) {
+    const int64_t total = A.nA * A.nB;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = p / A.nB, b = p - a * A.nB;
+        ub[p] = pair_ub_mv<KIND, ND>(A, qv + qoff[a] * ND, (int)(qoff[a + 1] - qoff[a]), rv + roff[b] * ND,
+                                     (int)(roff[b + 1] - roff[b]));
+    }
+}
+
+template <int KIND, int ND>
+__global__ void ub_condensed_mv_kernel(SweepArgs A, const double* v, const int64_t* off, int64_t n, double* cut) {
+    const int64_t total = n * (n - 1) / 2;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i, j;
+        condensed_ij(p, n, i, j);
+        cut[p] = next_up(pair_ub_mv<KIND, ND>(A, v + off[i] * ND, (int)(off[i + 1] - off[i]), v + off[j] * ND,
+                                               (int)(off[j + 1] - off[j])));
+    }
+}
+
 // Per-query scans over the nr candidates (seed choice, argmin, screen
 // filter): TPQ threads per query (64, 256 or 1024, from nr), a block of
 // max(256, TPQ) threads holding 256 / TPQ queries when TPQ < 256; queries by
@@ -1262,6 +1317,31 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t ub_mv_launch(int nd, bool condensed, const SweepArgs& a, const double* qv, const int64_t* qoff,
+                               const double* rv, const int64_t* roff, int64_t n, double* out, hipStream_t s) {
+    const int64_t total = condensed ? n * (n - 1) / 2 : a.nA * a.nB;
+    const dim3 g(blocks_for(total, 256)), b(256);
+#define EAP_MV(ND)                                                                                              \
+    if (condensed) hipLaunchKernelGGL((ub_condensed_mv_kernel<KIND, ND>), g, b, 0, s, a, qv, qoff, n, out);    \
+    else hipLaunchKernelGGL((ub_nn_mv_kernel<KIND, ND>), g, b, 0, s, a, qv, qoff, rv, roff, out);
+    switch (nd) {
+    case 2: EAP_MV(2); break;
+    case 3: EAP_MV(3); break;
+    case 4: EAP_MV(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef EAP_MV
+    return hipGetLastError();
+}
+
+hipError_t launch_ub_mv(int kind, int nd, bool condensed, const SweepArgs& a, const double* qv, const int64_t* qoff,
+                        const double* rv, const int64_t* roff, int64_t n, double* out, hipStream_t s) {
+    if (kind == DTW) return ub_mv_launch<DTW>(nd, condensed, a, qv, qoff, rv, roff, n, out, s);
+    if (kind == CDTW) return ub_mv_launch<CDTW>(nd, condensed, a, qv, qoff, rv, roff, n, out, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,

@@ -65,6 +65,37 @@ __device__ __forceinline__ double bperm(int addr, double v) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// One series point of ND channels (multivariate series: ND > 1), moved between
+// lanes channel by channel.
+template <typename V, int ND> struct Pt {
+    V c[ND];
+};
+template <typename V, int ND> __device__ __forceinline__ Pt<V, ND> shr1(const Pt<V, ND>& p) {
+    Pt<V, ND> r;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) r.c[i] = shr1(p.c[i]);
+    return r;
+}
+template <typename V, int ND> __device__ __forceinline__ Pt<V, ND> row_shr1_or(const Pt<V, ND>& p,
+                                                                              const Pt<V, ND>& first) {
+    Pt<V, ND> r;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) r.c[i] = row_shr1_or(p.c[i], first.c[i]);
+    return r;
+}
+template <typename V, int ND> __device__ __forceinline__ Pt<V, ND> bperm(int addr, const Pt<V, ND>& p) {
+    Pt<V, ND> r;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) r.c[i] = bperm(addr, p.c[i]);
+    return r;
+}
+template <typename V, int ND> __device__ __forceinline__ Pt<V, ND> pt_fill(V v) {
+    Pt<V, ND> r;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) r.c[i] = v;
+    return r;
+}
+
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
 // Non-negative doubles order like their bit patterns, +inf above every finite.

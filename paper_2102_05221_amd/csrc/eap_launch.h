@@ -89,8 +89,10 @@ struct SeriesPtrs {
 // one strip need a.edge with room for grid * 256 / G groups.  With `occ` set
 // nothing is launched: *occ = blocks of this kernel one CU holds at once.
 // xd: exact differences (FP32 WDTW only; A and B hold float64 values).
+// nd > 1: multivariate series of nd channels (2..4; DTW, and CDTW with its
+// window on the row sweep; FP64; shapes G in {8, 16, 32, 64} x 8).
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s, int* occ = nullptr, bool xd = false);
+                       hipStream_t s, int* occ = nullptr, bool xd = false, int nd = 1);
 int rows_lds_bytes(int kind, bool fp32, const SweepArgs& a);
 bool rows_shape_ok(int kind, RowsShape sh, bool fp32);
 
@@ -144,6 +146,12 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
                         double* lb, hipStream_t s);
 hipError_t launch_ub_condensed(int kind, const SweepArgs& a, const double* v, const int64_t* off, int64_t n,
                                double* cut, hipStream_t s);
+// Multivariate DTW / CDTW (nd = 2..4 channels): the path bound of every
+// (query, candidate) pair into out[a * nB + b] (condensed = false; qv / qoff
+// and rv / roff the two sets, n unused), or one ulp above it for every
+// condensed pair of the set qv / qoff of n series (condensed = true).
+hipError_t launch_ub_mv(int kind, int nd, bool condensed, const SweepArgs& a, const double* qv, const int64_t* qoff,
+                        const double* rv, const int64_t* roff, int64_t n, double* out, hipStream_t s);
 // Scratch of the split per-query scans (seed, argmin, screen filter) for a
 // few queries with many candidates: 2 x scan_part_entries(nq) doubles
 // (partial values, then partial indexes); part == nullptr runs the

@@ -59,17 +59,19 @@ constexpr int rows_min_blocks() {
 
 template <typename T, bool XD> using RowValue = typename std::conditional<XD, double, T>::type;
 
-template <int KIND, typename T, int G, int C, bool XD>
+template <int KIND, typename T, int G, int C, bool XD, int ND>
 __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows_kernel(
     SweepArgs A, Series<RowValue<T, XD>> SA, Series<RowValue<T, XD>> SB) {
     using V = RowValue<T, XD>;   // type of the series values
+    using P = Pt<V, ND>;         // one series point (ND channels for multivariate DTW / CDTW)
     constexpr bool DTAB = (KIND == TWE || KIND == WDTW);
     // steps between group decisions: long blocks share the block-end work
     // (ballots, cut-off, strip and pair bookkeeping) among more steps, and
     // stage more row inputs per lane (K / G) and, for TWE and WDTW, keep
     // C + K - 1 per-diagonal terms in registers; the distances with the most
-    // registers per column (MSM, TWE, WDTW) take shorter blocks with wide lanes
-    constexpr int K = (C > 8 && (KIND == MSM || DTAB)) ? 16 : 32;
+    // registers per column (MSM, TWE, WDTW) take shorter blocks with wide lanes,
+    // and so do multivariate lanes (K / G staged points of ND channels)
+    constexpr int K = (ND > 1 || (C > 8 && (KIND == MSM || DTAB))) ? 16 : 32;
     constexpr int W = G * C;
     constexpr int NW = DTAB ? C + K - 1 : 1;
     if (A.prio) __builtin_amdgcn_s_setprio(2);
@@ -113,26 +115,34 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     bool last = true, full_top = true;
     T cut = 0;
     T val[C], vb[C], aux[C];
-    V tv[C];
+    P tv[C];
     T adv[KIND == TWE ? C : 1];   // TWE: |s_{i-1} - t_j| of the previous row
     T dwin[NW];                   // per-diagonal terms of this block
     T dg = 0, lout = 0, brd0 = 0;
-    V sout = 0, sp = 0, tpm = 0, s0 = 0;
+    P sout = pt_fill<V, ND>(0), s0 = pt_fill<V, ND>(0);
+    V sp = 0, tpm = 0;
+    int wcap = 0;   // CDTW (multivariate, on the row sweep): the pair's window
     // Lane 0's inputs of a block's K rows (s_i and M(i, cb)) are staged across
     // the group: lane j holds rows R0 + 1 + j + G*i (i < RS; R0 = lane 0's row
     // before the block), loaded one block ahead, and lane 0 reads the one for
     // each step with a cross-lane permute.
     constexpr int RS = (K + G - 1) / G;
-    V st_s[RS], nx_s[RS];
+    P st_s[RS], nx_s[RS];
     T st_b[RS], nx_b[RS];
 #pragma unroll
-    for (int i = 0; i < RS; ++i) st_s[i] = st_b[i] = nx_s[i] = nx_b[i] = 0;
+    for (int i = 0; i < RS; ++i) {
+        st_s[i] = nx_s[i] = pt_fill<V, ND>(0);
+        st_b[i] = nx_b[i] = 0;
+    }
     // left inputs: bp[i] = M(i, cb) for e_lo <= i <= e_hi (until a pair is
     // fetched, and in the first strip of +inf borders, a valid dummy range)
     const T* bp = reinterpret_cast<const T*>(SA.v) - 1;
     unsigned long long ncells = 0, npairs = 0, nlb = 0;
 #pragma unroll
-    for (int u = 0; u < C; ++u) val[u] = vb[u] = tv[u] = aux[u] = 0;
+    for (int u = 0; u < C; ++u) {
+        val[u] = vb[u] = aux[u] = 0;
+        tv[u] = pt_fill<V, ND>(0);
+    }
 #pragma unroll
     for (int u = 0; u < (KIND == TWE ? C : 1); ++u) adv[u] = 0;
 #pragma unroll
@@ -142,9 +152,10 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     // strip) or the previous strip's edge, +inf outside its live rows.  Every
     // lane loads (rows clamped into 1..L_li, so every address is in bounds) and
     // only lane 0's values are used: no branch in the step.
-    auto load_row = [&](int r, V& sv, T& bv) {
+    auto load_row = [&](int r, P& sv, T& bv) {
         const unsigned rc = (unsigned)__builtin_elementwise_min(__builtin_elementwise_max(r, 1), Lli);
-        sv = li[rc - 1u];
+#pragma unroll
+        for (int ch = 0; ch < ND; ++ch) sv.c[ch] = li[(rc - 1u) * ND + ch];
         const T x = load_nc(bp + rc);
         bv = (r >= e_lo && r <= e_hi) ? x : INF;   // e_hi < e_lo: no live row
     };
@@ -174,16 +185,18 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         full_top = (r_start == 1);
         // column values t_j of the strip (+inf beyond L_co) and t_{c0-1} (t_0 = 0)
 #pragma unroll
-        for (int u = 0; u < C; ++u) tv[u] = (c0 + u <= Lco) ? co[c0 + u - 1] : inf_v<V>();
-        tpm = (c0 >= 2 && c0 - 1 <= Lco) ? co[c0 - 2] : (V)0;
+        for (int u = 0; u < C; ++u)
+#pragma unroll
+            for (int ch = 0; ch < ND; ++ch) tv[u].c[ch] = (c0 + u <= Lco) ? co[(c0 + u - 1) * ND + ch] : inf_v<V>();
+        tpm = (c0 >= 2 && c0 - 1 <= Lco) ? co[(c0 - 2) * ND] : (V)0;
 #pragma unroll
         for (int u = 0; u < C; ++u) {
-            const T tprev = (u == 0) ? tpm : tv[u - 1];
+            const T tprev = (u == 0) ? tpm : tv[u - 1].c[0];
             const bool ghost = c0 + u > Lco;
-            if constexpr (KIND == ERP) aux[u] = ghost ? INF : vabs(tv[u] - gap);
-            if constexpr (KIND == MSM) aux[u] = ghost ? INF : tv[u] - tprev;
-            if constexpr (KIND == TWE) aux[u] = ghost ? INF : (vabs(tv[u] - tprev) + nu) + lam;
-            if constexpr (KIND == TWE) adv[u] = vabs((T)0 - tv[u]);   // row 0: s_0 = 0
+            if constexpr (KIND == ERP) aux[u] = ghost ? INF : vabs(tv[u].c[0] - gap);
+            if constexpr (KIND == MSM) aux[u] = ghost ? INF : tv[u].c[0] - tprev;
+            if constexpr (KIND == TWE) aux[u] = ghost ? INF : (vabs(tv[u].c[0] - tprev) + nu) + lam;
+            if constexpr (KIND == TWE) adv[u] = vabs((T)0 - tv[u].c[0]);   // row 0: s_0 = 0
             // the row above the first: the top border M(0, j) (computed for ERP,
             // +inf otherwise), or +inf when the strip starts lower down
             if constexpr (KIND == ERP) val[u] = (ghost || !full_top) ? INF : cob[c0 + u - 1];
@@ -200,7 +213,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         // ERP's border M(0, c0-1), which makes the lane recompute its own top
         // border exactly, or +inf, which keeps +inf borders at +inf
         brd0 = (KIND == ERP) ? topl : INF;
-        s0 = (KIND == ERP) ? (V)gap : (V)0;
+        s0 = pt_fill<V, ND>((KIND == ERP) ? (V)gap : (V)0);
         // the last strip starts late enough that the last cell, (L_li, L_co) in
         // lane kend, is computed by the last step of a block: the result is then
         // read once, at the block end, from the buffer that step wrote
@@ -213,7 +226,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         }
         row = r_start - 1 - k - pad;
         lout = val[C - 1];
-        sout = 0;
+        sout = pt_fill<V, ND>(0);
         sp = 0;
         rec_lo = 1 << 30;
         rec_hi = -1;
@@ -237,11 +250,25 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
                 const int64_t oa = SA.off[it.a], ob = SB.off[it.b];
                 const int La = (int)(SA.off[it.a + 1] - oa), Lb = (int)(SB.off[it.b + 1] - ob);
                 if (La >= Lb) {
-                    li = SA.v + oa; lib = SA.border ? SA.border + oa : nullptr; Lli = La;
-                    co = SB.v + ob; cob = SB.border ? SB.border + ob : nullptr; Lco = Lb;
+                    li = SA.v + oa * ND; lib = SA.border ? SA.border + oa : nullptr; Lli = La;
+                    co = SB.v + ob * ND; cob = SB.border ? SB.border + ob : nullptr; Lco = Lb;
                 } else {
-                    li = SB.v + ob; lib = SB.border ? SB.border + ob : nullptr; Lli = Lb;
-                    co = SA.v + oa; cob = SA.border ? SA.border + oa : nullptr; Lco = La;
+                    li = SB.v + ob * ND; lib = SB.border ? SB.border + ob : nullptr; Lli = Lb;
+                    co = SA.v + oa * ND; cob = SA.border ? SA.border + oa : nullptr; Lco = La;
+                }
+                if constexpr (KIND == CDTW) {
+                    // the window of the pair; none that admits a path: +inf without a sweep
+                    const int L = Lli;
+                    const double wr = A.window_ratio;
+                    wcap = (wr >= 1.0) ? L : (int)floor(wr * (double)L);
+                    if (wcap > L) wcap = L;
+                    if (wcap < Lli - Lco) {
+                        if (k == 0) {
+                            A.res[it.out] = __builtin_huge_val();
+                            ++npairs;
+                        }
+                        continue;
+                    }
                 }
                 qa = it.a;
                 out = it.out;
@@ -310,12 +337,12 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         // the last row compute values nobody reads.
         auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t) {
             T lin;
-            V sin;
+            P sin;
             row += 1;
             {
                 // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G
                 const T bv = bperm(gaddr + 4 * (t % G), st_b[t / G]);   // M(row, cb)
-                const V sv = bperm(gaddr + 4 * (t % G), st_s[t / G]);   // s_row
+                const P sv = bperm(gaddr + 4 * (t % G), st_s[t / G]);   // s_row
                 if constexpr (G == 16) {
                     // a group is one DPP row: shift and feed lane 0 at once
                     lin = row_shr1_or(lout, bv);
@@ -339,16 +366,26 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
             if (!ns) dg = lin;          // M(r_start-1, c0-1) stays the diagonal of the first row
             T left = lin;
             T sg = 0, ds = 0, gA = 0, carry = 0;
-            if constexpr (KIND == ERP) sg = vabs(sin - gap);
-            if constexpr (KIND == MSM) ds = sin - sp;
-            if constexpr (KIND == TWE) gA = (vabs(sin - sp) + nu) + lam;
+            if constexpr (KIND == ERP) sg = vabs(sin.c[0] - gap);
+            if constexpr (KIND == MSM) ds = sin.c[0] - sp;
+            if constexpr (KIND == TWE) gA = (vabs(sin.c[0] - sp) + nu) + lam;
+            const int wd = c0 - row;   // j - i of the lane's first cell (CDTW on the row sweep)
 #pragma unroll
             for (int u = 0; u < C; ++u) {
                 const T top = src[u];
-                const T d = (T)(sin - tv[u]);   // XD: formed in float64, rounded once
+                const T d = (T)(sin.c[0] - tv[u].c[0]);   // XD: formed in float64, rounded once
                 T v;
                 if constexpr (KIND == DTW || KIND == CDTW) {
-                    v = (d * d) + vmin(vmin(diag, top), left);
+                    // multivariate: the channels' squared differences added in channel order
+                    T cost = d * d;
+#pragma unroll
+                    for (int ch = 1; ch < ND; ++ch) {
+                        const T e = (T)(sin.c[ch] - tv[u].c[ch]);
+                        cost = cost + e * e;
+                    }
+                    // CDTW on the row sweep: cells outside the window are +inf
+                    if constexpr (KIND == CDTW) cost = cost + ((wd + u > wcap || wd + u < -wcap) ? INF : (T)0);
+                    v = cost + vmin(vmin(diag, top), left);
                 } else if constexpr (KIND == WDTW) {
                     v = (dwin[u - t - 1 + K] * (d * d)) + vmin(vmin(diag, top), left);
                 } else if constexpr (KIND == ERP) {
@@ -383,7 +420,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
                 left = v;
             }
             if constexpr (KIND == TWE) adv[C - 1] = carry;
-            if (!ns) sp = sin;
+            if (!ns) sp = sin.c[0];
             {
                 // this strip's right edge, M(row, cb + W), for the next strip
                 const T e = dst[C - 1];
@@ -492,17 +529,42 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     wave_add_u64(&A.counters[4], nlb);
 }
 
-template <int KIND, typename T, int G, int C, bool XD>
+template <int KIND, typename T, int G, int C, bool XD, int ND = 1>
 static hipError_t go(const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s, int* occ) {
     using V = RowValue<T, XD>;
     const int lds = rows_lds_bytes(KIND, sizeof(T) == 4, a);
     if (occ)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ, reinterpret_cast<const void*>(&rows_kernel<KIND, T, G, C, XD>), 256, (size_t)lds);
+            occ, reinterpret_cast<const void*>(&rows_kernel<KIND, T, G, C, XD, ND>), 256, (size_t)lds);
     Series<V> A{(const V*)SA.v, SA.off, (const V*)SA.border};
     Series<V> B{(const V*)SB.v, SB.off, (const V*)SB.border};
-    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C, XD>), dim3(grid), dim3(256), lds, s, a, A, B);
+    hipLaunchKernelGGL((rows_kernel<KIND, T, G, C, XD, ND>), dim3(grid), dim3(256), lds, s, a, A, B);
     return hipGetLastError();
+}
+
+// Multivariate DTW and CDTW (FP64): G in {8, 16, 32, 64} x 8 columns per lane.
+template <int KIND, int ND>
+static hipError_t go_mv(RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid, hipStream_t s,
+                        int* occ) {
+    if (sh.c != 8) return hipErrorInvalidValue;
+    switch (sh.g) {
+    case 8: return go<KIND, double, 8, 8, false, ND>(a, SA, SB, grid, s, occ);
+    case 16: return go<KIND, double, 16, 8, false, ND>(a, SA, SB, grid, s, occ);
+    case 32: return go<KIND, double, 32, 8, false, ND>(a, SA, SB, grid, s, occ);
+    case 64: return go<KIND, double, 64, 8, false, ND>(a, SA, SB, grid, s, occ);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int KIND>
+static hipError_t go_mv_d(int nd, RowsShape sh, const SweepArgs& a, SeriesPtrs SA, SeriesPtrs SB, int grid,
+                          hipStream_t s, int* occ) {
+    switch (nd) {
+    case 2: return go_mv<KIND, 2>(sh, a, SA, SB, grid, s, occ);
+    case 3: return go_mv<KIND, 3>(sh, a, SA, SB, grid, s, occ);
+    case 4: return go_mv<KIND, 4>(sh, a, SA, SB, grid, s, occ);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int KIND, typename T, bool XD = false>
@@ -544,7 +606,13 @@ bool rows_shape_ok(int kind, RowsShape sh, bool fp32) {
 }
 
 hipError_t launch_rows(int kind, bool fp32, RowsShape sh, const SweepArgs& a, SeriesPtrs A, SeriesPtrs B, int grid,
-                       hipStream_t s, int* occ, bool xd) {
+                       hipStream_t s, int* occ, bool xd, int nd) {
+    if (nd > 1) {   // multivariate: DTW, and CDTW (window on the row sweep), FP64
+        if (fp32 || xd) return hipErrorInvalidValue;
+        if (kind == DTW) return go_mv_d<DTW>(nd, sh, a, A, B, grid, s, occ);
+        if (kind == CDTW) return go_mv_d<CDTW>(nd, sh, a, A, B, grid, s, occ);
+        return hipErrorInvalidValue;
+    }
     if (xd) {   // exact differences: FP32 WDTW on float64 series only
         if (fp32 && kind == WDTW) return go_w<WDTW, float, true>(sh, a, A, B, grid, s, occ);
         return hipErrorInvalidValue;

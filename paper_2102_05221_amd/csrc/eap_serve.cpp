@@ -181,6 +181,7 @@ eap_status eap_server_create(const double* refs, const int64_t* r_off, int64_t n
     if (!refs || !r_off || nr < 1 || !p || !o) return sfail(EAP_EINVAL, "NULL or empty argument");
     if (o->slots < 1 || o->slots > 16 || o->max_batch < 1 || o->max_query_len < 1 || o->mem_budget == 0)
         return sfail(EAP_EINVAL, "slots must be 1..16, max_batch, max_query_len and mem_budget positive");
+    if (p->dims > 1) return sfail(EAP_EINVAL, "the server takes univariate series only");
     eap_server* s = new (std::nothrow) eap_server;
     if (!s) return sfail(EAP_ENOMEM, "server object");
     s->p = *p;

@@ -83,6 +83,15 @@ def test_distance_argument_errors(L):
     assert L.eap_distance(FAKE, 10, FAKE, 12, ctypes.byref(p), 1.0, FAKE, None, need, None) == eap.EAP_EWORKSPACE
 
 
+def test_multivariate_argument_errors(L):
+    """Channels: 0..4, and more than one only for DTW and CDTW."""
+    ws = ctypes.c_void_p(0x2000)
+    for pp in (_p("dtw", dims=5), _p("dtw", dims=-1), _p("erp", dims=2), _p("msm", dims=3), _p("wdtw", dims=2)):
+        assert L.eap_distance(FAKE, 10, FAKE, 12, ctypes.byref(pp), 1.0, FAKE, ws, 1 << 20, None) == eap.EAP_EINVAL
+    for pp in (_p("dtw", dims=2), _p("cdtw", window_ratio=0.1, dims=4)):
+        assert L.eap_distance_workspace(10, 12, ctypes.byref(pp)) > 0
+
+
 def test_distance_noalloc_argument_errors(L):
     """The call without a workspace rejects the same arguments before it
     touches the device."""

@@ -986,3 +986,58 @@ def test_nn_prune_only_and_no_pruning(torch_dev, orc, p):
         gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, flags=flags)
         torch.cuda.synchronize()
         assert np.array_equal(gi.cpu().numpy(), oi) and np.array_equal(gd.cpu().numpy(), od), (flags, precision)
+
+
+def mv_series(rng, L, D):
+    """A z-normalised random-walk series of L points and D channels, point-major."""
+    x = np.cumsum(rng.normal(size=(L, D)), axis=0)
+    return ((x - x.mean(axis=0)) / x.std(axis=0).clip(1e-12)).ravel()
+
+
+MV = [dict(kind="dtw", dims=2), dict(kind="dtw", dims=3), dict(kind="dtw", dims=4),
+      dict(kind="cdtw", window_ratio=0.1, dims=3), dict(kind="cdtw", window_ratio=0.3, dims=2),
+      dict(kind="cdtw", window_ratio=0.0, dims=4)]
+
+
+@pytest.mark.parametrize("p", MV, ids=pid)
+def test_multivariate_distance_parity(torch_dev, orc, p):
+    torch, dev = torch_dev
+    D = p["dims"]
+    rng = np.random.default_rng(90 + D)
+    for lx, ly in [(1, 1), (7, 3), (64, 64), (65, 130), (333, 512), (700, 650)]:
+        x, y = mv_series(rng, lx, D), mv_series(rng, ly, D)
+        d = orc.dp(p, x, y)
+        xd, yd = to_dev(torch, dev, x), to_dev(torch, dev, y)
+        for c in [INF] + ([d, float(np.nextafter(d, -INF)), 0.5 * d] if 0 < d < INF else []):
+            log(f"multivariate distance {pid(p)} lx={lx} ly={ly} cut={c}")
+            g = float(eap.distance(xd, yd, p, c).item())
+            want = d if d <= c else INF
+            assert g == want or (math.isinf(g) and math.isinf(want)), (lx, ly, c, g, want)
+
+
+@pytest.mark.parametrize("p", MV, ids=pid)
+def test_multivariate_nn_and_pairwise_parity(torch_dev, orc, p):
+    torch, dev = torch_dev
+    D = p["dims"]
+    rng = np.random.default_rng(95 + D)
+    qs = [mv_series(rng, int(L), D) for L in rng.integers(20, 300, size=6)]
+    rs = [mv_series(rng, int(L), D) for L in rng.integers(15, 320, size=70)]
+    rs[5] = qs[2].copy()
+    qv, rv = np.concatenate(qs), np.concatenate(rs)
+    qo = np.concatenate([[0], np.cumsum([len(x) // D for x in qs])]).astype(np.int64)
+    ro = np.concatenate([[0], np.cumsum([len(x) // D for x in rs])]).astype(np.int64)
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    for precision, flags in ((0, 0), (1, 0), (0, eap.FLAG_PRUNE_ONLY), (0, eap.FLAG_NO_PRUNE), (0, eap.FLAG_PLAIN)):
+        log(f"multivariate nn {pid(p)} precision={precision} flags={flags}")
+        gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision, flags=flags)
+        torch.cuda.synchronize()
+        assert np.array_equal(gi.cpu().numpy(), oi) and np.array_equal(gd.cpu().numpy(), od), (precision, flags)
+    sv = np.concatenate(rs[:25])
+    so = ro[:26]
+    want = orc.pairwise(p, sv, so, "full")
+    for mode in ("prune", "full"):
+        log(f"multivariate pairwise {pid(p)} {mode}")
+        g = eap.pairwise(to_dev(torch, dev, sv), so, p, mode=mode)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.cpu().numpy(), want), mode
