@@ -163,11 +163,13 @@ def cpu_baseline(wl, kinds, gpu_idx, gpu_dist, eap_q, dp_q, dp_r=None, one_q=1, 
     cells = 0
     secs = 0.0
     match = True
+    seq_cells = {}   # cells the oracle's sequential EAPruned (Alg. 1 order) evaluates per distance
     for kind in kinds:
         p = wl["params"][kind]
         t0 = time.perf_counter()
-        idx, dist, _ = orc.nn1(p, qv, qo, wl["refs"], wl["ref_off"], "eap")
+        idx, dist, ocells = orc.nn1(p, qv, qo, wl["refs"], wl["ref_off"], "eap")
         secs += time.perf_counter() - t0
+        seq_cells[kind] = int(ocells)
         cells += dense_cells(kind, p, qo, wl["ref_off"])
         match &= bool(np.array_equal(idx, gpu_idx[kind][:eap_q]) and np.array_equal(dist, gpu_dist[kind][:eap_q]))
     dv, do = head(wl["query_off"], wl["queries"], dp_q)
@@ -200,6 +202,7 @@ def cpu_baseline(wl, kinds, gpu_idx, gpu_dist, eap_q, dp_q, dp_r=None, one_q=1, 
                 full_dp_gcups=dcells / sd / 1e9,
                 full_dp_sample=f"full DP of the first {dp_q} queries against the first {dp_r} candidates, "
                                f"{len(kinds)} distances, {sd:.1f} s",
+                sequential_eapruned_cells=seq_cells,
                 one_core_gcups=c1 / s1 / 1e9,
                 one_core_sample=f"EAPruned NN of the first {one_q} queries against the first {one_r} "
                                 f"candidates, {len(kinds)} distances, one thread, {s1:.1f} s")
@@ -229,14 +232,18 @@ def run_pairwise(args, torch, eap, synth):
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             eap.reset_counters(ws)
+            eap.profile_take()
+            eap.profile_enable(True)
             a.record()
             for _ in range(args.steps):
                 eap.pairwise(s, so, p, mode, ws=ws, out=out)
             b.record()
             torch.cuda.synchronize()
+            eap.profile_enable(False)
+            recs = [x for x in eap.profile_take() if x["stage"] == 2]
             ms = a.elapsed_time(b) / args.steps
             c = eap.read_counters(ws)
-            res[mode] = (ms, c["cells"] / args.steps, out.clone())
+            res[mode] = (ms, c["cells"] / args.steps, out.clone(), recs)
         # dense cells: all pairs (band cells for CDTW)
         lens = np.diff(so)
         if k == "cdtw":   # ordered pairs minus the diagonal, halved
@@ -245,20 +252,56 @@ def run_pairwise(args, torch, eap, synth):
         else:
             cells = int((lens.sum() ** 2 - (lens ** 2).sum()) // 2)
         same = bool(torch.equal(res["prune"][2], res["full"][2]))
+        recs = res["prune"][3]
+        sweep_ms = sum(x["ms"] for x in recs) / max(len(recs), 1)
         per[k] = dict(prune_ms=res["prune"][0], full_ms=res["full"][0], speedup=res["full"][0] / res["prune"][0],
                       dense_cells=cells, prune_executed_fraction=res["prune"][1] / cells,
                       prune_gcups_effective=cells / (res["prune"][0] * 1e-3) / 1e9,
-                      full_gcups=cells / (res["full"][0] * 1e-3) / 1e9, identical=same)
+                      full_gcups=cells / (res["full"][0] * 1e-3) / 1e9, identical=same,
+                      prune_sweep_ms=sweep_ms, prune_executed_cells=res["prune"][1],
+                      prune_kernel=kernel_label(recs[0]) if recs else None)
         tot_cells += cells
         tot_ms += res["prune"][0]
+        if args.cpu_queries:
+            # the oracle's prune-only matrix of the first 64 series, compared element by element
+            from oracle import oracle as orc
+            m = min(64, n)
+            sv = wl["refs"][: so[m]]
+            t = time.perf_counter()
+            want = orc.pairwise(p, sv, so[: m + 1], "prune")
+            secs = time.perf_counter() - t
+            got = eap.pairwise(s[: so[m]], so[: m + 1], p, "prune")
+            torch.cuda.synchronize()
+            mc = int(np.diff(so[: m + 1]).sum() ** 2 - (np.diff(so[: m + 1]) ** 2).sum()) // 2 if k != "cdtw" else None
+            per[k]["cpu"] = dict(seconds=secs, pairs=m * (m - 1) // 2, dense_cells=mc,
+                                 identical_to_gpu=bool(np.array_equal(got.cpu().numpy(), want)))
         del ws, out
+    # roofline: the dominant prune-only sweep, executed cells per launch over its launch time
+    dom = max(kinds, key=lambda k: per[k]["prune_sweep_ms"])
+    d = per[dom]
+    sk = swept_kind(dom, wl["params"][dom])
+    peak = LANE_OPS_PER_S / OPS_PER_CELL[sk] / 1e9
+    ach = d["prune_executed_cells"] / (d["prune_sweep_ms"] * 1e-3) / 1e9
+    roofline = dict(bound="alu", achieved=ach, peak=peak, unit="GCUPS", frac=ach / peak, traffic=None,
+                    kernel=f"{d['prune_kernel']} sweep, {sk.upper()} main stage, fp64",
+                    ops_per_cell=OPS_PER_CELL[sk], launch_ms=d["prune_sweep_ms"], convention=ROOFLINE_CONVENTION)
+    cpu = None
+    if args.cpu_queries:
+        from oracle import oracle as orc
+        secs = sum(per[k]["cpu"]["seconds"] for k in kinds)
+        cells_cpu = sum(per[k]["cpu"]["dense_cells"] or 0 for k in kinds if k != "cdtw")
+        cpu = dict(value=cells_cpu / sum(per[k]["cpu"]["seconds"] for k in kinds if k != "cdtw") / 1e9,
+                   unit="GCUPS", cores=orc.num_threads(), kind="oracle",
+                   sample="prune-only matrix of the first 64 series (2,016 pairs) per distance; GCUPS over DTW "
+                          "and MSM", seconds=secs,
+                   identical_to_gpu=all(per[k]["cpu"]["identical_to_gpu"] for k in kinds))
     print(json.dumps(dict(
         metric=METRIC, value=tot_cells / (tot_ms * 1e-3) / 1e9, unit="GCUPS", n_gpus=1, steps=args.steps,
         warmup=1, ms_per_step=tot_ms, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
         data="synthetic",
         config=dict(workload=f"all pairs of {n} random walks, length 1024, prune-only EAPruned vs plain DP: "
                              + ", ".join(kinds), series=n, pairs=n * (n - 1) // 2, distances=kinds),
-        per_distance=per)), flush=True)
+        roofline=roofline, cpu_baseline=cpu, per_distance=per)), flush=True)
 
 
 ap_default_kinds = "dtw,cdtw,wdtw,erp,msm,twe"
@@ -374,7 +417,7 @@ def main():
     ap.add_argument("--refs", type=int, default=0, help="workloads 3-6: series / candidate / window count (0: the full workload)")
     ap.add_argument("--queries", type=int, default=0, help="workloads 4-6: query count (0: the full workload)")
     args = ap.parse_args()
-    if args.cpu_queries is None:
+    if args.cpu_queries is None and args.workload != 5:   # workload 5: 500 CDTW / 20 MSM served queries
         args.cpu_queries = 16 if args.workload == 4 else 500
     if args.precision is None:
         args.precision = 0 if args.workload == 6 else 1
@@ -624,6 +667,13 @@ def main():
     if args.cpu_queries > 0:
         cpu = cpu_baseline(wl, kinds, gpu_idx, gpu_dist, eap_q=min(args.cpu_queries, nq), dp_q=min(args.cpu_queries, nq, 64),
                            derivative=args.derivative)
+        if args.cpu_queries >= nq:
+            # cells the GPU sweeps execute per step against those sequential
+            # EAPruned evaluates on the same queries (Alg. 1's order and cut-off)
+            for k in kinds:
+                seq = cpu["sequential_eapruned_cells"].get(k)
+                if seq:
+                    per[k]["executed_vs_sequential_eapruned"] = per[k]["executed_cells_per_step"] / seq
 
     total_dense = sum(dense.values())
     line = dict(
@@ -972,65 +1022,146 @@ def run_subseq(args, torch, eap, synth):
 def run_served(args, torch, eap, synth):
     """Workload 5: a request server over 50,000 resident random walks (lengths
     128..1024); queries (lengths 128..1024) arrive as a Poisson process at
-    2,000 q/s and are answered in batches on 4 slots (FP32 screen + FP64
-    recheck, admission by memory).  Latency = arrival -> result on the host.
-    Also the closed-loop capacity: every query submitted at once."""
+    2,000 q/s for 5 s of warm-up and 30 s measured, and are answered in
+    batches on 4 slots (FP32 screen + FP64 recheck, admission by memory).
+    Latency = arrival -> result on the host, over the queries that arrive in
+    the measured 30 s.  Also the closed-loop capacity (a block of queries
+    submitted at once) and, when the offered rate exceeds it, a run at 90% of
+    it (the sustainable rate) with the same warm-up and window.  The roofline
+    is the main sweeps' executed cells over their launch times (HIP events)
+    during 2 s of the measured window, from the server's own counters."""
     dev = torch.device("cuda:0")
-    wl = synth.make_workload(5, n_ref=args.refs or None, n_query=args.queries or None)
+    rate, warm_s, meas_s = 2000.0, 5.0, 30.0
+    nq_total = args.queries or int(rate * (warm_s + meas_s))
+    wl = synth.make_workload(5, n_ref=args.refs or None, n_query=nq_total)
     ro, qo = wl["ref_off"], wl["query_off"]
     nr, nq = len(ro) - 1, len(qo) - 1
     r = torch.from_numpy(wl["refs"]).to(dev)
     qs = [wl["queries"][qo[i]: qo[i + 1]] for i in range(nq)]
-    arrivals = wl["arrivals"][:nq]
+    times = wl["arrivals"][:nq] - wl["arrivals"][0]
     kinds = [k for k in args.kinds.split(",") if k in wl["params"]] or list(wl["params"])
     out = {}
     for k in kinds:
         p = wl["params"][k]
+        say(f"workload 5 {k}: {nq} queries over {nr} resident candidates")
         if not args.no_tune:   # shapes for this distance, on a sample of the traffic
             eap.tune_nn1(torch.from_numpy(wl["queries"][: qo[32]]).to(dev), qo[:33], r, ro, p, precision=1)
 
-        def serve(times):
+        def serve(tm, n, prof_window=None):
+            """Queries 0..n-1 submitted at times tm (s from the start); returns
+            completion times, results, stats and, for prof_window = (t0, t1),
+            the main sweeps' cells and launches within it."""
             srv = eap.Server(r, ro, p, slots=4, max_batch=64, max_query_len=1024, mem_budget=8 << 30, precision=1)
-            done = {}
+            done, prof = {}, None
             try:
                 t0 = time.perf_counter()
                 i = 0
-                while len(done) < nq:
+                phase = 0
+                c0 = None
+                while len(done) < n:
                     now = time.perf_counter() - t0
-                    while i < nq and times[i] <= now:
+                    if prof_window and phase == 0 and now >= prof_window[0]:
+                        c0 = srv.counters()
+                        eap.profile_take()
+                        eap.profile_enable(True)
+                        phase = 1
+                    elif prof_window and phase == 1 and now >= prof_window[1]:
+                        c1 = srv.counters()
+                        eap.profile_enable(False)
+                        recs = [x for x in eap.profile_take() if x["stage"] == 2]
+                        prof = dict(cells=c1["stage_cells"][2] - c0["stage_cells"][2], launches=recs)
+                        phase = 2
+                    while i < n and tm[i] <= now:
                         srv.submit(qs[i], i)
                         i += 1
                     res = srv.poll()
                     tnow = time.perf_counter() - t0
                     for tag, idx, dist, _ in res:
                         done[tag] = (tnow, idx, dist)
-                    if not res and (i == nq or times[i] > tnow + 2e-4):
+                    if not res and (i == n or tm[i] > tnow + 2e-4):
                         time.sleep(1e-4)
                 st = srv.stats()
             finally:
+                eap.profile_enable(False)
                 srv.close()
-            lat = np.array([done[j][0] - times[j] for j in range(nq)]) * 1e3
-            span = max(v[0] for v in done.values()) - times[0]
-            return lat, span, st, done
+            return done, st, prof
 
-        serve(np.zeros(nq))   # warm-up: every query at once
-        lat, span, st, done = serve(arrivals - arrivals[0])
-        cap_lat, cap_span, cap_st, cap_done = serve(np.zeros(nq))
-        same = all(done[j][1:] == cap_done[j][1:] for j in range(nq))
-        offered = nq / (arrivals[-1] - arrivals[0])
-        out[k] = dict(offered_qps=offered, achieved_qps=nq / span, p50_ms=float(np.percentile(lat, 50)),
-                      p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
-                      capacity_qps=nq / cap_span, batches=st["batches"], max_batch=st["max_batch_seen"],
-                      max_inflight=st["max_inflight"], results_identical_to_closed_loop=same)
+        def summary(tm, n, done):
+            meas = [j for j in range(n) if warm_s <= tm[j] < warm_s + meas_s]
+            lat = np.array([done[j][0] - tm[j] for j in meas]) * 1e3
+            completed = sum(1 for v in done.values() if warm_s <= v[0] < warm_s + meas_s)
+            return dict(offered_qps=len(meas) / meas_s, achieved_qps=completed / meas_s,
+                        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                        max_ms=float(lat.max()), measured_queries=len(meas)), meas
+
+        ncap = min(nq, 4000)
+        serve(np.zeros(min(nq, 500)), min(nq, 500))   # warm-up of the process: a first block
+        say(f"{k}: closed-loop capacity on {ncap} queries")
+        t = time.perf_counter()
+        cap_done, _, _ = serve(np.zeros(ncap), ncap)
+        cap_qps = ncap / max(v[0] for v in cap_done.values())
+        say(f"{k}: offered {rate:.0f} q/s for {warm_s + meas_s:.0f} s")
+        done, st, prof = serve(times, nq, prof_window=(warm_s + 5.0, warm_s + 7.0))
+        res, meas = summary(times, nq, done)
+        same = all(done[j][1:] == cap_done[j][1:] for j in range(ncap))
+        res.update(capacity_qps=cap_qps, batches=st["batches"], max_batch=st["max_batch_seen"],
+                   max_inflight=st["max_inflight"], results_identical_to_closed_loop=same)
+        if rate > 0.9 * cap_qps:
+            # the sustainable rate: the same arrival draws, slowed to 90% of capacity
+            rs = 0.9 * cap_qps
+            ts = times * (rate / rs)
+            ns = int(np.searchsorted(ts, warm_s + meas_s))
+            say(f"{k}: sustainable {rs:.0f} q/s for {warm_s + meas_s:.0f} s ({ns} queries)")
+            sdone, _, _ = serve(ts, ns)
+            sres, _ = summary(ts, ns, sdone)
+            res["sustainable"] = dict(sres, rate_qps=rs)
+        # roofline of the main sweeps inside the profiled window
+        if prof and prof["launches"]:
+            ms = sum(x["ms"] for x in prof["launches"])
+            labels = {}
+            for x in prof["launches"]:
+                labels[kernel_label(x)] = labels.get(kernel_label(x), 0) + 1
+            lab = max(labels, key=labels.get)
+            fp32 = bool(prof["launches"][0]["fp32"])
+            ops = ops_per_cell(swept_kind(k, p), fp32, bool(prof["launches"][0].get("exact_diff")))
+            peak = (LANE_OPS_PER_S_F32 if fp32 else LANE_OPS_PER_S) / ops / 1e9
+            ach = prof["cells"] / (ms * 1e-3) / 1e9
+            res["roofline"] = dict(bound="alu", achieved=ach, peak=peak, unit="GCUPS", frac=ach / peak, traffic=None,
+                                   kernel=f"{lab} sweep, {swept_kind(k, p).upper()} main stage, "
+                                          f"{'fp32' if fp32 else 'fp64'}",
+                                   launches=len(prof["launches"]), mean_launch_ms=ms / len(prof["launches"]),
+                                   note="2 s of the measured window; launches of the 4 slots overlap, so each "
+                                        "launch's time includes its share of the GPU",
+                                   convention=ROOFLINE_CONVENTION)
+        # the oracle on recorded served queries (the first measured ones)
+        ncpu = args.cpu_queries if args.cpu_queries is not None else (500 if k == "cdtw" else 20)
+        if ncpu > 0:
+            from oracle import oracle as orc
+            sel = meas[:ncpu]
+            sq = np.concatenate([qs[j] for j in sel])
+            so = np.concatenate([[0], np.cumsum([len(qs[j]) for j in sel])]).astype(np.int64)
+            say(f"{k}: CPU oracle on {len(sel)} served queries")
+            t = time.perf_counter()
+            oi, od, _ = orc.nn1(p, sq, so, wl["refs"], ro, "eap")
+            secs = time.perf_counter() - t
+            gi = np.array([done[j][1] for j in sel])
+            gd = np.array([done[j][2] for j in sel])
+            res["cpu_baseline"] = dict(value=len(sel) / secs, unit="queries/s", cores=orc.num_threads(),
+                                       kind="oracle", seconds=secs,
+                                       sample=f"EAPruned NN of the first {len(sel)} measured served queries "
+                                              f"against all {nr} candidates",
+                                       nn_identical_to_gpu=bool(np.array_equal(gi, oi) and np.array_equal(gd, od)))
+        out[k] = res
     k0 = kinds[0]
     print(json.dumps(dict(
         metric=METRIC, value=out[k0]["achieved_qps"], unit="queries/s", n_gpus=1, steps=1, warmup=1,
         ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32+f64",
         data="synthetic",
-        config=dict(workload=f"served 1-NN: {nr} resident random walks (lengths 128..1024), {nq} queries "
-                             "(lengths 128..1024) arriving as a Poisson process at 2000 q/s, CDTW w=5% and "
-                             "MSM c=0.5, FP32 screen + FP64 recheck, 4 slots x batches of at most 64",
+        config=dict(workload=f"served 1-NN: {nr} resident random walks (lengths 128..1024), queries (lengths "
+                             "128..1024) arriving as a Poisson process at 2000 q/s, 5 s warm-up + 30 s measured, "
+                             "CDTW w=5% and MSM c=0.5, FP32 screen + FP64 recheck, 4 slots x batches of at most 64",
                     candidates=nr, queries=nq, distances=kinds),
+        roofline=out[k0].get("roofline"), cpu_baseline=out[k0].get("cpu_baseline"),
         per_distance=out)), flush=True)
 
 

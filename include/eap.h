@@ -417,6 +417,10 @@ eap_status eap_server_submit(eap_server* s, const double* q, int64_t len, int64_
 /* Up to `cap` results into `out` (host), their number in *n; see above. */
 eap_status eap_server_poll(eap_server* s, eap_result* out, int32_t cap, int32_t* n);
 eap_status eap_server_stats_get(const eap_server* s, eap_server_stats* out);
+/* The sweep counters of every batch the server has run, summed over its
+ * slots (see eap_counters; a slot's workspace keeps accumulating them).
+ * Waits for the batches in flight. */
+eap_status eap_server_counters(const eap_server* s, eap_counters* out);
 /* Waits for the batches in flight and frees everything (NULL is accepted). */
 eap_status eap_server_destroy(eap_server* s);
 const char* eap_server_last_error(void);

@@ -16,11 +16,14 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", *CFLAGS, SRC, "-o", OUT + ".tmp", "-lm"]
+    # a private temporary per process, renamed into place atomically: test
+    # workers that find the library stale at the same time may all rebuild it
+    tmp = f"{OUT}.{os.getpid()}.tmp"
+    cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
+    os.replace(tmp, OUT)
     return OUT
 
 

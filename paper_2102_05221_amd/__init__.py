@@ -161,6 +161,8 @@ def lib():
         L.eap_server_poll.argtypes = [_vp, ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.eap_server_stats_get.restype = ctypes.c_int
         L.eap_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+        L.eap_server_counters.restype = ctypes.c_int
+        L.eap_server_counters.argtypes = [_vp, ctypes.POINTER(Counters)]
         L.eap_server_destroy.restype = ctypes.c_int
         L.eap_server_destroy.argtypes = [_vp]
         L.eap_server_last_error.restype = ctypes.c_char_p
@@ -461,6 +463,13 @@ class Server:
         _scheck(lib().eap_server_stats_get(self._h, ctypes.byref(s)))
         return dict(batches=s.batches, queries=s.queries, max_batch_seen=s.max_batch_seen,
                     max_inflight=s.max_inflight, waiting=s.waiting)
+
+    def counters(self) -> dict:
+        """Sweep counters summed over every batch run (waits for those in flight)."""
+        c = Counters()
+        _scheck(lib().eap_server_counters(self._h, ctypes.byref(c)))
+        return dict(cells=c.cells, pairs=c.pairs, rechecks=c.rechecks, overflows=c.overflows,
+                    stage_cells=list(c.stage_cells), stage_pairs=list(c.stage_pairs), lb_pruned=c.lb_pruned)
 
     def close(self) -> None:
         if self._h:

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "eap.h"
+#include "eap_internal.h"
 #include "eap_launch.h"
 #include "eap_screen.h"
 
@@ -307,10 +308,15 @@ int band_lanes(int kind, bool fp32, int diags) {
 }
 
 // Shape for launches with few pairs (one per query: the seed and recheck
-// sweeps), which are bound by the latency of a pair's chain of steps rather
-// than by throughput: 64 lanes per pair and the fewest columns per lane
-// (steps take time in proportion to the columns a lane owns).
-RowsShape latency_shape(int64_t lco_max) { return RowsShape{64, lco_max <= 512 ? 8 : 16}; }
+// sweeps, both FP64), which are bound by the latency of a pair's chain of
+// steps rather than by throughput: 64 lanes per pair and the fewest columns
+// per lane (steps take time in proportion to the columns a lane owns).  ERP,
+// MSM and TWE keep 8 columns per lane at any length: with 16 their FP64 lanes
+// spill registers inside the step loop.
+RowsShape latency_shape(int kind, int64_t lco_max) {
+    if (kind == EAP_ERP || kind == EAP_MSM || kind == EAP_TWE) return RowsShape{64, 8};
+    return RowsShape{64, lco_max <= 512 ? 8 : 16};
+}
 
 // What the sweep of one distance needs, for sets whose longest series have
 // lengths la_max and lb_max.
@@ -989,7 +995,8 @@ eap_status eap_nn1(const double* q, const int64_t* q_off, int64_t nq, const doub
     const bool rerun = pl.rerun;
     // the seed and recheck sweeps have one or a few pairs per query
     Plan few = pl;
-    few.r64 = few.r32 = dims_of(p) > 1 ? RowsShape{64, 8} : latency_shape(std::min(Q.maxlen, R.maxlen));
+    few.r64 = few.r32 =
+        dims_of(p) > 1 ? RowsShape{64, 8} : latency_shape(effective_kind(p), std::min(Q.maxlen, R.maxlen));
     if (seeded) {
         // 2. sweep the seed candidate of every query under its bound, in FP64
         //    also when screening: its exact distance is the tightest start for
@@ -1474,3 +1481,18 @@ eap_status eap_profile_take(eap_profile_rec* out, int32_t cap, int32_t* n) {
 }
 
 }  // extern "C"
+
+namespace eap {
+
+size_t nn1_workspace_sizes(const SetSizes& Q, const SetSizes& R, const eap_params* p, const eap_nn_opts* o) {
+    if (check_params(p) != EAP_OK || Q.n < 1 || R.n < 1) return 0;
+    SetInfo q, r;
+    q.n = Q.n; q.total = Q.total; q.maxlen = Q.maxlen; q.minlen = Q.minlen;
+    r.n = R.n; r.total = R.total; r.maxlen = R.maxlen; r.minlen = R.minlen;
+    NNLayout nl;
+    const bool prec1 = o && o->precision == 1 && dims_of(p) == 1;
+    nn_layout(q, r, p, prec1, prec1 && screen_possible(p, std::max(q.maxlen, r.maxlen)), lb_mode(p, o), nl);
+    return nl.L.off;
+}
+
+}  // namespace eap

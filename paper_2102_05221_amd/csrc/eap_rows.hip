@@ -49,12 +49,14 @@
 namespace eap {
 
 // Blocks per CU the register budget is sized for: 3 (168 VGPRs) for FP32,
-// except TWE and ERP lanes of 16 or more columns, which spill heavily at that
-// budget and run faster with 256 VGPRs at 2 blocks per CU (measured on the
-// 500 x 500, length-512 NN workload: TWE 8x16 3.49 against 4.87 ms); FP64: 2.
+// except TWE, ERP and MSM lanes of 16 or more columns (and exact-difference
+// lanes), which spill at that budget - MSM into its step loop, a scratch
+// reload and a wait on every step - and run with 256 VGPRs at 2 blocks per CU
+// (measured on the 500 x 500, length-512 NN workload: TWE 8x16 3.49 against
+// 4.87 ms); FP64: 2.
 template <int KIND, typename T, int C, bool XD>
 constexpr int rows_min_blocks() {
-    return (sizeof(T) == 4 && !(C >= 16 && (KIND == TWE || KIND == ERP || XD))) ? 3 : 2;
+    return (sizeof(T) == 4 && !(C >= 16 && (KIND == TWE || KIND == ERP || KIND == MSM || XD))) ? 3 : 2;
 }
 
 template <typename T, bool XD> using RowValue = typename std::conditional<XD, double, T>::type;
@@ -335,14 +337,22 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         // first row are fed their own left-border value and s = gap (ERP) or
         // +inf inputs, which reproduces their top border bit for bit; lanes past
         // the last row compute values nobody reads.
+        // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G; each
+        // step reads the next step's pair (M(row, cb), s_row) ahead, so the
+        // cross-lane read overlaps a step of cell updates
+        T pre_b = bperm(gaddr, st_b[0]);
+        P pre_s = bperm(gaddr, st_s[0]);
         auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t) {
             T lin;
             P sin;
             row += 1;
             {
-                // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G
-                const T bv = bperm(gaddr + 4 * (t % G), st_b[t / G]);   // M(row, cb)
-                const P sv = bperm(gaddr + 4 * (t % G), st_s[t / G]);   // s_row
+                const T bv = pre_b;   // M(row, cb)
+                const P sv = pre_s;   // s_row
+                if (t + 1 < K) {
+                    pre_b = bperm(gaddr + 4 * ((t + 1) % G), st_b[(t + 1) / G]);
+                    pre_s = bperm(gaddr + 4 * ((t + 1) % G), st_s[(t + 1) / G]);
+                }
                 if constexpr (G == 16) {
                     // a group is one DPP row: shift and feed lane 0 at once
                     lin = row_shr1_or(lout, bv);

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "eap.h"
+#include "eap_internal.h"
 
 namespace {
 
@@ -73,6 +74,7 @@ struct eap_server {
     const double* refs = nullptr;
     std::vector<int64_t> r_off;
     int64_t nr = 0;
+    eap::SetSizes rs;   // the candidates' sizes, checked once at creation
     const int32_t* labels = nullptr;
     char* pool = nullptr;
     std::vector<Slot> slots;
@@ -96,27 +98,32 @@ void free_server(eap_server* s) {
     delete s;
 }
 
-// Bytes a batch of these queries needs in a slot: NN workspace (at the slot's
-// start, so that what it derived from the candidates stays in place from batch
-// to batch), values, outputs.
-size_t batch_bytes(const eap_server* s, const std::vector<int64_t>& qoff) {
-    const int64_t nq = (int64_t)qoff.size() - 1;
-    const size_t ws = eap_nn1_workspace(qoff.data(), nq, s->r_off.data(), s->nr, &s->p, &s->nn);
+// Bytes a batch of queries of these sizes needs in a slot: NN workspace (at
+// the slot's start, so that what it derived from the candidates stays in
+// place from batch to batch), values, outputs.  From sizes alone: admission
+// reads neither the candidates' offsets nor the queries' again.
+size_t batch_bytes(const eap_server* s, const eap::SetSizes& q) {
+    const size_t ws = eap::nn1_workspace_sizes(q, s->rs, &s->p, &s->nn);
     if (ws == 0) return SIZE_MAX;
-    return up(ws) + up(sizeof(double) * (size_t)qoff.back()) + up(sizeof(int64_t) * (size_t)nq) +
-           up(sizeof(double) * (size_t)nq) + up(sizeof(int32_t) * (size_t)nq);
+    return up(ws) + up(sizeof(double) * (size_t)q.total) + up(sizeof(int64_t) * (size_t)q.n) +
+           up(sizeof(double) * (size_t)q.n) + up(sizeof(int32_t) * (size_t)q.n);
 }
 
 // Fill `sl` with the longest FIFO prefix that fits and start its search.
 eap_status launch_batch(eap_server* s, Slot& sl) {
     std::vector<int64_t> qoff{0};
+    eap::SetSizes q;
     size_t k = 0;
     while (k < s->fifo.size() && (int64_t)k < s->o.max_batch) {
-        qoff.push_back(qoff.back() + (int64_t)s->fifo[k].v.size());
-        if (batch_bytes(s, qoff) > sl.bytes) {
-            qoff.pop_back();
-            break;
-        }
+        const int64_t L = (int64_t)s->fifo[k].v.size();
+        eap::SetSizes q2 = q;
+        q2.n += 1;
+        q2.total += L;
+        q2.maxlen = std::max(q.maxlen, L);
+        q2.minlen = q.n ? std::min(q.minlen, L) : L;
+        if (batch_bytes(s, q2) > sl.bytes) break;
+        q = q2;
+        qoff.push_back(qoff.back() + L);
         ++k;
     }
     if (k == 0) return sfail(EAP_ENOMEM, "query %lld does not fit a slot of %zu bytes",
@@ -127,7 +134,7 @@ eap_status launch_batch(eap_server* s, Slot& sl) {
         std::memcpy(sl.hq + qoff[i], s->fifo[i].v.data(), sizeof(double) * s->fifo[i].v.size());
         sl.tags.push_back(s->fifo[i].tag);
     }
-    const size_t ws_bytes = eap_nn1_workspace(qoff.data(), nq, s->r_off.data(), s->nr, &s->p, &s->nn);
+    const size_t ws_bytes = eap::nn1_workspace_sizes(q, s->rs, &s->p, &s->nn);
     char* at = sl.dev;
     void* ws = at;
     at += up(ws_bytes);
@@ -192,6 +199,23 @@ eap_status eap_server_create(const double* refs, const int64_t* r_off, int64_t n
     s->refs = refs;
     s->r_off.assign(r_off, r_off + nr + 1);
     s->nr = nr;
+    // the candidates' offsets, checked once (the library's limits: lengths 1..2048)
+    if (r_off[0] != 0) {
+        delete s;
+        return sfail(EAP_EINVAL, "candidate offsets must start at 0");
+    }
+    s->rs.n = nr;
+    s->rs.minlen = INT64_MAX;
+    for (int64_t k = 0; k < nr; ++k) {
+        const int64_t L = r_off[k + 1] - r_off[k];
+        if (L < 1 || L > 2048) {
+            delete s;
+            return sfail(EAP_EINVAL, "candidate %lld has length %lld (1..2048)", (long long)k, (long long)L);
+        }
+        s->rs.maxlen = std::max(s->rs.maxlen, L);
+        s->rs.minlen = std::min(s->rs.minlen, L);
+    }
+    s->rs.total = r_off[nr];
     s->labels = r_labels;
     // the one allocation of the server: every slot's share of the pool
     const size_t per = o->mem_budget / (size_t)o->slots / kAlign * kAlign;
@@ -268,6 +292,26 @@ eap_status eap_server_stats_get(const eap_server* s, eap_server_stats* out) {
     if (!s || !out) return sfail(EAP_EINVAL, "bad stats arguments");
     *out = s->st;
     out->waiting = (int64_t)s->fifo.size();
+    return EAP_OK;
+}
+
+eap_status eap_server_counters(const eap_server* s, eap_counters* out) {
+    if (!s || !out) return sfail(EAP_EINVAL, "bad counters arguments");
+    std::memset(out, 0, sizeof *out);
+    for (const Slot& sl : s->slots) {
+        eap_counters c;
+        if (eap_read_counters(sl.dev, sl.bytes, &c, sl.stream) != EAP_OK)
+            return sfail(EAP_EDEVICE, "slot counters: %s", eap_last_error());
+        out->cells += c.cells;
+        out->pairs += c.pairs;
+        out->rechecks += c.rechecks;
+        out->overflows += c.overflows;
+        for (int i = 0; i < 8; ++i) {
+            out->stage_cells[i] += c.stage_cells[i];
+            out->stage_pairs[i] += c.stage_pairs[i];
+        }
+        out->lb_pruned += c.lb_pruned;
+    }
     return EAP_OK;
 }
 
