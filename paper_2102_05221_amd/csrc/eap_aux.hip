@@ -503,25 +503,124 @@ __global__ __launch_bounds__(256) void lb_reverse_kernel(const double* qv, const
     }
 }
 
-// UB of every (query, candidate) pair from the interleaved candidates: a block
-// takes one query (staged in LDS, read by all lanes at once) and 256
-// candidates (one per lane, coalesced).
-template <int KIND>
-__global__ void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qoff, const double* rT,
-                               const int64_t* roff, double* ub) {
-    extern __shared__ double qs[];
+// UB of every (query, candidate) pair from the interleaved candidates: the
+// terms of path_ub_acc in its order, for QT queries per pass over 256
+// candidates per block (a lane per candidate, its values read once, coalesced,
+// for all QT queries; query values by scalar loads).  The position loop is
+// uniform over the wave: the diagonal terms depend on the two values only
+// through |d| or d^2 (d and -d round alike), so they are formed from the pair
+// (q_k, r_k) whatever the orientation, and past the shorter series' end the
+// clamped index repeats its last value, which is the tail's fixed column
+// value.  Only the tail terms of ERP, MSM and TWE, which also depend on the
+// longer series' own previous value, pick the longer series by a select.
+template <int KIND, int QT>
+__global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qoff,
+                                                      const double* rT, const int64_t* roff, int lr_max, double* ub) {
+    typedef const __attribute__((address_space(4))) double* cdp;
+    typedef const __attribute__((address_space(4))) int64_t* cip;
     const int64_t nB = A.nB;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t a = blockIdx.y; a < A.nA; a += gridDim.y) {
-        const int lq = (int)(qoff[a + 1] - qoff[a]);
-        __syncthreads();
-        for (int k = threadIdx.x; k < lq; k += blockDim.x) qs[k] = qv[qoff[a] + k];
-        __syncthreads();
-        if (b < nB) {
-            const int lr = (int)(roff[b + 1] - roff[b]);
-            auto Q = [&](int k) { return qs[k]; };
-            auto R = [&](int k) { return rT[(int64_t)k * nB + b]; };
-            ub[a * nB + b] = (lq >= lr) ? path_ub_acc<KIND>(A, Q, lq, R, lr) : path_ub_acc<KIND>(A, R, lr, Q, lq);
+    const bool live = b < nB;
+    const int64_t bb = live ? b : nB - 1;   // lanes past the end read the last candidate, store nothing
+    const int lr = (int)(roff[bb + 1] - roff[bb]);
+    int lw = lr;   // the wave's longest candidate
+    for (int o = 32; o > 0; o >>= 1) lw = max(lw, __shfl_xor(lw, o));
+    lw = __builtin_amdgcn_readfirstlane(lw);
+    const double rlast = rT[(int64_t)(lr - 1) * nB + bb];
+    const double ratio = A.window_ratio;
+    const cip qo = (cip)qoff;
+    const cdp qc = (cdp)qv;
+    for (int64_t a0 = (int64_t)blockIdx.y * QT; a0 < A.nA; a0 += (int64_t)gridDim.y * QT) {
+        const int nqt = (int)((A.nA - a0) < QT ? (A.nA - a0) : QT);
+        int64_t qb[QT];
+        int lq[QT], Lco[QT], Lli[QT];
+        double acc[QT], sp[QT], wd[QT];
+        bool feasible[QT];
+        int kmax = lw;
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+            qb[t] = t < nqt ? qo[a0 + t] : 0;
+            lq[t] = t < nqt ? (int)(qo[a0 + t + 1] - qb[t]) : 1;
+            kmax = kmax > lq[t] ? kmax : lq[t];
+            Lco[t] = lq[t] < lr ? lq[t] : lr;
+            Lli[t] = lq[t] < lr ? lr : lq[t];
+            feasible[t] = true;
+            if constexpr (KIND == CDTW || KIND == ERP)
+                if (ratio < 1.0 && (int)floor(ratio * (double)Lli[t]) < Lli[t] - Lco[t]) feasible[t] = false;
+            wd[t] = 1.0;
+            if constexpr (KIND == WDTW) {
+                int gi = -Lli[t] + A.gtab_off;
+                gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
+                wd[t] = A.gtab[gi];
+            }
+            acc[t] = 0.0;
+            sp[t] = 0.0;
+        }
+        double rprev = 0.0;   // TWE: r_{k-1} (0 before the first)
+        constexpr int CH = 4;
+        for (int k0 = 0; k0 < kmax; k0 += CH) {
+            double rv[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int k = k0 + u;
+                rv[u] = (k < lr) ? rT[(int64_t)(k < lr_max ? k : lr_max - 1) * nB + bb] : rlast;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int k = k0 + u;
+                const double r = rv[u];
+#pragma unroll
+                for (int t = 0; t < QT; ++t) {
+                    if (t >= nqt) continue;
+                    const int kq = k < lq[t] ? k : lq[t] - 1;
+                    const double q = qc[qb[t] + kq];
+                    const bool dg = k < Lco[t], tl = !dg && k < Lli[t];
+                    const double d = q - r;
+                    double term = 0.0;
+                    // the longer series' value (rows of the path) and the previous one
+                    const double s = (lq[t] >= lr) ? q : r;
+                    if constexpr (KIND == DTW || KIND == CDTW) term = d * d;
+                    if constexpr (KIND == WDTW) {
+                        double w = wd[t];
+                        if (tl) {
+                            int gi = 2 * (k + 1 - Lco[t]) - Lli[t] + A.gtab_off;
+                            gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
+                            w = A.gtab[gi];
+                        }
+                        term = w * (d * d);
+                    }
+                    if constexpr (KIND == ERP) term = dg ? __builtin_fabs(d) : __builtin_fabs(s - A.gap);
+                    if constexpr (KIND == MSM) {
+                        if (dg) {
+                            term = __builtin_fabs(d);
+                        } else {
+                            // C(s_i, s_{i-1}, t) of eq. MSMCost, t the shorter series' last value
+                            const double x = sp[t], tt = (lq[t] >= lr) ? r : q;
+                            if ((x <= s && s <= tt) || (x >= s && s >= tt)) term = A.c;
+                            else {
+                                const double p1 = __builtin_fabs(s - x), p2 = __builtin_fabs(s - tt);
+                                term = A.c + (p1 < p2 ? p1 : p2);
+                            }
+                        }
+                    }
+                    if constexpr (KIND == TWE) {
+                        const double qp = k > 0 ? qc[qb[t] + (k - 1 < lq[t] ? k - 1 : lq[t] - 1)] : 0.0;
+                        term = dg ? ((__builtin_fabs(d) + __builtin_fabs(qp - rprev)) + A.nu * 0.0)
+                                  : ((__builtin_fabs(s - sp[t]) + A.nu) + A.lam);
+                    }
+                    if (dg || tl) {
+                        if constexpr (KIND == DTW || KIND == CDTW || KIND == WDTW) acc[t] = term + acc[t];
+                        else acc[t] = acc[t] + term;
+                    }
+                    sp[t] = s;
+                }
+                if constexpr (KIND == TWE) rprev = r;
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int t = 0; t < QT; ++t)
+                if (t < nqt) ub[(a0 + t) * nB + b] = feasible[t] ? acc[t] : __builtin_huge_val();
         }
     }
 }
@@ -1305,17 +1404,38 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
 #undef EAP_UBLB
         return hipGetLastError();
     }
-    const dim3 g((unsigned)((a.nB + 255) / 256), (unsigned)std::min<int64_t>(a.nA, 65535)), b(256);
-    const size_t lds = sizeof(double) * (size_t)lq_max;
+    // queries per block: the most that still leaves at least 2 blocks per CU
+    const int64_t bx = (a.nB + 255) / 256;
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    int qt = 1;
+    for (int c : {8, 4, 2})
+        if (bx * ((a.nA + c - 1) / c) >= 2 * (int64_t)cus) {
+            qt = c;
+            break;
+        }
+    const dim3 g((unsigned)bx, (unsigned)std::min<int64_t>((a.nA + qt - 1) / qt, 65535)), b(256);
+#define EAP_UBT(K, QT) hipLaunchKernelGGL((ub_nn_t_kernel<K, QT>), g, b, 0, s, a, qv, qoff, rT, roff, lr_max, ub)
+#define EAP_UBQ(K)             \
+    switch (qt) {              \
+    case 8: EAP_UBT(K, 8); break; \
+    case 4: EAP_UBT(K, 4); break; \
+    case 2: EAP_UBT(K, 2); break; \
+    default: EAP_UBT(K, 1); break; \
+    }
     switch (kind) {
-    case DTW: hipLaunchKernelGGL(ub_nn_t_kernel<DTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case CDTW: hipLaunchKernelGGL(ub_nn_t_kernel<CDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case WDTW: hipLaunchKernelGGL(ub_nn_t_kernel<WDTW>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case ERP: hipLaunchKernelGGL(ub_nn_t_kernel<ERP>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case MSM: hipLaunchKernelGGL(ub_nn_t_kernel<MSM>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
-    case TWE: hipLaunchKernelGGL(ub_nn_t_kernel<TWE>, g, b, lds, s, a, qv, qoff, rT, roff, ub); break;
+    case DTW: EAP_UBQ(DTW); break;
+    case CDTW: EAP_UBQ(CDTW); break;
+    case WDTW: EAP_UBQ(WDTW); break;
+    case ERP: EAP_UBQ(ERP); break;
+    case MSM: EAP_UBQ(MSM); break;
+    case TWE: EAP_UBQ(TWE); break;
     default: return hipErrorInvalidValue;
     }
+#undef EAP_UBQ
+#undef EAP_UBT
     return hipGetLastError();
 }
 

@@ -113,7 +113,15 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     int Lli = 1, Lco = 0, kend = 0, uend = 0, row = 0;
     int nstrip = 1, si = 0, cb = 0, c0 = 1, r_start = 1;
     int e_lo = 0, e_hi = -1;       // rows of the incoming edge that can be <= cut-off
-    int rec_lo = 0, rec_hi = -1;   // the same for the edge this strip writes (last lane)
+    // the same for the edge this strip writes, over the rows this lane has
+    // checked (reduced over the group when the strip ends)
+    int rec_lo = 0, rec_hi = -1;
+    // The last lane's right-edge values of the current block, one slot per
+    // step (beside their store to the edge buffer), checked by the whole
+    // group at the block end, K / G slots per lane: no per-step work beyond
+    // the store.  A group never spans two waves, so no barrier.
+    __shared__ T eblk[256 / G][K];
+    const int gslot = threadIdx.x / G;
     bool last = true, full_top = true;
     T cut = 0;
     T val[C], vb[C], aux[C];
@@ -185,6 +193,8 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
             if (!top_live) r_start = e_lo;
         }
         full_top = (r_start == 1);
+        rec_lo = 1 << 30;
+        rec_hi = -1;
         // column values t_j of the strip (+inf beyond L_co) and t_{c0-1} (t_0 = 0)
 #pragma unroll
         for (int u = 0; u < C; ++u)
@@ -230,8 +240,6 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         lout = val[C - 1];
         sout = pt_fill<V, ND>(0);
         sp = 0;
-        rec_lo = 1 << 30;
-        rec_hi = -1;
         // the first block's row inputs (the loop stages each next block)
 #pragma unroll
         for (int i = 0; i < RS; ++i) load_row(row + k + 1 + k + G * i, st_s[i], st_b[i]);
@@ -313,12 +321,18 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
 #pragma unroll
                 for (int m = 0; m < NW; ++m) dwin[m] = tp[m];
             } else {
+                // WDTW: entry 2|d| - L_li + tab_off, which is >= 0 for every d
+                // (tab_off >= L_li) and inside the table for |d| <= L_li (every
+                // cell of the matrix); beyond, the last entry.  With d = base + m,
+                // 2|d| = max(2 base + 2m, -2 base - 2m): per entry two adds of
+                // constants to per-lane values, a max and the clamp, on byte offsets
+                const int e = (int)sizeof(T), c = tab_off - Lli;
+                const int pa = (2 * base + c) * e, pb = (c - 2 * base) * e, hi = (tab_len - 1) * e;
+                const char* tb = reinterpret_cast<const char*>(tab);
 #pragma unroll
                 for (int m = 0; m < NW; ++m) {
-                    const int d = base + m;
-                    int x = 2 * (d < 0 ? -d : d) - Lli + tab_off;
-                    x = x < 0 ? 0 : (x >= tab_len ? tab_len - 1 : x);
-                    dwin[m] = tab[x];
+                    const int x = vmin(vmax(pa + 2 * e * m, pb - 2 * e * m), hi);
+                    dwin[m] = *reinterpret_cast<const T*>(tb + x);
                 }
             }
         }
@@ -336,13 +350,17 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         // alternate, so no value is copied).  Lanes that have not reached their
         // first row are fed their own left-border value and s = gap (ERP) or
         // +inf inputs, which reproduces their top border bit for bit; lanes past
-        // the last row compute values nobody reads.
+        // the last row compute values nobody reads.  A block in which no lane
+        // of the wave is before its first row or past the pair's last one (the
+        // interior of a strip, nearly every block of a long one) runs a step
+        // without those cases (FAST).
         // lane 0's row R0 + 1 + t is staged in lane t % G, slot t / G; each
         // step reads the next step's pair (M(row, cb), s_row) ahead, so the
         // cross-lane read overlaps a step of cell updates
         T pre_b = bperm(gaddr, st_b[0]);
         P pre_s = bperm(gaddr, st_s[0]);
-        auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t) {
+        auto step = [&](T (&src)[C], T (&dst)[C], bool check, int t, auto fast_tag) {
+            constexpr bool FAST = decltype(fast_tag)::value;
             T lin;
             P sin;
             row += 1;
@@ -366,12 +384,12 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
                     }
                 }
             }
-            const bool ns = row < r_start;   // not started: keep the top border
+            const bool ns = !FAST && row < r_start;   // not started: keep the top border
             if (ns) {
                 lin = brd0;
                 sin = s0;
             }
-            const bool act = have && !ns && row <= Lli;
+            const bool act = FAST ? have : (have && !ns && row <= Lli);
             T diag = ns ? brd0 : dg;
             if (!ns) dg = lin;          // M(r_start-1, c0-1) stays the diagonal of the first row
             T left = lin;
@@ -431,20 +449,16 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
             }
             if constexpr (KIND == TWE) adv[C - 1] = carry;
             if (!ns) sp = sin.c[0];
-            {
-                // this strip's right edge, M(row, cb + W), for the next strip
-                const T e = dst[C - 1];
-                const bool st = !last && k == G - 1 && act;
-                const bool el = st && (e <= cut);
-                rec_lo = (el && rec_lo > row) ? row : rec_lo;
-                rec_hi = el ? row : rec_hi;
-                if (st) eb[row] = e;
+            // this strip's right edge, M(row, cb + W), for the next strip
+            if (!last && k == G - 1 && act) {
+                eb[row] = dst[C - 1];
+                eblk[gslot][t] = dst[C - 1];
             }
             lout = dst[C - 1];
             sout = sin;
             if (check) {
                 bool lv;
-                if (!have || row > Lli) lv = false;
+                if (!have || (!FAST && row > Lli)) lv = false;
                 else if (ns) lv = (KIND == ERP) && full_top;   // the computed top border
                 else {
                     T m = lin;
@@ -458,15 +472,37 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
             }
         };
         // the staircase of the block's last two steps is the cut tested below
+        auto block = [&](auto fast_tag) {
 #pragma unroll
-        for (int t = 0; t < K; t += 2) {
-            step(val, vb, t >= K - 2, t);
-            step(vb, val, t + 1 >= K - 2, t + 1);
-        }
+            for (int t = 0; t < K; t += 2) {
+                step(val, vb, t >= K - 2, t, fast_tag);
+                step(vb, val, t + 1 >= K - 2, t + 1, fast_tag);
+            }
+        };
+        // rows row + 1 .. row + K of every lane with a pair within r_start..L_li
+        if (__all(!have || (row + 1 >= r_start && row + K <= Lli))) block(std::true_type{});
+        else block(std::false_type{});
 #pragma unroll
         for (int i = 0; i < RS; ++i) {
             st_s[i] = nx_s[i];
             st_b[i] = nx_b[i];
+        }
+        if (have && !last) {
+            // the rows of the edge written in this block that are <= cut-off:
+            // lane G-1 computed rows R + 1 .. R + K (R its row before the block),
+            // slot t holding row R + 1 + t where that step stored it
+            const int r1 = row + k - (G - 1) - K + 1;
+#pragma unroll
+            for (int i = 0; i < (K + G - 1) / G; ++i) {
+                const int t = k + G * i;
+                if (t < K) {
+                    const int r = r1 + t;
+                    if (r >= r_start && r <= Lli && eblk[gslot][t] <= cut) {
+                        rec_lo = vmin(rec_lo, r);
+                        rec_hi = vmax(rec_hi, r);
+                    }
+                }
+            }
         }
         if (have) {
             // rows of this block in r_start..L_li: the cells counted as executed
@@ -485,11 +521,18 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
         const unsigned long long sm = ballot(send_l);
         const unsigned long long lm = ballot(live_any);
         const bool lost = (ballot(lost_l) & gmask) != 0;
-        const int nlo = __shfl(rec_lo, lane - k + G - 1);
-        const int nhi = __shfl(rec_hi, lane - k + G - 1);
         const bool fin = (fm & gmask) != 0;
         const bool send = (sm & gmask) != 0;
         const bool alive = (lm & gmask) != 0;
+        // a strip that ends (not the last one): its live edge rows over the group
+        int nlo = rec_lo, nhi = rec_hi;
+        if (__any(have && !last && (send || !alive))) {
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) {
+                nlo = vmin(nlo, __shfl_xor(nlo, o));
+                nhi = vmax(nhi, __shfl_xor(nhi, o));
+            }
+        }
         if (fin_l) {
             T r = val[0];
 #pragma unroll
