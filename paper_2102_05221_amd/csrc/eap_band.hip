@@ -87,6 +87,11 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
     const T* li = nullptr;
     const T* co = nullptr;
     int Lli = 0, Lco = 0, a = 0, a_end = 0, apen = 0, dk = 0, w = 0, ke = 0, me = 0, i0 = 0, j0 = 0;
+    // cells counted as executed per step of either parity: the lane's
+    // diagonals inside the window (CDTW, ERP: the band padded to the group's
+    // width also sweeps diagonals that are +inf throughout), all of them for
+    // the unconstrained distances
+    int ncnt0 = C, ncnt1 = C;
     T cut = 0, res_v = 0;
     T val[M2], S[CB], Tt[CB], Sc[CB], Sn[CB], Tc[CB], Tn[CB], wt[M2], pen[M2];
     unsigned long long ncells = 0, npairs = 0, nlb = 0;
@@ -170,6 +175,16 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
                         }
                     }
                     continue;
+                }
+                if constexpr (WIN) {
+                    ncnt0 = ncnt1 = 0;
+#pragma unroll
+                    for (int m = 0; m < M2; ++m) {
+                        const int d = dlo + 2 * k * C + m;
+                        const int in = (d >= lo_need && d <= hi_need) ? 1 : 0;
+                        if (m & 1) ncnt1 += in;
+                        else ncnt0 += in;
+                    }
                 }
                 lo_open = !WIN && dlo > 1 - Lli;
                 hi_open = !WIN && dhi < Lco - 1;
@@ -294,7 +309,7 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
                     val[m] = v;
                     if (t >= NB - 2) mstep = vmin(mstep, v);
                 }
-                ncells += C;
+                ncells += (p == 0) ? ncnt0 : ncnt1;
                 if (t >= NB - 2) live_any = live_any || (mstep <= cut);
                 if (p == 0) {
                     if (k == 0 && lo_open && val[0] <= cut) ovf = true;
@@ -418,7 +433,9 @@ static hipError_t gob_d(int diags, int g, const SweepArgs& a, SeriesPtrs SA, Ser
 
 // The compiled band shapes: 4 or 8 diagonals per parity and lane (more only
 // for the widest band; the band's rings and weights make wider lanes spill out
-// of the register file).
+// of the register file).  16 diagonals on 2 lanes (4 per parity) were
+// measured for the narrowest windows and were slower: their blocks of 8 steps
+// fetch the entering series values too short a time ahead.
 bool band_shape_ok(int diags, int g) {
     switch (diags * 100 + g) {
     case 3202: case 3204: case 6404: case 6408:

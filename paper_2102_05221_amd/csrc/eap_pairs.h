@@ -73,17 +73,25 @@ template <typename T> __device__ __forceinline__ T nn_cut(const SweepArgs& A, in
     return t;
 }
 
-// Work slots are handed to a group A.chunk at a time (one atomic per chunk,
-// consecutive slots); `next`/`end` are the group's current chunk.
+// Work slots are handed to a group A.chunk at a time (consecutive slots);
+// `next`/`end` are the group's current chunk.  The groups of a wave that need
+// a chunk at the same time take theirs with one atomic (its first such group
+// adds all of them, each group takes its chunk by rank), so that lists of
+// many short items, taken one slot at a time, do not serialise on the counter.
 __device__ __forceinline__ unsigned int fetch_slot(const SweepArgs& A, unsigned int& next, unsigned int& end,
                                                    int lane, int k) {
-    if (next >= end) {
+    const bool need = next >= end;
+    const unsigned long long m = __ballot(need && k == 0);
+    if (need) {
         const unsigned int ch = A.chunk > 0 ? (unsigned int)A.chunk : 1u;
+        const int lead = __ffsll((long long)m) - 1;
         unsigned int base = 0;
-        if (k == 0) base = atomicAdd(A.queue, ch);
-        base = __shfl(base, lane - k);
-        next = base;
-        end = base + ch;
+        if (lane == lead) base = atomicAdd(A.queue, ch * (unsigned int)__popcll(m));
+        base = __shfl(base, lead);
+        const int g0 = lane - k;   // this group's first lane
+        const unsigned int rank = (unsigned int)__popcll(m & ((1ull << g0) - 1ull));
+        next = base + rank * ch;
+        end = next + ch;
     }
     return next++;
 }
