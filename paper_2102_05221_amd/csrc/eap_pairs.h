@@ -57,9 +57,20 @@ __device__ __forceinline__ Item decode_item(const SweepArgs& A, int64_t p) {
 
 __device__ __forceinline__ bool is_nn_mode(int mode) { return mode == PM_NN_ALL; }
 
-// The item index behind work slot p of a launch.
+// The item index behind work slot p of a launch.  An NN search over all
+// pairs takes them candidate by candidate (slot p -> query p % nA, candidate
+// p / nA): each query then has only a few pairs in flight at a time, and its
+// best-so-far tightens as its candidates complete, as in Alg. 1's loop; in
+// query order the pairs of one query would all start under the seed's
+// cut-off.  The item (a * nB + b) and its result slot are unchanged.
 __device__ __forceinline__ int64_t item_of(const SweepArgs& A, unsigned int p) {
-    return A.items ? (int64_t)A.items[p] : (int64_t)p;
+    if (A.items) return (int64_t)A.items[p];
+    if (A.mode == PM_NN_ALL && A.nA > 1) {
+        const unsigned int na = (unsigned int)A.nA;
+        const unsigned int b = p / na, a = p - b * na;
+        return (int64_t)a * A.nB + (int64_t)b;
+    }
+    return (int64_t)p;
 }
 
 // The cut-off of query a in NN mode: the best-so-far, widened for an FP32
