@@ -879,6 +879,19 @@ def run_batched(args, torch, eap, synth):
         gd = {k: outs[k][1].cpu().numpy() for k in kinds}
         cpu = cpu_baseline(wl, kinds, gi, gd, eap_q=min(args.cpu_queries, nq), dp_q=min(16, nq), dp_r=250,
                            one_q=1, one_r=2000)
+        # every cell the GPU search executes (seed, FP32 main sweep, FP64
+        # rechecks) on the oracle's sample, against the cells sequential
+        # EAPruned evaluates there (Alg. 1's order and cut-off)
+        cq = min(args.cpu_queries, nq)
+        ratio = {}
+        for k in kinds:
+            c0 = eap.read_counters(ws[k], stream=s)["cells"]
+            eap.nn1(q[: qo[cq]], qo[: cq + 1], r, ro, P[k], ref_labels=labels, precision=1, ws=ws[k], stream=s)
+            c1 = eap.read_counters(ws[k], stream=s)["cells"]
+            seq = cpu["sequential_eapruned_cells"].get(k)
+            if seq:
+                ratio[k] = (c1 - c0) / seq
+        cpu["gpu_executed_vs_sequential_eapruned"] = ratio
 
     total = sum(dense.values())
     print(json.dumps(dict(
