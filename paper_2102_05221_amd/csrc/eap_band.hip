@@ -103,149 +103,389 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
     auto sval = [&](int r) -> T { return r < 1 ? (T)0 : (r > Lli ? INF : li[r - 1]); };
     auto tval = [&](int c) -> T { return c < 1 ? (T)0 : (c > Lco ? INF : co[c - 1]); };
 
+    constexpr bool PF = sizeof(T) == 8;
+    // The group's next work item, fetched one stage per block while the
+    // current pair is swept, so that a short pair's successor does not wait
+    // on the chain of loads behind it (slot, item, offsets, lower bound) with
+    // the whole wave: pf 0 none, 1 slot claimed (the atomic's result in the
+    // group's first lane), 2 slot known, 3 item index loaded, 4 offsets and
+    // bound loaded, 5 no work left for this group.  A list's length is fixed
+    // before the launch, so it is read once.  FP64 instances only: the FP32
+    // ones are held to 168 registers, where the fetch state spills.
+    const int64_t n_items_pf = PF ? (A.npairs_dev ? (int64_t)*A.npairs_dev : A.npairs) : 0;
+    const unsigned int ch = A.chunk > 0 ? (unsigned int)A.chunk : 1u;
+    const int g0 = lane - k;
+    int pf = 0;
+    unsigned int pf_base = 0, pf_p = 0;
+    int64_t pf_item = 0, pf_o0 = 0, pf_o1 = 0, pf_o2 = 0, pf_o3 = 0;
+    double pf_lb = 0.0;
+    Item pf_it{};
+    // the offsets and the bound of the item decoded from pf_item
+    auto pf_request = [&]() {
+        pf_it = decode_item(A, pf_item);
+        if (!pf_it.skip) {
+            pf_o0 = SA.off[pf_it.a];
+            pf_o1 = SA.off[pf_it.a + 1];
+            pf_o2 = SB.off[pf_it.b];
+            pf_o3 = SB.off[pf_it.b + 1];
+            if (KIND == CDTW && nn && A.lb) pf_lb = A.lb[pf_it.out];
+        }
+    };
+
     for (;;) {
         if (!have && !done) {
-            for (;;) {
-                const unsigned int p = fetch_slot(A, fnext, fend, lane, k);
-                const int64_t n_items = A.npairs_dev ? (int64_t)*A.npairs_dev : A.npairs;
-                if ((int64_t)p >= n_items) {
-                    done = true;
-                    break;
-                }
-                item = item_of(A, p);
-                Item it = decode_item(A, item);
-                if (it.skip) continue;
-                const int64_t oa = SA.off[it.a], ob = SB.off[it.b];
-                const int La = (int)(SA.off[it.a + 1] - oa), Lb = (int)(SB.off[it.b + 1] - ob);
-                if (La >= Lb) {
-                    li = SA.v + oa; Lli = La; co = SB.v + ob; Lco = Lb;
-                } else {
-                    li = SB.v + ob; Lli = Lb; co = SA.v + oa; Lco = La;
-                }
-                qa = it.a;
-                out = it.out;
-                if (nn) cut = nn_cut<T>(A, it.a);
-                else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
-                const int L = Lli > Lco ? Lli : Lco;
-                const int d_end = Lco - Lli;
-                int lo_need, hi_need;
-                if constexpr (WIN) {
-                    const double r = A.window_ratio;
-                    w = (r >= 1.0) ? L : (int)floor(r * (double)L);
-                    if (w > L) w = L;
-                    if (w < Lli - Lco) {   // the window admits no warping path
-                        if (k == 0) {
-                            A.res[out] = __builtin_huge_val();
-                            ++npairs;
+            // FP64: the prefetched item, else one fetched now.  FP32: the plain
+            // fetch (its own copy of the loop, so that the FP32 instances keep
+            // their register allocation)
+            if constexpr (PF) {
+                for (;;) {
+                    Item it;
+                    int64_t oa, oa1, ob, ob1;
+                    double lbv = 0.0;
+                    if (pf != 0) {
+                        // the prefetched item: finish the stages the blocks have not done
+                        if (pf == 1) {
+                            const unsigned int base = __shfl(pf_base, g0);
+                            fnext = base;
+                            fend = base + ch;
+                            pf_p = fnext++;
+                            pf = 2;
                         }
-                        continue;
+                        if (pf == 2) {
+                            if ((int64_t)pf_p >= n_items_pf) pf = 5;
+                            else {
+                                pf_item = item_of(A, pf_p);
+                                pf = 3;
+                            }
+                        }
+                        if (pf == 3) {
+                            pf_request();
+                            pf = 4;
+                        }
+                        if (pf == 5) {
+                            done = true;
+                            break;
+                        }
+                        item = pf_item;
+                        it = pf_it;
+                        oa = pf_o0; oa1 = pf_o1; ob = pf_o2; ob1 = pf_o3;
+                        lbv = pf_lb;
+                        pf = 0;
+                    } else {
+                        const unsigned int p = fetch_slot(A, fnext, fend, lane, k);
+                        if ((int64_t)p >= n_items_pf) {
+                            done = true;
+                            break;
+                        }
+                        item = item_of(A, p);
+                        it = decode_item(A, item);
+                        if (it.skip) continue;
+                        oa = SA.off[it.a]; oa1 = SA.off[it.a + 1];
+                        ob = SB.off[it.b]; ob1 = SB.off[it.b + 1];
+                        if (KIND == CDTW && nn && A.lb) lbv = A.lb[it.out];
                     }
-                    if constexpr (KIND == CDTW) {
-                        // lower bound above the cut-off: D > cut-off, +inf without a sweep.
-                        // The factor covers the rounding of the bound and of the DP
-                        // (relative 1e-11 against under 1e-12 for 2 x 2048 terms).
-                        if (nn && A.lb && A.lb[out] * (1.0 - 1e-11) > (double)cut) {
+                    if (it.skip) continue;
+                    const int La = (int)(oa1 - oa), Lb = (int)(ob1 - ob);
+                    if (La >= Lb) {
+                        li = SA.v + oa; Lli = La; co = SB.v + ob; Lco = Lb;
+                    } else {
+                        li = SB.v + ob; Lli = Lb; co = SA.v + oa; Lco = La;
+                    }
+                    qa = it.a;
+                    out = it.out;
+                    if (nn) cut = nn_cut<T>(A, it.a);
+                    else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
+                    const int L = Lli > Lco ? Lli : Lco;
+                    const int d_end = Lco - Lli;
+                    int lo_need, hi_need;
+                    if constexpr (WIN) {
+                        const double r = A.window_ratio;
+                        w = (r >= 1.0) ? L : (int)floor(r * (double)L);
+                        if (w > L) w = L;
+                        if (w < Lli - Lco) {   // the window admits no warping path
                             if (k == 0) {
                                 A.res[out] = __builtin_huge_val();
                                 ++npairs;
-                                ++nlb;
                             }
                             continue;
                         }
-                    }
-                    const int wb = (KIND == ERP) ? w + 1 : w;
-                    lo_need = -(wb < Lli ? wb : Lli);
-                    hi_need = wb < Lco ? wb : Lco;
-                } else {
-                    const int H = A.band_half;
-                    lo_need = d_end - H;
-                    if (lo_need < 1 - Lli) lo_need = 1 - Lli;
-                    hi_need = H < Lco - 1 ? H : Lco - 1;
-                }
-                int dlo = lo_need;
-                if (dlo & 1) dlo -= 1;   // first step a = 2 has even parity
-                const int dhi = dlo + 2 * G * C - 1;
-                if (dhi < hi_need) {     // this band is too narrow: hand the item back
-                    if (k == 0) {
-                        if (A.ovf_items) {
-                            const unsigned int idx = atomicAdd(A.ovf_count, 1u);
-                            A.ovf_items[idx] = (int32_t)item;
-                        } else {
-                            A.res[out] = __builtin_nan("");
+                        if constexpr (KIND == CDTW) {
+                            // lower bound above the cut-off: D > cut-off, +inf without a sweep.
+                            // The factor covers the rounding of the bound and of the DP
+                            // (relative 1e-11 against under 1e-12 for 2 x 2048 terms).
+                            if (nn && A.lb && lbv * (1.0 - 1e-11) > (double)cut) {
+                                if (k == 0) {
+                                    A.res[out] = __builtin_huge_val();
+                                    ++npairs;
+                                    ++nlb;
+                                }
+                                continue;
+                            }
                         }
+                        const int wb = (KIND == ERP) ? w + 1 : w;
+                        lo_need = -(wb < Lli ? wb : Lli);
+                        hi_need = wb < Lco ? wb : Lco;
+                    } else {
+                        const int H = A.band_half;
+                        lo_need = d_end - H;
+                        if (lo_need < 1 - Lli) lo_need = 1 - Lli;
+                        hi_need = H < Lco - 1 ? H : Lco - 1;
                     }
-                    continue;
-                }
-                if constexpr (WIN) {
-                    ncnt0 = ncnt1 = 0;
-#pragma unroll
-                    for (int m = 0; m < M2; ++m) {
-                        const int d = dlo + 2 * k * C + m;
-                        const int in = (d >= lo_need && d <= hi_need) ? 1 : 0;
-                        if (m & 1) ncnt1 += in;
-                        else ncnt0 += in;
+                    int dlo = lo_need;
+                    if (dlo & 1) dlo -= 1;   // first step a = 2 has even parity
+                    const int dhi = dlo + 2 * G * C - 1;
+                    if (dhi < hi_need) {     // this band is too narrow: hand the item back
+                        if (k == 0) {
+                            if (A.ovf_items) {
+                                const unsigned int idx = atomicAdd(A.ovf_count, 1u);
+                                A.ovf_items[idx] = (int32_t)item;
+                            } else {
+                                A.res[out] = __builtin_nan("");
+                            }
+                        }
+                        continue;
                     }
-                }
-                lo_open = !WIN && dlo > 1 - Lli;
-                hi_open = !WIN && dhi < Lco - 1;
-                ke = (d_end - dlo) / M2;
-                me = (d_end - dlo) - ke * M2;
-                a_end = Lli + Lco;
-                a = 2;
-                dk = dlo + 2 * k * C;
-                const T H1 = (KIND == ERP) ? vabs(co[0] - gap) : INF;   // M(0,1)
-                const T V1 = (KIND == ERP) ? vabs(li[0] - gap) : INF;   // M(1,0)
-#pragma unroll
-                for (int m = 0; m < M2; ++m) {
-                    const int d = dk + m;
-                    val[m] = (d == 0) ? (T)0 : (d == 1 ? H1 : (d == -1 ? V1 : INF));
-                    const int ad = d < 0 ? -d : d;
-                    if constexpr (KIND == WDTW) {
-                        int gi = 2 * ad - L + A.gtab_off;
-                        gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
-                        wt[m] = (T)A.gtab[gi];
-                    }
-                    if constexpr (KIND == CDTW) pen[m] = (ad > w) ? INF : (T)0;
-                    if constexpr (KIND == ERP) pen[m] = (T)0;
-                }
-                apen = (KIND == ERP) ? w + 2 : 2;
-                if constexpr (KIND == ERP) {
-                    if (apen <= 2) {
-#pragma unroll
+                    if constexpr (WIN) {
+                        ncnt0 = ncnt1 = 0;
+    #pragma unroll
                         for (int m = 0; m < M2; ++m) {
-                            const int d = dk + m;
-                            pen[m] = ((d < 0 ? -d : d) > w) ? INF : (T)0;
+                            const int d = dlo + 2 * k * C + m;
+                            const int in = (d >= lo_need && d <= hi_need) ? 1 : 0;
+                            if (m & 1) ncnt1 += in;
+                            else ncnt0 += in;
                         }
                     }
-                }
-                i0 = (2 - dk) / 2;
-                j0 = (2 + dk) / 2;
-#pragma unroll
-                for (int q = 0; q < CB; ++q) {
-                    S[q] = sval(i0 - q);
-                    Tt[q] = tval(j0 + q);
-                }
-                if (k == 0) {
-#pragma unroll
-                    for (int n = 1; n <= CB; ++n) {
-                        Sc[n - 1] = sval(i0 + n);
-                        if constexpr (AHEAD) Sn[n - 1] = sval(i0 + CB + n);
+                    lo_open = !WIN && dlo > 1 - Lli;
+                    hi_open = !WIN && dhi < Lco - 1;
+                    ke = (d_end - dlo) / M2;
+                    me = (d_end - dlo) - ke * M2;
+                    a_end = Lli + Lco;
+                    a = 2;
+                    dk = dlo + 2 * k * C;
+                    const T H1 = (KIND == ERP) ? vabs(co[0] - gap) : INF;   // M(0,1)
+                    const T V1 = (KIND == ERP) ? vabs(li[0] - gap) : INF;   // M(1,0)
+    #pragma unroll
+                    for (int m = 0; m < M2; ++m) {
+                        const int d = dk + m;
+                        val[m] = (d == 0) ? (T)0 : (d == 1 ? H1 : (d == -1 ? V1 : INF));
+                        const int ad = d < 0 ? -d : d;
+                        if constexpr (KIND == WDTW) {
+                            int gi = 2 * ad - L + A.gtab_off;
+                            gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
+                            wt[m] = (T)A.gtab[gi];
+                        }
+                        if constexpr (KIND == CDTW) pen[m] = (ad > w) ? INF : (T)0;
+                        if constexpr (KIND == ERP) pen[m] = (T)0;
                     }
-                }
-                if (k == G - 1) {
-#pragma unroll
-                    for (int n = 1; n <= CB; ++n) {
-                        Tc[n - 1] = tval(j0 + C - 1 + n);
-                        if constexpr (AHEAD) Tn[n - 1] = tval(j0 + C - 1 + CB + n);
+                    apen = (KIND == ERP) ? w + 2 : 2;
+                    if constexpr (KIND == ERP) {
+                        if (apen <= 2) {
+    #pragma unroll
+                            for (int m = 0; m < M2; ++m) {
+                                const int d = dk + m;
+                                pen[m] = ((d < 0 ? -d : d) > w) ? INF : (T)0;
+                            }
+                        }
                     }
+                    i0 = (2 - dk) / 2;
+                    j0 = (2 + dk) / 2;
+    #pragma unroll
+                    for (int q = 0; q < CB; ++q) {
+                        S[q] = sval(i0 - q);
+                        Tt[q] = tval(j0 + q);
+                    }
+                    if (k == 0) {
+    #pragma unroll
+                        for (int n = 1; n <= CB; ++n) {
+                            Sc[n - 1] = sval(i0 + n);
+                            if constexpr (AHEAD) Sn[n - 1] = sval(i0 + CB + n);
+                        }
+                    }
+                    if (k == G - 1) {
+    #pragma unroll
+                        for (int n = 1; n <= CB; ++n) {
+                            Tc[n - 1] = tval(j0 + C - 1 + n);
+                            if constexpr (AHEAD) Tn[n - 1] = tval(j0 + C - 1 + CB + n);
+                        }
+                    }
+                    fin = false;
+                    ovf = false;
+                    have = true;
+                    break;
                 }
-                fin = false;
-                ovf = false;
-                have = true;
-                break;
+            } else {
+                for (;;) {
+                    const unsigned int p = fetch_slot(A, fnext, fend, lane, k);
+                    const int64_t n_items = A.npairs_dev ? (int64_t)*A.npairs_dev : A.npairs;
+                    if ((int64_t)p >= n_items) {
+                        done = true;
+                        break;
+                    }
+                    item = item_of(A, p);
+                    Item it = decode_item(A, item);
+                    if (it.skip) continue;
+                    const int64_t oa = SA.off[it.a], ob = SB.off[it.b];
+                    const int La = (int)(SA.off[it.a + 1] - oa), Lb = (int)(SB.off[it.b + 1] - ob);
+                    if (La >= Lb) {
+                        li = SA.v + oa; Lli = La; co = SB.v + ob; Lco = Lb;
+                    } else {
+                        li = SB.v + ob; Lli = Lb; co = SA.v + oa; Lco = La;
+                    }
+                    qa = it.a;
+                    out = it.out;
+                    if (nn) cut = nn_cut<T>(A, it.a);
+                    else cut = (A.pcut && !A.plain) ? (T)A.pcut[it.cutidx] : INF;
+                    const int L = Lli > Lco ? Lli : Lco;
+                    const int d_end = Lco - Lli;
+                    int lo_need, hi_need;
+                    if constexpr (WIN) {
+                        const double r = A.window_ratio;
+                        w = (r >= 1.0) ? L : (int)floor(r * (double)L);
+                        if (w > L) w = L;
+                        if (w < Lli - Lco) {   // the window admits no warping path
+                            if (k == 0) {
+                                A.res[out] = __builtin_huge_val();
+                                ++npairs;
+                            }
+                            continue;
+                        }
+                        if constexpr (KIND == CDTW) {
+                            // lower bound above the cut-off: D > cut-off, +inf without a sweep.
+                            // The factor covers the rounding of the bound and of the DP
+                            // (relative 1e-11 against under 1e-12 for 2 x 2048 terms).
+                            if (nn && A.lb && A.lb[out] * (1.0 - 1e-11) > (double)cut) {
+                                if (k == 0) {
+                                    A.res[out] = __builtin_huge_val();
+                                    ++npairs;
+                                    ++nlb;
+                                }
+                                continue;
+                            }
+                        }
+                        const int wb = (KIND == ERP) ? w + 1 : w;
+                        lo_need = -(wb < Lli ? wb : Lli);
+                        hi_need = wb < Lco ? wb : Lco;
+                    } else {
+                        const int H = A.band_half;
+                        lo_need = d_end - H;
+                        if (lo_need < 1 - Lli) lo_need = 1 - Lli;
+                        hi_need = H < Lco - 1 ? H : Lco - 1;
+                    }
+                    int dlo = lo_need;
+                    if (dlo & 1) dlo -= 1;   // first step a = 2 has even parity
+                    const int dhi = dlo + 2 * G * C - 1;
+                    if (dhi < hi_need) {     // this band is too narrow: hand the item back
+                        if (k == 0) {
+                            if (A.ovf_items) {
+                                const unsigned int idx = atomicAdd(A.ovf_count, 1u);
+                                A.ovf_items[idx] = (int32_t)item;
+                            } else {
+                                A.res[out] = __builtin_nan("");
+                            }
+                        }
+                        continue;
+                    }
+                    if constexpr (WIN) {
+                        ncnt0 = ncnt1 = 0;
+    #pragma unroll
+                        for (int m = 0; m < M2; ++m) {
+                            const int d = dlo + 2 * k * C + m;
+                            const int in = (d >= lo_need && d <= hi_need) ? 1 : 0;
+                            if (m & 1) ncnt1 += in;
+                            else ncnt0 += in;
+                        }
+                    }
+                    lo_open = !WIN && dlo > 1 - Lli;
+                    hi_open = !WIN && dhi < Lco - 1;
+                    ke = (d_end - dlo) / M2;
+                    me = (d_end - dlo) - ke * M2;
+                    a_end = Lli + Lco;
+                    a = 2;
+                    dk = dlo + 2 * k * C;
+                    const T H1 = (KIND == ERP) ? vabs(co[0] - gap) : INF;   // M(0,1)
+                    const T V1 = (KIND == ERP) ? vabs(li[0] - gap) : INF;   // M(1,0)
+    #pragma unroll
+                    for (int m = 0; m < M2; ++m) {
+                        const int d = dk + m;
+                        val[m] = (d == 0) ? (T)0 : (d == 1 ? H1 : (d == -1 ? V1 : INF));
+                        const int ad = d < 0 ? -d : d;
+                        if constexpr (KIND == WDTW) {
+                            int gi = 2 * ad - L + A.gtab_off;
+                            gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
+                            wt[m] = (T)A.gtab[gi];
+                        }
+                        if constexpr (KIND == CDTW) pen[m] = (ad > w) ? INF : (T)0;
+                        if constexpr (KIND == ERP) pen[m] = (T)0;
+                    }
+                    apen = (KIND == ERP) ? w + 2 : 2;
+                    if constexpr (KIND == ERP) {
+                        if (apen <= 2) {
+    #pragma unroll
+                            for (int m = 0; m < M2; ++m) {
+                                const int d = dk + m;
+                                pen[m] = ((d < 0 ? -d : d) > w) ? INF : (T)0;
+                            }
+                        }
+                    }
+                    i0 = (2 - dk) / 2;
+                    j0 = (2 + dk) / 2;
+    #pragma unroll
+                    for (int q = 0; q < CB; ++q) {
+                        S[q] = sval(i0 - q);
+                        Tt[q] = tval(j0 + q);
+                    }
+                    if (k == 0) {
+    #pragma unroll
+                        for (int n = 1; n <= CB; ++n) {
+                            Sc[n - 1] = sval(i0 + n);
+                            if constexpr (AHEAD) Sn[n - 1] = sval(i0 + CB + n);
+                        }
+                    }
+                    if (k == G - 1) {
+    #pragma unroll
+                        for (int n = 1; n <= CB; ++n) {
+                            Tc[n - 1] = tval(j0 + C - 1 + n);
+                            if constexpr (AHEAD) Tn[n - 1] = tval(j0 + C - 1 + CB + n);
+                        }
+                    }
+                    fin = false;
+                    ovf = false;
+                    have = true;
+                    break;
+                }
             }
         }
         if (__all(done)) break;
+
+        // one stage of the next item's fetch; its loads complete during the block
+        if constexpr (PF) {
+            if (have) {
+                if (pf == 3) {
+                    pf_request();
+                    pf = 4;
+                } else if (pf == 2) {
+                    if ((int64_t)pf_p >= n_items_pf) pf = 5;
+                    else {
+                        pf_item = item_of(A, pf_p);
+                        pf = 3;
+                    }
+                } else if (pf == 1) {
+                    const unsigned int base = __shfl(pf_base, g0);
+                    fnext = base;
+                    fend = base + ch;
+                    pf_p = fnext++;
+                    pf = 2;
+                } else if (pf == 0) {
+                    if (fnext < fend) {
+                        pf_p = fnext++;
+                        pf = 2;
+                    } else {
+                        if (k == 0) pf_base = atomicAdd(A.queue, ch);
+                        pf = 1;
+                    }
+                }
+            }
+        }
 
         // the query's best-so-far, read now and applied at the block end (a cut-off
         // one block old is only larger, so still safe)
