@@ -402,6 +402,9 @@ def main():
                          "streams (round-robin), main sweeps one at a time (chained by events), the "
                          "latency-bound stages overlapping them; serial: one after the other on one stream; "
                          "concurrent: six streams, no ordering")
+    ap.add_argument("--batch-schedule", default="serial", choices=("serial", "concurrent"),
+                    help="workload 4: the six searches of the captured step one after the other on one stream, "
+                         "or each on its own stream (forked and joined inside the graph)")
     ap.add_argument("--derivative", action="store_true",
                     help="workload 2 with the derivative variants: the series' first derivatives computed "
                          "inside every step, then DDTW, DCDTW and DWDTW (default --kinds dtw,cdtw,wdtw)")
@@ -750,19 +753,34 @@ def run_batched(args, torch, eap, synth):
                 tuning[k] = next(f"{x['g']}x{x['c']}" for x in recs if x["chosen"])
 
     s = torch.cuda.Stream(dev)
+    kst = {k: torch.cuda.Stream(dev) for k in kinds}
+
+    def issue(flags=0, schedule="serial"):
+        """The six searches of a step on `s`: one after the other, or
+        (concurrent) each on a stream of its own forked from `s` and joined
+        back, so that one search's latency-bound stages (bounds, seed sweep,
+        recheck) can run beside another's main sweep."""
+        if schedule == "concurrent":
+            for k in kinds:
+                kst[k].wait_stream(s)
+                eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, flags=flags, ws=ws[k], out=outs[k],
+                        stream=kst[k])
+            for k in kinds:
+                s.wait_stream(kst[k])
+        else:
+            for k in kinds:
+                eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, flags=flags, ws=ws[k], out=outs[k],
+                        stream=s)
 
     def eager():
-        for k in kinds:
-            eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, ws=ws[k], out=outs[k], stream=s)
+        issue()
 
     say("eager run and graph capture")
     eager()   # uploads offsets and tables into the workspaces
     s.synchronize()
     want = {k: (outs[k][0].clone(), outs[k][1].clone(), outs[k][2].clone()) for k in kinds}
     eap.capture_begin(s)
-    for k in kinds:
-        eap.nn1(q, qo, r, ro, P[k], ref_labels=labels, precision=1, flags=eap.FLAG_PREPARED, ws=ws[k], out=outs[k],
-                stream=s)
+    issue(eap.FLAG_PREPARED, args.batch_schedule)
     graph = eap.capture_end(s)
     for _ in range(args.warmup):
         graph.launch(stream=s)
@@ -902,7 +920,8 @@ def run_batched(args, torch, eap, synth):
                              "uniform in [64, 2048], 5 warped-sine classes, six distances (CDTW w=10%, WDTW "
                              "g=0.05, ERP gap=0, MSM c=0.5, TWE nu=0.001 lambda=1), FP32 screen + FP64 recheck "
                              "(margin 1e-4 relative), one HIP graph launch per step", queries=nq, candidates=nr,
-                    lengths=[64, 2048], distances=kinds, precision="fp32 screen + fp64 recheck"),
+                    lengths=[64, 2048], distances=kinds, precision="fp32 screen + fp64 recheck",
+                    schedule=args.batch_schedule),
         queries_per_s=nq * len(kinds) / (ms_per_step * 1e-3),
         step_ms_p50=float(np.percentile(step_ms, 50)), step_ms_p99=float(np.percentile(step_ms, 99)),
         graph_results_identical_to_eager=same, tuning=tuning, per_distance=per, plain_gpu_dp=plain,

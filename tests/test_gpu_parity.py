@@ -155,10 +155,13 @@ def test_tuner_shapes_agree(torch_dev, orc, kind, precision):
     assert np.array_equal(gd.cpu().numpy(), od)
 
 
-def test_graph_replays_match_eager(torch_dev, orc):
+@pytest.mark.parametrize("forked", [False, True], ids=["one_stream", "forked_streams"])
+def test_graph_replays_match_eager(torch_dev, orc, forked):
     """The six searches of a workload-4-shaped batch (FP32 screen + FP64
-    recheck) captured in one HIP graph: every replay, with eager work on the
-    same buffers in between, gives the eager results, which are the oracle's."""
+    recheck) captured in one HIP graph, on the capturing stream or each on a
+    stream of its own forked from it and joined back: every replay, with eager
+    work on the same buffers in between, gives the eager results, which are
+    the oracle's."""
     torch, dev = torch_dev
     wl = synth.make_workload(4, n_ref=40, n_query=8, length=(64, 700))
     qo, ro = wl["query_off"], wl["ref_off"]
@@ -177,10 +180,18 @@ def test_graph_replays_match_eager(torch_dev, orc):
     for k in synth.SIX:
         oi, od, _ = orc.nn1(P[k], wl["queries"], qo, wl["refs"], ro, "dp")
         assert np.array_equal(want[k][0].cpu().numpy(), oi) and np.array_equal(want[k][1].cpu().numpy(), od)
-    log("graph: capture")
+    log(f"graph: capture (forked={forked})")
+    ks = {k: torch.cuda.Stream(dev) for k in synth.SIX}
     eap.capture_begin(s)
     for k in synth.SIX:
-        eap.nn1(q, qo, r, ro, P[k], precision=1, flags=eap.FLAG_PREPARED, ws=ws[k], out=outs[k], stream=s)
+        st = s
+        if forked:
+            ks[k].wait_stream(s)
+            st = ks[k]
+        eap.nn1(q, qo, r, ro, P[k], precision=1, flags=eap.FLAG_PREPARED, ws=ws[k], out=outs[k], stream=st)
+    if forked:
+        for k in synth.SIX:
+            s.wait_stream(ks[k])
     g = eap.capture_end(s)
     try:
         for rep in range(3):
