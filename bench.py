@@ -46,10 +46,13 @@ METRIC = "GCUPS (cell updates/s) & queries/s for 1-NN search vs plain GPU DP; p5
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 LANE_OPS_PER_S_F32 = 2 * LANE_OPS_PER_S
 OPS_PER_CELL = {"dtw": 5, "cdtw": 5, "wdtw": 6, "erp": 6, "msm": 16, "twe": 8}
-OPS_PER_CELL_F32 = {"dtw": 4, "cdtw": 4, "wdtw": 5, "erp": 5, "msm": 9, "twe": 7}
+# FP32 sweeps fuse the squared costs' (weighted) square with the add (one
+# lane-op for the FMA): DTW sub, min3, fma; CDTW (band) sub, min3, the window's
+# add, fma; WDTW sub, weight mul, min3, fma
+OPS_PER_CELL_F32 = {"dtw": 3, "cdtw": 4, "wdtw": 4, "erp": 5, "msm": 9, "twe": 7}
 # FP32 WDTW with exact differences: the float64 subtraction, at half the FP32
 # lane-op rate, counts as two FP32 operations, plus its conversion to FP32
-OPS_PER_CELL_F32_XD = {"wdtw": 7}
+OPS_PER_CELL_F32_XD = {"wdtw": 6}
 HBM_PEAK_GBS = 8000.0
 ROOFLINE_CONVENTION = ("achieved = executed cells of the dominant kernel's launch / its launch time; peak = VALU "
                        "lane-op rate / minimal lane-ops per cell of its distance and precision, with the lane-op "

@@ -537,7 +537,14 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
                     const T left = (m >= 1) ? val[m - 1] : xv;
                     const T d = s - tt;
                     T v;
-                    if constexpr (KIND == DTW) {
+                    if constexpr (sizeof(T) == 4 && (KIND == DTW || KIND == CDTW || KIND == WDTW)) {
+                        // FP32 screen: the square (weighted) and the add fused; the
+                        // window's penalty (0 or +inf) added to the minimum exactly
+                        const T mn = vmin(vmin(diag, top), left);
+                        if constexpr (KIND == DTW) v = __builtin_fmaf(d, d, mn);
+                        if constexpr (KIND == CDTW) v = __builtin_fmaf(d, d, mn + pen[m]);
+                        if constexpr (KIND == WDTW) v = __builtin_fmaf(wt[m] * d, d, mn);
+                    } else if constexpr (KIND == DTW) {
                         v = (d * d) + vmin(vmin(diag, top), left);
                     } else if constexpr (KIND == CDTW) {
                         v = ((d * d) + pen[m]) + vmin(vmin(diag, top), left);

@@ -3,8 +3,9 @@
 // For a warping path of exact cost B (real arithmetic on the float64 inputs)
 // with at most N steps over values of magnitude <= A (ERP: A also bounds
 // |gap|), eps(B) bounds |V32 - B|, where V32 is the path's cost evaluated in
-// FP32 the way the recurrence adds it (u = 2^-24 the unit roundoff; no fused
-// operations).  The FP32 dynamic programme returns the least V32 over all
+// FP32 the way the recurrence adds it (u = 2^-24 the unit roundoff).  The
+// FP32 sweeps of the squared costs fuse the (weighted) square with the add:
+// that removes roundings from the accounting below and keeps the bound.  The FP32 dynamic programme returns the least V32 over all
 // paths (min is exact and rounded addition is monotone), so its result D32
 // satisfies D32 <= D + eps(D) and D <= screen_bound(D32).
 //

@@ -24,8 +24,16 @@ F = np.float32
 INF32 = np.float32(np.inf)
 
 
-def fp32_dp(kind, x, y, prm, exact_diff=False):
-    """float32 DP over anti-diagonals (rows x, columns y)."""
+def fma32(a, b, c):
+    """float32 fused multiply-add: the product of two float32 values is exact
+    in float64, the sum is rounded there and then to float32 (double rounding:
+    within the bound's factor 1.01 of a single one)."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(F)
+
+
+def fp32_dp(kind, x, y, prm, exact_diff=False, fused=False):
+    """float32 DP over anti-diagonals (rows x, columns y).  fused: the squared
+    costs' (weighted) square fused with the add, as the FP32 sweeps do."""
     lx, ly = len(x), len(y)
     xs, ys = x.astype(F), y.astype(F)
     M = np.full((lx + 1, ly + 1), INF32, dtype=F)
@@ -59,7 +67,11 @@ def fp32_dp(kind, x, y, prm, exact_diff=False):
             d = (x[i - 1] - y[j - 1]).astype(F)
         else:
             d = si - tj
-        if kind in ("dtw", "cdtw"):
+        if kind in ("dtw", "cdtw") and fused:
+            v = fma32(d, d, np.minimum(np.minimum(diag, top), left))
+        elif kind == "wdtw" and fused:
+            v = fma32(W[np.abs(i - j)] * d, d, np.minimum(np.minimum(diag, top), left))
+        elif kind in ("dtw", "cdtw"):
             v = d * d + np.minimum(np.minimum(diag, top), left)
         elif kind == "wdtw":
             v = W[np.abs(i - j)] * (d * d) + np.minimum(np.minimum(diag, top), left)
@@ -163,6 +175,27 @@ def test_fp32_dp_exact_differences_within_relative_bound(orc, kind):
         assert d64 <= eap.screen_bound(kind, d32, N, 0.0, exact_diff=True), (kind, name, d32, d64)
         if d64 > 0:
             assert abs(d32 - d64) <= 1.01 * 2.0 ** -24 * (N + 5) * d64 + N * 4e-38
+
+
+@pytest.mark.parametrize("kind", ["dtw", "cdtw", "wdtw"])
+def test_fp32_dp_fused_within_certified_bound(orc, kind):
+    """The FP32 sweeps of the squared costs fuse the (weighted) square with
+    the add: one rounding fewer per cell, still inside both bounds (input
+    rounding, and exact differences)."""
+    p = PARAMS[kind]
+    for name, x, y in CASES:
+        d64 = orc.dp(p, x, y)
+        if math.isinf(d64):
+            continue
+        N = len(x) + len(y)
+        A = max(np.abs(x).max(), np.abs(y).max())
+        d32 = fp32_dp(kind, x, y, p, fused=True)
+        assert d32 <= d64 + eap.screen_eps(kind, d64, N, A), (kind, name, d32, d64)
+        assert d64 <= eap.screen_bound(kind, d32, N, A), (kind, name, d32, d64)
+        if kind != "cdtw":
+            dx = fp32_dp(kind, x, y, p, exact_diff=True, fused=True)
+            assert dx <= d64 + eap.screen_eps(kind, d64, N, 0.0, exact_diff=True), (kind, name, dx, d64)
+            assert d64 <= eap.screen_bound(kind, dx, N, 0.0, exact_diff=True), (kind, name, dx, d64)
 
 
 def test_missing_square_term_would_fail(orc):
