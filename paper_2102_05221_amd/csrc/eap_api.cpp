@@ -145,17 +145,28 @@ constexpr size_t kHeaderBytes = (sizeof(Header) + kAlign - 1) / kAlign * kAlign;
 constexpr int kClearedWords = (int)(offsetof(Header, absmax_r) / 8) - kCounterWords;
 
 // ------------------------------------------------------------------ tables
-// WDTW: G[m] = 1 / (1 + exp(-g * (m / 2))) for m = 2k - L in [-Lmax, 2 Lmax]; the
-// weight of |i-j| = k for longer length L is G[2k - L] (eq. WDTW with w_max = 1:
-// (double)k - (double)L / 2 equals m / 2 exactly).
-int64_t wdtw_table_len(int64_t lmax) { return 3 * lmax + 1; }
-void wdtw_fill(double g, int64_t lmax, double* t) {
-    for (int64_t m = -lmax; m <= 2 * lmax; ++m) t[(size_t)(m + lmax)] = 1.0 / (1.0 + std::exp(-g * ((double)m / 2.0)));
+// WDTW: G[m] = 1 / (1 + exp(-g * (m / 2))) for m = 2k - L; the weight of
+// |i-j| = k for longer length L is G[2k - L] (eq. WDTW with w_max = 1:
+// (double)k - (double)L / 2 equals m / 2 exactly).  Layout: kWdtwZero zeros,
+// then m = -Lmax .. Lmax + kWdtwHi at index m + Lmax + kWdtwZero.  The row
+// sweep reads its window without bounds checks, as the larger of the entries
+// of 2d - L and -2d - L (entries never decrease for g >= 0): with rows from
+// -(G + K) to L + G + 2K and columns up to L + W + C, |d| <= L + W + G + 3K +
+// C <= L + 2240 (G <= 64, K <= 32, C <= 32, W <= 2048), so m <= Lmax + 4480;
+// the other side of a window that crosses d = 0 reaches down to m = -L -
+// 2 (C + K - 2) >= -Lmax - 92, inside the zeros.
+constexpr int64_t kWdtwZero = 128, kWdtwHi = 4608;
+int64_t wdtw_table_len(int64_t lmax) { return kWdtwZero + 2 * lmax + kWdtwHi + 1; }
+int64_t wdtw_table_off(int64_t lmax) { return lmax + kWdtwZero; }
+double wdtw_entry(double g, int64_t lmax, int64_t e) {
+    if (e < kWdtwZero) return 0.0;
+    const int64_t m = e - wdtw_table_off(lmax);
+    return 1.0 / (1.0 + std::exp(-g * ((double)m / 2.0)));
 }
 void wdtw_table(double g, int64_t lmax, std::vector<double>& t, int& off) {
-    off = (int)lmax;
+    off = (int)wdtw_table_off(lmax);
     t.resize((size_t)wdtw_table_len(lmax));
-    wdtw_fill(g, lmax, t.data());
+    for (size_t e = 0; e < t.size(); ++e) t[e] = wdtw_entry(g, lmax, (int64_t)e);
 }
 
 // TWE: nu * (2|k|) for k = j - i in [-Lmax, Lmax + 1024] (eq. TWECost with tau_i = i).
@@ -413,7 +424,7 @@ void plan_common(Layout& L, Common& c, const eap_params* p, const SetInfo& A, co
     }
     if (p->kind == EAP_WDTW) {
         if (build_tables) wdtw_table(p->g, lmax, c.gtabv, c.gtab_off);
-        c.gtab_off = (int)lmax;
+        c.gtab_off = (int)wdtw_table_off(lmax);
         c.gtab_len = (int)wdtw_table_len(lmax);
         c.gtab = L.take(sizeof(double) * (size_t)c.gtab_len);
     }
@@ -629,8 +640,7 @@ eap_status put_table(int kind, const eap_params* p, int64_t lmax, double* dst, h
                 const int64_t k = e - (lmax + kTweLo);
                 buf[x] = p->nu * (double)(2 * (k < 0 ? -k : k));
             } else {
-                const int64_t mm = e - lmax;
-                buf[x] = 1.0 / (1.0 + std::exp(-p->g * ((double)mm / 2.0)));
+                buf[x] = wdtw_entry(p->g, lmax, e);
             }
         }
         unsigned long long w[kPutWords];

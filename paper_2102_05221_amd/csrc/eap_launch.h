@@ -46,6 +46,7 @@ struct SweepArgs {
     const double* tab;
     int tab_off, tab_len;
     // WDTW: G[m] = 1/(1+exp(-g*m/2)) for m = 2k - L, indexed m + gtab_off
+    // (zeros below m = -Lmax; covers every m the row sweep reads)
     const double* gtab;
     int gtab_off, gtab_len;
     // window (CDTW / ERP): ratio as given; <0 means none

@@ -311,9 +311,10 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
 
         if constexpr (DTAB) {
             // the per-diagonal terms of the next K steps: d = j - i runs over
-            // c0 - row - K .. c0 + C - 2 - row (WDTW: clamped into the table;
-            // entries outside the matrix only reach cells nobody reads)
-            const int base = c0 - row - K;
+            // c0 - row - K .. c0 + C - 2 - row.  A group without a pair reads
+            // the window of d = 0 .. NW - 1 (its rows keep advancing while the
+            // wave's other groups sweep, which would leave the table's range).
+            const int base = have ? c0 - row - K : 0;
             if constexpr (KIND == TWE) {
                 // the table covers every d this sweep forms (see its
                 // construction): one address, the entries at fixed offsets
@@ -321,18 +322,37 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
 #pragma unroll
                 for (int m = 0; m < NW; ++m) dwin[m] = tp[m];
             } else {
-                // WDTW: entry 2|d| - L_li + tab_off, which is >= 0 for every d
-                // (tab_off >= L_li) and inside the table for |d| <= L_li (every
-                // cell of the matrix); beyond, the last entry.  With d = base + m,
-                // 2|d| = max(2 base + 2m, -2 base - 2m): per entry two adds of
-                // constants to per-lane values, a max and the clamp, on byte offsets
-                const int e = (int)sizeof(T), c = tab_off - Lli;
-                const int pa = (2 * base + c) * e, pb = (c - 2 * base) * e, hi = (tab_len - 1) * e;
-                const char* tb = reinterpret_cast<const char*>(tab);
+                // WDTW: the weight of d is entry 2|d| - L_li + tab_off.  Entries
+                // never decrease (g >= 0) and the table opens with zeros, so it
+                // is the larger of the entries of 2d and -2d, two runs of NW
+                // entries two apart read from fixed offsets: 2 (base + m) + c
+                // upwards, and c - 2 (base + m) read from its far end.  A lane
+                // whose window lies on one side of d = 0 points the other run at
+                // the zeros.  Every entry read is inside the table: the table
+                // covers |d| up to what the sweep forms, and the wrong side of a
+                // window that crosses 0 stays at or above c - 2 (NW - 1) >= 0.
+                const int c = tab_off - Lli;
+                const T* const pp = tab + ((base + NW - 1 >= 0) ? 2 * base + c : 0);
+                const T* const pn = tab + ((base <= 0) ? c - 2 * (base + NW - 1) : 0);
+                // Eight entries at a time: their loads in flight together, and
+                // each entry formed here (the empty asm keeps the maximum from
+                // being sunk into the steps, where both runs would stay live).
+                constexpr int CH = 8;
 #pragma unroll
-                for (int m = 0; m < NW; ++m) {
-                    const int x = vmin(vmax(pa + 2 * e * m, pb - 2 * e * m), hi);
-                    dwin[m] = *reinterpret_cast<const T*>(tb + x);
+                for (int m0 = 0; m0 < NW; m0 += CH) {
+                    T rp[CH], rn[CH];
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (m0 + j < NW) {
+                            rp[j] = pp[2 * (m0 + j)];
+                            rn[j] = pn[2 * (NW - 1 - m0 - j)];
+                        }
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (m0 + j < NW) {
+                            dwin[m0 + j] = vmax(rp[j], rn[j]);
+                            asm volatile("" : "+v"(dwin[m0 + j]));
+                        }
                 }
             }
         }
