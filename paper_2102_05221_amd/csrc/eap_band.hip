@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
     T cut = 0, res_v = 0;
     T val[M2], S[CB], Tt[CB], Sc[CB], Sn[CB], Tc[CB], Tn[CB], wt[M2], pen[M2];
     unsigned long long ncells = 0, npairs = 0, nlb = 0;
+    unsigned int nblk = 0;   // blocks swept by the wave (the cut-off refresh)
 #pragma unroll
     for (int m = 0; m < M2; ++m) val[m] = wt[m] = pen[m] = 0;
 #pragma unroll
@@ -488,8 +489,12 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
         }
 
         // the query's best-so-far, read now and applied at the block end (a cut-off
-        // one block old is only larger, so still safe)
-        const T cut_next = (nn && have) ? nn_cut<T>(A, qa) : INF;
+        // one block old is only larger, so still safe); every fourth block only:
+        // the read waits on memory that every group of every wave updates, at a
+        // latency that a block of steps does not cover, and a cut-off a few
+        // blocks old is still safe
+        const bool refresh = (++nblk & 3) == 0;
+        const T cut_next = (nn && have && refresh) ? nn_cut<T>(A, qa) : INF;
         bool live_any = false;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
