@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
     T* const eb = A.edge ? reinterpret_cast<T*>(A.edge) + gid * A.edge_stride : nullptr;
 
     bool have = false, done = false;
+    unsigned int nblk = 0;              // blocks swept by the wave (the cut-off refresh)
     unsigned int fnext = 0, fend = 0;   // this group's chunk of work slots
     int32_t qa = 0;
     int64_t out = 0;
@@ -361,8 +362,11 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
 #pragma unroll
         for (int i = 0; i < RS; ++i) load_row(row + k + K + 1 + k + G * i, nx_s[i], nx_b[i]);
         // the query's best-so-far, read now and applied at the block end (a cut-off
-        // one block old is only larger, so still safe)
-        const T cut_next = (nn && have) ? nn_cut<T>(A, qa) : INF;
+        // one block old is only larger, so still safe); every fourth block only:
+        // the read waits on memory that every group of every wave updates, and a
+        // cut-off a few blocks old is still safe
+        const bool refresh = (++nblk & 3) == 0;
+        const T cut_next = (nn && have && refresh) ? nn_cut<T>(A, qa) : INF;
 
         bool live_any = false;
         // One step: every lane computes its columns for its current row, reading
