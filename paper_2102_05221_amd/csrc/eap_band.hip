@@ -489,11 +489,11 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
         }
 
         // the query's best-so-far, read now and applied at the block end (a cut-off
-        // one block old is only larger, so still safe); every fourth block only:
+        // one block old is only larger, so still safe); every eighth block only:
         // the read waits on memory that every group of every wave updates, at a
         // latency that a block of steps does not cover, and a cut-off a few
         // blocks old is still safe
-        const bool refresh = (++nblk & 3) == 0;
+        const bool refresh = (++nblk & 7) == 0;
         const T cut_next = (nn && have && refresh) ? nn_cut<T>(A, qa) : INF;
         bool live_any = false;
 #pragma unroll

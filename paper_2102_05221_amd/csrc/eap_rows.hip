@@ -362,10 +362,10 @@ __global__ __launch_bounds__(256, (rows_min_blocks<KIND, T, C, XD>())) void rows
 #pragma unroll
         for (int i = 0; i < RS; ++i) load_row(row + k + K + 1 + k + G * i, nx_s[i], nx_b[i]);
         // the query's best-so-far, read now and applied at the block end (a cut-off
-        // one block old is only larger, so still safe); every fourth block only:
+        // one block old is only larger, so still safe); every eighth block only:
         // the read waits on memory that every group of every wave updates, and a
         // cut-off a few blocks old is still safe
-        const bool refresh = (++nblk & 3) == 0;
+        const bool refresh = (++nblk & 7) == 0;
         const T cut_next = (nn && have && refresh) ? nn_cut<T>(A, qa) : INF;
 
         bool live_any = false;
