@@ -568,7 +568,7 @@ __global__ __launch_bounds__(256, (band_min_blocks<T, C>())) void band_kernel(Sw
                 } else {
                     if (k == G - 1 && hi_open && val[M2 - 1] <= cut) ovf = true;
                 }
-                if (a == a_end) {
+                if (__builtin_expect(a == a_end, 0)) {   // once per pair: its code out of line
                     if (k == ke) {
                         T r = val[0];
 #pragma unroll
