@@ -883,6 +883,43 @@ def test_fp32_screen_exact_differences_wdtw_long(torch_dev, orc, margin):
     assert c["rechecks"] >= 2
 
 
+def test_exact_difference_row_shapes_wdtw_long(torch_dev, orc):
+    """The FP32 WDTW sweep with float64 differences (long series: weights near
+    the diagonal around 1e-22) with every row-sweep shape pinned in turn, strips
+    of 32 to 2048 columns whose weight windows reach |j - i| near the longer
+    length plus a strip: each gives the FP64 oracle's NN bit for bit, and its
+    main stage ran as pinned."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(91)
+    qs = synth.random_walks(rng, 3, (1500, 2048))
+    rs = synth.random_walks(rng, 12, (64, 2048))
+    rs[5] = qs[1] + rng.normal(0, 1e-9, size=len(qs[1]))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(kind="wdtw", g=0.05)
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    lco = min(max(np.diff(qo)), max(np.diff(ro)))
+    try:
+        for g, c in ROW_SHAPES64 + [(16, 32), (32, 32), (64, 32)]:
+            eap.tune_reset()
+            eap.tune_set("wdtw", 1, lco, g, c)
+            log(f"exact-difference WDTW, shape {g}x{c}")
+            eap.profile_take()
+            eap.profile_enable(True)
+            gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=1)
+            torch.cuda.synchronize()
+            eap.profile_enable(False)
+            main = [x for x in eap.profile_take() if x["stage"] == 2]
+            assert main and all(x["kernel"] == "rows" and x["fp32"] and x["exact_diff"] for x in main), main
+            assert all(x["group"] == g and x["size"] == g * c for x in main), (g, c, main)
+            assert np.array_equal(gi.cpu().numpy(), oi), (g, c)
+            assert np.array_equal(gd.cpu().numpy(), od), (g, c)
+    finally:
+        eap.profile_enable(False)
+        eap.tune_reset()
+
+
 def test_fp32_screen_ragged_windows(torch_dev, orc):
     torch, dev = torch_dev
     rng = np.random.default_rng(8)
