@@ -920,6 +920,36 @@ def test_exact_difference_row_shapes_wdtw_long(torch_dev, orc):
         eap.tune_reset()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["erp", "msm", "twe"])
+def test_every_row_shape_long_series(torch_dev, orc, kind, precision):
+    """Long series (queries of 1500..2048 values, candidates of 64..2048) with
+    every row-sweep shape pinned in turn: strips up to 1024 columns, TWE's
+    per-diagonal window at the far ends of its table, the edge buffers of many
+    strips.  Each shape gives the oracle's NN bit for bit."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(92 + precision)
+    qs = synth.random_walks(rng, 3, (1500, 2048))
+    rs = synth.random_walks(rng, 10, (64, 2048))
+    qv, qo = synth.pack(qs)
+    rv, ro = synth.pack(rs)
+    p = dict(synth.DEFAULT_PARAMS[kind])
+    oi, od, _ = orc.nn1(p, qv, qo, rv, ro, "dp")
+    q, r = to_dev(torch, dev, qv), to_dev(torch, dev, rv)
+    lco = min(max(np.diff(qo)), max(np.diff(ro)))
+    try:
+        for g, c in ROW_SHAPES64:
+            eap.tune_reset()
+            eap.tune_set(kind, precision, lco, g, c)
+            log(f"long series {kind} precision={precision} shape {g}x{c}")
+            gi, gd, _ = eap.nn1(q, qo, r, ro, p, precision=precision)
+            torch.cuda.synchronize()
+            assert np.array_equal(gi.cpu().numpy(), oi), (g, c)
+            assert np.array_equal(gd.cpu().numpy(), od), (g, c)
+    finally:
+        eap.tune_reset()
+
+
 def test_fp32_screen_ragged_windows(torch_dev, orc):
     torch, dev = torch_dev
     rng = np.random.default_rng(8)
