@@ -556,65 +556,112 @@ __global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double*
             acc[t] = 0.0;
             sp[t] = 0.0;
         }
-        double rprev = 0.0;   // TWE: r_{k-1} (0 before the first)
-        constexpr int CH = 4;
-        for (int k0 = 0; k0 < kmax; k0 += CH) {
-            double rv[CH];
+        if constexpr (KIND == DTW || KIND == CDTW || KIND == WDTW) {
+            constexpr int CH = 2;
+            // The squared costs, a chunk of CH positions at a time: the candidate
+            // values (coalesced loads) and the queries' values (scalar loads) are
+            // all issued before any is used, and each term enters its sum through
+            // a select, so no branch sits between a load and its use (a branch
+            // around each term would hold each query value's load until its use).
+            // A full tile of QT queries runs without a per-query guard.
+            auto chunk = [&](int k0, auto full_tag) {
+                constexpr bool FULL = decltype(full_tag)::value;
+                double rv[CH], qv[QT][CH];
+                // past its end a lane reads its own last value (the tail's fixed
+                // column value): the index is clamped, the load unconditional
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int k = k0 + u;
-                rv[u] = (k < lr) ? rT[(int64_t)(k < lr_max ? k : lr_max - 1) * nB + bb] : rlast;
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int k = k0 + u;
-                const double r = rv[u];
+                for (int u = 0; u < CH; ++u) {
+                    const int k = k0 + u;
+                    rv[u] = rT[(int64_t)(k < lr ? k : lr - 1) * nB + bb];
+                }
 #pragma unroll
                 for (int t = 0; t < QT; ++t) {
-                    if (t >= nqt) continue;
-                    const int kq = k < lq[t] ? k : lq[t] - 1;
-                    const double q = qc[qb[t] + kq];
-                    const bool dg = k < Lco[t], tl = !dg && k < Lli[t];
-                    const double d = q - r;
-                    double term = 0.0;
-                    // the longer series' value (rows of the path) and the previous one
-                    const double s = (lq[t] >= lr) ? q : r;
-                    if constexpr (KIND == DTW || KIND == CDTW) term = d * d;
-                    if constexpr (KIND == WDTW) {
-                        double w = wd[t];
-                        if (tl) {
+                    if (!FULL && t >= nqt) continue;
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int k = k0 + u;
+                        qv[t][u] = qc[qb[t] + (k < lq[t] ? k : lq[t] - 1)];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int k = k0 + u;
+                    const double r = rv[u];
+#pragma unroll
+                    for (int t = 0; t < QT; ++t) {
+                        if (!FULL && t >= nqt) continue;
+                        const double q = qv[t][u];
+                        const bool dg = k < Lco[t], tl = !dg && k < Lli[t];
+                        const double d = q - r;
+                        double term = 0.0;
+                        if constexpr (KIND == DTW || KIND == CDTW) term = d * d;
+                        if constexpr (KIND == WDTW) {
                             int gi = 2 * (k + 1 - Lco[t]) - Lli[t] + A.gtab_off;
                             gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
-                            w = A.gtab[gi];
+                            const double wt = A.gtab[gi];
+                            term = (tl ? wt : wd[t]) * (d * d);
                         }
-                        term = w * (d * d);
+                        const double na = term + acc[t];
+                        acc[t] = (dg || tl) ? na : acc[t];
                     }
-                    if constexpr (KIND == ERP) term = dg ? __builtin_fabs(d) : __builtin_fabs(s - A.gap);
-                    if constexpr (KIND == MSM) {
-                        if (dg) {
-                            term = __builtin_fabs(d);
-                        } else {
-                            // C(s_i, s_{i-1}, t) of eq. MSMCost, t the shorter series' last value
-                            const double x = sp[t], tt = (lq[t] >= lr) ? r : q;
-                            if ((x <= s && s <= tt) || (x >= s && s >= tt)) term = A.c;
-                            else {
-                                const double p1 = __builtin_fabs(s - x), p2 = __builtin_fabs(s - tt);
-                                term = A.c + (p1 < p2 ? p1 : p2);
+                }
+            };
+            if (nqt == QT) {
+                for (int k0 = 0; k0 < kmax; k0 += CH) chunk(k0, std::true_type{});
+            } else {
+                for (int k0 = 0; k0 < kmax; k0 += CH) chunk(k0, std::false_type{});
+            }
+        } else {
+            // ERP, MSM and TWE: one query load per term (their tail terms also
+            // take the longer series' previous value, and batching their loads
+            // costs more registers than it saves)
+            double rprev = 0.0;   // TWE: r_{k-1} (0 before the first)
+            constexpr int CH = 4;
+            for (int k0 = 0; k0 < kmax; k0 += CH) {
+                double rv[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int k = k0 + u;
+                    rv[u] = (k < lr) ? rT[(int64_t)(k < lr_max ? k : lr_max - 1) * nB + bb] : rlast;
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int k = k0 + u;
+                    const double r = rv[u];
+#pragma unroll
+                    for (int t = 0; t < QT; ++t) {
+                        if (t >= nqt) continue;
+                        const int kq = k < lq[t] ? k : lq[t] - 1;
+                        const double q = qc[qb[t] + kq];
+                        const bool dg = k < Lco[t], tl = !dg && k < Lli[t];
+                        const double d = q - r;
+                        double term = 0.0;
+                        // the longer series' value (rows of the path) and the previous one
+                        const double s = (lq[t] >= lr) ? q : r;
+                        if constexpr (KIND == ERP) term = dg ? __builtin_fabs(d) : __builtin_fabs(s - A.gap);
+                        if constexpr (KIND == MSM) {
+                            if (dg) {
+                                term = __builtin_fabs(d);
+                            } else {
+                                // C(s_i, s_{i-1}, t) of eq. MSMCost, t the shorter series' last value
+                                const double x = sp[t], tt = (lq[t] >= lr) ? r : q;
+                                if ((x <= s && s <= tt) || (x >= s && s >= tt)) term = A.c;
+                                else {
+                                    const double p1 = __builtin_fabs(s - x), p2 = __builtin_fabs(s - tt);
+                                    term = A.c + (p1 < p2 ? p1 : p2);
+                                }
                             }
                         }
+                        if constexpr (KIND == TWE) {
+                            const double qp = k > 0 ? qc[qb[t] + (k - 1 < lq[t] ? k - 1 : lq[t] - 1)] : 0.0;
+                            term = dg ? ((__builtin_fabs(d) + __builtin_fabs(qp - rprev)) + A.nu * 0.0)
+                                      : ((__builtin_fabs(s - sp[t]) + A.nu) + A.lam);
+                        }
+                        if (dg || tl) acc[t] = acc[t] + term;
+                        sp[t] = s;
                     }
-                    if constexpr (KIND == TWE) {
-                        const double qp = k > 0 ? qc[qb[t] + (k - 1 < lq[t] ? k - 1 : lq[t] - 1)] : 0.0;
-                        term = dg ? ((__builtin_fabs(d) + __builtin_fabs(qp - rprev)) + A.nu * 0.0)
-                                  : ((__builtin_fabs(s - sp[t]) + A.nu) + A.lam);
-                    }
-                    if (dg || tl) {
-                        if constexpr (KIND == DTW || KIND == CDTW || KIND == WDTW) acc[t] = term + acc[t];
-                        else acc[t] = acc[t] + term;
-                    }
-                    sp[t] = s;
+                    if constexpr (KIND == TWE) rprev = r;
                 }
-                if constexpr (KIND == TWE) rprev = r;
             }
         }
         if (live) {
