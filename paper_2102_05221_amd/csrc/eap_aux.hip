@@ -640,17 +640,15 @@ __global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double*
                         const double s = (lq[t] >= lr) ? q : r;
                         if constexpr (KIND == ERP) term = dg ? __builtin_fabs(d) : __builtin_fabs(s - A.gap);
                         if constexpr (KIND == MSM) {
-                            if (dg) {
-                                term = __builtin_fabs(d);
-                            } else {
-                                // C(s_i, s_{i-1}, t) of eq. MSMCost, t the shorter series' last value
-                                const double x = sp[t], tt = (lq[t] >= lr) ? r : q;
-                                if ((x <= s && s <= tt) || (x >= s && s >= tt)) term = A.c;
-                                else {
-                                    const double p1 = __builtin_fabs(s - x), p2 = __builtin_fabs(s - tt);
-                                    term = A.c + (p1 < p2 ? p1 : p2);
-                                }
-                            }
+                            // C(s_i, s_{i-1}, t) of eq. MSMCost, t the shorter series'
+                            // last value: c, plus the distance from s to the nearer end
+                            // of [min(x, t), max(x, t)] when s lies outside it (that
+                            // end's rounded difference is the smaller of the two, so
+                            // the value equals the case-by-case form), without branches
+                            const double x = sp[t], tt = (lq[t] >= lr) ? r : q;
+                            const double lo = fmin(x, tt), hi = fmax(x, tt);
+                            const double tail = A.c + fmax(fmax(lo - s, s - hi), 0.0);
+                            term = dg ? __builtin_fabs(d) : tail;
                         }
                         if constexpr (KIND == TWE) {
                             const double qp = k > 0 ? qc[qb[t] + (k - 1 < lq[t] ? k - 1 : lq[t] - 1)] : 0.0;
