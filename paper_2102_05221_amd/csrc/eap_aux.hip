@@ -615,7 +615,10 @@ __global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double*
             // ERP, MSM and TWE: one query load per term (their tail terms also
             // take the longer series' previous value, and batching their loads
             // costs more registers than it saves)
-            double rprev = 0.0;   // TWE: r_{k-1} (0 before the first)
+            // TWE: |q_{k-1} - r_{k-1}|, the previous position's |d| (0 before the first)
+            double adp[KIND == TWE ? QT : 1];
+#pragma unroll
+            for (int t = 0; t < (KIND == TWE ? QT : 1); ++t) adp[t] = 0.0;
             constexpr int CH = 4;
             for (int k0 = 0; k0 < kmax; k0 += CH) {
                 double rv[CH];
@@ -651,14 +654,15 @@ __global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double*
                             term = dg ? __builtin_fabs(d) : tail;
                         }
                         if constexpr (KIND == TWE) {
-                            const double qp = k > 0 ? qc[qb[t] + (k - 1 < lq[t] ? k - 1 : lq[t] - 1)] : 0.0;
-                            term = dg ? ((__builtin_fabs(d) + __builtin_fabs(qp - rprev)) + A.nu * 0.0)
+                            // the match's second difference is the previous position's
+                            // (the same operands, so the same rounded value)
+                            term = dg ? ((__builtin_fabs(d) + adp[t < (KIND == TWE ? QT : 1) ? t : 0]) + A.nu * 0.0)
                                       : ((__builtin_fabs(s - sp[t]) + A.nu) + A.lam);
+                            adp[t < (KIND == TWE ? QT : 1) ? t : 0] = __builtin_fabs(d);
                         }
                         if (dg || tl) acc[t] = acc[t] + term;
                         sp[t] = s;
                     }
-                    if constexpr (KIND == TWE) rprev = r;
                 }
             }
         }
