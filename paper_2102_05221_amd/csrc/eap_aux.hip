@@ -773,11 +773,14 @@ __global__ __launch_bounds__(256) void ub_lb_kernel(SweepArgs A, const double* q
         if (nqt == QT) sweep(std::true_type{});
         else sweep(std::false_type{});
         // queries longer than the candidate: their tail against its last value
+        // (not for a pair whose window admits no path: its bound stays +inf, and
+        // the wave's loop then runs only as long as its feasible pairs' tails)
         const double xl = rv ? rv[ro + lr - 1] : rT[(int64_t)(lr - 1) * nB + bb];
 #pragma unroll
         for (int t = 0; t < QT; ++t) {
             if (t >= nqt) continue;
-            for (int i = lr; i < lq[t]; ++i) {
+            const int iend = (acc[t] < __builtin_huge_val()) ? lq[t] : lr;
+            for (int i = lr; i < iend; ++i) {
                 const double d = qv[qb[t] + i] - xl;
                 acc[t] = (d * d) + acc[t];
             }
