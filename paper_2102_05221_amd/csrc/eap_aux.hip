@@ -515,9 +515,18 @@ __global__ __launch_bounds__(256) void lb_reverse_kernel(const double* qv, const
 // longer series' own previous value, pick the longer series by a select.
 template <int KIND, int QT>
 __global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double* qv, const int64_t* qoff,
-                                                      const double* rT, const int64_t* roff, int lr_max, double* ub) {
+                                                      const double* rT, const int64_t* roff, int lr_max, int ltab,
+                                                      double* ub) {
     typedef const __attribute__((address_space(4))) double* cdp;
     typedef const __attribute__((address_space(4))) int64_t* cip;
+    // WDTW: the weights of m = -ltab .. ltab (every m = 2|d| - L a pair of
+    // these lengths forms) copied to LDS, gsh[m + ltab]: the tail's weight is a
+    // different entry for every lane, an LDS read instead of a global gather
+    extern __shared__ double gsh[];
+    if constexpr (KIND == WDTW) {
+        for (int i = threadIdx.x; i <= 2 * ltab; i += blockDim.x) gsh[i] = A.gtab[A.gtab_off - ltab + i];
+        __syncthreads();
+    }
     const int64_t nB = A.nB;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = b < nB;
@@ -596,9 +605,10 @@ __global__ __launch_bounds__(256) void ub_nn_t_kernel(SweepArgs A, const double*
                         double term = 0.0;
                         if constexpr (KIND == DTW || KIND == CDTW) term = d * d;
                         if constexpr (KIND == WDTW) {
-                            int gi = 2 * (k + 1 - Lco[t]) - Lli[t] + A.gtab_off;
-                            gi = gi < 0 ? 0 : (gi >= A.gtab_len ? A.gtab_len - 1 : gi);
-                            const double wt = A.gtab[gi];
+                            // a tail cell's m lies in 2 - L .. L; others read a clamped entry
+                            int gi = 2 * (k + 1 - Lco[t]) - Lli[t] + ltab;
+                            gi = gi < 0 ? 0 : (gi > 2 * ltab ? 2 * ltab : gi);
+                            const double wt = gsh[gi];
                             term = (tl ? wt : wd[t]) * (d * d);
                         }
                         const double na = term + acc[t];
@@ -1469,7 +1479,11 @@ hipError_t launch_ub_nn(int kind, const SweepArgs& a, const double* qv, const in
             break;
         }
     const dim3 g((unsigned)bx, (unsigned)std::min<int64_t>((a.nA + qt - 1) / qt, 65535)), b(256);
-#define EAP_UBT(K, QT) hipLaunchKernelGGL((ub_nn_t_kernel<K, QT>), g, b, 0, s, a, qv, qoff, rT, roff, lr_max, ub)
+    // WDTW's weight table in LDS: m = 2|d| - L within -lmax .. lmax
+    const int ltab = std::max(lq_max, lr_max);
+    const size_t lds = (kind == WDTW) ? sizeof(double) * (size_t)(2 * ltab + 1) : 0;
+#define EAP_UBT(K, QT) \
+    hipLaunchKernelGGL((ub_nn_t_kernel<K, QT>), g, b, lds, s, a, qv, qoff, rT, roff, lr_max, ltab, ub)
 #define EAP_UBQ(K)             \
     switch (qt) {              \
     case 8: EAP_UBT(K, 8); break; \
